@@ -1,0 +1,191 @@
+"""OPMM oracle -- test infrastructure only.
+
+A plain, serial FP64 CPU implementation (``opmm_oracle.c``) of what the OPMM
+estimation path computes, plus the plain numpy reference for the surrogate MLP
+(``mlp_ref``).  Only the test-suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the GPU path and never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "opmm_oracle.c")
+_SO = os.path.join(_HERE, "libopmm_oracle.so")
+NP_ = 18
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc: FP64, no fast-math, no FMA contraction."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC,
+                               "-lm", "-lpthread"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_SO)
+        d, i, f = ctypes.c_double, ctypes.c_int, ctypes.c_float
+        P = ctypes.c_void_p
+        u64, i64, u32 = ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32
+        L.oracle_nominal.argtypes = [d, P]
+        L.oracle_rhs.argtypes = [P, P, d, d, d, d, P]
+        L.oracle_equilibrium.argtypes = [P, d, d, P]
+        L.oracle_control_levels.argtypes = [P, d, P]
+        L.oracle_simulate_levels.argtypes = [P, P, i, d, i, P, P]
+        L.oracle_simulate_levels.restype = i
+        L.oracle_simulate.argtypes = [P, d, i, d, i, P]
+        L.oracle_simulate.restype = i
+        L.oracle_cost.argtypes = [P, P, i, i, d, P, P]
+        L.oracle_splitmix64.argtypes = [u64, u64]
+        L.oracle_splitmix64.restype = u64
+        L.oracle_candidate.argtypes = [u64, u32, u32, P, P, P, P, P]
+        L.oracle_initial_box.argtypes = [d, f, P, P, P, P]
+        L.oracle_score.argtypes = [P, i64, P, i, i, d, d, d, i, i, P, P]
+        L.oracle_score.restype = i
+        L.oracle_fit.argtypes = [P, i, i, d, d, d, d, u64, i64, i, f, f, f, P, i, i,
+                                 P, P, P, P, P, P]
+        L.oracle_fit.restype = i
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None:
+        assert a.shape == (n,), a.shape
+    return a
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+NSUB = 16  # RK4 substeps per sample
+
+
+def nominal(dur_ms: float) -> np.ndarray:
+    out = np.zeros(NP_)
+    lib().oracle_nominal(float(dur_ms), _p(out))
+    return out
+
+
+def rhs(p, x, n_ag, n_ant, tau_ag, tau_ant) -> np.ndarray:
+    p = _f64(p, NP_); x = _f64(x, 6); dx = np.zeros(6)
+    lib().oracle_rhs(_p(p), _p(x), n_ag, n_ant, tau_ag, tau_ant, _p(dx))
+    return dx
+
+
+def equilibrium(p, f_ag, f_ant) -> np.ndarray:
+    p = _f64(p, NP_); x = np.zeros(6)
+    lib().oracle_equilibrium(_p(p), float(f_ag), float(f_ant), _p(x))
+    return x
+
+
+def control_levels(p, amp) -> np.ndarray:
+    p = _f64(p, NP_); lv = np.zeros(6)
+    lib().oracle_control_levels(_p(p), float(amp), _p(lv))
+    return lv
+
+
+def simulate_levels(p, levels, T, dt_ms=1.0, nsub=NSUB, states=False):
+    p = _f64(p, NP_); lv = _f64(levels, 6)
+    th = np.zeros(max(T, 1)); st = np.zeros((max(T, 1), 6)) if states else None
+    rc = lib().oracle_simulate_levels(_p(p), _p(lv), int(T), float(dt_ms), int(nsub), _p(th),
+                                      _p(st) if states else None)
+    assert rc == 0
+    return (th[:T], st[:T]) if states else th[:T]
+
+
+def simulate(p, amp, T, dt_ms=1.0, nsub=NSUB) -> np.ndarray:
+    p = _f64(p, NP_); th = np.zeros(max(T, 1))
+    assert lib().oracle_simulate(_p(p), float(amp), int(T), float(dt_ms), int(nsub), _p(th)) == 0
+    return th[:T]
+
+
+def cost(theta, pos, dir_deg):
+    theta = _f64(theta); pos = _f32(pos)
+    T = theta.shape[0]; C = pos.shape[1]
+    assert pos.shape == (T, C)
+    r = ctypes.c_double(); m = ctypes.c_double()
+    lib().oracle_cost(_p(theta), _p(pos), T, C, float(dir_deg), ctypes.byref(r), ctypes.byref(m))
+    return r.value, m.value
+
+
+def splitmix64(seed: int, n: int) -> int:
+    return int(lib().oracle_splitmix64(ctypes.c_uint64(seed), ctypes.c_uint64(n)))
+
+
+def initial_box(dur_ms, frac=0.25):
+    c, w, lo, hi = (np.zeros(NP_, np.float32) for _ in range(4))
+    lib().oracle_initial_box(float(dur_ms), ctypes.c_float(frac), _p(c), _p(w), _p(lo), _p(hi))
+    return c, w, lo, hi
+
+
+def candidate(seed, rnd, idx, c, w, lo, hi) -> np.ndarray:
+    out = np.zeros(NP_, np.float32)
+    c, w, lo, hi = (_f32(a) for a in (c, w, lo, hi))
+    lib().oracle_candidate(ctypes.c_uint64(seed), rnd, idx, _p(c), _p(w), _p(lo), _p(hi), _p(out))
+    return out
+
+
+def candidates(seed, rnd, idxs, c, w, lo, hi) -> np.ndarray:
+    return np.stack([candidate(seed, rnd, int(i), c, w, lo, hi) for i in idxs])
+
+
+def score(opc, pos, amp, dir_deg, dt_ms=1.0, nsub=NSUB, nthreads=1):
+    """RMSE and mean-abs of each FP32 candidate (promoted to FP64) against one saccade."""
+    opc = _f32(opc).reshape(-1, NP_); pos = _f32(pos)
+    n = opc.shape[0]; T, C = pos.shape
+    r = np.zeros(n); m = np.zeros(n)
+    assert lib().oracle_score(_p(opc), n, _p(pos), T, C, float(amp), float(dir_deg), float(dt_ms),
+                              nsub, int(nthreads), _p(r), _p(m)) == 0
+    return r, m
+
+
+def fit(pos, amp, dir_deg, dur_ms, seed, n_cand, n_rounds, *, dt_ms=1.0, box_frac=0.25,
+        w_init_frac=1.0, shrink=0.5, c_init=None, nsub=NSUB, nthreads=1):
+    pos = _f32(pos); T, C = pos.shape
+    opc = np.zeros(NP_, np.float32); rm = ctypes.c_double(); ma = ctypes.c_double()
+    bi = np.zeros(n_rounds, np.int64); br = np.zeros(n_rounds); cen = np.zeros((n_rounds, NP_), np.float32)
+    ci = None if c_init is None else _f32(c_init)
+    rc = lib().oracle_fit(_p(pos), T, C, float(amp), float(dir_deg), float(dur_ms), float(dt_ms),
+                          ctypes.c_uint64(seed), int(n_cand), int(n_rounds), ctypes.c_float(box_frac),
+                          ctypes.c_float(w_init_frac), ctypes.c_float(shrink),
+                          None if ci is None else _p(ci), nsub, int(nthreads), _p(opc),
+                          ctypes.byref(rm), ctypes.byref(ma), _p(bi), _p(br), _p(cen))
+    assert rc == 0
+    return dict(opc=opc, rmse=rm.value, mae=ma.value, best_idx=bi, best_rmse=br, centres=cen)
+
+
+def true_opc(mult, dur_ms) -> np.ndarray:
+    """A synthetic 'true' OPC: the Table 1 nominal scaled component-wise."""
+    return nominal(dur_ms) * np.asarray(mult, np.float64)
+
+
+def make_target(p_true, amp, dir_deg, T, C, noise_z, sigma):
+    """Recorded-trace stand-in: the plant's prediction along the direction plus
+    Gaussian noise, built in FP64 and rounded once to FP32, [T][C]."""
+    th = simulate(p_true, amp, T)
+    phi = np.deg2rad(dir_deg)
+    u = np.array([np.cos(phi), np.sin(phi)])[:C]
+    pos = th[:, None] * u[None, :] + sigma * np.asarray(noise_z, np.float64).reshape(T, C)
+    return pos.astype(np.float32)

@@ -1,0 +1,400 @@
+/*
+ * OPMM oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, serial, FP64 CPU implementation of what the OPMM estimation path
+ * computes, written to be checked by eye against the paper (arXiv 2007.09884,
+ * "Parallel Oculomotor Plant Mathematical Model for Large Scale Eye Movement
+ * Simulation").  Only the test-suite, the smoke check and the CPU-baseline leg
+ * of the benchmark may load it; the product library never does, and this file
+ * shares no code, header, table or helper with the GPU path.
+ *
+ * Units here are the paper's Table 1 units: time in seconds for the mechanics
+ * (J in g*s^2/deg, B in g*s/deg), time constants and the pulse width in ms as
+ * printed, angles in degrees, forces in grams.  (The GPU path works in ms; the
+ * two were written independently.)
+ *
+ * What the paper fixes and what is a reading (each reading is listed in the
+ * design notes):
+ *   - Parameter set, order and nominal values: Section 2.2.1, Table 1.
+ *   - Component semantics (series elasticity, length-tension, force-velocity,
+ *     tension slope/intercept, inertia, passive viscosity; pulse-step control
+ *     with activation at onset and deactivation at offset): Section 2.1.
+ *   - The equations themselves are not printed.  The plant below is the
+ *     linear homeomorphic reading: 6 states (theta, omega, x_ag, x_ant, F_ag,
+ *     F_ant), passive elasticity K_P = N_C_AG + N_C_ANT, step levels that hold
+ *     the eye at the fixation before and after the saccade.
+ *   - Cost: root-mean-square difference between recorded and simulated
+ *     trajectories (mean absolute difference, the paper's OptErr of
+ *     Section 3.4, is reported alongside).
+ *   - Search: uniform candidates in a box around the centre, argmin, box
+ *     halving (the paper's estimator is Nelder-Mead, Section 3.3; the box
+ *     search is the build's data-parallel estimator).
+ *
+ * Integrator: classical fixed-step RK4, nsub substeps per sample, the sample
+ * that contains the pulse end split exactly at PW.  Pinned in the tests
+ * against the matrix-exponential solution of the piecewise-LTI plant.
+ */
+#define _GNU_SOURCE
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+
+#define NP 18
+
+/* Table 1 (Section 2.2.1): nominal values in the table's order and units.
+ * The pulse width PW has no number in the table: it is the saccade duration
+ * minus 6 ms, filled in by oracle_nominal(). */
+static const double TABLE1_NOMINAL[17] = {
+    2.5,      /* K_SE_AG  series elasticity, agonist (g/deg)        */
+    2.5,      /* K_SE_ANT series elasticity, antagonist             */
+    1.2,      /* K_LT_AG  length-tension, agonist (g/deg)           */
+    1.2,      /* K_LT_ANT length-tension, antagonist                */
+    0.046,    /* B_AG     force-velocity, agonist (g s/deg)         */
+    0.022,    /* B_ANT    force-velocity, antagonist                */
+    0.06,     /* B_P      passive viscosity (g s/deg)               */
+    0.8,      /* N_C_AG   tension slope, agonist (g/deg)            */
+    0.5,      /* N_C_ANT  tension slope, antagonist                 */
+    0.000043, /* J        inertial mass (g s^2/deg)                 */
+    11.7,     /* tau_AC_AG  activation time, agonist (ms)           */
+    2.4,      /* tau_AC_ANT activation time, antagonist (ms)        */
+    2.0,      /* tau_DE_AG  deactivation time, agonist (ms)         */
+    1.9,      /* tau_DE_ANT deactivation time, antagonist (ms)      */
+    14.0,     /* N_C_FIX  tension intercept (g)                     */
+    55.0,     /* N_SAC_AG neural pulse height, agonist (g)          */
+    0.5,      /* N_SAC_ANT neural pulse height, antagonist (g)      */
+};
+
+void oracle_nominal(double dur_ms, double out[NP])
+{
+    for (int j = 0; j < 17; ++j) out[j] = TABLE1_NOMINAL[j];
+    out[17] = dur_ms - 6.0; /* Table 1: PW = saccade duration - 6 ms */
+}
+
+/* ------------------------------------------------------------------------- */
+/* Plant                                                                      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double kse_ag, kse_ant, klt_ag, klt_ant;
+    double b_ag, b_ant, bp, kp, j;
+    double tac_ag, tac_ant, tde_ag, tde_ant; /* seconds */
+    double pw;                               /* seconds */
+} plant_t;
+
+static void plant_from_opc(const double p[NP], plant_t* q)
+{
+    q->kse_ag = p[0];  q->kse_ant = p[1];
+    q->klt_ag = p[2];  q->klt_ant = p[3];
+    q->b_ag = p[4];    q->b_ant = p[5];   q->bp = p[6];
+    q->kp = p[7] + p[8];        /* passive elasticity: the tension slopes' sum */
+    q->j = p[9];
+    q->tac_ag = p[10] * 1e-3;  q->tac_ant = p[11] * 1e-3;
+    q->tde_ag = p[12] * 1e-3;  q->tde_ant = p[13] * 1e-3;
+    q->pw = p[17] * 1e-3;
+}
+
+/* Fixation tensions of Section 2.1 ("muscle force at eccentricities at the
+ * equilibrium points"): T_AG(th) = N_C_FIX + N_C_AG*th,
+ * T_ANT(th) = N_C_FIX - N_C_ANT*th.  The neural step that holds the eye at th
+ * adds what the length-tension element and the series element take up:
+ * S_AG = T_AG*(K_SE+K_LT)/K_SE + K_LT_AG*th, S_ANT = T_ANT*(K_SE+K_LT)/K_SE - K_LT_ANT*th. */
+static void step_levels(const double p[NP], double th, double* s_ag, double* s_ant)
+{
+    double t_ag = p[14] + p[7] * th;
+    double t_ant = p[14] - p[8] * th;
+    *s_ag = t_ag * (p[0] + p[2]) / p[0] + p[2] * th;
+    *s_ant = t_ant * (p[1] + p[3]) / p[1] - p[3] * th;
+}
+
+/* Time derivative of the state x = (theta, omega, x_ag, x_ant, F_ag, F_ant)
+ * under constant neural inputs n_ag, n_ant and active-state time constants
+ * tau_ag, tau_ant (s).  x_m is the contractile-element shortening of muscle m
+ * in degree-equivalents; the series element of the agonist is stretched by
+ * x_ag - theta, that of the antagonist by x_ant + theta.
+ *   globe:           J w' = K_SE_AG(x_ag - th) - K_SE_ANT(x_ant + th) - B_P w - K_P th
+ *   force-velocity:  B_m x_m' = F_m - K_LT_m x_m - (series tension)
+ *   active state:    tau_m F_m' = N_m - F_m                                 */
+void oracle_rhs(const double p[NP], const double x[6], double n_ag, double n_ant,
+                double tau_ag, double tau_ant, double dx[6])
+{
+    plant_t q;
+    plant_from_opc(p, &q);
+    double th = x[0], w = x[1], xa = x[2], xn = x[3], fa = x[4], fn = x[5];
+    double t_se_ag = q.kse_ag * (xa - th);
+    double t_se_ant = q.kse_ant * (xn + th);
+    dx[0] = w;
+    dx[1] = (t_se_ag - t_se_ant - q.bp * w - q.kp * th) / q.j;
+    dx[2] = (fa - q.klt_ag * xa - t_se_ag) / q.b_ag;
+    dx[3] = (fn - q.klt_ant * xn - t_se_ant) / q.b_ant;
+    dx[4] = (n_ag - fa) / tau_ag;
+    dx[5] = (n_ant - fn) / tau_ant;
+}
+
+/* Equilibrium of the plant when both active states sit at (f_ag, f_ant):
+ * set every derivative to zero and solve the statics in closed form. */
+void oracle_equilibrium(const double p[NP], double f_ag, double f_ant, double x[6])
+{
+    plant_t q;
+    plant_from_opc(p, &q);
+    double c_ag = q.kse_ag / (q.kse_ag + q.klt_ag);
+    double c_ant = q.kse_ant / (q.kse_ant + q.klt_ant);
+    double th = (c_ag * f_ag - c_ant * f_ant) / (q.kp + c_ag * q.klt_ag + c_ant * q.klt_ant);
+    double t_ag = c_ag * (f_ag - q.klt_ag * th);   /* series tensions */
+    double t_ant = c_ant * (f_ant + q.klt_ant * th);
+    x[0] = th;
+    x[1] = 0.0;
+    x[2] = th + t_ag / q.kse_ag;
+    x[3] = t_ant / q.kse_ant - th;
+    x[4] = f_ag;
+    x[5] = f_ant;
+}
+
+static void rk4_span(const double p[NP], double x[6], double span, int nsub,
+                     double n_ag, double n_ant, double tau_ag, double tau_ant)
+{
+    double h = span / nsub;
+    for (int s = 0; s < nsub; ++s) {
+        double k1[6], k2[6], k3[6], k4[6], y[6];
+        oracle_rhs(p, x, n_ag, n_ant, tau_ag, tau_ant, k1);
+        for (int i = 0; i < 6; ++i) y[i] = x[i] + 0.5 * h * k1[i];
+        oracle_rhs(p, y, n_ag, n_ant, tau_ag, tau_ant, k2);
+        for (int i = 0; i < 6; ++i) y[i] = x[i] + 0.5 * h * k2[i];
+        oracle_rhs(p, y, n_ag, n_ant, tau_ag, tau_ant, k3);
+        for (int i = 0; i < 6; ++i) y[i] = x[i] + h * k3[i];
+        oracle_rhs(p, y, n_ag, n_ant, tau_ag, tau_ant, k4);
+        for (int i = 0; i < 6; ++i) x[i] += h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+    }
+}
+
+/* Pulse-step simulation with explicit control levels (Section 2.1): the eye
+ * rests at the equilibrium of the pre-saccadic levels (pre_ag, pre_ant); the
+ * pulse (pul_ag, pul_ant) is on for t in [0, PW) with the activation time
+ * constants; from t = PW on the post-saccadic step (post_ag, post_ant) acts
+ * with the deactivation time constants.  theta at t_k = k*dt_ms, k < T. */
+int oracle_simulate_levels(const double p[NP], const double lv[6], int T, double dt_ms,
+                           int nsub, double* theta, double* state_out)
+{
+    if (T < 0 || !(dt_ms > 0) || nsub < 1) return -1;
+    plant_t q;
+    plant_from_opc(p, &q);
+    double x[6];
+    oracle_equilibrium(p, lv[0], lv[1], x);
+    double dt = dt_ms * 1e-3;
+    for (int k = 0; k < T; ++k) {
+        theta[k] = x[0];
+        if (state_out) memcpy(state_out + 6 * k, x, sizeof x);
+        if (k == T - 1) break;
+        double t0 = k * dt, t1 = (k + 1) * dt;
+        if (t1 <= q.pw) {
+            rk4_span(p, x, dt, nsub, lv[2], lv[3], q.tac_ag, q.tac_ant);
+        } else if (t0 >= q.pw) {
+            rk4_span(p, x, dt, nsub, lv[4], lv[5], q.tde_ag, q.tde_ant);
+        } else { /* the pulse ends inside this sample: split exactly at PW */
+            rk4_span(p, x, q.pw - t0, nsub, lv[2], lv[3], q.tac_ag, q.tac_ant);
+            rk4_span(p, x, t1 - q.pw, nsub, lv[4], lv[5], q.tde_ag, q.tde_ant);
+        }
+    }
+    return 0;
+}
+
+/* The model's own control for a saccade of amplitude amp (deg): the step
+ * holds fixation at 0 before and at amp after; the pulse heights are the
+ * OPC's N_SAC_AG and N_SAC_ANT. */
+void oracle_control_levels(const double p[NP], double amp, double lv[6])
+{
+    step_levels(p, 0.0, &lv[0], &lv[1]);
+    lv[2] = p[15];
+    lv[3] = p[16];
+    step_levels(p, amp, &lv[4], &lv[5]);
+}
+
+int oracle_simulate(const double p[NP], double amp, int T, double dt_ms, int nsub, double* theta)
+{
+    double lv[6];
+    oracle_control_levels(p, amp, lv);
+    return oracle_simulate_levels(p, lv, T, dt_ms, nsub, theta, NULL);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cost                                                                       */
+/* ------------------------------------------------------------------------- */
+
+/* The 1-D plant moves along the saccade direction phi (Section 2.2: either
+ * version simulates one-dimensional movement).  With C = 2 the prediction is
+ * (theta cos phi, theta sin phi); with C = 1 the single channel is the
+ * horizontal one, theta cos phi.  RMSE over all samples and channels; the
+ * mean absolute difference (the paper's OptErr) alongside. */
+void oracle_cost(const double* theta, const float* pos, int T, int C, double dir_deg,
+                 double* rmse, double* mae)
+{
+    double phi = dir_deg * (M_PI / 180.0);
+    double u[2] = {cos(phi), sin(phi)};
+    double sq = 0.0, ab = 0.0;
+    for (int k = 0; k < T; ++k)
+        for (int c = 0; c < C; ++c) {
+            double e = (double)pos[k * C + c] - theta[k] * u[c];
+            sq += e * e;
+            ab += fabs(e);
+        }
+    double n = (double)T * C;
+    double r = sqrt(sq / n);
+    if (!(r <= HUGE_VAL)) r = HUGE_VAL; /* NaN ranks last */
+    *rmse = r;
+    if (mae) *mae = ab / n;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Candidates                                                                 */
+/* ------------------------------------------------------------------------- */
+
+/* SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): the n-th output (n >= 1) of
+ * the generator seeded with `seed` is mix(seed + n * golden_gamma). */
+uint64_t oracle_splitmix64(uint64_t seed, uint64_t n)
+{
+    uint64_t z = seed + n * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* Candidate idx of round r for a saccade keyed by seed.  Candidate 0 is the
+ * centre itself.  Otherwise draw k (k = 0..8) is SplitMix64 output number
+ * 1 + (r << 36 | idx << 4 | k); its top 24 bits give parameter 2k and the next
+ * 24 bits parameter 2k+1.  A 24-bit draw u maps to s = u/2^23 - 1 in [-1, 1)
+ * (exact in FP32), the parameter is fma(w, s, c) rounded once to FP32 and then
+ * clamped to the search box [lo, hi]. */
+void oracle_candidate(uint64_t seed, uint32_t round, uint32_t idx, const float c[NP],
+                      const float w[NP], const float lo[NP], const float hi[NP], float out[NP])
+{
+    if (idx == 0) {
+        memcpy(out, c, NP * sizeof(float));
+        return;
+    }
+    for (int k = 0; k < 9; ++k) {
+        uint64_t n = 1 + (((uint64_t)round << 36) | ((uint64_t)idx << 4) | (uint64_t)k);
+        uint64_t z = oracle_splitmix64(seed, n);
+        uint32_t ua = (uint32_t)(z >> 40);
+        uint32_t ub = (uint32_t)((z >> 16) & 0xFFFFFFu);
+        uint32_t us[2] = {ua, ub};
+        for (int h = 0; h < 2; ++h) {
+            int j = 2 * k + h;
+            float s = (float)us[h] * 0x1p-23f - 1.0f;
+            float v = fmaf(w[j], s, c[j]);
+            if (v < lo[j]) v = lo[j];
+            if (v > hi[j]) v = hi[j];
+            out[j] = v;
+        }
+    }
+}
+
+/* Round-0 box: centre = nominal rounded to FP32 (PW from the duration),
+ * half-width = frac * centre, bounds = centre -/+ half-width in FP32. */
+void oracle_initial_box(double dur_ms, float frac, float c0[NP], float w0[NP], float lo[NP], float hi[NP])
+{
+    double nom[NP];
+    oracle_nominal(dur_ms, nom);
+    for (int j = 0; j < NP; ++j) {
+        c0[j] = (float)nom[j];
+        w0[j] = frac * c0[j];
+        lo[j] = c0[j] - w0[j];
+        hi[j] = c0[j] + w0[j];
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Scoring many candidates against one saccade (optionally threaded)          */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    const float* opc; int64_t n0, n1;
+    const float* pos; int T, C; double amp, dir, dt; int nsub;
+    double* rmse; double* mae;
+} score_job;
+
+static void* score_worker(void* arg)
+{
+    score_job* jb = (score_job*)arg;
+    double* th = (double*)malloc(sizeof(double) * (jb->T > 0 ? jb->T : 1));
+    for (int64_t i = jb->n0; i < jb->n1; ++i) {
+        double p[NP];
+        for (int j = 0; j < NP; ++j) p[j] = (double)jb->opc[i * NP + j];
+        oracle_simulate(p, jb->amp, jb->T, jb->dt, jb->nsub, th);
+        oracle_cost(th, jb->pos, jb->T, jb->C, jb->dir, &jb->rmse[i], jb->mae ? &jb->mae[i] : NULL);
+    }
+    free(th);
+    return NULL;
+}
+
+int oracle_score(const float* opc, int64_t n, const float* pos, int T, int C, double amp,
+                 double dir_deg, double dt_ms, int nsub, int nthreads, double* rmse, double* mae)
+{
+    if (n < 0 || T < 1 || (C != 1 && C != 2)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    pthread_t tid[256];
+    score_job jobs[256];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = (score_job){opc, n * t / nthreads, n * (t + 1) / nthreads, pos, T, C, amp, dir_deg, dt_ms, nsub, rmse, mae};
+        if (nthreads > 1) pthread_create(&tid[t], NULL, score_worker, &jobs[t]);
+        else score_worker(&jobs[t]);
+    }
+    if (nthreads > 1)
+        for (int t = 0; t < nthreads; ++t) pthread_join(tid[t], NULL);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Box search: candidates, argmin, halving                                    */
+/* ------------------------------------------------------------------------- */
+
+/* Fit one saccade.  Round r draws n_cand candidates around centre c^r with
+ * half-width w^r (candidate 0 = c^r), scores them all, takes the argmin (lowest
+ * RMSE, ties to the lowest index, NaN ranks last), and sets c^{r+1} to the
+ * winner and w^{r+1} = shrink * w^r.  c_init (nullable) replaces the nominal
+ * round-0 centre (it is clamped into the box); w_init_frac scales the round-0
+ * half-width relative to the box half-width.  Outputs: the final OPC, its
+ * RMSE and mean-abs, and per round the winner index, its RMSE and the centre
+ * the round was drawn around (centres: [n_rounds][18], nullable). */
+int oracle_fit(const float* pos, int T, int C, double amp, double dir_deg, double dur_ms,
+               double dt_ms, uint64_t seed, int64_t n_cand, int n_rounds, float box_frac,
+               float w_init_frac, float shrink, const float* c_init, int nsub, int nthreads,
+               float opc_out[NP], double* rmse_out, double* mae_out,
+               int64_t* best_idx, double* best_rmse, float* centres)
+{
+    if (n_cand < 1 || n_rounds < 1 || T < 1 || n_cand > 0xFFFFFFFFLL) return -1;
+    float c[NP], w[NP], lo[NP], hi[NP];
+    oracle_initial_box(dur_ms, box_frac, c, w, lo, hi);
+    for (int j = 0; j < NP; ++j) w[j] = w[j] * w_init_frac;
+    if (c_init)
+        for (int j = 0; j < NP; ++j) {
+            float v = c_init[j];
+            c[j] = v < lo[j] ? lo[j] : (v > hi[j] ? hi[j] : v);
+        }
+    float* cand = (float*)malloc(sizeof(float) * NP * n_cand);
+    double* cost = (double*)malloc(sizeof(double) * n_cand);
+    for (int r = 0; r < n_rounds; ++r) {
+        if (centres) memcpy(centres + (size_t)r * NP, c, sizeof c);
+        for (int64_t i = 0; i < n_cand; ++i)
+            oracle_candidate(seed, (uint32_t)r, (uint32_t)i, c, w, lo, hi, cand + i * NP);
+        oracle_score(cand, n_cand, pos, T, C, amp, dir_deg, dt_ms, nsub, nthreads, cost, NULL);
+        int64_t b = 0;
+        for (int64_t i = 1; i < n_cand; ++i)
+            if (cost[i] < cost[b]) b = i;
+        if (best_idx) best_idx[r] = b;
+        if (best_rmse) best_rmse[r] = cost[b];
+        memcpy(c, cand + b * NP, sizeof c);
+        for (int j = 0; j < NP; ++j) w[j] = w[j] * shrink;
+    }
+    double p[NP];
+    for (int j = 0; j < NP; ++j) p[j] = c[j];
+    double* th = (double*)malloc(sizeof(double) * T);
+    oracle_simulate(p, amp, T, dt_ms, nsub, th);
+    oracle_cost(th, pos, T, C, dir_deg, rmse_out, mae_out);
+    memcpy(opc_out, c, sizeof c);
+    free(th);
+    free(cand);
+    free(cost);
+    return 0;
+}
