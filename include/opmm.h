@@ -1,0 +1,192 @@
+/*
+ * opmm.h -- C ABI of the MI355X (gfx950) OPMM estimation library, libopmm.so.
+ *
+ * The library estimates oculomotor plant characteristics (OPCs) from recorded
+ * saccades as described in "Parallel Oculomotor Plant Mathematical Model for
+ * Large Scale Eye Movement Simulation" (Karpov, Liberman, Lohr, Komogortsev,
+ * arXiv 2007.09884): a saccade trajectory goes in, an 18-parameter OPC vector
+ * comes out (Section 2, problem statement; Algorithm 1 input/output;
+ * Section 3.4 output = OPC vector plus optimisation error).  The plant is the
+ * 18-parameter model of Section 2.2.1 (Table 1 lists the parameters), driven
+ * by the pulse-step control of Section 2.1.
+ *
+ * Conventions for every call:
+ *   - Array arguments are DEVICE pointers unless marked "host".  The caller
+ *     owns them; they must stay valid until the work queued on `stream` has
+ *     completed.  The library keeps no caller pointer past that point (the
+ *     plan calls below are the one exception and say so).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is queued on it; calls return once it is queued.
+ *   - Return value: OPMM_OK or a negative OPMM_E* code; no exception crosses
+ *     the ABI.  opmm_last_error() gives the text of the last failure on that
+ *     context.  Argument errors are detected on the host before anything is
+ *     queued.
+ *   - OPC vectors are FP32 [18] in Table 1 order:
+ *       0 K_SE_AG   1 K_SE_ANT  2 K_LT_AG   3 K_LT_ANT  (g/deg)
+ *       4 B_AG      5 B_ANT     6 B_P                   (g s/deg)
+ *       7 N_C_AG    8 N_C_ANT                            (g/deg)
+ *       9 J                                              (g s^2/deg)
+ *      10 tau_AC_AG 11 tau_AC_ANT 12 tau_DE_AG 13 tau_DE_ANT (ms)
+ *      14 N_C_FIX  15 N_SAC_AG  16 N_SAC_ANT             (g)
+ *      17 PW                                             (ms)
+ *   - A context is bound to one device and is not thread-safe; calls on one
+ *     context must not overlap.
+ */
+#ifndef OPMM_H
+#define OPMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OPMM_P 18          /* OPC vector length (Table 1)                */
+#define OPMM_MAX_T 2048    /* longest trace, samples                      */
+
+enum {
+    OPMM_OK = 0,
+    OPMM_EINVAL = -1,      /* bad argument; nothing was queued            */
+    OPMM_ENOMEM = -2,      /* device or pinned-host allocation failed     */
+    OPMM_EDEVICE = -3,     /* HIP runtime error                           */
+    OPMM_ENOTREADY = -4    /* object not initialised (e.g. no surrogate)  */
+};
+
+/* Per-saccade status bits written by opmm_fit. */
+enum {
+    OPMM_ST_OK = 0,
+    OPMM_ST_NONFINITE_INPUT = 1,    /* trace holds NaN/Inf: not fitted, outputs NaN */
+    OPMM_ST_NO_FINITE_CANDIDATE = 2,/* some round had no candidate with finite cost */
+    OPMM_ST_SEEDED = 4,             /* search started from a supplied/learned seed  */
+    OPMM_ST_FALLBACK = 8            /* seeded result rejected; plain search used    */
+};
+
+typedef struct opmm_ctx opmm_ctx;
+
+/* One recorded saccade (Section 3.1: extracted saccades are the input).
+ * Host-side record; its trace lives in a packed device buffer of FP32
+ * positions (deg), [T][C] row-major, starting at element pos_offset.
+ * Time 0 (sample 0) is the pulse onset.  The plant is one-dimensional
+ * (Section 2.2) and moves along direction dir_deg: with C = 2 the predicted
+ * trace is theta*(cos dir, sin dir); with C = 1 the single channel is the
+ * horizontal one and dir_deg must be 0 or 180. */
+typedef struct {
+    int64_t pos_offset;  /* first element of this trace in `pos`             */
+    int32_t T;           /* samples, 1..OPMM_MAX_T                           */
+    int32_t C;           /* channels: 1 (H) or 2 (H, V)                      */
+    float amp_deg;       /* amplitude A >= 0: the post-saccadic fixation     */
+    float dir_deg;       /* direction of the movement                        */
+    float dur_ms;        /* duration D > 6: nominal PW = D - 6 (Table 1)     */
+    int32_t n_cand;      /* candidates per round; 0 = opmm_fit_params.n_cand */
+    uint64_t seed;       /* key of the candidate stream: results depend only
+                            on (seed, trace, params), never on batch layout  */
+} opmm_saccade;
+
+enum { OPMM_FIT_ROUNDS = 0, OPMM_FIT_PERSISTENT = 1 };
+
+/* Box search parameters.  Round r draws n_cand candidates uniformly in
+ * centre^r +/- w^r (candidate 0 = centre^r), clamped to the search box
+ * nominal +/- box_frac*nominal; the argmin (lowest RMSE, ties to the lowest
+ * index) becomes centre^{r+1} and w^{r+1} = shrink*w^r.  Round 0 is centred
+ * on the nominal OPC (Section 3.2: initialised to literature defaults) or on
+ * a supplied seed, with w^0 = w_init_frac*box_frac*nominal. */
+typedef struct {
+    int32_t n_cand;      /* default candidates per round, >= 1               */
+    int32_t n_rounds;    /* rounds R, 1..4096                                */
+    float box_frac;      /* search box half-width / nominal, (0, 1)  [0.25]  */
+    float w_init_frac;   /* round-0 half-width / box half-width, [0, 1] [1]  */
+    float shrink;        /* half-width factor per round, (0, 1]      [0.5]   */
+    float dt_ms;         /* sample period, (0, 1]                    [1.0]   */
+    int32_t mode;        /* OPMM_FIT_ROUNDS: one launch per round;
+                            OPMM_FIT_PERSISTENT: one work-queue launch for
+                            every round and saccade (uneven batches)         */
+    int32_t tile;        /* kernel shape index; -1 = autotuned/default       */
+} opmm_fit_params;
+
+/* Defaults: n_cand 4096, n_rounds 1, box 0.25, w_init 1, shrink 0.5, dt 1 ms. */
+void opmm_fit_params_default(opmm_fit_params* p);
+
+/* Nominal OPC for a saccade of duration dur_ms (Table 1; PW = D - 6 ms).
+ * host out[18]. */
+void opmm_nominal(float dur_ms, float* out);
+
+/* Context: binds a device, owns the device scratch (per-saccade search state,
+ * projected traces, round keys) and the autotuner cache.  Scratch grows on
+ * demand and is freed by opmm_destroy. */
+int opmm_create(opmm_ctx** out, int device);
+int opmm_destroy(opmm_ctx* ctx);
+const char* opmm_last_error(const opmm_ctx* ctx);
+
+/* Candidate vectors of the search stream (for replay and for callers that
+ * score their own candidate sets).  Writes out[n][18] for candidate indices
+ * idx0 .. idx0+n-1 of round `round` of the stream keyed by `seed`, drawn
+ * around centre c with half-width w and clamped to [lo, hi] (all host [18]).
+ * Rule: SplitMix64 output 1 + (round<<36 | idx<<4 | k), k = 0..8, gives two
+ * 24-bit uniforms u (top 24 bits -> parameter 2k, next 24 -> 2k+1);
+ * s = u/2^23 - 1; p = clamp(fmaf(w, s, c), lo, hi).  Index 0 is c itself. */
+int opmm_candidates(opmm_ctx* ctx, uint64_t seed, uint32_t round, uint32_t idx0, int64_t n,
+                    const float* c, const float* w, const float* lo, const float* hi,
+                    float* out, void* stream);
+
+/* Simulate the plant (Sections 2.1-2.2.1) for n OPC vectors opc[n][18], each
+ * with its own amplitude amp[n] (deg): the eye rests at 0, the pulse acts on
+ * [0, PW), the step holds amp afterwards.  traj_out[n][T] = theta at t_k =
+ * k*dt_ms (deg).  FP32; within 1e-4 deg of the FP64 solution for OPCs within
+ * +/-30% of nominal.  T in 1..OPMM_MAX_T. */
+int opmm_simulate(opmm_ctx* ctx, const float* opc, const float* amp, int64_t n, int32_t T,
+                  float dt_ms, float* traj_out, void* stream);
+
+/* Score n candidate OPC vectors opc[n][18] against one saccade: rmse_out[n] =
+ * sqrt(sum_k sum_c (pos - pred)^2 / (C*T)), the fit criterion (NaN -> +Inf).
+ * pos is the packed trace buffer of pos_len elements; sac (host) locates the
+ * trace.  The optimisation error of Section 3.4, recomputed per candidate. */
+int opmm_score(opmm_ctx* ctx, const float* opc, int64_t n, const float* pos, int64_t pos_len,
+               const opmm_saccade* sac, float dt_ms, float* rmse_out, void* stream);
+
+/* Estimate the OPC vector of each of S saccades (Algorithm 1: one task per
+ * saccade, all on the device; Section 3.3: the data stay on the GPU).
+ *   pos, pos_len   packed traces (device), see opmm_saccade
+ *   sacs           host [S]
+ *   seed_opc       NULL, or device [S][18] round-0 centres (clamped into the
+ *                  box; status gets OPMM_ST_SEEDED)
+ *   opc_out        device [S][18]  fitted OPC (the final argmin)
+ *   rmse_out       device [S]      its RMSE over both channels (deg)
+ *   mae_out        NULL or device [S]: its mean absolute difference (OptErr)
+ *   status_out     NULL or device [S]: OPMM_ST_* bits
+ *   round_keys     NULL or device [n_rounds][S]: per round the argmin key
+ *                  (float bits of the winner's projected SSE << 32 | index)
+ * Results are bit-identical between modes, kernel shapes and batch layouts. */
+int opmm_fit(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs,
+             int32_t S, const opmm_fit_params* params, const float* seed_opc, float* opc_out,
+             float* rmse_out, float* mae_out, int32_t* status_out, uint64_t* round_keys,
+             void* stream);
+
+/* A fit captured once into a HIP graph and replayed: the same work as
+ * opmm_fit with the same arguments, bound to these buffers.  Creation runs
+ * the fit once (synchronously) and then captures it; opmm_plan_launch replays
+ * the whole fit as one graph launch.  The plan owns its own device scratch
+ * and keeps the caller's device pointers (not the host records) until
+ * opmm_plan_destroy; replays must not overlap each other. */
+typedef struct opmm_plan opmm_plan;
+int opmm_fit_plan_create(opmm_ctx* ctx, const float* pos, int64_t pos_len,
+                         const opmm_saccade* sacs, int32_t S, const opmm_fit_params* params,
+                         const float* seed_opc, float* opc_out, float* rmse_out, float* mae_out,
+                         int32_t* status_out, uint64_t* round_keys, void* stream,
+                         opmm_plan** out);
+int opmm_plan_launch(opmm_plan* plan, void* stream);
+int opmm_plan_destroy(opmm_plan* plan);
+
+/* Autotuner: time every kernel shape on a representative sample of this
+ * batch (mode PERSISTENT) and keep the fastest for batches of this kind.
+ * Writes the chosen shape index to *tile_out (host, nullable). */
+int opmm_autotune(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs,
+                  int32_t S, const opmm_fit_params* params, int32_t* tile_out, void* stream);
+/* Number of kernel shapes and a description of shape i (host string). */
+int opmm_tile_count(void);
+const char* opmm_tile_name(int i);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OPMM_H */

@@ -1,0 +1,1089 @@
+// libopmm: OPMM estimation on MI355X (gfx950) -- kernels and the C ABI of
+// include/opmm.h.
+//
+// Hot path (one fused kernel per candidate tile):
+//   candidate draw (SplitMix64 stream, in registers)
+//   -> per-candidate plant setup (D-form one-sample transition, equilibria)
+//   -> T-sample recurrence with the projected target trace in LDS and the
+//      squared residual accumulated on the fly
+//   -> wave/block argmin of a packed (SSE bits, index) key -> one 64-bit
+//      atomicMin per tile on the saccade's round slot.
+// Candidates of a tile are ordered by the sample that holds their pulse end
+// (a counting sort in LDS) before they are assigned to lanes, so the lanes of
+// a wave switch from the pulse to the step within one or two samples of each
+// other and the recurrence stays branch-free elsewhere.  The ordering changes
+// nothing in any lane's arithmetic, and the argmin key is order-independent,
+// so results are bit-identical for every tile shape and batch layout.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/opmm.h"
+#include "plant.hpp"
+
+using namespace opmm;
+
+namespace {
+
+constexpr int NBIN = 256;  // pulse-end sample bins of the in-tile sort
+
+struct SacDev {
+    int64_t pos_off;
+    int64_t proj_off;
+    double cphi, sphi;
+    uint64_t seed;
+    int32_t T, C;
+    float amp, dur;
+    int32_t n_cand, tiles, tile_base, pad;
+};
+
+// ---------------------------------------------------------------------------
+// Small kernels
+// ---------------------------------------------------------------------------
+
+__global__ void fill_u64_kernel(uint64_t* p, int64_t n, uint64_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Project each trace on the movement direction: r_k = h cos + v sin, and the
+// energy orthogonal to it, Q = sum (v cos - h sin)^2.  Then
+// sum_k sum_c (pos - theta u)^2 = sum_k (r_k - theta_k)^2 + Q for every theta.
+__global__ void prep_kernel(int S, const SacDev* __restrict__ sacs, const float* __restrict__ pos,
+                            float* __restrict__ proj, double* __restrict__ qorth,
+                            int32_t* __restrict__ status)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const SacDev sd = sacs[s];
+    bool ok = true;
+    double q = 0.0;
+    for (int k = 0; k < sd.T; ++k) {
+        double h = pos[sd.pos_off + (int64_t)k * sd.C];
+        double v = sd.C == 2 ? (double)pos[sd.pos_off + (int64_t)k * sd.C + 1] : 0.0;
+        ok = ok && isfinite(h) && isfinite(v);
+        double r = h * sd.cphi + v * sd.sphi;
+        if (sd.C == 2) {
+            double o = v * sd.cphi - h * sd.sphi;
+            q += o * o;
+        }
+        proj[sd.proj_off + k] = (float)r;
+    }
+    qorth[s] = q;
+    status[s] = ok ? OPMM_ST_OK : OPMM_ST_NONFINITE_INPUT;
+}
+
+// Round-0 box: centre = nominal (PW = D - 6), w = box_frac * centre, bounds
+// centre -/+ w; optional seed centre (clamped) and narrower round-0 width.
+__global__ void init_kernel(int S, const SacDev* __restrict__ sacs, float box_frac, float w_init_frac,
+                            const float* __restrict__ seed_opc, float* __restrict__ centre,
+                            float* __restrict__ hw, float* __restrict__ lo, float* __restrict__ hi,
+                            int32_t* __restrict__ status)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S * P) return;
+    int s = i / P, j = i % P;
+    float c0 = nominal_param(j, sacs[s].dur);
+    float w0 = box_frac * c0;
+    float l = c0 - w0, h = c0 + w0;
+    float c = c0;
+    if (seed_opc) {
+        float v = seed_opc[i];
+        c = (v == v) ? fminf(fmaxf(v, l), h) : c0;
+        if (j == 0) status[s] |= OPMM_ST_SEEDED;
+    }
+    centre[i] = c;
+    hw[i] = w0 * w_init_frac;
+    lo[i] = l;
+    hi[i] = h;
+}
+
+__device__ __forceinline__ void load_box(Box& b, int s, const float* centre, const float* hw,
+                                         const float* lo, const float* hi)
+{
+    for (int i = threadIdx.x; i < 4 * P; i += blockDim.x) {
+        int a = i / P, j = i % P;
+        const float* src = a == 0 ? centre : a == 1 ? hw : a == 2 ? lo : hi;
+        float v = src[s * P + j];
+        if (a == 0) b.c[j] = v;
+        else if (a == 1) b.w[j] = v;
+        else if (a == 2) b.lo[j] = v;
+        else b.hi[j] = v;
+    }
+}
+
+// next centre = winner of round r, half-width *= shrink (one thread / saccade)
+__device__ __forceinline__ void refine_one(const SacDev& sd, int s, int r, uint64_t key, float shrink,
+                                           float* centre, float* hw, const float* lo, const float* hi,
+                                           int32_t* status)
+{
+    Box b;
+    for (int j = 0; j < P; ++j) {
+        b.c[j] = centre[s * P + j];
+        b.w[j] = hw[s * P + j];
+        b.lo[j] = lo[s * P + j];
+        b.hi[j] = hi[s * P + j];
+    }
+    uint32_t idx = (uint32_t)(key & 0xFFFFFFFFull);
+    if ((key >> 32) >= 0x7F800000ull) {
+        status[s] |= OPMM_ST_NO_FINITE_CANDIDATE;
+        idx = 0;
+    }
+    float p[P];
+    draw_candidate(sd.seed, (uint32_t)r, idx, b, p);
+    for (int j = 0; j < P; ++j) {
+        centre[s * P + j] = p[j];
+        hw[s * P + j] = b.w[j] * shrink;
+    }
+}
+
+__global__ void refine_kernel(int S, const SacDev* __restrict__ sacs, int r, const uint64_t* __restrict__ keys,
+                              float shrink, float* centre, float* hw, const float* lo, const float* hi,
+                              int32_t* status)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    if (status[s] & OPMM_ST_NONFINITE_INPUT) return;
+    refine_one(sacs[s], s, r, keys[(int64_t)r * S + s], shrink, centre, hw, lo, hi, status);
+}
+
+// ---------------------------------------------------------------------------
+// Sinks for run_trajectory
+// ---------------------------------------------------------------------------
+
+struct SseSink {  // squared residual against the projected trace in LDS
+    const float* r;
+    float sse;
+    __device__ __forceinline__ void operator()(int k, float dth, float theq)
+    {
+        float e = (r[k] - theq) - dth;
+        sse = __fmaf_rn(e, e, sse);
+    }
+};
+
+struct TrajSink {  // theta_k to global memory
+    float* out;
+    __device__ __forceinline__ void operator()(int k, float dth, float theq) { out[k] = dth + theq; }
+};
+
+struct Cost2dSink {  // both channels, FP64 accumulation (reporting only)
+    const float* pos;
+    int C;
+    double cphi, sphi, sq, ab;
+    __device__ __forceinline__ void operator()(int k, float dth, float theq)
+    {
+        double th = (double)(dth + theq);
+        double e0 = (double)pos[(int64_t)k * C] - th * cphi;
+        sq += e0 * e0;
+        ab += fabs(e0);
+        if (C == 2) {
+            double e1 = (double)pos[(int64_t)k * C + 1] - th * sphi;
+            sq += e1 * e1;
+            ab += fabs(e1);
+        }
+    }
+};
+
+__device__ __forceinline__ uint64_t cost_key(float sse, uint32_t idx)
+{
+    float c = (sse >= 0.0f && sse <= 3.402823466e38f) ? sse : __int_as_float(0x7F800000);
+    return ((uint64_t)__float_as_uint(c) << 32) | idx;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        uint64_t w = (uint64_t)__shfl_xor((unsigned long long)v, o);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Fused tile: draw, sort by pulse-end sample, simulate + score, argmin
+// ---------------------------------------------------------------------------
+
+template <int TPB, int PASSES>
+struct TileSmem {
+    float r[OPMM_MAX_T];
+    Box box;
+    int hist[NBIN];
+    uint16_t perm[TPB * PASSES];
+    uint64_t red[TPB / 64];
+};
+
+// Returns the block's best key (valid in thread 0).
+template <int TPB, int PASSES, int UNROLL>
+__device__ __forceinline__ uint64_t process_tile(TileSmem<TPB, PASSES>& sm, const SacDev& sd, int s, int t,
+                                                 int round, float dt, const float* __restrict__ proj,
+                                                 const float* centre, const float* hw, const float* lo,
+                                                 const float* hi)
+{
+    constexpr int TILE = TPB * PASSES;
+    const int tid = threadIdx.x;
+    const int T = sd.T;
+    for (int k = tid; k < T; k += TPB) sm.r[k] = proj[sd.proj_off + k];
+    load_box(sm.box, s, centre, hw, lo, hi);
+    for (int i = tid; i < NBIN; i += TPB) sm.hist[i] = 0;
+    __syncthreads();
+
+    // Phase A: bin every candidate of the tile by its pulse-end sample.
+    const uint32_t base = (uint32_t)t * TILE;
+    const float kbase = floorf(sm.box.lo[17] * rcp(dt));
+    int mybin[PASSES];
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps) {
+        uint32_t idx = base + ps * TPB + tid;
+        int bin = NBIN - 1;
+        if ((int64_t)idx < sd.n_cand) {
+            float pw = draw_pw(sd.seed, (uint32_t)round, idx, sm.box) * rcp(dt);
+            float rel = fminf(fmaxf(floorf(pw) - kbase, 0.0f), (float)(NBIN - 2));
+            bin = (int)rel;
+        }
+        mybin[ps] = bin;
+        atomicAdd(&sm.hist[bin], 1);
+    }
+    __syncthreads();
+    if (tid < 64) {  // exclusive scan of the histogram by wave 0
+        int v[NBIN / 64];
+        int run = 0;
+#pragma unroll
+        for (int i = 0; i < NBIN / 64; ++i) { v[i] = sm.hist[tid * (NBIN / 64) + i]; run += v[i]; }
+        int incl = run;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            int u = __shfl_up(incl, o);
+            if (tid >= o) incl += u;
+        }
+        int acc = incl - run;
+#pragma unroll
+        for (int i = 0; i < NBIN / 64; ++i) { sm.hist[tid * (NBIN / 64) + i] = acc; acc += v[i]; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ps = 0; ps < PASSES; ++ps) {
+        int slot = atomicAdd(&sm.hist[mybin[ps]], 1);
+        sm.perm[slot] = (uint16_t)(ps * TPB + tid);
+    }
+    __syncthreads();
+
+    // Phase B: simulate and score in sorted order.
+    uint64_t best = ~0ull;
+    for (int ps = 0; ps < PASSES; ++ps) {
+        const uint32_t j = sm.perm[ps * TPB + tid];
+        const uint32_t idx = base + j;
+        const bool valid = (int64_t)idx < sd.n_cand;
+        if (!__any(valid)) continue;
+        float p[P];
+        draw_candidate(sd.seed, (uint32_t)round, idx, sm.box, p);
+        Plant pl;
+        plant_setup(p, sd.amp, dt, pl);
+        float frac;
+        int k0 = pulse_end_sample(pl.pw, T, frac);
+        int kmin = wave_min(valid ? k0 : 0x7FFFFFFF);
+        int kmax = wave_max(valid ? k0 : -0x7FFFFFFF);
+        kmin = __builtin_amdgcn_readfirstlane(kmin);
+        kmax = __builtin_amdgcn_readfirstlane(kmax);
+        SseSink sink{sm.r, 0.0f};
+        if (valid) {
+            run_trajectory<UNROLL>(pl, T, dt, k0, frac, kmin, kmax, sink);
+            uint64_t key = cost_key(sink.sse, idx);
+            best = key < best ? key : best;
+        }
+    }
+    best = wave_min_u64(best);
+    if ((tid & 63) == 0) sm.red[tid >> 6] = best;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < TPB / 64; ++w) best = sm.red[w] < best ? sm.red[w] : best;
+    }
+    return best;
+}
+
+__device__ __forceinline__ int find_saccade(const SacDev* __restrict__ sacs, int S, int b)
+{
+    int lo = 0, hi = S - 1;  // last s with tile_base <= b
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (sacs[mid].tile_base <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int TPB, int PASSES, int UNROLL>
+__global__ __launch_bounds__(TPB) void fit_round_kernel(const SacDev* __restrict__ sacs, int S, int round,
+                                                        float dt, const float* __restrict__ proj,
+                                                        const float* centre, const float* hw,
+                                                        const float* lo, const float* hi,
+                                                        const int32_t* __restrict__ status,
+                                                        uint64_t* keys)
+{
+    __shared__ TileSmem<TPB, PASSES> sm;
+    __shared__ int s_s;
+    if (threadIdx.x == 0) s_s = find_saccade(sacs, S, blockIdx.x);
+    __syncthreads();
+    const int s = s_s;
+    const SacDev sd = sacs[s];
+    if (status[s] & OPMM_ST_NONFINITE_INPUT) return;
+    const int t = blockIdx.x - sd.tile_base;
+    uint64_t best = process_tile<TPB, PASSES, UNROLL>(sm, sd, s, t, round, dt, proj, centre, hw, lo, hi);
+    if (threadIdx.x == 0 && best != ~0ull)
+        atomicMin((unsigned long long*)&keys[(int64_t)round * S + s], (unsigned long long)best);
+}
+
+// Every round of every saccade in one launch: a work queue of (round, tile)
+// items in round-major order.  The block that finishes the last tile of a
+// saccade's round refines that saccade and publishes the next round; a block
+// that takes a tile of a later round waits for that.  Every item it can wait
+// on was handed out earlier to a running block, so the queue always drains.
+template <int TPB, int PASSES, int UNROLL>
+__global__ __launch_bounds__(TPB) void fit_persistent_kernel(
+    const SacDev* __restrict__ sacs, int S, int R, int tiles_per_round, float dt, float shrink,
+    const float* __restrict__ proj, float* centre, float* hw, const float* lo, const float* hi,
+    int32_t* status, uint64_t* keys, uint32_t* head, uint32_t* done, uint32_t* ready, uint32_t* errflag)
+{
+    __shared__ TileSmem<TPB, PASSES> sm;
+    __shared__ int s_item;
+    const int64_t total = (int64_t)R * tiles_per_round;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(head, 1u);
+        __syncthreads();
+        const int64_t item = s_item;
+        if (item >= total) break;
+        const int r = (int)(item / tiles_per_round);
+        const int b = (int)(item % tiles_per_round);
+        const int s = find_saccade(sacs, S, b);
+        const SacDev sd = sacs[s];
+        const int t = b - sd.tile_base;
+        const bool skip = (status[s] & OPMM_ST_NONFINITE_INPUT) != 0;
+        if (!skip) {
+            if (r > 0) {
+                if (threadIdx.x == 0) {
+                    uint32_t spins = 0;
+                    while (__hip_atomic_load(&ready[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+                           (uint32_t)r) {
+                        __builtin_amdgcn_s_sleep(2);
+                        if (++spins > (1u << 26)) {  // safety valve: never hang the queue
+                            atomicOr(errflag, 1u);
+                            break;
+                        }
+                    }
+                }
+                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            uint64_t best = process_tile<TPB, PASSES, UNROLL>(sm, sd, s, t, r, dt, proj, centre, hw, lo, hi);
+            if (threadIdx.x == 0) {
+                if (best != ~0ull)
+                    atomicMin((unsigned long long*)&keys[(int64_t)r * S + s], (unsigned long long)best);
+                __threadfence();
+                uint32_t old = atomicAdd(&done[s], 1u);
+                if (old + 1 == (uint32_t)((r + 1) * sd.tiles)) {
+                    __threadfence();
+                    uint64_t key = __hip_atomic_load(&keys[(int64_t)r * S + s], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                    refine_one(sd, s, r, key, shrink, centre, hw, lo, hi, status);
+                    __threadfence();
+                    __hip_atomic_store(&ready[s], (uint32_t)(r + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Final report: re-simulate each saccade's winner and score it on the full
+// 2-channel trace (RMSE and mean absolute difference), FP64 accumulation.
+__global__ void report_kernel(int S, const SacDev* __restrict__ sacs, const float* __restrict__ pos,
+                              float dt, const float* __restrict__ centre, float* opc_out, float* rmse_out,
+                              float* mae_out, const int32_t* __restrict__ status, int32_t* status_out)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    bool act = s < S;
+    SacDev sd = sacs[act ? s : 0];
+    float p[P];
+    for (int j = 0; j < P; ++j) p[j] = centre[(act ? s : 0) * P + j];
+    Plant pl;
+    plant_setup(p, sd.amp, dt, pl);
+    float frac;
+    int k0 = pulse_end_sample(pl.pw, sd.T, frac);
+    Cost2dSink sink{pos + sd.pos_off, sd.C, sd.cphi, sd.sphi, 0.0, 0.0};
+    run_trajectory<1>(pl, sd.T, dt, k0, frac, k0, k0, sink);
+    if (!act) return;
+    const int32_t st = status[s];
+    const bool bad = (st & OPMM_ST_NONFINITE_INPUT) != 0;
+    const double n = (double)sd.T * sd.C;
+    for (int j = 0; j < P; ++j) opc_out[s * P + j] = bad ? __int_as_float(0x7FC00000) : p[j];
+    double rm = sqrt(sink.sq / n);
+    rmse_out[s] = bad ? __int_as_float(0x7FC00000) : (float)rm;
+    if (mae_out) mae_out[s] = bad ? __int_as_float(0x7FC00000) : (float)(sink.ab / n);
+    if (status_out) status_out[s] = st;
+}
+
+// ---------------------------------------------------------------------------
+// Standalone simulate / score / candidates
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void simulate_kernel(int64_t n, const float* __restrict__ opc,
+                                                       const float* __restrict__ amp, int T, float dt,
+                                                       float* __restrict__ traj)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool valid = i < n;
+    int64_t ii = valid ? i : 0;
+    float p[P];
+    for (int j = 0; j < P; ++j) p[j] = opc[ii * P + j];
+    Plant pl;
+    plant_setup(p, amp[ii], dt, pl);
+    float frac;
+    int k0 = pulse_end_sample(pl.pw, T, frac);
+    int kmin = wave_min(valid ? k0 : 0x7FFFFFFF), kmax = wave_max(valid ? k0 : -0x7FFFFFFF);
+    if (!valid) return;
+    TrajSink sink{traj + ii * T};
+    run_trajectory<2>(pl, T, dt, k0, frac, kmin, kmax, sink);
+}
+
+__global__ __launch_bounds__(256) void score_kernel(int64_t n, const float* __restrict__ opc,
+                                                    const float* __restrict__ proj, int T, int C,
+                                                    const double* __restrict__ qorth, float amp, float dt,
+                                                    float* __restrict__ rmse)
+{
+    __shared__ float r[OPMM_MAX_T];
+    for (int k = threadIdx.x; k < T; k += blockDim.x) r[k] = proj[k];
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool valid = i < n;
+    int64_t ii = valid ? i : 0;
+    float p[P];
+    for (int j = 0; j < P; ++j) p[j] = opc[ii * P + j];
+    Plant pl;
+    plant_setup(p, amp, dt, pl);
+    float frac;
+    int k0 = pulse_end_sample(pl.pw, T, frac);
+    int kmin = wave_min(valid ? k0 : 0x7FFFFFFF), kmax = wave_max(valid ? k0 : -0x7FFFFFFF);
+    if (!valid) return;
+    SseSink sink{r, 0.0f};
+    run_trajectory<2>(pl, T, dt, k0, frac, kmin, kmax, sink);
+    double tot = ((double)sink.sse + qorth[0]) / ((double)T * C);
+    float v = (float)sqrt(tot);
+    rmse[i] = (v >= 0.0f && v <= 3.402823466e38f) ? v : __int_as_float(0x7F800000);
+}
+
+struct BoxArg {
+    float v[4][P];
+};
+
+__global__ void candidates_kernel(uint64_t seed, uint32_t round, uint32_t idx0, int64_t n, BoxArg ba,
+                                  float* __restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Box b;
+    for (int j = 0; j < P; ++j) {
+        b.c[j] = ba.v[0][j]; b.w[j] = ba.v[1][j]; b.lo[j] = ba.v[2][j]; b.hi[j] = ba.v[3][j];
+    }
+    float p[P];
+    draw_candidate(seed, round, idx0 + (uint32_t)i, b, p);
+    for (int j = 0; j < P; ++j) out[i * P + j] = p[j];
+}
+
+// ---------------------------------------------------------------------------
+// Kernel shapes
+// ---------------------------------------------------------------------------
+
+struct Shape {
+    int tpb, passes, unroll;
+    const char* name;
+};
+const Shape kShapes[] = {
+    {256, 4, 1, "tpb256_pass4_unroll1"},
+    {256, 2, 1, "tpb256_pass2_unroll1"},
+    {256, 8, 1, "tpb256_pass8_unroll1"},
+    {128, 8, 1, "tpb128_pass8_unroll1"},
+    {256, 4, 2, "tpb256_pass4_unroll2"},
+    {256, 4, 4, "tpb256_pass4_unroll4"},
+    {64, 16, 1, "tpb64_pass16_unroll1"},
+};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+struct FitLaunch {
+    const SacDev* sacs;
+    int S, R, tiles_per_round;
+    float dt, shrink;
+    const float* proj;
+    float *centre, *hw, *lo, *hi;
+    int32_t* status;
+    uint64_t* keys;
+    uint32_t *head, *done, *ready, *errflag;
+    int grid_persistent;
+};
+
+template <int TPB, int PASSES, int UNROLL>
+hipError_t launch_shape(const FitLaunch& L, bool persistent, int round, hipStream_t st)
+{
+    if (persistent) {
+        hipLaunchKernelGGL((fit_persistent_kernel<TPB, PASSES, UNROLL>), dim3(L.grid_persistent), dim3(TPB), 0,
+                           st, L.sacs, L.S, L.R, L.tiles_per_round, L.dt, L.shrink, L.proj, L.centre, L.hw,
+                           L.lo, L.hi, L.status, L.keys, L.head, L.done, L.ready, L.errflag);
+    } else {
+        hipLaunchKernelGGL((fit_round_kernel<TPB, PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(TPB), 0, st,
+                           L.sacs, L.S, round, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status, L.keys);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fit_kernel(int shape, const FitLaunch& L, bool persistent, int round, hipStream_t st)
+{
+    switch (shape) {
+    case 0: return launch_shape<256, 4, 1>(L, persistent, round, st);
+    case 1: return launch_shape<256, 2, 1>(L, persistent, round, st);
+    case 2: return launch_shape<256, 8, 1>(L, persistent, round, st);
+    case 3: return launch_shape<128, 8, 1>(L, persistent, round, st);
+    case 4: return launch_shape<256, 4, 2>(L, persistent, round, st);
+    case 5: return launch_shape<256, 4, 4>(L, persistent, round, st);
+    default: return launch_shape<64, 16, 1>(L, persistent, round, st);
+    }
+}
+
+template <int TPB, int PASSES, int UNROLL>
+int persistent_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fit_persistent_kernel<TPB, PASSES, UNROLL>, TPB, 0) !=
+        hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+int shape_blocks_per_cu(int shape)
+{
+    switch (shape) {
+    case 0: return persistent_blocks_per_cu<256, 4, 1>();
+    case 1: return persistent_blocks_per_cu<256, 2, 1>();
+    case 2: return persistent_blocks_per_cu<256, 8, 1>();
+    case 3: return persistent_blocks_per_cu<128, 8, 1>();
+    case 4: return persistent_blocks_per_cu<256, 4, 2>();
+    case 5: return persistent_blocks_per_cu<256, 4, 4>();
+    default: return persistent_blocks_per_cu<64, 16, 1>();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Device scratch of one fit
+// ---------------------------------------------------------------------------
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+struct FitScratch {
+    DevBuf sacs, proj, qorth, box, keys, status, counters;
+    ~FitScratch()
+    {
+        for (DevBuf* b : {&sacs, &proj, &qorth, &box, &keys, &status, &counters})
+            if (b->p) (void)hipFree(b->p);
+    }
+};
+
+}  // namespace
+
+struct opmm_ctx {
+    int device = 0;
+    int cu_count = 0;
+    std::string err;
+    FitScratch scratch;
+    float* d_cand = nullptr;  // small per-call staging for opmm_score (projected trace)
+    size_t d_cand_cap = 0;
+    int tuned_shape = -1;
+    hipStream_t cap_stream = nullptr;
+};
+
+struct opmm_plan {
+    opmm_ctx* ctx = nullptr;
+    FitScratch scratch;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+int fail(opmm_ctx* ctx, int code, const std::string& msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int hip_fail(opmm_ctx* ctx, hipError_t e, const char* what)
+{
+    return fail(ctx, OPMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define OPMM_HIP(ctx, call)                                  \
+    do {                                                     \
+        hipError_t _e = (call);                              \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, #call); \
+    } while (0)
+
+int ensure(opmm_ctx* ctx, DevBuf& b, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    if (b.cap >= bytes) return OPMM_OK;
+    if (b.p) {
+        OPMM_HIP(ctx, hipDeviceSynchronize());
+        OPMM_HIP(ctx, hipFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t cap = std::max(bytes, b.cap * 2);
+    if (hipMalloc(&b.p, cap) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(ctx, OPMM_ENOMEM, "device allocation of " + std::to_string(cap) + " bytes failed");
+    }
+    b.cap = cap;
+    return OPMM_OK;
+}
+
+int blocks_for(int64_t n, int tpb) { return (int)((n + tpb - 1) / tpb); }
+
+int validate_saccade(opmm_ctx* ctx, const opmm_saccade& s, int64_t pos_len, int i)
+{
+    std::string at = " (saccade " + std::to_string(i) + ")";
+    if (s.T < 1 || s.T > OPMM_MAX_T) return fail(ctx, OPMM_EINVAL, "T out of range" + at);
+    if (s.C != 1 && s.C != 2) return fail(ctx, OPMM_EINVAL, "C must be 1 or 2" + at);
+    if (s.C == 1 && !(s.dir_deg == 0.0f || s.dir_deg == 180.0f))
+        return fail(ctx, OPMM_EINVAL, "C = 1 needs dir_deg 0 or 180" + at);
+    if (!std::isfinite(s.amp_deg) || s.amp_deg < 0.0f) return fail(ctx, OPMM_EINVAL, "amp_deg must be finite and >= 0" + at);
+    if (!std::isfinite(s.dir_deg)) return fail(ctx, OPMM_EINVAL, "dir_deg must be finite" + at);
+    if (!std::isfinite(s.dur_ms) || !(s.dur_ms > 6.0f)) return fail(ctx, OPMM_EINVAL, "dur_ms must be > 6" + at);
+    if (s.pos_offset < 0 || s.pos_offset + (int64_t)s.T * s.C > pos_len)
+        return fail(ctx, OPMM_EINVAL, "trace lies outside pos[0, pos_len)" + at);
+    if (s.n_cand < 0) return fail(ctx, OPMM_EINVAL, "n_cand must be >= 0" + at);
+    return OPMM_OK;
+}
+
+int validate_params(opmm_ctx* ctx, const opmm_fit_params* p)
+{
+    if (!p) return fail(ctx, OPMM_EINVAL, "params is NULL");
+    if (p->n_cand < 1) return fail(ctx, OPMM_EINVAL, "n_cand must be >= 1");
+    if (p->n_rounds < 1 || p->n_rounds > 4096) return fail(ctx, OPMM_EINVAL, "n_rounds must be in 1..4096");
+    if (!(p->box_frac > 0.0f && p->box_frac < 1.0f)) return fail(ctx, OPMM_EINVAL, "box_frac must be in (0, 1)");
+    if (!(p->w_init_frac >= 0.0f && p->w_init_frac <= 1.0f)) return fail(ctx, OPMM_EINVAL, "w_init_frac must be in [0, 1]");
+    if (!(p->shrink > 0.0f && p->shrink <= 1.0f)) return fail(ctx, OPMM_EINVAL, "shrink must be in (0, 1]");
+    if (!(p->dt_ms > 0.0f && p->dt_ms <= 1.0f)) return fail(ctx, OPMM_EINVAL, "dt_ms must be in (0, 1]");
+    if (p->mode != OPMM_FIT_ROUNDS && p->mode != OPMM_FIT_PERSISTENT) return fail(ctx, OPMM_EINVAL, "bad mode");
+    if (p->tile < -1 || p->tile >= kNumShapes) return fail(ctx, OPMM_EINVAL, "bad tile index");
+    return OPMM_OK;
+}
+
+// Host records -> device records, prefix sums of tiles; uploads synchronously
+// (the records are small) so the caller's host array can be reused at once.
+int upload_saccades(opmm_ctx* ctx, FitScratch& sc, const opmm_saccade* sacs, int S,
+                    const opmm_fit_params* prm, int tile_size, int64_t* total_T, int* tiles_per_round,
+                    hipStream_t st)
+{
+    std::vector<SacDev> h(S);
+    int64_t toff = 0;
+    int64_t tiles = 0;
+    for (int i = 0; i < S; ++i) {
+        const opmm_saccade& s = sacs[i];
+        SacDev& d = h[i];
+        d.pos_off = s.pos_offset;
+        d.proj_off = toff;
+        double phi = (double)s.dir_deg * (M_PI / 180.0);
+        d.cphi = std::cos(phi);
+        d.sphi = std::sin(phi);
+        if (s.C == 1) { d.cphi = s.dir_deg == 0.0f ? 1.0 : -1.0; d.sphi = 0.0; }
+        d.seed = s.seed;
+        d.T = s.T;
+        d.C = s.C;
+        d.amp = s.amp_deg;
+        d.dur = s.dur_ms;
+        d.n_cand = s.n_cand > 0 ? s.n_cand : (prm ? prm->n_cand : 1);
+        d.tiles = (int)((d.n_cand + tile_size - 1) / tile_size);
+        d.tile_base = (int)tiles;
+        d.pad = 0;
+        toff += s.T;
+        tiles += d.tiles;
+    }
+    if (tiles > 0x7FFFFFFF / 8) return fail(ctx, OPMM_EINVAL, "too many candidate tiles in one batch");
+    int rc;
+    if ((rc = ensure(ctx, sc.sacs, sizeof(SacDev) * S)) != OPMM_OK) return rc;
+    OPMM_HIP(ctx, hipMemcpyAsync(sc.sacs.p, h.data(), sizeof(SacDev) * S, hipMemcpyHostToDevice, st));
+    OPMM_HIP(ctx, hipStreamSynchronize(st));
+    *total_T = toff;
+    *tiles_per_round = (int)tiles;
+    return OPMM_OK;
+}
+
+// Queue the whole fit on `st` (no host synchronisation inside: capturable).
+int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t total_T, int tiles_per_round,
+                const opmm_fit_params* prm, int shape, const float* seed_opc, float* opc_out, float* rmse_out,
+                float* mae_out, int32_t* status_out, uint64_t* round_keys, hipStream_t st)
+{
+    const int R = prm->n_rounds;
+    int rc;
+    if ((rc = ensure(ctx, sc.proj, sizeof(float) * total_T)) != OPMM_OK) return rc;
+    if ((rc = ensure(ctx, sc.qorth, sizeof(double) * S)) != OPMM_OK) return rc;
+    if ((rc = ensure(ctx, sc.box, sizeof(float) * 4 * P * S)) != OPMM_OK) return rc;
+    if ((rc = ensure(ctx, sc.status, sizeof(int32_t) * S)) != OPMM_OK) return rc;
+    if ((rc = ensure(ctx, sc.counters, sizeof(uint32_t) * (2 * (size_t)S + 2))) != OPMM_OK) return rc;
+    uint64_t* keys = round_keys;
+    if (!keys) {
+        if ((rc = ensure(ctx, sc.keys, sizeof(uint64_t) * (size_t)R * S)) != OPMM_OK) return rc;
+        keys = (uint64_t*)sc.keys.p;
+    }
+    const SacDev* d_sacs = (const SacDev*)sc.sacs.p;
+    float* proj = (float*)sc.proj.p;
+    double* qorth = (double*)sc.qorth.p;
+    float* centre = (float*)sc.box.p;
+    float* hw = centre + P * S;
+    float* lo = hw + P * S;
+    float* hi = lo + P * S;
+    int32_t* status = (int32_t*)sc.status.p;
+    uint32_t* done = (uint32_t*)sc.counters.p;
+    uint32_t* ready = done + S;
+    uint32_t* head = ready + S;
+    uint32_t* errflag = head + 1;
+
+    hipLaunchKernelGGL(prep_kernel, dim3(blocks_for(S, 128)), dim3(128), 0, st, S, d_sacs, pos, proj, qorth, status);
+    hipLaunchKernelGGL(init_kernel, dim3(blocks_for((int64_t)S * P, 256)), dim3(256), 0, st, S, d_sacs, prm->box_frac,
+                       prm->w_init_frac, seed_opc, centre, hw, lo, hi, status);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for((int64_t)R * S, 256)), dim3(256), 0, st, keys,
+                       (int64_t)R * S, ~0ull);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(2 * (int64_t)S + 2, 256)), dim3(256), 0, st, done,
+                       2 * (int64_t)S + 2, 0u);
+    OPMM_HIP(ctx, hipGetLastError());
+
+    FitLaunch L;
+    L.sacs = d_sacs; L.S = S; L.R = R; L.tiles_per_round = tiles_per_round; L.dt = prm->dt_ms;
+    L.shrink = prm->shrink; L.proj = proj; L.centre = centre; L.hw = hw; L.lo = lo; L.hi = hi;
+    L.status = status; L.keys = keys; L.head = head; L.done = done; L.ready = ready; L.errflag = errflag;
+    L.grid_persistent = 0;
+    if (tiles_per_round > 0) {
+        if (prm->mode == OPMM_FIT_PERSISTENT) {
+            int64_t want = (int64_t)shape_blocks_per_cu(shape) * std::max(ctx->cu_count, 1);
+            int64_t total = (int64_t)R * tiles_per_round;
+            L.grid_persistent = (int)std::max<int64_t>(1, std::min(want, total));
+            OPMM_HIP(ctx, launch_fit_kernel(shape, L, true, 0, st));
+        } else {
+            for (int r = 0; r < R; ++r) {
+                OPMM_HIP(ctx, launch_fit_kernel(shape, L, false, r, st));
+                hipLaunchKernelGGL(refine_kernel, dim3(blocks_for(S, 128)), dim3(128), 0, st, S, d_sacs, r, keys,
+                                   prm->shrink, centre, hw, lo, hi, status);
+                OPMM_HIP(ctx, hipGetLastError());
+            }
+        }
+    }
+    hipLaunchKernelGGL(report_kernel, dim3(blocks_for(S, 64)), dim3(64), 0, st, S, d_sacs, pos, prm->dt_ms, centre,
+                       opc_out, rmse_out, mae_out, status, status_out);
+    OPMM_HIP(ctx, hipGetLastError());
+    return OPMM_OK;
+}
+
+int shape_tile(int shape) { return kShapes[shape].tpb * kShapes[shape].passes; }
+
+int pick_shape(opmm_ctx* ctx, const opmm_fit_params* prm)
+{
+    if (prm->tile >= 0) return prm->tile;
+    return ctx->tuned_shape >= 0 ? ctx->tuned_shape : 0;
+}
+
+int check_fit_args(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
+                   const opmm_fit_params* prm, float* opc_out, float* rmse_out)
+{
+    if (!ctx) return OPMM_EINVAL;
+    int rc;
+    if ((rc = validate_params(ctx, prm)) != OPMM_OK) return rc;
+    if (S < 0) return fail(ctx, OPMM_EINVAL, "S must be >= 0");
+    if (S > 0 && (!pos || !sacs || !opc_out || !rmse_out)) return fail(ctx, OPMM_EINVAL, "NULL array argument");
+    if (pos_len < 0) return fail(ctx, OPMM_EINVAL, "pos_len must be >= 0");
+    for (int i = 0; i < S; ++i)
+        if ((rc = validate_saccade(ctx, sacs[i], pos_len, i)) != OPMM_OK) return rc;
+    return OPMM_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+void opmm_fit_params_default(opmm_fit_params* p)
+{
+    if (!p) return;
+    p->n_cand = 4096;
+    p->n_rounds = 1;
+    p->box_frac = 0.25f;
+    p->w_init_frac = 1.0f;
+    p->shrink = 0.5f;
+    p->dt_ms = 1.0f;
+    p->mode = OPMM_FIT_ROUNDS;
+    p->tile = -1;
+}
+
+void opmm_nominal(float dur_ms, float* out)
+{
+    if (!out) return;
+    for (int j = 0; j < P; ++j) out[j] = nominal_param(j, dur_ms);
+}
+
+int opmm_create(opmm_ctx** out, int device)
+{
+    if (!out) return OPMM_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return OPMM_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return OPMM_EDEVICE;
+    opmm_ctx* c = new (std::nothrow) opmm_ctx();
+    if (!c) return OPMM_ENOMEM;
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return OPMM_EDEVICE;
+    }
+    *out = c;
+    return OPMM_OK;
+}
+
+int opmm_destroy(opmm_ctx* ctx)
+{
+    if (!ctx) return OPMM_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->d_cand) (void)hipFree(ctx->d_cand);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+    return OPMM_OK;
+}
+
+const char* opmm_last_error(const opmm_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+int opmm_tile_count(void) { return kNumShapes; }
+
+const char* opmm_tile_name(int i) { return (i >= 0 && i < kNumShapes) ? kShapes[i].name : ""; }
+
+int opmm_candidates(opmm_ctx* ctx, uint64_t seed, uint32_t round, uint32_t idx0, int64_t n, const float* c,
+                    const float* w, const float* lo, const float* hi, float* out, void* stream)
+{
+    if (!ctx) return OPMM_EINVAL;
+    if (n < 0 || (n > 0 && (!c || !w || !lo || !hi || !out))) return fail(ctx, OPMM_EINVAL, "bad arguments");
+    if ((uint64_t)idx0 + (uint64_t)n > 0x100000000ull) return fail(ctx, OPMM_EINVAL, "index beyond 2^32");
+    if (round >= (1u << 28)) return fail(ctx, OPMM_EINVAL, "round beyond 2^28");
+    if (n == 0) return OPMM_OK;
+    OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    BoxArg ba;
+    std::memcpy(ba.v[0], c, sizeof(float) * P);
+    std::memcpy(ba.v[1], w, sizeof(float) * P);
+    std::memcpy(ba.v[2], lo, sizeof(float) * P);
+    std::memcpy(ba.v[3], hi, sizeof(float) * P);
+    hipLaunchKernelGGL(candidates_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, seed, round,
+                       idx0, n, ba, out);
+    OPMM_HIP(ctx, hipGetLastError());
+    return OPMM_OK;
+}
+
+int opmm_simulate(opmm_ctx* ctx, const float* opc, const float* amp, int64_t n, int32_t T, float dt_ms,
+                  float* traj_out, void* stream)
+{
+    if (!ctx) return OPMM_EINVAL;
+    if (n < 0) return fail(ctx, OPMM_EINVAL, "n must be >= 0");
+    if (T < 1 || T > OPMM_MAX_T) return fail(ctx, OPMM_EINVAL, "T out of range");
+    if (!(dt_ms > 0.0f && dt_ms <= 1.0f)) return fail(ctx, OPMM_EINVAL, "dt_ms must be in (0, 1]");
+    if (n > 0 && (!opc || !amp || !traj_out)) return fail(ctx, OPMM_EINVAL, "NULL array argument");
+    if (n == 0) return OPMM_OK;
+    OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(simulate_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, (hipStream_t)stream, n, opc, amp, T,
+                       dt_ms, traj_out);
+    OPMM_HIP(ctx, hipGetLastError());
+    return OPMM_OK;
+}
+
+int opmm_score(opmm_ctx* ctx, const float* opc, int64_t n, const float* pos, int64_t pos_len,
+               const opmm_saccade* sac, float dt_ms, float* rmse_out, void* stream)
+{
+    if (!ctx) return OPMM_EINVAL;
+    if (!sac) return fail(ctx, OPMM_EINVAL, "sac is NULL");
+    int rc;
+    if ((rc = validate_saccade(ctx, *sac, pos_len, 0)) != OPMM_OK) return rc;
+    if (!(dt_ms > 0.0f && dt_ms <= 1.0f)) return fail(ctx, OPMM_EINVAL, "dt_ms must be in (0, 1]");
+    if (n < 0) return fail(ctx, OPMM_EINVAL, "n must be >= 0");
+    if (n > 0 && (!opc || !pos || !rmse_out)) return fail(ctx, OPMM_EINVAL, "NULL array argument");
+    if (n == 0) return OPMM_OK;
+    OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    FitScratch& sc = ctx->scratch;
+    int64_t total_T;
+    int tiles;
+    if ((rc = upload_saccades(ctx, sc, sac, 1, nullptr, 1, &total_T, &tiles, st)) != OPMM_OK) return rc;
+    if ((rc = ensure(ctx, sc.proj, sizeof(float) * total_T)) != OPMM_OK) return rc;
+    if ((rc = ensure(ctx, sc.qorth, sizeof(double))) != OPMM_OK) return rc;
+    if ((rc = ensure(ctx, sc.status, sizeof(int32_t))) != OPMM_OK) return rc;
+    hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(128), 0, st, 1, (const SacDev*)sc.sacs.p, pos, (float*)sc.proj.p,
+                       (double*)sc.qorth.p, (int32_t*)sc.status.p);
+    hipLaunchKernelGGL(score_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, opc, (const float*)sc.proj.p,
+                       sac->T, sac->C, (const double*)sc.qorth.p, sac->amp_deg, dt_ms, rmse_out);
+    OPMM_HIP(ctx, hipGetLastError());
+    return OPMM_OK;
+}
+
+int opmm_fit(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
+             const opmm_fit_params* params, const float* seed_opc, float* opc_out, float* rmse_out, float* mae_out,
+             int32_t* status_out, uint64_t* round_keys, void* stream)
+{
+    int rc = check_fit_args(ctx, pos, pos_len, sacs, S, params, opc_out, rmse_out);
+    if (rc != OPMM_OK) return rc;
+    if (S == 0) return OPMM_OK;
+    OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int shape = pick_shape(ctx, params);
+    int64_t total_T;
+    int tiles;
+    if ((rc = upload_saccades(ctx, ctx->scratch, sacs, S, params, shape_tile(shape), &total_T, &tiles, st)) != OPMM_OK)
+        return rc;
+    return enqueue_fit(ctx, ctx->scratch, pos, S, total_T, tiles, params, shape, seed_opc, opc_out, rmse_out, mae_out,
+                       status_out, round_keys, st);
+}
+
+int opmm_fit_plan_create(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
+                         const opmm_fit_params* params, const float* seed_opc, float* opc_out, float* rmse_out,
+                         float* mae_out, int32_t* status_out, uint64_t* round_keys, void* stream, opmm_plan** out)
+{
+    if (!out) return fail(ctx, OPMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = check_fit_args(ctx, pos, pos_len, sacs, S, params, opc_out, rmse_out);
+    if (rc != OPMM_OK) return rc;
+    if (S == 0) return fail(ctx, OPMM_EINVAL, "a plan needs S >= 1");
+    OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    opmm_plan* pl = new (std::nothrow) opmm_plan();
+    if (!pl) return fail(ctx, OPMM_ENOMEM, "plan allocation failed");
+    pl->ctx = ctx;
+    const int shape = pick_shape(ctx, params);
+    int64_t total_T;
+    int tiles;
+    hipStream_t cs = ctx->cap_stream;
+    rc = upload_saccades(ctx, pl->scratch, sacs, S, params, shape_tile(shape), &total_T, &tiles, cs);
+    if (rc == OPMM_OK) {
+        // allocate outside the capture: enqueue once for real, then capture
+        rc = enqueue_fit(ctx, pl->scratch, pos, S, total_T, tiles, params, shape, seed_opc, opc_out, rmse_out,
+                         mae_out, status_out, round_keys, cs);
+    }
+    if (rc == OPMM_OK && hipStreamSynchronize(cs) != hipSuccess) rc = fail(ctx, OPMM_EDEVICE, "plan warm-up failed");
+    if (rc == OPMM_OK) {
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) rc = hip_fail(ctx, e, "hipStreamBeginCapture");
+        else {
+            rc = enqueue_fit(ctx, pl->scratch, pos, S, total_T, tiles, params, shape, seed_opc, opc_out, rmse_out,
+                             mae_out, status_out, round_keys, cs);
+            hipError_t e2 = hipStreamEndCapture(cs, &pl->graph);
+            if (rc == OPMM_OK && e2 != hipSuccess) rc = hip_fail(ctx, e2, "hipStreamEndCapture");
+        }
+    }
+    if (rc == OPMM_OK) {
+        hipError_t e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = hip_fail(ctx, e, "hipGraphInstantiate");
+    }
+    (void)stream;
+    if (rc != OPMM_OK) {
+        opmm_plan_destroy(pl);
+        return rc;
+    }
+    *out = pl;
+    return OPMM_OK;
+}
+
+int opmm_plan_launch(opmm_plan* plan, void* stream)
+{
+    if (!plan || !plan->exec) return OPMM_EINVAL;
+    opmm_ctx* ctx = plan->ctx;
+    OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    OPMM_HIP(ctx, hipGraphLaunch(plan->exec, (hipStream_t)stream));
+    return OPMM_OK;
+}
+
+int opmm_plan_destroy(opmm_plan* plan)
+{
+    if (!plan) return OPMM_OK;
+    (void)hipSetDevice(plan->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
+    return OPMM_OK;
+}
+
+int opmm_autotune(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
+                  const opmm_fit_params* params, int32_t* tile_out, void* stream)
+{
+    int rc = check_fit_args(ctx, pos, pos_len, sacs, S, params, (float*)1, (float*)1);
+    if (rc != OPMM_OK) return rc;
+    if (S == 0) return fail(ctx, OPMM_EINVAL, "autotune needs S >= 1");
+    OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    // sample: every k-th saccade, at most 256, two rounds, persistent mode
+    const int stride = std::max(1, S / 256);
+    std::vector<opmm_saccade> sub;
+    for (int i = 0; i < S; i += stride) sub.push_back(sacs[i]);
+    const int Ss = (int)sub.size();
+    opmm_fit_params pp = *params;
+    pp.n_rounds = std::min(params->n_rounds, 2);
+    pp.mode = OPMM_FIT_PERSISTENT;
+    DevBuf out;
+    if ((rc = ensure(ctx, out, sizeof(float) * (size_t)Ss * (P + 1))) != OPMM_OK) return rc;
+    float* d_opc = (float*)out.p;
+    float* d_rmse = d_opc + (size_t)Ss * P;
+    hipEvent_t e0, e1;
+    OPMM_HIP(ctx, hipEventCreate(&e0));
+    OPMM_HIP(ctx, hipEventCreate(&e1));
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int sh = 0; sh < kNumShapes && rc == OPMM_OK; ++sh) {
+        pp.tile = sh;
+        float ms_best = 1e30f;
+        for (int rep = 0; rep < 3 && rc == OPMM_OK; ++rep) {
+            (void)hipEventRecord(e0, st);
+            rc = opmm_fit(ctx, pos, pos_len, sub.data(), Ss, &pp, nullptr, d_opc, d_rmse, nullptr, nullptr, nullptr,
+                          stream);
+            (void)hipEventRecord(e1, st);
+            if (rc == OPMM_OK && hipEventSynchronize(e1) == hipSuccess) {
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0) ms_best = std::min(ms_best, ms);
+            }
+        }
+        if (ms_best < best_ms) {
+            best_ms = ms_best;
+            best = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(out.p);
+    if (rc != OPMM_OK) return rc;
+    ctx->tuned_shape = best;
+    if (tile_out) *tile_out = best;
+    return OPMM_OK;
+}
+
+}  // extern "C"

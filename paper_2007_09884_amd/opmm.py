@@ -1,0 +1,227 @@
+"""Thin Python binding of libopmm (include/opmm.h).
+
+Argument marshalling only: every step of the estimation path runs in the HIP
+kernels of libopmm.so.  Tensors are torch CUDA tensors (device memory and the
+current stream are all PyTorch is used for).  If the library is not built the
+import of this module fails: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libopmm.so")
+P = 18
+MAX_T = 2048
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTREADY = 0, -1, -2, -3, -4
+ST_OK, ST_NONFINITE_INPUT, ST_NO_FINITE_CANDIDATE, ST_SEEDED, ST_FALLBACK = 0, 1, 2, 4, 8
+FIT_ROUNDS, FIT_PERSISTENT = 0, 1
+
+SACCADE_DTYPE = np.dtype([("pos_offset", "<i8"), ("T", "<i4"), ("C", "<i4"), ("amp_deg", "<f4"),
+                          ("dir_deg", "<f4"), ("dur_ms", "<f4"), ("n_cand", "<i4"), ("seed", "<u8")])
+assert SACCADE_DTYPE.itemsize == 40
+
+
+class FitParams(ctypes.Structure):
+    _fields_ = [("n_cand", ctypes.c_int32), ("n_rounds", ctypes.c_int32), ("box_frac", ctypes.c_float),
+                ("w_init_frac", ctypes.c_float), ("shrink", ctypes.c_float), ("dt_ms", ctypes.c_float),
+                ("mode", ctypes.c_int32), ("tile", ctypes.c_int32)]
+
+
+class OpmmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("opmm error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libopmm.so is not built (run __graft_entry__.build()); there is no fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64, f = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                 ctypes.c_uint64, ctypes.c_float)
+    sig = {
+        "opmm_fit_params_default": (None, [ctypes.POINTER(FitParams)]),
+        "opmm_nominal": (None, [f, vp]),
+        "opmm_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int]),
+        "opmm_destroy": (ctypes.c_int, [vp]),
+        "opmm_last_error": (ctypes.c_char_p, [vp]),
+        "opmm_candidates": (ctypes.c_int, [vp, u64, u32, u32, i64, vp, vp, vp, vp, vp, vp]),
+        "opmm_simulate": (ctypes.c_int, [vp, vp, vp, i64, i32, f, vp, vp]),
+        "opmm_score": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, f, vp, vp]),
+        "opmm_fit": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(FitParams), vp, vp, vp, vp, vp,
+                                    vp, vp]),
+        "opmm_fit_plan_create": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(FitParams), vp, vp,
+                                                vp, vp, vp, vp, vp, ctypes.POINTER(vp)]),
+        "opmm_plan_launch": (ctypes.c_int, [vp, vp]),
+        "opmm_plan_destroy": (ctypes.c_int, [vp]),
+        "opmm_autotune": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(FitParams),
+                                         ctypes.POINTER(i32), vp]),
+        "opmm_tile_count": (ctypes.c_int, []),
+        "opmm_tile_name": (ctypes.c_char_p, [ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+lib = _load()
+
+
+def fit_params(**kw) -> FitParams:
+    p = FitParams()
+    lib.opmm_fit_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError("unknown fit parameter %r" % k)
+        setattr(p, k, v)
+    return p
+
+
+def nominal(dur_ms: float) -> np.ndarray:
+    out = np.zeros(P, np.float32)
+    lib.opmm_nominal(ctypes.c_float(dur_ms), out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def tile_names():
+    return [lib.opmm_tile_name(i).decode() for i in range(lib.opmm_tile_count())]
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous(), "need a contiguous CUDA tensor"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def saccade_records(T, C, amp, dir_deg, dur_ms, seed, n_cand=None, pos_offset=None) -> np.ndarray:
+    """Host opmm_saccade records; offsets default to back-to-back [T][C] traces."""
+    T = np.asarray(T, np.int64).reshape(-1)
+    S = T.shape[0]
+    rec = np.zeros(S, SACCADE_DTYPE)
+    Cs = np.broadcast_to(np.asarray(C, np.int64), (S,))
+    if pos_offset is None:
+        pos_offset = np.concatenate([[0], np.cumsum(T * Cs)[:-1]]) if S else np.zeros(0, np.int64)
+    rec["pos_offset"] = pos_offset
+    rec["T"] = T
+    rec["C"] = Cs
+    rec["amp_deg"] = amp
+    rec["dir_deg"] = dir_deg
+    rec["dur_ms"] = dur_ms
+    rec["n_cand"] = 0 if n_cand is None else n_cand
+    rec["seed"] = np.asarray(seed, np.uint64)
+    return rec
+
+
+class Context:
+    """One libopmm context on one device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        rc = lib.opmm_create(ctypes.byref(h), int(device))
+        if rc != OK:
+            raise OpmmError(rc, "opmm_create(device=%d) failed" % device)
+        self._h = h
+
+    def close(self):
+        if self._h:
+            lib.opmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != OK:
+            raise OpmmError(rc, lib.opmm_last_error(self._h).decode())
+
+    # -- calls -------------------------------------------------------------------------------
+    def candidates(self, seed, rnd, idx0, n, c, w, lo, hi, out, stream=None):
+        arr = [np.ascontiguousarray(a, np.float32) for a in (c, w, lo, hi)]
+        ps = [a.ctypes.data_as(ctypes.c_void_p) for a in arr]
+        self._check(lib.opmm_candidates(self._h, ctypes.c_uint64(int(seed)), int(rnd), int(idx0), int(n),
+                                        *ps, _ptr(out), _stream(stream)))
+
+    def simulate(self, opc, amp, T, traj_out, dt_ms=1.0, stream=None):
+        n = opc.shape[0]
+        self._check(lib.opmm_simulate(self._h, _ptr(opc), _ptr(amp), n, int(T), ctypes.c_float(dt_ms),
+                                      _ptr(traj_out), _stream(stream)))
+
+    def score(self, opc, pos, sac_rec, rmse_out, dt_ms=1.0, stream=None):
+        rec = np.ascontiguousarray(sac_rec, SACCADE_DTYPE).reshape(1)
+        self._check(lib.opmm_score(self._h, _ptr(opc), opc.shape[0], _ptr(pos), pos.numel(),
+                                   rec.ctypes.data_as(ctypes.c_void_p), ctypes.c_float(dt_ms), _ptr(rmse_out),
+                                   _stream(stream)))
+
+    def fit(self, pos, recs, params: FitParams, opc_out, rmse_out, mae_out=None, status_out=None,
+            round_keys=None, seed_opc=None, stream=None):
+        recs = np.ascontiguousarray(recs, SACCADE_DTYPE)
+        self._check(lib.opmm_fit(self._h, _ptr(pos), pos.numel(), recs.ctypes.data_as(ctypes.c_void_p),
+                                 recs.shape[0], ctypes.byref(params), _ptr(seed_opc), _ptr(opc_out),
+                                 _ptr(rmse_out), _ptr(mae_out), _ptr(status_out), _ptr(round_keys),
+                                 _stream(stream)))
+
+    def autotune(self, pos, recs, params: FitParams, stream=None) -> int:
+        recs = np.ascontiguousarray(recs, SACCADE_DTYPE)
+        t = ctypes.c_int32(-1)
+        self._check(lib.opmm_autotune(self._h, _ptr(pos), pos.numel(), recs.ctypes.data_as(ctypes.c_void_p),
+                                      recs.shape[0], ctypes.byref(params), ctypes.byref(t), _stream(stream)))
+        return t.value
+
+    def plan(self, pos, recs, params: FitParams, opc_out, rmse_out, mae_out=None, status_out=None,
+             round_keys=None, seed_opc=None, stream=None) -> "Plan":
+        recs = np.ascontiguousarray(recs, SACCADE_DTYPE)
+        h = ctypes.c_void_p()
+        self._check(lib.opmm_fit_plan_create(self._h, _ptr(pos), pos.numel(),
+                                             recs.ctypes.data_as(ctypes.c_void_p), recs.shape[0],
+                                             ctypes.byref(params), _ptr(seed_opc), _ptr(opc_out),
+                                             _ptr(rmse_out), _ptr(mae_out), _ptr(status_out),
+                                             _ptr(round_keys), _stream(stream), ctypes.byref(h)))
+        return Plan(self, h)
+
+
+class Plan:
+    """A fit captured in a HIP graph; launch() replays it."""
+
+    def __init__(self, ctx: Context, h):
+        self._ctx, self._h = ctx, h
+
+    def launch(self, stream=None):
+        rc = lib.opmm_plan_launch(self._h, _stream(stream))
+        if rc != OK:
+            raise OpmmError(rc, lib.opmm_last_error(self._ctx._h).decode())
+
+    def close(self):
+        if self._h:
+            lib.opmm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pack_traces(traces):
+    """List of [T_i][C] float arrays -> one packed float32 array (the pos buffer)."""
+    if not traces:
+        return np.zeros(0, np.float32)
+    return np.concatenate([np.asarray(t, np.float32).reshape(-1) for t in traces])

@@ -1,0 +1,354 @@
+"""GPU path vs the FP64 oracle, through the C ABI.
+
+Tolerances (float path vs FP64 oracle):
+  * trajectories: max |theta_gpu - theta_oracle| <= 1e-4 deg;
+  * candidate stream: bit-exact (integer hash + one correctly rounded fma);
+  * per-candidate cost (the paper's CPU_check pattern, Section 3.4): |rmse_gpu - rmse_oracle|
+    <= 1e-6 * max(1, rmse), from the FP32 error budget of the recurrence;
+  * argmin: the GPU's winner w must satisfy rmse_oracle(w) - min_i rmse_oracle(i) <= 1e-6; where the
+    oracle's best beats its runner-up by more than 1e-6 the winner is unique and must be that index.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2007_09884_amd import synth
+from workload import f32, make_batch, records
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+NTH = max(1, min(16, os.cpu_count() or 1))
+GAP = 1e-6
+
+
+@pytest.fixture(scope="module")
+def opmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_09884_amd import opmm as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(opmm):
+    c = opmm.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def cost_tol(r):
+    return 1e-6 * np.maximum(1.0, r)
+
+
+def check_argmin(ref, w, where=""):
+    best = ref.min()
+    assert ref[w] - best <= GAP, (where, w, ref[w], best)
+    order = np.argsort(ref, kind="stable")
+    if ref[order[1]] - ref[order[0]] > GAP:
+        assert w == order[0], (where, w, int(order[0]))
+
+
+def run_fit(ctx, opmm, b, traces, n_cand, R, mode=0, tile=-1, n_cand_per=None, seed_opc=None):
+    S = b["S"]
+    recs = records(b, opmm, n_cand=n_cand_per)
+    pos = dev(opmm.pack_traces(traces))
+    prm = opmm.fit_params(n_cand=n_cand, n_rounds=R, mode=mode, tile=tile)
+    opc = torch.zeros(S, 18, device="cuda")
+    rmse = torch.zeros(S, device="cuda")
+    mae = torch.zeros(S, device="cuda")
+    st = torch.zeros(S, dtype=torch.int32, device="cuda")
+    keys = torch.zeros(R, S, dtype=torch.int64, device="cuda")
+    ctx.fit(pos, recs, prm, opc, rmse, mae, st, keys, seed_opc=seed_opc)
+    torch.cuda.synchronize()
+    return dict(opc=opc.cpu().numpy(), rmse=rmse.cpu().numpy(), mae=mae.cpu().numpy(),
+                status=st.cpu().numpy(), keys=keys.cpu().numpy().view(np.uint64))
+
+
+def centre_chain(b, s, keys, R):
+    """Round centres implied by the GPU's winners, rebuilt with the oracle's candidate rule."""
+    c, w, lo, hi = oracle.initial_box(b["dur_ms"][s])
+    cen = [c]
+    for r in range(R):
+        idx = int(keys[r, s] & np.uint64(0xFFFFFFFF))
+        cen.append(oracle.candidate(int(b["seed"][s]), r, idx, cen[-1], w * np.float32(0.5 ** r), lo, hi))
+    return cen, w, lo, hi
+
+
+# --- simulate ------------------------------------------------------------------------------------
+
+def test_simulate_trajectories_match_oracle(ctx, opmm):
+    rng = np.random.default_rng(11)
+    n, T = 256, 150
+    amp = f32(rng.uniform(2, 30, n))
+    dur = f32(2.2 * amp + 21)
+    opc = np.stack([oracle.nominal(d) * rng.uniform(0.7, 1.3, 18) for d in dur]).astype(np.float32)
+    opc[0, 17] = 200.0   # pulse beyond the trace
+    opc[1, 17] = 0.3     # pulse ends inside the first sample
+    opc[2, 17] = 40.0    # pulse ends exactly on a sample
+    out = torch.zeros(n, T, device="cuda")
+    ctx.simulate(dev(opc), dev(amp.astype(np.float32)), T, out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    worst = 0.0
+    for i in range(n):
+        ref = oracle.simulate(opc[i].astype(np.float64), amp[i], T)
+        worst = max(worst, np.abs(g[i] - ref).max())
+    print("simulate worst |err| = %.3g deg" % worst)
+    assert worst <= 1e-4
+
+
+def test_simulate_half_ms_sampling(ctx, opmm):
+    rng = np.random.default_rng(12)
+    n, T = 64, 200
+    amp = f32(rng.uniform(2, 30, n))
+    opc = np.stack([oracle.nominal(2.2 * a + 21) * rng.uniform(0.75, 1.25, 18) for a in amp]).astype(np.float32)
+    out = torch.zeros(n, T, device="cuda")
+    ctx.simulate(dev(opc), dev(amp.astype(np.float32)), T, out, dt_ms=0.5)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    worst = max(np.abs(g[i] - oracle.simulate(opc[i].astype(np.float64), amp[i], T, dt_ms=0.5)).max()
+                for i in range(n))
+    assert worst <= 1e-4
+
+
+# --- candidate stream ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed,rnd,idx0,n", [(1, 0, 0, 3000), (2**63 + 12345, 7, 70000, 1000),
+                                             (987654321, 2**27, 2**32 - 500, 500)])
+def test_candidates_bit_exact(ctx, opmm, seed, rnd, idx0, n):
+    c, w, lo, hi = oracle.initial_box(61.0)
+    w = w * np.float32(0.5 ** (rnd % 11))
+    out = torch.zeros(n, 18, device="cuda")
+    ctx.candidates(seed, rnd, idx0, n, c, w, lo, hi, out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    pick = np.unique(np.r_[0, 1, n - 1, np.random.default_rng(0).integers(0, n, 200)])
+    ref = oracle.candidates(seed, rnd, idx0 + pick, c, w, lo, hi)
+    assert np.array_equal(g[pick].view(np.uint32), ref.view(np.uint32))
+
+
+# --- score ---------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kind", ["tiny", "full"])
+def test_score_matches_oracle(ctx, opmm, kind):
+    b, traces = make_batch(3, kind)
+    for s in range(3):
+        c, w, lo, hi = oracle.initial_box(b["dur_ms"][s])
+        cands = oracle.candidates(int(b["seed"][s]), 0, range(600), c, w, lo, hi)
+        rec = records(synth.subset(b, [s]), opmm)
+        rec["pos_offset"] = 0
+        out = torch.zeros(600, device="cuda")
+        ctx.score(dev(cands), dev(traces[s].reshape(-1)), rec, out)
+        torch.cuda.synchronize()
+        g = out.cpu().numpy().astype(np.float64)
+        ref, _ = oracle.score(cands, traces[s], b["amp"][s], b["dir_deg"][s], nthreads=NTH)
+        assert np.all(np.abs(g - ref) <= cost_tol(ref)), np.abs(g - ref).max()
+
+
+# --- fit -----------------------------------------------------------------------------------------
+
+def test_fit_tiny_single_pass(ctx, opmm):
+    """One horizontal 10 deg saccade, 4096 candidates in +/-25%, one argmin pass."""
+    b, traces = make_batch(1, "tiny")
+    res = run_fit(ctx, opmm, b, traces, 4096, 1)
+    idx = int(res["keys"][0, 0] & np.uint64(0xFFFFFFFF))
+    c, w, lo, hi = oracle.initial_box(b["dur_ms"][0])
+    cands = oracle.candidates(int(b["seed"][0]), 0, range(4096), c, w, lo, hi)
+    ref, mref = oracle.score(cands, traces[0], 10.0, 0.0, nthreads=NTH)
+    check_argmin(ref, idx)
+    assert np.array_equal(res["opc"][0].view(np.uint32), cands[idx].view(np.uint32))
+    assert abs(res["rmse"][0] - ref[idx]) <= 1e-6
+    assert abs(res["mae"][0] - mref[idx]) <= 1e-6
+    assert res["status"][0] == 0
+
+
+def test_fit_replay_rounds(ctx, opmm):
+    """Full-estimation saccades (2-D, main-sequence durations), ragged candidate count, 4 rounds:
+    every round's winner checked against the oracle on the round's whole candidate set."""
+    full, traces_all = make_batch(8, "full")
+    pick = [0, 3, 5]
+    b = synth.subset(full, pick)
+    traces = [traces_all[i] for i in pick]
+    N, R = 2500, 4
+    res = run_fit(ctx, opmm, b, traces, N, R)
+    for s in range(b["S"]):
+        cen, w, lo, hi = centre_chain(b, s, res["keys"], R)
+        prev = None
+        for r in range(R):
+            cands = oracle.candidates(int(b["seed"][s]), r, range(N), cen[r], w * np.float32(0.5 ** r), lo, hi)
+            ref, _ = oracle.score(cands, traces[s], b["amp"][s], b["dir_deg"][s], nthreads=NTH)
+            idx = int(res["keys"][r, s] & np.uint64(0xFFFFFFFF))
+            check_argmin(ref, idx, (s, r))
+            if prev is not None:
+                assert ref[idx] <= prev + 1e-12   # incumbent is candidate 0: monotone
+            prev = ref[idx]
+        assert np.array_equal(res["opc"][s].view(np.uint32), cen[R].view(np.uint32))
+        ref_final, mae_final = oracle.cost(oracle.simulate(cen[R].astype(np.float64), b["amp"][s],
+                                                           int(b["T"][s])), traces[s], b["dir_deg"][s])
+        assert abs(res["rmse"][s] - ref_final) <= 1e-6 * max(1, ref_final)
+
+
+def test_fit_full_size_sampled(ctx, opmm):
+    """65536 candidates x 10 halving rounds on two full-estimation saccades.  Rounds 0 and 9 are
+    checked on a sample the oracle can afford: the GPU re-scores the whole round (opmm_score on the
+    regenerated candidates), the oracle scores the 64 best and the winner."""
+    full, traces_all = make_batch(16, "full")
+    pick = [1, 9]
+    b = synth.subset(full, pick)
+    traces = [traces_all[i] for i in pick]
+    N, R = 65536, 10
+    res = run_fit(ctx, opmm, b, traces, N, R, mode=opmm.FIT_PERSISTENT)
+    res2 = run_fit(ctx, opmm, b, traces, N, R, mode=opmm.FIT_ROUNDS)
+    assert np.array_equal(res["keys"], res2["keys"]) and np.array_equal(res["opc"], res2["opc"])
+    for s in range(b["S"]):
+        cen, w, lo, hi = centre_chain(b, s, res["keys"], R)
+        rec = records(synth.subset(b, [s]), opmm)
+        rec["pos_offset"] = 0
+        for r in (0, R - 1):
+            ww = w * np.float32(0.5 ** r)
+            allc = torch.zeros(N, 18, device="cuda")
+            ctx.candidates(int(b["seed"][s]), r, 0, N, cen[r], ww, lo, hi, allc)
+            g = torch.zeros(N, device="cuda")
+            ctx.score(allc, dev(traces[s].reshape(-1)), rec, g)
+            torch.cuda.synchronize()
+            g = g.cpu().numpy().astype(np.float64)
+            idx = int(res["keys"][r, s] & np.uint64(0xFFFFFFFF))
+            assert g[idx] == g.min() or g[idx] - g.min() <= 1e-7   # fused kernel and score agree
+            top = np.argsort(g, kind="stable")[:64]
+            sample = np.unique(np.r_[top, idx])
+            cands = oracle.candidates(int(b["seed"][s]), r, sample, cen[r], ww, lo, hi)
+            ref, _ = oracle.score(cands, traces[s], b["amp"][s], b["dir_deg"][s], nthreads=NTH)
+            assert np.all(np.abs(g[sample] - ref) <= cost_tol(ref))
+            # no unsampled candidate can be the oracle's argmin: its GPU cost is too high
+            margin = g[top[-1]] - g[idx]
+            wi = int(np.where(sample == idx)[0][0])
+            assert ref[wi] - ref.min() <= GAP
+            assert margin > 2e-6 or len(top) == N
+
+
+def test_modes_and_shapes_bit_identical(ctx, opmm):
+    b, traces = make_batch(5, "uneven")
+    ncand = np.array([1, 300, 1024, 2049, 5000], np.int32)
+    ref = None
+    for mode in (opmm.FIT_ROUNDS, opmm.FIT_PERSISTENT):
+        for tile in range(opmm.lib.opmm_tile_count()):
+            res = run_fit(ctx, opmm, b, traces, 64, 3, mode=mode, tile=tile, n_cand_per=ncand)
+            if ref is None:
+                ref = res
+            else:
+                assert np.array_equal(res["keys"], ref["keys"]), (mode, tile)
+                assert np.array_equal(res["opc"].view(np.uint32), ref["opc"].view(np.uint32)), (mode, tile)
+    assert np.all(ref["keys"][:, 0] & np.uint64(0xFFFFFFFF) == 0)   # n_cand = 1: only the centre
+
+
+def test_alone_equals_in_batch(ctx, opmm):
+    b, traces = make_batch(6, "full")
+    allres = run_fit(ctx, opmm, b, traces, 3000, 3, mode=opmm.FIT_PERSISTENT)
+    for s in (0, 4):
+        one = run_fit(ctx, opmm, synth.subset(b, [s]), [traces[s]], 3000, 3)
+        assert np.array_equal(one["keys"][:, 0], allres["keys"][:, s])
+        assert np.array_equal(one["opc"][0].view(np.uint32), allres["opc"][s].view(np.uint32))
+
+
+def test_graph_plan_replays(ctx, opmm):
+    b, traces = make_batch(7, "uneven")
+    ncand = np.array([4096, 16384, 4096, 1000, 7000, 50, 3000], np.int32)
+    eager = run_fit(ctx, opmm, b, traces, 64, 3, mode=opmm.FIT_PERSISTENT, n_cand_per=ncand)
+    S, R = b["S"], 3
+    recs = records(b, opmm, n_cand=ncand)
+    pos = dev(opmm.pack_traces(traces))
+    prm = opmm.fit_params(n_cand=64, n_rounds=R, mode=opmm.FIT_PERSISTENT)
+    opc = torch.zeros(S, 18, device="cuda")
+    rmse = torch.zeros(S, device="cuda")
+    keys = torch.zeros(R, S, dtype=torch.int64, device="cuda")
+    plan = ctx.plan(pos, recs, prm, opc, rmse, round_keys=keys)
+    for rep in range(3):
+        opc.zero_(); keys.zero_()
+        x = torch.randn(1000, device="cuda").sum()   # unrelated eager work between replays
+        plan.launch()
+        torch.cuda.synchronize()
+        assert float(x) == float(x)
+        assert np.array_equal(keys.cpu().numpy().view(np.uint64), eager["keys"]), rep
+        assert np.array_equal(opc.cpu().numpy().view(np.uint32), eager["opc"].view(np.uint32)), rep
+    plan.close()
+
+
+# --- edge cases ----------------------------------------------------------------------------------
+
+def test_edge_cases(ctx, opmm):
+    # leftward 1-channel saccade, pulse longer than the trace, a one-sample trace, NaN trace
+    rng = np.random.default_rng(5)
+    p1 = oracle.nominal(43.0) * rng.uniform(0.9, 1.1, 18)
+    tr_left = oracle.make_target(p1, 10.0, 180.0, 80, 1, rng.standard_normal((80, 1)), 0.05)
+    tr_short = oracle.make_target(p1, 10.0, 0.0, 20, 1, rng.standard_normal((20, 1)), 0.05)
+    tr_one = np.array([[0.01]], np.float32)
+    tr_nan = tr_short.copy(); tr_nan[5, 0] = np.nan
+    traces = [tr_left, tr_short, tr_one, tr_nan]
+    recs = opmm.saccade_records([80, 20, 1, 20], 1, [10.0] * 4, [180.0, 0.0, 0.0, 0.0], [43.0] * 4,
+                                np.array([11, 12, 13, 14], np.uint64))
+    S, N = 4, 1500
+    pos = dev(opmm.pack_traces(traces))
+    prm = opmm.fit_params(n_cand=N, n_rounds=1)
+    opc = torch.zeros(S, 18, device="cuda"); rmse = torch.zeros(S, device="cuda")
+    st = torch.zeros(S, dtype=torch.int32, device="cuda"); keys = torch.zeros(1, S, dtype=torch.int64, device="cuda")
+    ctx.fit(pos, recs, prm, opc, rmse, None, st, keys)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy(); keys = keys.cpu().numpy().view(np.uint64)
+    assert list(st) == [0, 0, 0, opmm.ST_NONFINITE_INPUT]
+    assert np.all(np.isnan(opc.cpu().numpy()[3])) and np.isnan(rmse.cpu().numpy()[3])
+    for s, (T, phi) in enumerate([(80, 180.0), (20, 0.0), (1, 0.0)]):
+        c, w, lo, hi = oracle.initial_box(43.0)
+        cands = oracle.candidates(11 + s, 0, range(N), c, w, lo, hi)
+        ref, _ = oracle.score(cands, traces[s], 10.0, phi, nthreads=NTH)
+        idx = int(keys[0, s] & np.uint64(0xFFFFFFFF))
+        if T == 1:   # theta_0 = 0 for every candidate: all tie, index 0 wins
+            assert idx == 0
+        else:
+            check_argmin(ref, idx, s)
+
+
+def test_maximum_trace_length(ctx, opmm):
+    rng = np.random.default_rng(6)
+    T = opmm.MAX_T
+    amp = np.array([25.0, 3.0], np.float32)
+    opc = np.stack([oracle.nominal(76.0) * rng.uniform(0.8, 1.2, 18) for _ in amp]).astype(np.float32)
+    out = torch.zeros(2, T, device="cuda")
+    ctx.simulate(dev(opc), dev(amp), T, out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    for i in range(2):
+        ref = oracle.simulate(opc[i].astype(np.float64), amp[i], T, nsub=4)
+        assert np.abs(g[i] - ref).max() <= 1e-4
+        assert abs(g[i, -1] - amp[i]) <= 1e-4   # settled at the amplitude
+
+
+def test_invalid_arguments_rejected(ctx, opmm):
+    pos = torch.zeros(200, device="cuda")
+    opc = torch.zeros(1, 18, device="cuda"); rmse = torch.zeros(1, device="cuda")
+    good = dict(T=[80], C=1, amp=[10.0], dir_deg=[0.0], dur_ms=[43.0], seed=[1])
+    bad = [dict(T=[0]), dict(T=[opmm.MAX_T + 1]), dict(C=3), dict(dir_deg=[45.0]), dict(dur_ms=[5.0]),
+           dict(amp=[float("nan")]), dict(T=[201])]
+    for b in bad:
+        kw = dict(good); kw.update(b)
+        recs = opmm.saccade_records(**kw)
+        with pytest.raises(opmm.OpmmError) as e:
+            ctx.fit(pos, recs, opmm.fit_params(), opc, rmse)
+        assert e.value.code == opmm.EINVAL, b
+    recs = opmm.saccade_records(**good)
+    for kw in (dict(n_cand=0), dict(n_rounds=0), dict(box_frac=1.5), dict(shrink=0.0), dict(dt_ms=2.0),
+               dict(mode=7), dict(tile=99)):
+        with pytest.raises(opmm.OpmmError) as e:
+            ctx.fit(pos, recs, opmm.fit_params(**kw), opc, rmse)
+        assert e.value.code == opmm.EINVAL, kw
+    # empty batch is a no-op
+    ctx.fit(pos, recs[:0], opmm.fit_params(), opc, rmse)

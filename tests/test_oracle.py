@@ -106,6 +106,12 @@ def test_initial_state_is_equilibrium_and_theta0_zero():
         dx = oracle.rhs(p, x0, lv[0], lv[1], 1e-3, 1e-3)
         assert np.abs(dx).max() < 1e-9 * max(1.0, np.abs(x0).max() / p[9])
         assert abs(x0[0]) < 1e-13
+        # any constant active state: the closed-form statics zero every derivative
+        fa, fn = rng.uniform(0, 80), rng.uniform(0, 40)
+        xe = oracle.equilibrium(p, fa, fn)
+        de = oracle.rhs(p, xe, fa, fn, 1e-3, 1e-3)
+        assert abs(xe[0]) > 1e-3
+        assert np.abs(de).max() < 1e-9 * max(1.0, np.abs(xe).max() / p[9])
 
 
 def test_zero_deviation_input_gives_no_motion():
