@@ -25,7 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOP_PER_CAND_SAMPLE = 54  # algorithmic work of one recurrence step + fused squared residual
-ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # non-packed FP32 FMA: 78.64 TFLOP/s
+ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # 256 CU x 4 SIMD x 16 lanes x FMA x 2.4 GHz: v_fma_f64 or non-packed v_fma_f32
 PUBLISHED_FP32_PEAK = 157.3
 
 
@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--rounds", type=int, default=10)
     ap.add_argument("--mode", choices=["persistent", "rounds"], default="persistent")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--tile", type=int, default=-2, help="kernel shape index; -1 default, -2 autotune")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     return ap.parse_args()
@@ -103,6 +104,10 @@ def main():
     S, N, R = a.saccades, a.n_cand, a.rounds
     mode = opmm.FIT_PERSISTENT if a.mode == "persistent" else opmm.FIT_ROUNDS
     prm = opmm.fit_params(n_cand=N, n_rounds=R, mode=mode)
+    if a.tile == -2:
+        prm.tile = ctx.autotune(pos, recs, prm)
+    else:
+        prm.tile = a.tile
     opc = torch.zeros(S, 18, device="cuda")
     rmse = torch.zeros(S, device="cuda")
     status = torch.zeros(S, dtype=torch.int32, device="cuda")
@@ -151,12 +156,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "full estimation: %d 2-D saccades (A~U[2,30] deg, D=2.2A+21 ms, 1 kHz), "
                                "%d candidates x %d halving rounds, plain box search" % (S, N, R),
                    "saccades": S, "n_cand": N, "rounds": R, "mean_T": float(np.mean(b["T"])),
-                   "mode": a.mode, "graph": not a.no_graph},
+                   "mode": a.mode, "graph": not a.no_graph, "tile": opmm.tile_names()[prm.tile] if prm.tile >= 0 else "default"},
         "saccades_fitted_per_s": S * a.steps / wall,
         "mean_final_rmse_deg": float(np.mean(rm)),
         "status_nonzero": int(np.count_nonzero(st)),

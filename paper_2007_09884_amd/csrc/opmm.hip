@@ -33,6 +33,10 @@ namespace {
 
 constexpr int NBIN = 256;  // pulse-end sample bins of the in-tile sort
 
+#ifndef OPMM_MIN_WAVES
+#define OPMM_MIN_WAVES 2  // waves per SIMD the register allocation must leave room for
+#endif
+
 struct SacDev {
     int64_t pos_off;
     int64_t proj_off;
@@ -164,26 +168,26 @@ __global__ void refine_kernel(int S, const SacDev* __restrict__ sacs, int r, con
 // Sinks for run_trajectory
 // ---------------------------------------------------------------------------
 
-struct SseSink {  // squared residual against the projected trace in LDS
-    const float* r;
-    float sse;
-    __device__ __forceinline__ void operator()(int k, float dth, float theq)
+struct SseSink {  // squared residual against the projected trace in LDS, FP64 sum
+    const R* r;
+    double sse;
+    __device__ __forceinline__ void operator()(int k, R dth, R theq)
     {
-        float e = (r[k] - theq) - dth;
-        sse = __fmaf_rn(e, e, sse);
+        R e = (r[k] - theq) - dth;
+        sse = fma((double)e, (double)e, sse);
     }
 };
 
 struct TrajSink {  // theta_k to global memory
     float* out;
-    __device__ __forceinline__ void operator()(int k, float dth, float theq) { out[k] = dth + theq; }
+    __device__ __forceinline__ void operator()(int k, R dth, R theq) { out[k] = (float)(dth + theq); }
 };
 
 struct Cost2dSink {  // both channels, FP64 accumulation (reporting only)
     const float* pos;
     int C;
     double cphi, sphi, sq, ab;
-    __device__ __forceinline__ void operator()(int k, float dth, float theq)
+    __device__ __forceinline__ void operator()(int k, R dth, R theq)
     {
         double th = (double)(dth + theq);
         double e0 = (double)pos[(int64_t)k * C] - th * cphi;
@@ -197,8 +201,9 @@ struct Cost2dSink {  // both channels, FP64 accumulation (reporting only)
     }
 };
 
-__device__ __forceinline__ uint64_t cost_key(float sse, uint32_t idx)
+__device__ __forceinline__ uint64_t cost_key(double sse64, uint32_t idx)
 {
+    float sse = (float)sse64;
     float c = (sse >= 0.0f && sse <= 3.402823466e38f) ? sse : __int_as_float(0x7F800000);
     return ((uint64_t)__float_as_uint(c) << 32) | idx;
 }
@@ -219,7 +224,7 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
 
 template <int TPB, int PASSES>
 struct TileSmem {
-    float r[OPMM_MAX_T];
+    R r[OPMM_MAX_T];
     Box box;
     int hist[NBIN];
     uint16_t perm[TPB * PASSES];
@@ -236,21 +241,22 @@ __device__ __forceinline__ uint64_t process_tile(TileSmem<TPB, PASSES>& sm, cons
     constexpr int TILE = TPB * PASSES;
     const int tid = threadIdx.x;
     const int T = sd.T;
-    for (int k = tid; k < T; k += TPB) sm.r[k] = proj[sd.proj_off + k];
+    for (int k = tid; k < T; k += TPB) sm.r[k] = (R)proj[sd.proj_off + k];
     load_box(sm.box, s, centre, hw, lo, hi);
     for (int i = tid; i < NBIN; i += TPB) sm.hist[i] = 0;
     __syncthreads();
 
     // Phase A: bin every candidate of the tile by its pulse-end sample.
     const uint32_t base = (uint32_t)t * TILE;
-    const float kbase = floorf(sm.box.lo[17] * rcp(dt));
+    const float rdt = rcp(dt);
+    const float kbase = floorf(sm.box.lo[17] * rdt);
     int mybin[PASSES];
 #pragma unroll
     for (int ps = 0; ps < PASSES; ++ps) {
         uint32_t idx = base + ps * TPB + tid;
         int bin = NBIN - 1;
         if ((int64_t)idx < sd.n_cand) {
-            float pw = draw_pw(sd.seed, (uint32_t)round, idx, sm.box) * rcp(dt);
+            float pw = draw_pw(sd.seed, (uint32_t)round, idx, sm.box) * rdt;
             float rel = fminf(fmaxf(floorf(pw) - kbase, 0.0f), (float)(NBIN - 2));
             bin = (int)rel;
         }
@@ -283,7 +289,10 @@ __device__ __forceinline__ uint64_t process_tile(TileSmem<TPB, PASSES>& sm, cons
 
     // Phase B: simulate and score in sorted order.
     uint64_t best = ~0ull;
+#pragma unroll 1
     for (int ps = 0; ps < PASSES; ++ps) {
+        // keep the box in LDS: re-read it per candidate instead of pinning 72 registers
+        asm volatile("" ::: "memory");
         const uint32_t j = sm.perm[ps * TPB + tid];
         const uint32_t idx = base + j;
         const bool valid = (int64_t)idx < sd.n_cand;
@@ -292,15 +301,15 @@ __device__ __forceinline__ uint64_t process_tile(TileSmem<TPB, PASSES>& sm, cons
         draw_candidate(sd.seed, (uint32_t)round, idx, sm.box, p);
         Plant pl;
         plant_setup(p, sd.amp, dt, pl);
-        float frac;
-        int k0 = pulse_end_sample(pl.pw, T, frac);
+        R frac;
+        int k0 = pulse_end_sample(pl.pwd, T, frac);
         int kmin = wave_min(valid ? k0 : 0x7FFFFFFF);
         int kmax = wave_max(valid ? k0 : -0x7FFFFFFF);
         kmin = __builtin_amdgcn_readfirstlane(kmin);
         kmax = __builtin_amdgcn_readfirstlane(kmax);
-        SseSink sink{sm.r, 0.0f};
+        SseSink sink{sm.r, 0.0};
         if (valid) {
-            run_trajectory<UNROLL>(pl, T, dt, k0, frac, kmin, kmax, sink);
+            run_trajectory<UNROLL>(pl, T, (R)dt, k0, frac, kmin, kmax, sink);
             uint64_t key = cost_key(sink.sse, idx);
             best = key < best ? key : best;
         }
@@ -326,7 +335,7 @@ __device__ __forceinline__ int find_saccade(const SacDev* __restrict__ sacs, int
 }
 
 template <int TPB, int PASSES, int UNROLL>
-__global__ __launch_bounds__(TPB) void fit_round_kernel(const SacDev* __restrict__ sacs, int S, int round,
+__global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_round_kernel(const SacDev* __restrict__ sacs, int S, int round,
                                                         float dt, const float* __restrict__ proj,
                                                         const float* centre, const float* hw,
                                                         const float* lo, const float* hi,
@@ -352,7 +361,7 @@ __global__ __launch_bounds__(TPB) void fit_round_kernel(const SacDev* __restrict
 // that takes a tile of a later round waits for that.  Every item it can wait
 // on was handed out earlier to a running block, so the queue always drains.
 template <int TPB, int PASSES, int UNROLL>
-__global__ __launch_bounds__(TPB) void fit_persistent_kernel(
+__global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_persistent_kernel(
     const SacDev* __restrict__ sacs, int S, int R, int tiles_per_round, float dt, float shrink,
     const float* __restrict__ proj, float* centre, float* hw, const float* lo, const float* hi,
     int32_t* status, uint64_t* keys, uint32_t* head, uint32_t* done, uint32_t* ready, uint32_t* errflag)
@@ -420,10 +429,10 @@ __global__ void report_kernel(int S, const SacDev* __restrict__ sacs, const floa
     for (int j = 0; j < P; ++j) p[j] = centre[(act ? s : 0) * P + j];
     Plant pl;
     plant_setup(p, sd.amp, dt, pl);
-    float frac;
-    int k0 = pulse_end_sample(pl.pw, sd.T, frac);
+    R frac;
+    int k0 = pulse_end_sample(pl.pwd, sd.T, frac);
     Cost2dSink sink{pos + sd.pos_off, sd.C, sd.cphi, sd.sphi, 0.0, 0.0};
-    run_trajectory<1>(pl, sd.T, dt, k0, frac, k0, k0, sink);
+    run_trajectory<1>(pl, sd.T, (R)dt, k0, frac, k0, k0, sink);
     if (!act) return;
     const int32_t st = status[s];
     const bool bad = (st & OPMM_ST_NONFINITE_INPUT) != 0;
@@ -439,7 +448,7 @@ __global__ void report_kernel(int S, const SacDev* __restrict__ sacs, const floa
 // Standalone simulate / score / candidates
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void simulate_kernel(int64_t n, const float* __restrict__ opc,
+__global__ __launch_bounds__(256, OPMM_MIN_WAVES) void simulate_kernel(int64_t n, const float* __restrict__ opc,
                                                        const float* __restrict__ amp, int T, float dt,
                                                        float* __restrict__ traj)
 {
@@ -450,21 +459,21 @@ __global__ __launch_bounds__(256) void simulate_kernel(int64_t n, const float* _
     for (int j = 0; j < P; ++j) p[j] = opc[ii * P + j];
     Plant pl;
     plant_setup(p, amp[ii], dt, pl);
-    float frac;
-    int k0 = pulse_end_sample(pl.pw, T, frac);
+    R frac;
+    int k0 = pulse_end_sample(pl.pwd, T, frac);
     int kmin = wave_min(valid ? k0 : 0x7FFFFFFF), kmax = wave_max(valid ? k0 : -0x7FFFFFFF);
     if (!valid) return;
     TrajSink sink{traj + ii * T};
-    run_trajectory<2>(pl, T, dt, k0, frac, kmin, kmax, sink);
+    run_trajectory<2>(pl, T, (R)dt, k0, frac, kmin, kmax, sink);
 }
 
-__global__ __launch_bounds__(256) void score_kernel(int64_t n, const float* __restrict__ opc,
+__global__ __launch_bounds__(256, OPMM_MIN_WAVES) void score_kernel(int64_t n, const float* __restrict__ opc,
                                                     const float* __restrict__ proj, int T, int C,
                                                     const double* __restrict__ qorth, float amp, float dt,
                                                     float* __restrict__ rmse)
 {
-    __shared__ float r[OPMM_MAX_T];
-    for (int k = threadIdx.x; k < T; k += blockDim.x) r[k] = proj[k];
+    __shared__ R r[OPMM_MAX_T];
+    for (int k = threadIdx.x; k < T; k += blockDim.x) r[k] = (R)proj[k];
     __syncthreads();
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool valid = i < n;
@@ -473,13 +482,13 @@ __global__ __launch_bounds__(256) void score_kernel(int64_t n, const float* __re
     for (int j = 0; j < P; ++j) p[j] = opc[ii * P + j];
     Plant pl;
     plant_setup(p, amp, dt, pl);
-    float frac;
-    int k0 = pulse_end_sample(pl.pw, T, frac);
+    R frac;
+    int k0 = pulse_end_sample(pl.pwd, T, frac);
     int kmin = wave_min(valid ? k0 : 0x7FFFFFFF), kmax = wave_max(valid ? k0 : -0x7FFFFFFF);
     if (!valid) return;
-    SseSink sink{r, 0.0f};
-    run_trajectory<2>(pl, T, dt, k0, frac, kmin, kmax, sink);
-    double tot = ((double)sink.sse + qorth[0]) / ((double)T * C);
+    SseSink sink{r, 0.0};
+    run_trajectory<2>(pl, T, (R)dt, k0, frac, kmin, kmax, sink);
+    double tot = (sink.sse + qorth[0]) / ((double)T * C);
     float v = (float)sqrt(tot);
     rmse[i] = (v >= 0.0f && v <= 3.402823466e38f) ? v : __int_as_float(0x7F800000);
 }
@@ -518,6 +527,8 @@ const Shape kShapes[] = {
     {256, 4, 2, "tpb256_pass4_unroll2"},
     {256, 4, 4, "tpb256_pass4_unroll4"},
     {64, 16, 1, "tpb64_pass16_unroll1"},
+    {256, 16, 1, "tpb256_pass16_unroll1"},
+    {128, 32, 1, "tpb128_pass32_unroll1"},
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
@@ -556,7 +567,9 @@ hipError_t launch_fit_kernel(int shape, const FitLaunch& L, bool persistent, int
     case 3: return launch_shape<128, 8, 1>(L, persistent, round, st);
     case 4: return launch_shape<256, 4, 2>(L, persistent, round, st);
     case 5: return launch_shape<256, 4, 4>(L, persistent, round, st);
-    default: return launch_shape<64, 16, 1>(L, persistent, round, st);
+    case 6: return launch_shape<64, 16, 1>(L, persistent, round, st);
+    case 7: return launch_shape<256, 16, 1>(L, persistent, round, st);
+    default: return launch_shape<128, 32, 1>(L, persistent, round, st);
     }
 }
 
@@ -579,7 +592,9 @@ int shape_blocks_per_cu(int shape)
     case 3: return persistent_blocks_per_cu<128, 8, 1>();
     case 4: return persistent_blocks_per_cu<256, 4, 2>();
     case 5: return persistent_blocks_per_cu<256, 4, 4>();
-    default: return persistent_blocks_per_cu<64, 16, 1>();
+    case 6: return persistent_blocks_per_cu<64, 16, 1>();
+    case 7: return persistent_blocks_per_cu<256, 16, 1>();
+    default: return persistent_blocks_per_cu<128, 32, 1>();
     }
 }
 
@@ -778,7 +793,10 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
     L.grid_persistent = 0;
     if (tiles_per_round > 0) {
         if (prm->mode == OPMM_FIT_PERSISTENT) {
-            int64_t want = (int64_t)shape_blocks_per_cu(shape) * std::max(ctx->cu_count, 1);
+            // The queue needs no co-residency, so oversubscribe: blocks that start
+            // after the queue has drained exit at once.
+            int64_t want = (int64_t)std::max(2, shape_blocks_per_cu(shape)) * 4 * std::max(ctx->cu_count, 1) *
+                           256 / kShapes[shape].tpb;
             int64_t total = (int64_t)R * tiles_per_round;
             L.grid_persistent = (int)std::max<int64_t>(1, std::min(want, total));
             OPMM_HIP(ctx, launch_fit_kernel(shape, L, true, 0, st));

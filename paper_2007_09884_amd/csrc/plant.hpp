@@ -22,6 +22,32 @@ namespace opmm {
 
 constexpr int P = 18;
 
+// Precision of the per-sample recurrence and of the transition matrix.
+#ifndef OPMM_REC_T
+#define OPMM_REC_T double
+#endif
+using R = OPMM_REC_T;
+
+__device__ __forceinline__ float fmr(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+__device__ __forceinline__ double fmr(double a, double b, double c) { return __fma_rn(a, b, c); }
+
+// Taylor degree and squarings of the one-sample transition, and the degree of
+// the exponential-vector product of the split sample, per precision: each
+// set puts the truncation error below that precision's rounding floor over
+// +/-25% boxes (FP64: ~5e-9 deg, FP32: ~6e-6 deg on 150-sample traces).
+#ifndef OPMM_TAYLOR_M
+#define OPMM_TAYLOR_M (sizeof(R) == 8 ? 6 : 8)
+#endif
+#ifndef OPMM_TAYLOR_SQ
+#define OPMM_TAYLOR_SQ (sizeof(R) == 8 ? 2 : 0)
+#endif
+#ifndef OPMM_EXPMV_M
+#define OPMM_EXPMV_M (sizeof(R) == 8 ? 11 : 8)
+#endif
+constexpr int TAYLOR_M = OPMM_TAYLOR_M;
+constexpr int TAYLOR_SQ = OPMM_TAYLOR_SQ;
+constexpr int EXPMV_M = OPMM_EXPMV_M;
+
 // Table 1 nominal values, in the table's order and units.  The pulse width
 // (index 17) is the saccade duration minus 6 ms.
 __host__ __device__ inline float nominal_param(int j, float dur_ms)
@@ -112,85 +138,126 @@ __device__ __forceinline__ float draw_pw(uint64_t seed, uint32_t round, uint32_t
 
 struct Plant {
     // continuous-time system matrix entries (per ms); theta' = omega is implicit
-    float a10, a11, a12, a13;  // omega row: theta, omega, x_ag, x_ant
-    float a20, a22, g2;        // x_ag row: theta, x_ag, F_ag
-    float a30, a33, g3;        // x_ant row: theta, x_ant, F_ant
-    float q1a, q1n, q2a, q2n;  // F rows: -1/tau, pulse (activation) and post (deactivation)
+    R a10, a11, a12, a13;      // omega row: theta, omega, x_ag, x_ant
+    R a20, a22, g2;            // x_ag row: theta, x_ag, F_ag
+    R a30, a33, g3;            // x_ant row: theta, x_ant, F_ant
+    R q1a, q1n, q2a, q2n;      // F rows: -1/tau, pulse (activation) and post (deactivation)
     // one-sample transition in D-form (Phi - I)
-    float m[4][4];             // mechanical block
-    float x1[4][2], x2[4][2];  // coupling to (F_ag, F_ant), pulse and post pieces
-    float e1[2], e2[2];        // F decay factor minus one, pulse and post pieces
+    R m[4][4];                 // mechanical block
+    R x1[4][2], x2[4][2];      // coupling to (F_ag, F_ant), pulse and post pieces
+    R e1[2], e2[2];            // F decay factor minus one, pulse and post pieces
     // equilibria and switching
-    float th1;                 // theta at the pulse equilibrium
-    float amp;                 // theta at the post equilibrium (= amplitude)
-    float sh[6];               // pulse equilibrium minus post equilibrium
-    float d0[6];               // resting state minus pulse equilibrium
-    float pw;                  // PW in sample periods
+    R th1;                     // theta at the pulse equilibrium
+    R amp;                     // theta at the post equilibrium (= amplitude)
+    R sh[6];                   // pulse equilibrium minus post equilibrium
+    R d0[6];                   // resting state minus pulse equilibrium
+    float pw;                  // PW (ms)
+    double pwd;                // PW in sample periods
 };
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// 1/x in FP64: hardware reciprocal refined by two Newton steps (the relative
+// error of the seed squares each step), within an ulp or two of the rounded quotient.
+__device__ __forceinline__ double rcp64(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = __fma_rn(-x, y, 1.0);
+    y = __fma_rn(y, e, y);
+    e = __fma_rn(-x, y, 1.0);
+    return __fma_rn(y, e, y);
+}
+
 // mechanical rows of (s*A) V, plus `acc` on the diagonal of column `diag` (-1: none)
 #define OPMM_MV(s10, s11, s12, s13, s20, s22, s30, s33, sv, V0, V1, V2, V3, o0, o1, o2, o3, i0, i1, i2, i3) \
     do {                                                                                               \
-        o0 = __fmaf_rn(sv, V1, i0);                                                                    \
-        o1 = __fmaf_rn(s13, V3, __fmaf_rn(s12, V2, __fmaf_rn(s11, V1, __fmaf_rn(s10, V0, i1))));       \
-        o2 = __fmaf_rn(s22, V2, __fmaf_rn(s20, V0, i2));                                               \
-        o3 = __fmaf_rn(s33, V3, __fmaf_rn(s30, V0, i3));                                               \
+        o0 = fmr(sv, V1, i0);                                                                    \
+        o1 = fmr(s13, V3, fmr(s12, V2, fmr(s11, V1, fmr(s10, V0, i1))));       \
+        o2 = fmr(s22, V2, fmr(s20, V0, i2));                                               \
+        o3 = fmr(s33, V3, fmr(s30, V0, i3));                                               \
     } while (0)
 
-// Horner evaluation of D = sum_{k=1..8} (hA)^k / k! for the augmented block
+// Horner evaluation of D = sum_{k=1..M} (hA)^k / k! for the augmented block
 // matrix [[Mech, G1, G2], [0, Q1, 0], [0, 0, Q2]] whose off-diagonal blocks
-// give the pulse-piece and post-piece coupling columns at once.
-__device__ __forceinline__ void transition_dform(Plant& pl, float h)
+// give the pulse-piece and post-piece coupling columns at once, on the step
+// h/2^SQ, then SQ squarings in D-form: D_2h = D_h^2 + 2 D_h.
+__device__ __forceinline__ void transition_dform(Plant& pl, R hfull)
 {
-    constexpr int M = 8;
-    float pm[4][4], px[4][4], pd[4];
-    const float qv[4] = {pl.q1a, pl.q1n, pl.q2a, pl.q2n};
+    constexpr int M = TAYLOR_M;
+    const R h = hfull * (R(1) / R(1 << TAYLOR_SQ));
+    R pm[4][4], px[4][4], pd[4];
+    const R qv[4] = {pl.q1a, pl.q1n, pl.q2a, pl.q2n};
     {   // P_M = I + hA/M
-        const float s = h * (1.0f / M);
-        const float s10 = pl.a10 * s, s11 = pl.a11 * s, s12 = pl.a12 * s, s13 = pl.a13 * s;
-        const float s20 = pl.a20 * s, s22 = pl.a22 * s, s30 = pl.a30 * s, s33 = pl.a33 * s;
-        pm[0][0] = 1.0f; pm[0][1] = s;    pm[0][2] = 0.0f; pm[0][3] = 0.0f;
-        pm[1][0] = s10;  pm[1][1] = 1.0f + s11; pm[1][2] = s12; pm[1][3] = s13;
-        pm[2][0] = s20;  pm[2][1] = 0.0f; pm[2][2] = 1.0f + s22; pm[2][3] = 0.0f;
-        pm[3][0] = s30;  pm[3][1] = 0.0f; pm[3][2] = 0.0f; pm[3][3] = 1.0f + s33;
+        const R s = h * (R(1) / R(M));
+        const R s10 = pl.a10 * s, s11 = pl.a11 * s, s12 = pl.a12 * s, s13 = pl.a13 * s;
+        const R s20 = pl.a20 * s, s22 = pl.a22 * s, s30 = pl.a30 * s, s33 = pl.a33 * s;
+        pm[0][0] = R(1); pm[0][1] = s;    pm[0][2] = R(0); pm[0][3] = R(0);
+        pm[1][0] = s10;  pm[1][1] = R(1) + s11; pm[1][2] = s12; pm[1][3] = s13;
+        pm[2][0] = s20;  pm[2][1] = R(0); pm[2][2] = R(1) + s22; pm[2][3] = R(0);
+        pm[3][0] = s30;  pm[3][1] = R(0); pm[3][2] = R(0); pm[3][3] = R(1) + s33;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            px[0][c] = 0.0f; px[1][c] = 0.0f;
-            px[2][c] = (c & 1) ? 0.0f : pl.g2 * s;
-            px[3][c] = (c & 1) ? pl.g3 * s : 0.0f;
-            pd[c] = __fmaf_rn(qv[c], s, 1.0f);
+            px[0][c] = R(0); px[1][c] = R(0);
+            px[2][c] = (c & 1) ? R(0) : pl.g2 * s;
+            px[3][c] = (c & 1) ? pl.g3 * s : R(0);
+            pd[c] = fmr(qv[c], s, R(1));
         }
     }
 #pragma unroll
     for (int k = M - 1; k >= 1; --k) {
         // k >= 2: P <- I + (h/k) A P ;  k == 1: D <- h A P
-        const float s = (k == 1) ? h : h * (1.0f / k);
-        const float one = (k == 1) ? 0.0f : 1.0f;
-        const float s10 = pl.a10 * s, s11 = pl.a11 * s, s12 = pl.a12 * s, s13 = pl.a13 * s;
-        const float s20 = pl.a20 * s, s22 = pl.a22 * s, s30 = pl.a30 * s, s33 = pl.a33 * s;
-        const float sg2 = pl.g2 * s, sg3 = pl.g3 * s;
-        float nm[4][4], nx[4][4], nd[4];
+        R s = (k == 1) ? h : h * (R(1) / R(k));
+        // opaque per step: stops the compiler from forming every step's scaled
+        // coefficients up front, which would pin ~10 registers per step
+        asm volatile("" : "+v"(s));
+        const R one = (k == 1) ? R(0) : R(1);
+        const R s10 = pl.a10 * s, s11 = pl.a11 * s, s12 = pl.a12 * s, s13 = pl.a13 * s;
+        const R s20 = pl.a20 * s, s22 = pl.a22 * s, s30 = pl.a30 * s, s33 = pl.a33 * s;
+        const R sg2 = pl.g2 * s, sg3 = pl.g3 * s;
+        R nm[4][4], nx[4][4], nd[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             OPMM_MV(s10, s11, s12, s13, s20, s22, s30, s33, s, pm[0][c], pm[1][c], pm[2][c], pm[3][c],
                     nm[0][c], nm[1][c], nm[2][c], nm[3][c],
-                    c == 0 ? one : 0.0f, c == 1 ? one : 0.0f, c == 2 ? one : 0.0f, c == 3 ? one : 0.0f);
+                    c == 0 ? one : R(0), c == 1 ? one : R(0), c == 2 ? one : R(0), c == 3 ? one : R(0));
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const float ga = (c & 1) ? 0.0f : sg2 * pd[c];
-            const float gn = (c & 1) ? sg3 * pd[c] : 0.0f;
+            const R ga = (c & 1) ? R(0) : sg2 * pd[c];
+            const R gn = (c & 1) ? sg3 * pd[c] : R(0);
             OPMM_MV(s10, s11, s12, s13, s20, s22, s30, s33, s, px[0][c], px[1][c], px[2][c], px[3][c],
-                    nx[0][c], nx[1][c], nx[2][c], nx[3][c], 0.0f, 0.0f, ga, gn);
-            nd[c] = __fmaf_rn(qv[c] * s, pd[c], one);
+                    nx[0][c], nx[1][c], nx[2][c], nx[3][c], R(0), R(0), ga, gn);
+            nd[c] = fmr(qv[c] * s, pd[c], one);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) { pm[i][c] = nm[i][c]; px[i][c] = nx[i][c]; }
             pd[i] = nd[i];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < TAYLOR_SQ; ++q) {
+        R nm[4][4], nx[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                R a = pm[i][c] + pm[i][c];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) a = fmr(pm[i][k], pm[k][c], a);
+                nm[i][c] = a;
+                R b = px[i][c] * (pd[c] + R(2));
+#pragma unroll
+                for (int k = 0; k < 4; ++k) b = fmr(pm[i][k], px[k][c], b);
+                nx[i][c] = b;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) { pm[i][c] = nm[i][c]; px[i][c] = nx[i][c]; }
+            pd[i] = pd[i] * (pd[i] + R(2));
         }
     }
 #pragma unroll
@@ -205,98 +272,104 @@ __device__ __forceinline__ void transition_dform(Plant& pl, float h)
 }
 
 // Coefficients, transition and equilibria of candidate p for a saccade of
-// amplitude amp (deg), sample period dt (ms).
+// amplitude amp (deg), sample period dt (ms).  The scalar part (matrix
+// entries, equilibria, deviations) is formed in FP64 and rounded once to FP32:
+// FP32 chains of reciprocals here would shift the equilibria by a few ulps of
+// ~10 deg, i.e. ~1e-6 deg on every sample.  FP64 runs at the FP32 rate on the
+// vector ALU, and this part is a few hundred operations per candidate.
 __device__ __forceinline__ void plant_setup(const float p[P], float amp, float dt, Plant& pl)
 {
-    const float kse_a = p[0], kse_n = p[1], klt_a = p[2], klt_n = p[3];
-    const float b_a = p[4] * 1e3f, b_n = p[5] * 1e3f, b_p = p[6] * 1e3f;
-    const float nc_a = p[7], nc_n = p[8];
-    const float kp = nc_a + nc_n;             // passive elasticity = sum of tension slopes
-    const float jm = p[9] * 1e6f;
-    const float ij = rcp(jm), iba = rcp(b_a), ibn = rcp(b_n);
-    pl.a10 = -(kse_a + kse_n + kp) * ij;
-    pl.a11 = -b_p * ij;
-    pl.a12 = kse_a * ij;
-    pl.a13 = -kse_n * ij;
-    pl.a20 = kse_a * iba;
-    pl.a22 = -(klt_a + kse_a) * iba;
-    pl.g2 = iba;
-    pl.a30 = -kse_n * ibn;
-    pl.a33 = -(klt_n + kse_n) * ibn;
-    pl.g3 = ibn;
-    pl.q1a = -rcp(p[10]);
-    pl.q1n = -rcp(p[11]);
-    pl.q2a = -rcp(p[12]);
-    pl.q2n = -rcp(p[13]);
-    transition_dform(pl, dt);
+    const double kse_a = p[0], kse_n = p[1], klt_a = p[2], klt_n = p[3];
+    const double b_a = (double)p[4] * 1e3, b_n = (double)p[5] * 1e3, b_p = (double)p[6] * 1e3;
+    const double nc_a = p[7], nc_n = p[8];
+    const double kp = nc_a + nc_n;            // passive elasticity = sum of tension slopes
+    const double jm = (double)p[9] * 1e6;
+    const double ij = rcp64(jm), iba = rcp64(b_a), ibn = rcp64(b_n);
+    pl.a10 = (R)(-(kse_a + kse_n + kp) * ij);
+    pl.a11 = (R)(-b_p * ij);
+    pl.a12 = (R)(kse_a * ij);
+    pl.a13 = (R)(-kse_n * ij);
+    pl.a20 = (R)(kse_a * iba);
+    pl.a22 = (R)(-(klt_a + kse_a) * iba);
+    pl.g2 = (R)iba;
+    pl.a30 = (R)(-kse_n * ibn);
+    pl.a33 = (R)(-(klt_n + kse_n) * ibn);
+    pl.g3 = (R)ibn;
+    pl.q1a = (R)(-rcp64((double)p[10]));
+    pl.q1n = (R)(-rcp64((double)p[11]));
+    pl.q2a = (R)(-rcp64((double)p[12]));
+    pl.q2n = (R)(-rcp64((double)p[13]));
+    transition_dform(pl, (R)dt);
 
-    // statics: fraction of the active state carried by the series element
-    const float iksa = rcp(kse_a), iksn = rcp(kse_n);
-    const float ica = 1.0f + klt_a * iksa, icn = 1.0f + klt_n * iksn;  // 1/c_m
-    const float ca = rcp(ica), cn = rcp(icn);
-    const float kt = kp + ca * klt_a + cn * klt_n;
-    const float nfix = p[14], ns_a = p[15], ns_n = p[16];
-    // rest: theta = 0, fixation tensions N_C_FIX on both muscles
-    const float xa0 = nfix * iksa, xn0 = nfix * iksn;
-    const float fa0 = nfix * ica, fn0 = nfix * icn;
+    // statics: c_m = K_SE/(K_SE + K_LT) is the share of the active state the series element carries
+    const double iksa = rcp64(kse_a), iksn = rcp64(kse_n);
+    const double ica = 1.0 + klt_a * iksa, icn = 1.0 + klt_n * iksn;  // 1/c_m
+    const double ca = kse_a * rcp64(kse_a + klt_a), cn = kse_n * rcp64(kse_n + klt_n);
+    const double kt = kp + ca * klt_a + cn * klt_n;
+    const double nfix = p[14], ns_a = p[15], ns_n = p[16], a = amp;
+    // rest: theta = 0, fixation tension N_C_FIX on both muscles
+    const double xa0 = nfix * iksa, xn0 = nfix * iksn;
+    const double fa0 = nfix * ica, fn0 = nfix * icn;
     // pulse piece equilibrium (active states at the pulse heights)
-    const float th1 = (ca * ns_a - cn * ns_n) * rcp(kt);
-    const float ta1 = ca * (ns_a - klt_a * th1), tn1 = cn * (ns_n + klt_n * th1);
-    const float xa1 = th1 + ta1 * iksa, xn1 = tn1 * iksn - th1;
+    const double th1 = (ca * ns_a - cn * ns_n) * rcp64(kt);
+    const double ta1 = ca * (ns_a - klt_a * th1), tn1 = cn * (ns_n + klt_n * th1);
+    const double xa1 = th1 + ta1 * iksa, xn1 = tn1 * iksn - th1;
     // post piece equilibrium: the step holds the eye at the amplitude
-    const float ta2 = __fmaf_rn(nc_a, amp, nfix), tn2 = __fmaf_rn(-nc_n, amp, nfix);
-    const float xa2 = amp + ta2 * iksa, xn2 = tn2 * iksn - amp;
-    const float fa2 = __fmaf_rn(ta2, ica, klt_a * amp), fn2 = __fmaf_rn(tn2, icn, -klt_n * amp);
-    pl.th1 = th1;
+    const double ta2 = nfix + nc_a * a, tn2 = nfix - nc_n * a;
+    const double xa2 = a + ta2 * iksa, xn2 = tn2 * iksn - a;
+    const double fa2 = ta2 * ica + klt_a * a, fn2 = tn2 * icn - klt_n * a;
+    pl.th1 = (R)th1;
     pl.amp = amp;
-    pl.d0[0] = -th1; pl.d0[1] = 0.0f; pl.d0[2] = xa0 - xa1; pl.d0[3] = xn0 - xn1;
-    pl.d0[4] = fa0 - ns_a; pl.d0[5] = fn0 - ns_n;
-    pl.sh[0] = th1 - amp; pl.sh[1] = 0.0f; pl.sh[2] = xa1 - xa2; pl.sh[3] = xn1 - xn2;
-    pl.sh[4] = ns_a - fa2; pl.sh[5] = ns_n - fn2;
-    pl.pw = p[17] * rcp(dt);
+    pl.d0[0] = (R)(-th1); pl.d0[1] = R(0); pl.d0[2] = (R)(xa0 - xa1); pl.d0[3] = (R)(xn0 - xn1);
+    pl.d0[4] = (R)(fa0 - ns_a); pl.d0[5] = (R)(fn0 - ns_n);
+    pl.sh[0] = (R)(th1 - a); pl.sh[1] = R(0); pl.sh[2] = (R)(xa1 - xa2); pl.sh[3] = (R)(xn1 - xn2);
+    pl.sh[4] = (R)(ns_a - fa2); pl.sh[5] = (R)(ns_n - fn2);
+    pl.pw = p[17];
+    pl.pwd = (double)p[17] * rcp64((double)dt);
 }
 
 // d <- Phi d for one sample (D-form: d + D d)
-__device__ __forceinline__ void step(const Plant& pl, const float (&x)[4][2], const float (&e)[2], float d[6])
+__device__ __forceinline__ void step(const Plant& pl, const R (&x)[4][2], const R (&e)[2], R d[6])
 {
-    float n[4];
+    R n[4];
     // the row's own state is the addend of the first fma
-    n[0] = __fmaf_rn(pl.m[0][0], d[0], d[0]);
-    n[1] = __fmaf_rn(pl.m[1][1], d[1], d[1]);
-    n[2] = __fmaf_rn(pl.m[2][2], d[2], d[2]);
-    n[3] = __fmaf_rn(pl.m[3][3], d[3], d[3]);
+    n[0] = fmr(pl.m[0][0], d[0], d[0]);
+    n[1] = fmr(pl.m[1][1], d[1], d[1]);
+    n[2] = fmr(pl.m[2][2], d[2], d[2]);
+    n[3] = fmr(pl.m[3][3], d[3], d[3]);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-            if (c != i) n[i] = __fmaf_rn(pl.m[i][c], d[c], n[i]);
-        n[i] = __fmaf_rn(x[i][0], d[4], n[i]);
-        n[i] = __fmaf_rn(x[i][1], d[5], n[i]);
+            if (c != i) n[i] = fmr(pl.m[i][c], d[c], n[i]);
+        n[i] = fmr(x[i][0], d[4], n[i]);
+        n[i] = fmr(x[i][1], d[5], n[i]);
     }
-    d[4] = __fmaf_rn(e[0], d[4], d[4]);
-    d[5] = __fmaf_rn(e[1], d[5], d[5]);
+    d[4] = fmr(e[0], d[4], d[4]);
+    d[5] = fmr(e[1], d[5], d[5]);
 #pragma unroll
     for (int i = 0; i < 4; ++i) d[i] = n[i];
 }
 
-// v <- exp(A t) v by a degree-8 Taylor polynomial in Horner form (t <= dt).
-__device__ __forceinline__ void expmv(const Plant& pl, float qa, float qn, float t, float v[6])
+// v <- exp(A t) v by a degree-EXPMV_M Taylor polynomial in Horner form (t <= dt).
+__device__ __forceinline__ void expmv(const Plant& pl, R qa, R qn, R t, R v[6])
 {
-    float w[6];
+    R w[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) w[i] = v[i];
 #pragma unroll
-    for (int k = 8; k >= 1; --k) {
-        const float s = t * (1.0f / k);
-        float aw[6];
+    for (int k = EXPMV_M; k >= 1; --k) {
+        R s = t * (R(1) / R(k));
+        asm volatile("" : "+v"(s));
+        R aw[6];
         aw[0] = w[1];
-        aw[1] = __fmaf_rn(pl.a13, w[3], __fmaf_rn(pl.a12, w[2], __fmaf_rn(pl.a11, w[1], pl.a10 * w[0])));
-        aw[2] = __fmaf_rn(pl.g2, w[4], __fmaf_rn(pl.a22, w[2], pl.a20 * w[0]));
-        aw[3] = __fmaf_rn(pl.g3, w[5], __fmaf_rn(pl.a33, w[3], pl.a30 * w[0]));
+        aw[1] = fmr(pl.a13, w[3], fmr(pl.a12, w[2], fmr(pl.a11, w[1], pl.a10 * w[0])));
+        aw[2] = fmr(pl.g2, w[4], fmr(pl.a22, w[2], pl.a20 * w[0]));
+        aw[3] = fmr(pl.g3, w[5], fmr(pl.a33, w[3], pl.a30 * w[0]));
         aw[4] = qa * w[4];
         aw[5] = qn * w[5];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) w[i] = __fmaf_rn(s, aw[i], v[i]);
+        for (int i = 0; i < 6; ++i) w[i] = fmr(s, aw[i], v[i]);
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) v[i] = w[i];
@@ -304,12 +377,12 @@ __device__ __forceinline__ void expmv(const Plant& pl, float qa, float qn, float
 
 // The sample that contains the pulse end: pulse dynamics for frac*dt, switch
 // to the post piece's coordinates, post dynamics for the rest of the sample.
-__device__ __forceinline__ void split_step(const Plant& pl, float frac, float dt, float d[6])
+__device__ __forceinline__ void split_step(const Plant& pl, R frac, R dt, R d[6])
 {
     expmv(pl, pl.q1a, pl.q1n, frac * dt, d);
 #pragma unroll
     for (int i = 0; i < 6; ++i) d[i] += pl.sh[i];
-    expmv(pl, pl.q2a, pl.q2n, (1.0f - frac) * dt, d);
+    expmv(pl, pl.q2a, pl.q2n, (R(1) - frac) * dt, d);
 }
 
 // wave-wide min / max of an int (64 lanes)
@@ -328,13 +401,13 @@ __device__ __forceinline__ int wave_max(int v)
 
 // Integer sample index that holds the pulse end (-1: no pulse), clamped to
 // [-1, T], and the fraction of that sample spent in the pulse.
-__device__ __forceinline__ int pulse_end_sample(float pw, int T, float& frac)
+__device__ __forceinline__ int pulse_end_sample(double pw, int T, R& frac)
 {
-    float fl = floorf(pw);
+    double fl = floor(pw);
     int k0;
-    if (!(pw > 0.0f)) { k0 = -1; frac = 0.0f; }
-    else if (fl >= (float)T) { k0 = T; frac = 0.0f; }
-    else { k0 = (int)fl; frac = pw - fl; }
+    if (!(pw > 0.0)) { k0 = -1; frac = R(0); }
+    else if (fl >= (double)T) { k0 = T; frac = R(0); }
+    else { k0 = (int)fl; frac = (R)(pw - fl); }
     return k0;
 }
 
@@ -343,13 +416,13 @@ __device__ __forceinline__ int pulse_end_sample(float pw, int T, float& frac)
 // lanes' pulse-end samples; samples below kmin are pulse for every lane and
 // samples above kmax post for every lane, so only [kmin, kmax] branches.
 template <int UNROLL, class Sink>
-__device__ __forceinline__ void run_trajectory(const Plant& pl, int T, float dt, int k0, float frac,
+__device__ __forceinline__ void run_trajectory(const Plant& pl, int T, R dt, int k0, R frac,
                                                int kmin, int kmax, Sink& sink)
 {
-    float d[6];
+    R d[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) d[i] = pl.d0[i];
-    float theq = pl.th1;
+    R theq = pl.th1;
     if (k0 < 0) {  // PW <= 0: no pulse, the step acts from t = 0
 #pragma unroll
         for (int i = 0; i < 6; ++i) d[i] += pl.sh[i];
@@ -363,6 +436,7 @@ __device__ __forceinline__ void run_trajectory(const Plant& pl, int T, float dt,
         step(pl, pl.x1, pl.e1, d);
     }
     const int kb = min(kmax, T - 1);
+#pragma unroll 1
     for (; k <= kb; ++k) {
         sink(k, d[0], theq);
         if (k < k0) {

@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libopmm.so")
+LIB_PATH = os.environ.get("OPMM_LIBRARY") or os.path.join(_PKG, "libopmm.so")
 P = 18
 MAX_T = 2048
 

@@ -228,12 +228,15 @@ def test_fit_full_size_sampled(ctx, opmm):
             sample = np.unique(np.r_[top, idx])
             cands = oracle.candidates(int(b["seed"][s]), r, sample, cen[r], ww, lo, hi)
             ref, _ = oracle.score(cands, traces[s], b["amp"][s], b["dir_deg"][s], nthreads=NTH)
-            assert np.all(np.abs(g[sample] - ref) <= cost_tol(ref))
-            # no unsampled candidate can be the oracle's argmin: its GPU cost is too high
-            margin = g[top[-1]] - g[idx]
+            err = np.abs(g[sample] - ref)
+            assert np.all(err <= cost_tol(ref))
             wi = int(np.where(sample == idx)[0][0])
             assert ref[wi] - ref.min() <= GAP
-            assert margin > 2e-6 or len(top) == N
+            # An unsampled candidate j has oracle cost >= g[top[-1]] - eps, so it cannot undercut the
+            # winner by more than GAP once the GPU margin exceeds 2 eps - GAP (eps: cost error bound).
+            eps = 2 * err.max() + 1e-9
+            margin = g[top[-1]] - g[idx]
+            assert margin >= 2 * eps - GAP, (margin, eps)
 
 
 def test_modes_and_shapes_bit_identical(ctx, opmm):
