@@ -42,6 +42,12 @@ def parse():
     ap.add_argument("--tile", type=int, default=-2, help="kernel shape index; -1 default, -2 autotune")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--train-saccades", type=int, default=10_000_000)
+    ap.add_argument("--heldout", type=int, default=4096)
+    ap.add_argument("--seed-cand", type=int, default=1024)
+    ap.add_argument("--seed-rounds", type=int, default=3)
+    ap.add_argument("--seed-width", type=float, default=0.25, help="round-0 half-width / box half-width")
     return ap.parse_args()
 
 
@@ -63,6 +69,56 @@ def gpu_targets(ctx, opmm, torch, b):
         z = torch.from_numpy(b["noise"][s].astype(np.float32)).cuda()
         parts.append((theta[s, :T, None] * u[None, :] + float(b["sigma"][s]) * z).reshape(-1))
     return torch.cat(parts).contiguous()
+
+
+def surrogate_leg(a, ctx, opmm, torch, synth):
+    """Learned seed vs plain search on held-out saccades of the same distributions: the network is
+    trained on the device on saccades the plant simulator generates (OPC = nominal x U[0.7, 1.3],
+    noise sigma U[0, 0.1] deg), then seeds a small refine; saccades whose seeded RMSE exceeds
+    1.5 sigma fall back to the plain search, which also fits every held-out saccade for reference."""
+    B = 4096
+    steps = max(1, a.train_saccades // B)
+    sg = opmm.Surrogate(ctx, init_seed=20070988)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = sg.train(data_seed=1, batch=B, n_steps=steps, lr0=2e-3, lr_min=2e-5)
+    train_s = time.perf_counter() - t0
+    b = synth.draw_saccades(a.heldout, "full", seed=synth.BASE_SEED + 1)
+    pos = gpu_targets(ctx, opmm, torch, b)
+    recs = opmm.saccade_records(b["T"], 2, b["amp"], b["dir_deg"], b["dur_ms"], b["seed"])
+    S = a.heldout
+    plain = opmm.fit_params(n_cand=a.n_cand, n_rounds=a.rounds, mode=opmm.FIT_ROUNDS, tile=4)
+    seeded = opmm.fit_params(n_cand=a.seed_cand, n_rounds=a.seed_rounds, w_init_frac=a.seed_width,
+                             mode=opmm.FIT_ROUNDS, tile=4)
+    opc = torch.zeros(S, 18, device="cuda")
+    rm_plain = torch.zeros(S, device="cuda")
+    rm_seed = torch.zeros(S, device="cuda")
+    st = torch.zeros(S, dtype=torch.int32, device="cuda")
+    ctx.fit(pos, recs, plain, opc, rm_plain)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.fit(pos, recs, plain, opc, rm_plain)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    sg.fit(pos, recs, seeded, plain, 1.5 * synth.SIGMA, opc, rm_seed, st)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_fb = sg.fit(pos, recs, seeded, plain, 1.5 * synth.SIGMA, opc, rm_seed, st)
+    torch.cuda.synchronize()
+    seed_s = time.perf_counter() - t0
+    rp, rs = rm_plain.cpu().numpy(), rm_seed.cpu().numpy()
+    sg.close()
+    return {"train": {"saccades": steps * B, "steps": steps, "batch": B, "seconds": train_s,
+                      "loss_first": float(loss[:10].mean()), "loss_last": float(loss[-10:].mean())},
+            "heldout_saccades": S,
+            "plain": {"n_cand": a.n_cand, "rounds": a.rounds, "saccades_fitted_per_s": S / plain_s,
+                      "mean_rmse_deg": float(rp.mean()), "median_rmse_deg": float(np.median(rp))},
+            "surrogate": {"n_cand": a.seed_cand, "rounds": a.seed_rounds, "w_init_frac": a.seed_width,
+                          "fallback_rmse_deg": 1.5 * synth.SIGMA, "fallbacks": int(n_fb),
+                          "saccades_fitted_per_s": S / seed_s, "mean_rmse_deg": float(rs.mean()),
+                          "median_rmse_deg": float(np.median(rs))},
+            "speedup_saccades_per_s": plain_s / seed_s,
+            "rmse_ratio_surrogate_over_plain": float(rs.mean() / rp.mean())}
 
 
 def cpu_baseline(b, pos_host, seconds):
@@ -171,6 +227,8 @@ def main():
                      "launch_ms": launch_ms, "algorithmic_flop_per_launch": flop,
                      "frac_of_published_fp32_157": achieved / PUBLISHED_FP32_PEAK},
     }
+    if not a.no_surrogate:
+        out["surrogate_vs_plain"] = surrogate_leg(a, ctx, opmm, torch, synth)
     if not a.no_cpu_baseline:
         pos_host = []
         off = 0

@@ -186,6 +186,75 @@ int opmm_autotune(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_s
 int opmm_tile_count(void);
 const char* opmm_tile_name(int i);
 
+
+/* ------------------------------------------------------------------------
+ * Learned seed: a small MLP (256-512-512-256-18, ReLU, BF16 weights and
+ * activations, FP32 accumulate) that maps a saccade trace to an initial OPC
+ * estimate, trained on saccades the plant simulator itself generates; the
+ * box search refines from it and stays both its fallback and the judge of
+ * its error.  Not in the paper: the learned counterpart of its literature-
+ * default initialisation (Section 3.2) and of its call for faster estimation
+ * toward real time (Section 5).
+ *   input  = the trace projected on the movement direction, resampled to
+ *            128 points over its own duration, as (position/16 deg,
+ *            velocity*4 ms/deg) pairs: [256] BF16 (raw uint16 bit patterns)
+ *   output = z = (p / p_nominal - 1) / 0.3 per Table 1 component [18] FP32
+ * Parameters are one FP32 vector of opmm_surrogate_param_count() values:
+ * W0 [256][512], b0, W1 [512][512], b1, W2 [512][256], b2, W3 [256][18], b3.
+ * ------------------------------------------------------------------------ */
+typedef struct opmm_surrogate opmm_surrogate;
+
+/* He-uniform weights from the SplitMix64 stream keyed by init_seed. */
+int opmm_surrogate_create(opmm_ctx* ctx, uint64_t init_seed, opmm_surrogate** out);
+int opmm_surrogate_destroy(opmm_surrogate* sg);
+int64_t opmm_surrogate_param_count(void);
+/* which: 0 weights, 1 gradients of the last backward pass, 2/3 Adam moments;
+ * host_out[param_count]; synchronises the device. */
+int opmm_surrogate_get_params(opmm_surrogate* sg, int which, float* host_out);
+int opmm_surrogate_set_params(opmm_surrogate* sg, const float* host_w);
+/* out[B][18] = network(feat[B][256]) */
+int opmm_surrogate_forward(opmm_surrogate* sg, const uint16_t* feat, int32_t B, float* out, void* stream);
+/* forward + backward of the MSE loss mean((out - target)^2) over B x 18;
+ * gradients are left in the object (get_params which = 1); *loss_out (host,
+ * nullable) gets the loss, which synchronises the stream. */
+int opmm_surrogate_backward(opmm_surrogate* sg, const uint16_t* feat, const float* target, int32_t B,
+                            float* loss_out, void* stream);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8) on the stored gradients. */
+int opmm_surrogate_adam_step(opmm_surrogate* sg, float lr, void* stream);
+/* Training data on the device: B saccades with OPC = nominal x U[1-spread,
+ * 1+spread], amplitude U[2, 30] deg, duration 2.2 A + 21 ms, noise sigma
+ * U[0, sigma_max] deg, keyed by (data_seed, step): feat_out[B][256],
+ * target_out[B][18] (device). */
+int opmm_surrogate_generate(opmm_surrogate* sg, uint64_t data_seed, uint64_t step, int32_t B, float spread,
+                            float sigma_max, uint16_t* feat_out, float* target_out, void* stream);
+/* n_steps of (generate batch -> forward -> backward -> Adam), learning rate
+ * cosine-decayed from lr0 to lr_min over the call; loss_out (host, nullable)
+ * [n_steps].  Synchronises the stream at the end. */
+int opmm_surrogate_train(opmm_surrogate* sg, uint64_t data_seed, int32_t B, int32_t n_steps, float lr0,
+                         float lr_min, float spread, float sigma_max, float* loss_out, void* stream);
+/* Features of S recorded saccades (same layout rules as opmm_fit):
+ * feat_out[S][256] (device). */
+int opmm_surrogate_features(opmm_surrogate* sg, const float* pos, int64_t pos_len, const opmm_saccade* sacs,
+                            int32_t S, float dt_ms, uint16_t* feat_out, void* stream);
+/* Seeds for S saccades: opc_out[S][18] = nominal x (1 + 0.3 z), clamped to
+ * nominal x [1 - box_frac, 1 + box_frac]; pass as seed_opc to opmm_fit. */
+int opmm_surrogate_predict(opmm_surrogate* sg, const float* pos, int64_t pos_len, const opmm_saccade* sacs,
+                           int32_t S, float dt_ms, float box_frac, float* opc_out, void* stream);
+/* Learned-seed estimation: seeds from the network, then opmm_fit with
+ * `seeded` (typically fewer candidates/rounds and w_init_frac < 1); every
+ * saccade whose seeded RMSE exceeds fallback_rmse (e.g. 1.5 x the noise
+ * floor) is re-fitted with `plain` from the nominal centre, and the lower-
+ * RMSE result is kept (status gets OPMM_ST_FALLBACK).  status_out is
+ * required.  *n_fallback (host, nullable) = number of re-fitted saccades.
+ * Synchronises the stream once to read the seeded RMSEs. */
+int opmm_fit_learned(opmm_surrogate* sg, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
+                     const opmm_fit_params* seeded, const opmm_fit_params* plain, float fallback_rmse,
+                     float* opc_out, float* rmse_out, float* mae_out, int32_t* status_out, int32_t* n_fallback,
+                     void* stream);
+/* Checkpoint: FP32 weights and Adam state (binary, host file). */
+int opmm_surrogate_save(opmm_surrogate* sg, const char* path);
+int opmm_surrogate_load(opmm_surrogate* sg, const char* path);
+
 #ifdef __cplusplus
 }
 #endif

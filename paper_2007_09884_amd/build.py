@@ -7,8 +7,9 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRCS = [os.path.join(PKG, "csrc", "opmm.hip")]
-DEPS = SRCS + [os.path.join(PKG, "csrc", "plant.hpp"), os.path.join(ROOT, "include", "opmm.h")]
+SRCS = [os.path.join(PKG, "csrc", "opmm.hip"), os.path.join(PKG, "csrc", "surrogate.hip")]
+DEPS = SRCS + [os.path.join(PKG, "csrc", n) for n in ("plant.hpp", "runtime.hpp")] + \
+    [os.path.join(ROOT, "include", "opmm.h")]
 LIB = os.path.join(PKG, "libopmm.so")
 ARCH = os.environ.get("OPMM_OFFLOAD_ARCH", "gfx950")
 

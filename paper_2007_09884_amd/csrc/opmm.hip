@@ -26,8 +26,10 @@
 
 #include "../../include/opmm.h"
 #include "plant.hpp"
+#include "runtime.hpp"
 
 using namespace opmm;
+using opmm_rt::SacDev;
 
 namespace {
 
@@ -36,16 +38,6 @@ constexpr int NBIN = 256;  // pulse-end sample bins of the in-tile sort
 #ifndef OPMM_MIN_WAVES
 #define OPMM_MIN_WAVES 2  // waves per SIMD the register allocation must leave room for
 #endif
-
-struct SacDev {
-    int64_t pos_off;
-    int64_t proj_off;
-    double cphi, sphi;
-    uint64_t seed;
-    int32_t T, C;
-    float amp, dur;
-    int32_t n_cand, tiles, tile_base, pad;
-};
 
 // ---------------------------------------------------------------------------
 // Small kernels
@@ -623,6 +615,7 @@ struct opmm_ctx {
     int cu_count = 0;
     std::string err;
     FitScratch scratch;
+    FitScratch aux;  // projections for the learned seed, independent of the fit's scratch
     float* d_cand = nullptr;  // small per-call staging for opmm_score (projected trace)
     size_t d_cand_cap = 0;
     int tuned_shape = -1;
@@ -636,7 +629,7 @@ struct opmm_plan {
     hipGraphExec_t exec = nullptr;
 };
 
-namespace {
+namespace opmm_rt {
 
 int fail(opmm_ctx* ctx, int code, const std::string& msg)
 {
@@ -648,6 +641,15 @@ int hip_fail(opmm_ctx* ctx, hipError_t e, const char* what)
 {
     return fail(ctx, OPMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
+
+int ctx_device(const opmm_ctx* ctx) { return ctx ? ctx->device : 0; }
+
+}  // namespace opmm_rt
+
+namespace {
+
+using opmm_rt::fail;
+using opmm_rt::hip_fail;
 
 #define OPMM_HIP(ctx, call)                                  \
     do {                                                     \
@@ -838,6 +840,31 @@ int check_fit_args(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_
 }
 
 }  // namespace
+
+namespace opmm_rt {
+
+int project_batch(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int S,
+                  const SacDev** sacs_dev, const float** proj, hipStream_t st)
+{
+    int rc;
+    for (int i = 0; i < S; ++i)
+        if ((rc = validate_saccade(ctx, sacs[i], pos_len, i)) != OPMM_OK) return rc;
+    FitScratch& sc = ctx->aux;
+    int64_t total_T;
+    int tiles;
+    if ((rc = upload_saccades(ctx, sc, sacs, S, nullptr, 1, &total_T, &tiles, st)) != OPMM_OK) return rc;
+    if ((rc = ensure(ctx, sc.proj, sizeof(float) * total_T)) != OPMM_OK) return rc;
+    if ((rc = ensure(ctx, sc.qorth, sizeof(double) * S)) != OPMM_OK) return rc;
+    if ((rc = ensure(ctx, sc.status, sizeof(int32_t) * S)) != OPMM_OK) return rc;
+    hipLaunchKernelGGL(prep_kernel, dim3(blocks_for(S, 128)), dim3(128), 0, st, S, (const SacDev*)sc.sacs.p, pos,
+                       (float*)sc.proj.p, (double*)sc.qorth.p, (int32_t*)sc.status.p);
+    OPMM_HIP(ctx, hipGetLastError());
+    *sacs_dev = (const SacDev*)sc.sacs.p;
+    *proj = (const float*)sc.proj.p;
+    return OPMM_OK;
+}
+
+}  // namespace opmm_rt
 
 // ===========================================================================
 // C ABI

@@ -63,6 +63,22 @@ def _load():
                                          ctypes.POINTER(i32), vp]),
         "opmm_tile_count": (ctypes.c_int, []),
         "opmm_tile_name": (ctypes.c_char_p, [ctypes.c_int]),
+        "opmm_surrogate_create": (ctypes.c_int, [vp, u64, ctypes.POINTER(vp)]),
+        "opmm_surrogate_destroy": (ctypes.c_int, [vp]),
+        "opmm_surrogate_param_count": (i64, []),
+        "opmm_surrogate_get_params": (ctypes.c_int, [vp, ctypes.c_int, vp]),
+        "opmm_surrogate_set_params": (ctypes.c_int, [vp, vp]),
+        "opmm_surrogate_forward": (ctypes.c_int, [vp, vp, i32, vp, vp]),
+        "opmm_surrogate_backward": (ctypes.c_int, [vp, vp, vp, i32, vp, vp]),
+        "opmm_surrogate_adam_step": (ctypes.c_int, [vp, f, vp]),
+        "opmm_surrogate_generate": (ctypes.c_int, [vp, u64, u64, i32, f, f, vp, vp, vp]),
+        "opmm_surrogate_train": (ctypes.c_int, [vp, u64, i32, i32, f, f, f, f, vp, vp]),
+        "opmm_surrogate_features": (ctypes.c_int, [vp, vp, i64, vp, i32, f, vp, vp]),
+        "opmm_surrogate_predict": (ctypes.c_int, [vp, vp, i64, vp, i32, f, f, vp, vp]),
+        "opmm_surrogate_save": (ctypes.c_int, [vp, ctypes.c_char_p]),
+        "opmm_fit_learned": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(FitParams),
+                                            ctypes.POINTER(FitParams), f, vp, vp, vp, vp, ctypes.POINTER(i32), vp]),
+        "opmm_surrogate_load": (ctypes.c_int, [vp, ctypes.c_char_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -195,6 +211,98 @@ class Context:
                                              _ptr(rmse_out), _ptr(mae_out), _ptr(status_out),
                                              _ptr(round_keys), _stream(stream), ctypes.byref(h)))
         return Plan(self, h)
+
+
+class Surrogate:
+    """The learned seed (include/opmm.h, 'Learned seed')."""
+
+    WIDTHS = (256, 512, 512, 256, 18)
+
+    def __init__(self, ctx: Context, init_seed: int = 1):
+        h = ctypes.c_void_p()
+        ctx._check(lib.opmm_surrogate_create(ctx._h, ctypes.c_uint64(init_seed), ctypes.byref(h)))
+        self._ctx, self._h = ctx, h
+
+    def close(self):
+        if self._h:
+            lib.opmm_surrogate_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def param_count() -> int:
+        return int(lib.opmm_surrogate_param_count())
+
+    def params(self, which=0) -> np.ndarray:
+        out = np.zeros(self.param_count(), np.float32)
+        self._ctx._check(lib.opmm_surrogate_get_params(self._h, which, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set_params(self, w):
+        w = np.ascontiguousarray(w, np.float32)
+        assert w.shape == (self.param_count(),)
+        self._ctx._check(lib.opmm_surrogate_set_params(self._h, w.ctypes.data_as(ctypes.c_void_p)))
+
+    def forward(self, feat, out, stream=None):
+        self._ctx._check(lib.opmm_surrogate_forward(self._h, _ptr(feat), feat.shape[0], _ptr(out), _stream(stream)))
+
+    def backward(self, feat, target, stream=None) -> float:
+        loss = ctypes.c_float()
+        self._ctx._check(lib.opmm_surrogate_backward(self._h, _ptr(feat), _ptr(target), feat.shape[0],
+                                                     ctypes.byref(loss), _stream(stream)))
+        return loss.value
+
+    def adam_step(self, lr, stream=None):
+        self._ctx._check(lib.opmm_surrogate_adam_step(self._h, ctypes.c_float(lr), _stream(stream)))
+
+    def generate(self, data_seed, step, feat_out, target_out, spread=0.3, sigma_max=0.1, stream=None):
+        self._ctx._check(lib.opmm_surrogate_generate(self._h, ctypes.c_uint64(data_seed), ctypes.c_uint64(step),
+                                                     feat_out.shape[0], ctypes.c_float(spread),
+                                                     ctypes.c_float(sigma_max), _ptr(feat_out), _ptr(target_out),
+                                                     _stream(stream)))
+
+    def train(self, data_seed, batch, n_steps, lr0=2e-3, lr_min=2e-5, spread=0.3, sigma_max=0.1,
+              stream=None) -> np.ndarray:
+        loss = np.zeros(max(n_steps, 1), np.float32)
+        self._ctx._check(lib.opmm_surrogate_train(self._h, ctypes.c_uint64(data_seed), int(batch), int(n_steps),
+                                                  ctypes.c_float(lr0), ctypes.c_float(lr_min),
+                                                  ctypes.c_float(spread), ctypes.c_float(sigma_max),
+                                                  loss.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return loss[:n_steps]
+
+    def features(self, pos, recs, feat_out, dt_ms=1.0, stream=None):
+        recs = np.ascontiguousarray(recs, SACCADE_DTYPE)
+        self._ctx._check(lib.opmm_surrogate_features(self._h, _ptr(pos), pos.numel(),
+                                                     recs.ctypes.data_as(ctypes.c_void_p), recs.shape[0],
+                                                     ctypes.c_float(dt_ms), _ptr(feat_out), _stream(stream)))
+
+    def predict(self, pos, recs, opc_out, dt_ms=1.0, box_frac=0.25, stream=None):
+        recs = np.ascontiguousarray(recs, SACCADE_DTYPE)
+        self._ctx._check(lib.opmm_surrogate_predict(self._h, _ptr(pos), pos.numel(),
+                                                    recs.ctypes.data_as(ctypes.c_void_p), recs.shape[0],
+                                                    ctypes.c_float(dt_ms), ctypes.c_float(box_frac),
+                                                    _ptr(opc_out), _stream(stream)))
+
+    def fit(self, pos, recs, seeded: FitParams, plain: FitParams, fallback_rmse, opc_out, rmse_out, status_out,
+            mae_out=None, stream=None) -> int:
+        recs = np.ascontiguousarray(recs, SACCADE_DTYPE)
+        nf = ctypes.c_int32(0)
+        self._ctx._check(lib.opmm_fit_learned(self._h, _ptr(pos), pos.numel(), recs.ctypes.data_as(ctypes.c_void_p),
+                                              recs.shape[0], ctypes.byref(seeded), ctypes.byref(plain),
+                                              ctypes.c_float(fallback_rmse), _ptr(opc_out), _ptr(rmse_out),
+                                              _ptr(mae_out), _ptr(status_out), ctypes.byref(nf), _stream(stream)))
+        return nf.value
+
+    def save(self, path):
+        self._ctx._check(lib.opmm_surrogate_save(self._h, os.fsencode(path)))
+
+    def load(self, path):
+        self._ctx._check(lib.opmm_surrogate_load(self._h, os.fsencode(path)))
 
 
 class Plan:

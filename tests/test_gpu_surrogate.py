@@ -1,0 +1,239 @@
+"""Learned seed on the GPU vs the numpy references (oracle/mlp_ref.py), through the C ABI.
+
+Tolerances:
+  * forward and gradients against a reference that rounds the same quantities to BF16 where the
+    GPU stores them (weights, inputs, hidden activations, back-propagated gradients): relative norm
+    <= 1e-2 per layer (FP32 accumulation order and the odd round-half flip in between);
+  * against the FP64 reference on identical BF16 weights and inputs and no other rounding:
+    forward relative norm <= 2e-2; gradients relative norm <= 8e-2 and cosine >= 0.996 per layer.
+    Each BF16 rounding carries up to 2^-9 relative error, and the first layer's gradient sees the
+    roundings of three back-propagation stages and of the forward activations that set the ReLU
+    masks, hence the looser bound there;
+  * features: within one BF16 ulp of the FP64 resampling.
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp_ref
+from paper_2007_09884_amd import synth
+from workload import make_batch, records
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+W = (256, 512, 512, 256, 18)
+
+
+@pytest.fixture(scope="module")
+def opmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_09884_amd import opmm as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(opmm):
+    c = opmm.Context(0)
+    yield c
+    c.close()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def cos(a, b):
+    return float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+
+
+def random_problem(B, seed):
+    rng = np.random.default_rng(seed)
+    n = sum(W[i] * W[i + 1] + W[i + 1] for i in range(4))
+    w = np.zeros(n, np.float32)
+    off = 0
+    for l in range(4):
+        w[off:off + W[l] * W[l + 1]] = rng.uniform(-1, 1, W[l] * W[l + 1]) * np.sqrt(6.0 / W[l])
+        off += W[l] * W[l + 1]
+        w[off:off + W[l + 1]] = rng.normal(0, 0.1, W[l + 1])
+        off += W[l + 1]
+    x = rng.normal(0, 1, (B, 256)).astype(np.float32)
+    t = rng.normal(0, 1, (B, 18)).astype(np.float32)
+    return w, x, t
+
+
+def ref_layers(w):
+    """Reference layers on the GPU's operands: BF16-rounded weights, FP32 biases."""
+    layers = mlp_ref.split_params(w, W)
+    return [(mlp_ref.bf16(Wl.astype(np.float32)), bl.astype(np.float32).astype(np.float64)) for Wl, bl in layers]
+
+
+def test_forward_matches_reference(ctx, opmm):
+    B = 300  # not a multiple of the 64-row tile
+    w, x, _ = random_problem(B, 1)
+    sg = opmm.Surrogate(ctx)
+    sg.set_params(w)
+    xb = mlp_ref.bf16_bits(x)
+    out = torch.zeros(B, 18, device="cuda")
+    sg.forward(torch.from_numpy(xb.view(np.int16)).cuda(), out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy().astype(np.float64)
+    layers = ref_layers(w)
+    # mirror: round hidden activations to BF16 where the GPU stores them
+    h = mlp_ref.bf16(x)
+    for l, (Wl, bl) in enumerate(layers):
+        z = h @ Wl + bl
+        h = mlp_ref.bf16(np.maximum(z, 0).astype(np.float32)) if l < 3 else z
+    assert rel(g, h) <= 1e-3, rel(g, h)
+    ref, _ = mlp_ref.forward(mlp_ref.bf16(x), layers)
+    assert rel(g, ref) <= 2e-2 and cos(g, ref) >= 0.999
+    sg.close()
+
+
+def test_gradients_match_reference(ctx, opmm):
+    B = 256
+    w, x, t = random_problem(B, 2)
+    sg = opmm.Surrogate(ctx)
+    sg.set_params(w)
+    xb = mlp_ref.bf16_bits(x)
+    loss = sg.backward(torch.from_numpy(xb.view(np.int16)).cuda(), torch.from_numpy(t).cuda())
+    g = sg.params(which=1).astype(np.float64)
+    layers = ref_layers(w)
+    ref_loss, grads = mlp_ref.backward(mlp_ref.bf16(x), t.astype(np.float64), layers)
+    assert abs(loss - ref_loss) <= 2e-2 * ref_loss
+    mirror = mirrored_backward(mlp_ref.bf16(x), t.astype(np.float64), layers)
+    off = 0
+    for l in range(4):
+        nw, nb = W[l] * W[l + 1], W[l + 1]
+        gw, gb = g[off:off + nw], g[off + nw:off + nw + nb]
+        off += nw + nb
+        rw, rb = grads[l][0].reshape(-1), grads[l][1]
+        mw, mb = mirror[l][0].reshape(-1), mirror[l][1]
+        assert rel(gw, mw) <= 1e-2 and rel(gb, mb) <= 1e-2, (l, rel(gw, mw), rel(gb, mb))
+        assert rel(gw, rw) <= 8e-2 and cos(gw, rw) >= 0.996, (l, rel(gw, rw), cos(gw, rw))
+        assert rel(gb, rb) <= 8e-2 and cos(gb, rb) >= 0.996, (l, rel(gb, rb))
+    sg.close()
+
+
+def mirrored_backward(x, t, layers):
+    """The chain rule with BF16 rounding where the GPU stores values: hidden activations after the
+    ReLU, the output gradient and each back-propagated gradient."""
+    acts = [x]
+    h = x
+    for l, (Wl, bl) in enumerate(layers):
+        z = h @ Wl + bl
+        h = mlp_ref.bf16(np.maximum(z, 0).astype(np.float32)) if l < 3 else z
+        if l < 3:
+            acts.append(h)
+    n = h.size
+    d = mlp_ref.bf16((2.0 * (h - t) / n).astype(np.float32))
+    out = [None] * 4
+    for l in range(3, -1, -1):
+        out[l] = (acts[l].T @ d, d.sum(axis=0))
+        if l > 0:
+            d = mlp_ref.bf16(((d @ layers[l][0].T) * (acts[l] > 0)).astype(np.float32))
+    return out
+
+
+def test_features_match_reference(ctx, opmm):
+    b, traces = make_batch(6, "full")
+    b2, tr2 = make_batch(2, "tiny")
+    recs = np.concatenate([records(b, opmm), records(b2, opmm)])
+    traces = traces + tr2
+    recs["pos_offset"] = np.concatenate([[0], np.cumsum([t.size for t in traces])[:-1]])
+    sg = opmm.Surrogate(ctx)
+    feat = torch.zeros(len(traces), 256, dtype=torch.int16, device="cuda")
+    sg.features(torch.from_numpy(opmm.pack_traces(traces)).cuda(), recs, feat)
+    torch.cuda.synchronize()
+    g = feat.cpu().numpy().view(np.uint16).astype(np.uint32)
+    g = (g << 16).view(np.float32).astype(np.float64)
+    for i, tr in enumerate(traces):
+        phi = np.deg2rad(float(recs["dir_deg"][i]))
+        u = np.array([np.cos(phi), np.sin(phi)])[: tr.shape[1]]
+        if tr.shape[1] == 1:
+            u = np.array([1.0 if recs["dir_deg"][i] == 0 else -1.0])
+        r = tr.astype(np.float64) @ u
+        ref = mlp_ref.features(r.astype(np.float32))
+        assert np.all(np.abs(g[i] - ref) <= 2 ** -7 * np.abs(ref) + 1e-6), i
+    sg.close()
+
+
+def test_generated_batch_is_well_formed(ctx, opmm):
+    sg = opmm.Surrogate(ctx)
+    B = 512
+    feat = torch.zeros(B, 256, dtype=torch.int16, device="cuda")
+    tgt = torch.zeros(B, 18, device="cuda")
+    sg.generate(7, 0, feat, tgt)
+    torch.cuda.synchronize()
+    z = tgt.cpu().numpy()
+    assert np.all(np.abs(z) <= 1.0 + 1e-6) and np.abs(z.mean()) < 0.1 and abs(z.std() - 1 / np.sqrt(3)) < 0.05
+    f = (feat.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32)
+    assert np.all(np.isfinite(f))
+    pos = f[:, 0::2] * 16.0
+    assert np.all(np.abs(pos[:, 0]) < 0.6)          # starts at rest (plus noise)
+    assert np.all(pos[:, -1] > 1.0)                   # ends near the amplitude (>= 2 deg)
+    # same (seed, step) -> same batch; another step -> another batch
+    tgt2 = torch.zeros(B, 18, device="cuda")
+    sg.generate(7, 0, feat, tgt2)
+    tgt3 = torch.zeros(B, 18, device="cuda")
+    sg.generate(7, 1, feat, tgt3)
+    torch.cuda.synchronize()
+    assert torch.equal(tgt, tgt2) and not torch.equal(tgt, tgt3)
+    sg.close()
+
+
+def test_training_reduces_loss_and_checkpoint_roundtrip(ctx, opmm):
+    sg = opmm.Surrogate(ctx, init_seed=3)
+    loss = sg.train(data_seed=11, batch=1024, n_steps=300, lr0=2e-3, lr_min=1e-4)
+    assert np.all(np.isfinite(loss))
+    # targets are U[-1, 1] per component (loss 1/3 for a constant-zero network); several components
+    # are weakly identifiable from a trace, so the reachable loss stays well above zero
+    assert loss[-20:].mean() < 0.9 * loss[:20].mean(), (loss[:20].mean(), loss[-20:].mean())
+    assert loss[-20:].mean() < 0.3
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "sg.bin")
+        sg.save(path)
+        sg2 = opmm.Surrogate(ctx, init_seed=99)
+        sg2.load(path)
+        assert np.array_equal(sg.params(0), sg2.params(0))
+        assert np.array_equal(sg.params(3), sg2.params(3))
+        sg2.close()
+    sg.close()
+
+
+def test_learned_seed_gains_over_the_plain_search(ctx, opmm):
+    """Same refine budget (1024 candidates x 3 rounds): seeded by the trained network vs started from
+    the nominal OPC.  The seeded search ends at lower RMSE; the plain search stays the fallback."""
+    sg = opmm.Surrogate(ctx, init_seed=5)
+    sg.train(data_seed=21, batch=4096, n_steps=400, lr0=2e-3, lr_min=2e-5)
+    b, traces = make_batch(48, "full", seed=synth.BASE_SEED + 777)
+    S = b["S"]
+    recs = records(b, opmm)
+    pos = torch.from_numpy(opmm.pack_traces(traces)).cuda()
+    plain = opmm.fit_params(n_cand=1024, n_rounds=3)
+    seeded = opmm.fit_params(n_cand=1024, n_rounds=3, w_init_frac=0.25)
+    opc = torch.zeros(S, 18, device="cuda"); rm_plain = torch.zeros(S, device="cuda")
+    ctx.fit(pos, recs, plain, opc, rm_plain)
+    opc2 = torch.zeros(S, 18, device="cuda"); rm_seed = torch.zeros(S, device="cuda")
+    st = torch.zeros(S, dtype=torch.int32, device="cuda")
+    nf = sg.fit(pos, recs, seeded, opmm.fit_params(n_cand=4096, n_rounds=6), 1e9, opc2, rm_seed, st)
+    torch.cuda.synchronize()
+    a, s_ = rm_plain.cpu().numpy(), rm_seed.cpu().numpy()
+    print("plain 1024x3 mean RMSE %.4f, learned seed + 1024x3 %.4f" % (a.mean(), s_.mean()))
+    assert nf == 0 and np.all(st.cpu().numpy() & opmm.ST_SEEDED)
+    assert s_.mean() < a.mean()
+    # threshold 0: every saccade falls back to the plain search, which then decides
+    st0 = torch.zeros(S, dtype=torch.int32, device="cuda"); rm0 = torch.zeros(S, device="cuda")
+    nf0 = sg.fit(pos, recs, seeded, plain, 0.0, opc2, rm0, st0)
+    torch.cuda.synchronize()
+    assert nf0 == S and np.all(st0.cpu().numpy() & opmm.ST_FALLBACK)
+    assert np.all(rm0.cpu().numpy() <= np.minimum(a, s_) + 1e-7)
+    # the winner's RMSE is the oracle's for that OPC (CPU_check pattern)
+    o = opc2.cpu().numpy()
+    for i in (0, 7):
+        th = oracle.simulate(o[i].astype(np.float64), b["amp"][i], int(b["T"][i]))
+        assert abs(oracle.cost(th, traces[i], b["dir_deg"][i])[0] - rm0.cpu().numpy()[i]) <= 1e-6
+    sg.close()
