@@ -48,6 +48,13 @@ def parse():
     ap.add_argument("--seed-cand", type=int, default=1024)
     ap.add_argument("--seed-rounds", type=int, default=3)
     ap.add_argument("--seed-width", type=float, default=0.25, help="round-0 half-width / box half-width")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-nm", action="store_true")
+    ap.add_argument("--nm-iter", type=int, default=2000)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 512 MiB device-to-device copy 3 times (calibrates HBM byte counters)")
+    ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000")
+    ap.add_argument("--serve-seconds", type=float, default=1.0, help="arrival window per rate")
     return ap.parse_args()
 
 
@@ -71,7 +78,7 @@ def gpu_targets(ctx, opmm, torch, b):
     return torch.cat(parts).contiguous()
 
 
-def surrogate_leg(a, ctx, opmm, torch, synth):
+def surrogate_leg(a, ctx, opmm, torch, synth, keep=False):
     """Learned seed vs plain search on held-out saccades of the same distributions: the network is
     trained on the device on saccades the plant simulator generates (OPC = nominal x U[0.7, 1.3],
     noise sigma U[0, 0.1] deg), then seeds a small refine; saccades whose seeded RMSE exceeds
@@ -107,8 +114,10 @@ def surrogate_leg(a, ctx, opmm, torch, synth):
     torch.cuda.synchronize()
     seed_s = time.perf_counter() - t0
     rp, rs = rm_plain.cpu().numpy(), rm_seed.cpu().numpy()
-    sg.close()
-    return {"train": {"saccades": steps * B, "steps": steps, "batch": B, "seconds": train_s,
+    if not keep:
+        sg.close()
+        sg = None
+    return sg, {"train": {"saccades": steps * B, "steps": steps, "batch": B, "seconds": train_s,
                       "loss_first": float(loss[:10].mean()), "loss_last": float(loss[-10:].mean())},
             "heldout_saccades": S,
             "plain": {"n_cand": a.n_cand, "rounds": a.rounds, "saccades_fitted_per_s": S / plain_s,
@@ -119,6 +128,69 @@ def surrogate_leg(a, ctx, opmm, torch, synth):
                           "median_rmse_deg": float(np.median(rs))},
             "speedup_saccades_per_s": plain_s / seed_s,
             "rmse_ratio_surrogate_over_plain": float(rs.mean() / rp.mean())}
+
+
+def nm_leg(a, ctx, opmm, torch, pos, recs, rm_box, box_s):
+    """The paper's estimator (parallel Nelder-Mead, one task per saccade, all transforms of an
+    iteration at once) on the same batch, from the nominal OPC, against the box search."""
+    S = recs.shape[0]
+    prm = opmm.nm_params(max_iter=a.nm_iter, tol_x=1e-4, tol_f=1e-6)
+    opc = torch.zeros(S, 18, device="cuda")
+    rm = torch.zeros(S, device="cuda")
+    it = torch.zeros(S, dtype=torch.int32, device="cuda")
+    ctx.fit_nm(pos, recs, prm, opc, rm, it)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.fit_nm(pos, recs, prm, opc, rm, it)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    r, its = rm.cpu().numpy(), it.cpu().numpy()
+    return {"max_iter": a.nm_iter, "tol_x": 1e-4, "tol_f": 1e-6, "saccades_fitted_per_s": S / dt,
+            "mean_rmse_deg": float(r.mean()), "mean_iters": float(its.mean()),
+            "converged": int(np.count_nonzero(its < a.nm_iter)),
+            "box_search_saccades_fitted_per_s": S / box_s, "box_search_mean_rmse_deg": float(rm_box.mean())}
+
+
+def serve_leg(a, ctx, opmm, torch, synth, sg):
+    """Continuous batching: saccades of the full-estimation distributions arrive as a Poisson stream;
+    the server admits them into device slots, seeds them from the learned network and advances every
+    resident request by one round per step.  Latency = arrival to result on the host."""
+    rates = [float(r) for r in a.serve_rates.split(",") if r]
+    out = []
+    for lam in rates:
+        n = max(16, int(lam * a.serve_seconds))
+        b = synth.draw_saccades(n, "full", seed=synth.BASE_SEED + 100 + int(lam))
+        pos = gpu_targets(ctx, opmm, torch, b).cpu().numpy()
+        recs = opmm.saccade_records(b["T"], 2, b["amp"], b["dir_deg"], b["dur_ms"], b["seed"])
+        rng = np.random.default_rng(int(lam))
+        arrive = np.cumsum(rng.exponential(1.0 / lam, n))
+        prm = opmm.serve_params(max_slots=65536, hbm_budget_bytes=1 << 30, fallback_rmse=1.5 * synth.SIGMA)
+        prm.seeded.n_cand, prm.seeded.n_rounds, prm.seeded.w_init_frac = a.seed_cand, a.seed_rounds, a.seed_width
+        prm.plain.n_cand, prm.plain.n_rounds = 16384, 10
+        sv = opmm.Server(ctx, prm, sg)
+        t0 = sv.now()
+        nxt, done, lat, rm, fb = 0, 0, [], [], 0
+        while done < n:
+            now = sv.now() - t0
+            k = int(np.searchsorted(arrive, now, side="right"))
+            if k > nxt:
+                sv.submit_many(pos, recs[nxt:k], t0 + arrive[nxt:k])
+                nxt = k
+            sv.step()
+            r = sv.poll()
+            done += len(r["id"])
+            lat.append(r["t_done"] - r["t_arrival"])
+            rm.append(r["rmse"])
+            fb += int(np.count_nonzero(r["status"] & opmm.ST_FALLBACK))
+        span = sv.now() - t0
+        st = sv.stats()
+        sv.close()
+        lat = np.concatenate(lat) * 1e3
+        out.append({"rate_per_s": lam, "requests": n, "p50_ms": float(np.percentile(lat, 50)),
+                    "p99_ms": float(np.percentile(lat, 99)), "sustained_per_s": n / span,
+                    "mean_rmse_deg": float(np.concatenate(rm).mean()), "fallbacks": fb, "steps": st["steps"],
+                    "slots": st["slots"]})
+    return out
 
 
 def cpu_baseline(b, pos_host, seconds):
@@ -149,6 +221,15 @@ def main():
               "build measures the one-GPU share; --gpus %d is not supported" % a.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
+
+    if a.copy_probe:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": src.numel(), "launches": 3}))
+        return
 
     from paper_2007_09884_amd import opmm, synth
 
@@ -227,8 +308,13 @@ def main():
                      "launch_ms": launch_ms, "algorithmic_flop_per_launch": flop,
                      "frac_of_published_fp32_157": achieved / PUBLISHED_FP32_PEAK},
     }
+    if not a.no_nm:
+        out["nelder_mead"] = nm_leg(a, ctx, opmm, torch, pos, recs, rm, ms_per_step * 1e-3)
     if not a.no_surrogate:
-        out["surrogate_vs_plain"] = surrogate_leg(a, ctx, opmm, torch, synth)
+        sg, out["surrogate_vs_plain"] = surrogate_leg(a, ctx, opmm, torch, synth, keep=not a.no_serve)
+        if not a.no_serve:
+            out["serving"] = serve_leg(a, ctx, opmm, torch, synth, sg)
+            sg.close()
     if not a.no_cpu_baseline:
         pos_host = []
         off = 0

@@ -178,7 +178,8 @@ int opmm_plan_launch(opmm_plan* plan, void* stream);
 int opmm_plan_destroy(opmm_plan* plan);
 
 /* Autotuner: time every kernel shape on a representative sample of this
- * batch (mode PERSISTENT) and keep the fastest for batches of this kind.
+ * batch (at most 256 saccades, up to 4 rounds, the caller's mode) and keep
+ * the fastest for later calls on this context with tile = -1.
  * Writes the chosen shape index to *tile_out (host, nullable). */
 int opmm_autotune(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs,
                   int32_t S, const opmm_fit_params* params, int32_t* tile_out, void* stream);
@@ -254,6 +255,90 @@ int opmm_fit_learned(opmm_surrogate* sg, const float* pos, int64_t pos_len, cons
 /* Checkpoint: FP32 weights and Adam state (binary, host file). */
 int opmm_surrogate_save(opmm_surrogate* sg, const char* path);
 int opmm_surrogate_load(opmm_surrogate* sg, const char* path);
+
+/* ------------------------------------------------------------------------
+ * Continuous-batching server: saccades streamed one by one are estimated
+ * as they arrive (the real-time goal of Section 5: as fast as recording).
+ * Each admitted request owns a device slot (trace, projection, search box,
+ * status, round key stay resident in HBM); opmm_server_step advances every
+ * occupied slot by one search round in one launch, whatever round each is
+ * at, and admits waiting requests as slots free up.  The slot count is the
+ * HBM budget divided by one slot's footprint (capped by max_slots).  A
+ * result depends only on its own request: the same alone and in the mix.
+ * With a surrogate, requests start from the learned seed (`seeded`) and fall
+ * back to `plain` when the seeded RMSE exceeds fallback_rmse (the lower-RMSE
+ * result is kept, status gets OPMM_ST_FALLBACK); without, they run `plain`.
+ * The server owns its stream; calls on one server must not overlap.
+ * ------------------------------------------------------------------------ */
+typedef struct opmm_server opmm_server;
+typedef struct {
+    int32_t max_slots;        /* upper bound on resident requests            */
+    int32_t max_T;            /* longest trace accepted, <= OPMM_MAX_T       */
+    size_t hbm_budget_bytes;  /* device memory the slots may use             */
+    opmm_fit_params plain;    /* search from the nominal OPC (and fallback)  */
+    opmm_fit_params seeded;   /* search from the learned seed                */
+    float fallback_rmse;      /* deg; e.g. 1.5 x the noise floor             */
+    int32_t pad;
+} opmm_serve_params;
+
+/* Defaults: 4096 slots, max_T 160, 1 GiB; plain 4096 x 10, seeded 1024 x 3
+ * with w_init_frac 0.25; fallback 0.075 deg.  plain and seeded must share
+ * dt_ms, box_frac and shrink. */
+void opmm_serve_params_default(opmm_serve_params* p);
+/* sg nullable (no learned seed).  The server keeps ctx and sg. */
+int opmm_server_create(opmm_ctx* ctx, opmm_surrogate* sg, const opmm_serve_params* prm, opmm_server** out);
+int opmm_server_destroy(opmm_server* sv);
+int opmm_server_slots(const opmm_server* sv);
+/* Seconds on the server's clock (steady); use it for arrival timestamps. */
+double opmm_server_now(void);
+/* Queue one request: host_trace [T][C] FP32 (copied), sac (host; pos_offset
+ * ignored), t_arrival on opmm_server_now()'s clock.  *id_out = request id. */
+int opmm_server_submit(opmm_server* sv, const float* host_trace, const opmm_saccade* sac, double t_arrival,
+                       int64_t* id_out);
+/* Queue n requests at once: traces in host_pos (pos_len floats) located by
+ * sacs[i].pos_offset, arrival times t_arrival[n]; ids_out[n] nullable.  All
+ * records are validated before any is queued. */
+int opmm_server_submit_many(opmm_server* sv, const float* host_pos, int64_t pos_len, const opmm_saccade* sacs,
+                            int32_t n, const double* t_arrival, int64_t* ids_out);
+/* Admit, run one round over all occupied slots, harvest finished requests
+ * (synchronises the server stream).  *n_done_out (nullable) = requests
+ * completed by this step. */
+int opmm_server_step(opmm_server* sv, int32_t* n_done_out);
+/* Pop up to max completed results (host arrays, each nullable except n_out):
+ * ids[n], opc[n][18], rmse[n], mae[n], status[n], t_arrival[n], t_done[n]. */
+int opmm_server_poll(opmm_server* sv, int64_t max, int64_t* ids, float* opc, float* rmse, float* mae,
+                     int32_t* status, double* t_arrival, double* t_done, int64_t* n_out);
+/* out[7] = pending, occupied slots, admitted, completed, fallbacks, steps, slots. */
+int opmm_server_stats(const opmm_server* sv, int64_t* out);
+
+/* ------------------------------------------------------------------------
+ * The paper's estimator: parallel Nelder-Mead (Section 3.3, Algorithm 1) in
+ * the variant of Lagarias et al. (reflection 1, expansion 2, contraction
+ * 1/2, shrink 1/2), one task per saccade with all simplex transforms of an
+ * iteration evaluated simultaneously and the simplex sorted (stable) every
+ * iteration.  Coordinates are the OPC relative to the Table 1 nominal; the
+ * initial simplex is x0 and x0 with one coordinate scaled by 1.05; the cost
+ * (RMSE, as opmm_fit) is evaluated at the point clamped to nominal x
+ * [1 - box_frac, 1 + box_frac] and rounded to FP32.  Exit when every vertex
+ * is within tol_x of the best in every coordinate AND every value within
+ * tol_f of the best (both, Section 3.3), or after max_iter iterations.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t max_iter;   /* iteration cap                    [500]  */
+    float tol_x;        /* coordinate tolerance (relative)  [1e-4] */
+    float tol_f;        /* value tolerance (deg RMSE)       [1e-6] */
+    float box_frac;     /* evaluation clamp                 [0.25] */
+    float dt_ms;        /* sample period                    [1.0]  */
+} opmm_nm_params;
+void opmm_nm_params_default(opmm_nm_params* p);
+/* seed_opc: NULL (start at nominal) or device [S][18].  Outputs (device):
+ * opc_out [S][18] best vertex, rmse_out [S] its cost, iters_out [S]
+ * (nullable) iterations taken, decisions_out (nullable) [S][max_iter]:
+ * per iteration 0 reflect, 1 expand, 2 outside contraction, 3 inside
+ * contraction, 4 shrink; status_out (nullable) [S]. */
+int opmm_fit_nm(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
+                const opmm_nm_params* prm, const float* seed_opc, float* opc_out, float* rmse_out, int32_t* iters_out,
+                int8_t* decisions_out, int32_t* status_out, void* stream);
 
 #ifdef __cplusplus
 }

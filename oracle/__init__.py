@@ -60,6 +60,8 @@ def lib():
         L.oracle_fit.argtypes = [P, i, i, d, d, d, d, u64, i64, i, f, f, f, P, i, i,
                                  P, P, P, P, P, P]
         L.oracle_fit.restype = i
+        L.oracle_nelder_mead.argtypes = [P, i, i, d, d, d, d, P, i, d, d, d, d, i, P, P, P, P, P]
+        L.oracle_nelder_mead.restype = i
         _lib = L
     return _lib
 
@@ -189,3 +191,22 @@ def make_target(p_true, amp, dir_deg, T, C, noise_z, sigma):
     u = np.array([np.cos(phi), np.sin(phi)])[:C]
     pos = th[:, None] * u[None, :] + sigma * np.asarray(noise_z, np.float64).reshape(T, C)
     return pos.astype(np.float32)
+
+
+def nelder_mead(pos, amp, dir_deg, dur_ms, *, x0=None, max_iter=500, tol_x=1e-4, tol_f=1e-6, lo=0.75, hi=1.25,
+                dt_ms=1.0, nsub=NSUB, forced=None):
+    """The paper's Nelder-Mead (Lagarias variant) on the RMSE.  Returns dict(opc, rmse, iters, own, margin):
+    own/margin per iteration = the oracle's own decision and the smallest gap it rested on; with forced
+    (decision codes) the run follows those decisions instead."""
+    pos = _f32(pos); T, C = pos.shape
+    opc = np.zeros(NP_, np.float32); f = ctypes.c_double()
+    own = np.full(max(max_iter, 1), -1, np.int8); mar = np.zeros(max(max_iter, 1))
+    x0p = None if x0 is None else _p(_f32(x0))
+    fc = None
+    if forced is not None:
+        fc = np.zeros(max(max_iter, 1), np.int8)
+        fc[:len(forced)] = forced
+    it = lib().oracle_nelder_mead(_p(pos), T, C, float(amp), float(dir_deg), float(dur_ms), float(dt_ms), x0p,
+                                  int(max_iter), float(tol_x), float(tol_f), float(lo), float(hi), int(nsub),
+                                  None if fc is None else _p(fc), _p(own), _p(mar), _p(opc), ctypes.byref(f))
+    return dict(opc=opc, rmse=f.value, iters=it, own=own[:it], margin=mar[:it])

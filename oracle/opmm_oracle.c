@@ -398,3 +398,155 @@ int oracle_fit(const float* pos, int T, int C, double amp, double dir_deg, doubl
     free(cost);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Nelder-Mead (Section 3.3, Algorithm 1)                                     */
+/* ------------------------------------------------------------------------- */
+
+/* The paper's estimator: Nelder-Mead in the variant of Lagarias, Reeds, Wright
+ * and Wright (SIAM J. Optim. 9, 1998) -- reflection 1, expansion 2,
+ * contraction 1/2, shrink 1/2 -- iterated until the simplex is within TolX of
+ * its best vertex in every coordinate AND its values within TolFun of the best
+ * value, or until max_iter iterations (Section 3.3).  Coordinates are the OPC
+ * relative to nominal (x_j = p_j / nominal_j; the method is affine-equivariant,
+ * so this only fixes the units of TolX); the initial simplex is x0 and x0 with
+ * one coordinate scaled by 1.05.  The cost is evaluated at the point clamped
+ * to [lo_frac, hi_frac] x nominal and rounded to FP32 (the candidate format).
+ * Ties in the ordering keep the earlier vertex first (stable insertion). */
+
+typedef struct {
+    const float* pos; int T, C; double amp, dir, dt; int nsub;
+    double nom[NP]; double lo, hi;
+    int64_t nfev;
+} nm_problem;
+
+static double nm_cost(nm_problem* pb, const double x[NP])
+{
+    double p[NP];
+    for (int j = 0; j < NP; ++j) {
+        double v = x[j];
+        if (v < pb->lo) v = pb->lo;
+        if (v > pb->hi) v = pb->hi;
+        p[j] = (double)(float)(v * pb->nom[j]);
+    }
+    double* th = (double*)malloc(sizeof(double) * pb->T);
+    oracle_simulate(p, pb->amp, pb->T, pb->dt, pb->nsub, th);
+    double r, m;
+    oracle_cost(th, pb->pos, pb->T, pb->C, pb->dir, &r, &m);
+    free(th);
+    pb->nfev++;
+    return r;
+}
+
+/* sort vertices by value, stable: v[(NP+1)][NP], f[NP+1] */
+static void nm_sort(double v[][NP], double f[])
+{
+    for (int i = 1; i <= NP; ++i) {
+        double fi = f[i], vi[NP];
+        memcpy(vi, v[i], sizeof vi);
+        int k = i - 1;
+        while (k >= 0 && f[k] > fi) {
+            f[k + 1] = f[k];
+            memcpy(v[k + 1], v[k], sizeof vi);
+            --k;
+        }
+        f[k + 1] = fi;
+        memcpy(v[k + 1], vi, sizeof vi);
+    }
+}
+
+/* Decision codes: 0 reflect, 1 expand, 2 outside contraction, 3 inside
+ * contraction, 4 shrink. */
+
+/* Returns the number of iterations; opc_out gets the best vertex (as FP32 OPC),
+ * *f_out its cost.  forced (nullable, [max_iter]): follow these decisions
+ * instead of the oracle's own (replay of another implementation's run);
+ * own (nullable, [max_iter]) gets the oracle's own decision at every iteration
+ * and margin (nullable, [max_iter]) the smallest gap between two values that
+ * decision compared. */
+int oracle_nelder_mead(const float* pos, int T, int C, double amp, double dir_deg, double dur_ms, double dt_ms,
+                       const float* x0_opc, int max_iter, double tol_x, double tol_f, double lo_frac,
+                       double hi_frac, int nsub, const signed char* forced, signed char* own, double* margin,
+                       float opc_out[NP], double* f_out)
+{
+    nm_problem pb = {pos, T, C, amp, dir_deg, dt_ms, nsub, {0}, lo_frac, hi_frac, 0};
+    oracle_nominal(dur_ms, pb.nom);
+    double v[NP + 1][NP], f[NP + 1];
+    for (int j = 0; j < NP; ++j) v[0][j] = x0_opc ? (double)x0_opc[j] / pb.nom[j] : 1.0;
+    for (int i = 1; i <= NP; ++i) {
+        memcpy(v[i], v[0], sizeof v[0]);
+        v[i][i - 1] = v[0][i - 1] * 1.05;
+    }
+    for (int i = 0; i <= NP; ++i) f[i] = nm_cost(&pb, v[i]);
+    nm_sort(v, f);
+    int it = 0;
+    for (; it < max_iter; ++it) {
+        double dx = 0.0, df = 0.0;
+        for (int i = 1; i <= NP; ++i) {
+            df = fmax(df, fabs(f[i] - f[0]));
+            for (int j = 0; j < NP; ++j) dx = fmax(dx, fabs(v[i][j] - v[0][j]));
+        }
+        if (dx <= tol_x && df <= tol_f) break;
+        double xb[NP], pt[4][NP], fp[4];
+        int have[4] = {0, 0, 0, 0};
+        for (int j = 0; j < NP; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < NP; ++i) s += v[i][j];
+            xb[j] = s / NP;
+        }
+        for (int j = 0; j < NP; ++j) {
+            pt[0][j] = xb[j] + (xb[j] - v[NP][j]);         /* reflection          */
+            pt[1][j] = xb[j] + 2.0 * (xb[j] - v[NP][j]);   /* expansion           */
+            pt[2][j] = xb[j] + 0.5 * (xb[j] - v[NP][j]);   /* outside contraction */
+            pt[3][j] = xb[j] - 0.5 * (xb[j] - v[NP][j]);   /* inside contraction  */
+        }
+#define NM_F(k) (have[k] ? fp[k] : (have[k] = 1, fp[k] = nm_cost(&pb, pt[k])))
+        /* the oracle's own decision and the smallest gap it rested on */
+        double m = HUGE_VAL;
+        int d;
+        double fr = NM_F(0);
+        m = fmin(m, fabs(fr - f[0]));
+        if (fr < f[0]) {
+            double fe = NM_F(1);
+            m = fmin(m, fabs(fe - fr));
+            d = fe < fr ? 1 : 0;
+        } else {
+            m = fmin(m, fabs(fr - f[NP - 1]));
+            if (fr < f[NP - 1]) d = 0;
+            else {
+                m = fmin(m, fabs(fr - f[NP]));
+                if (fr < f[NP]) {
+                    double fc = NM_F(2);
+                    m = fmin(m, fabs(fc - fr));
+                    d = fc <= fr ? 2 : 4;
+                } else {
+                    double fcc = NM_F(3);
+                    m = fmin(m, fabs(fcc - f[NP]));
+                    d = fcc < f[NP] ? 3 : 4;
+                }
+            }
+        }
+        if (own) own[it] = (signed char)d;
+        if (margin) margin[it] = m;
+        if (forced) d = forced[it];
+        if (d < 4) {
+            memcpy(v[NP], pt[d], sizeof pt[d]);
+            f[NP] = NM_F(d);
+        } else {
+            for (int i = 1; i <= NP; ++i) {
+                for (int j = 0; j < NP; ++j) v[i][j] = v[0][j] + 0.5 * (v[i][j] - v[0][j]);
+                f[i] = nm_cost(&pb, v[i]);
+            }
+        }
+#undef NM_F
+        nm_sort(v, f);
+    }
+    for (int j = 0; j < NP; ++j) {
+        double x = v[0][j];
+        if (x < lo_frac) x = lo_frac;
+        if (x > hi_frac) x = hi_frac;
+        opc_out[j] = (float)(x * pb.nom[j]);
+    }
+    *f_out = f[0];
+    return it;
+}

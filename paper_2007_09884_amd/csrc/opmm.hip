@@ -78,8 +78,8 @@ __global__ void prep_kernel(int S, const SacDev* __restrict__ sacs, const float*
         }
         proj[sd.proj_off + k] = (float)r;
     }
-    qorth[s] = q;
-    status[s] = ok ? OPMM_ST_OK : OPMM_ST_NONFINITE_INPUT;
+    qorth[sd.slot] = q;
+    status[sd.slot] = ok ? OPMM_ST_OK : OPMM_ST_NONFINITE_INPUT;
 }
 
 // Round-0 box: centre = nominal (PW = D - 6), w = box_frac * centre, bounds
@@ -92,6 +92,7 @@ __global__ void init_kernel(int S, const SacDev* __restrict__ sacs, float box_fr
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= S * P) return;
     int s = i / P, j = i % P;
+    const int slot = sacs[s].slot;
     float c0 = nominal_param(j, sacs[s].dur);
     float w0 = box_frac * c0;
     float l = c0 - w0, h = c0 + w0;
@@ -99,12 +100,19 @@ __global__ void init_kernel(int S, const SacDev* __restrict__ sacs, float box_fr
     if (seed_opc) {
         float v = seed_opc[i];
         c = (v == v) ? fminf(fmaxf(v, l), h) : c0;
-        if (j == 0) status[s] |= OPMM_ST_SEEDED;
+        if (j == 0) status[slot] |= OPMM_ST_SEEDED;
     }
-    centre[i] = c;
-    hw[i] = w0 * w_init_frac;
-    lo[i] = l;
-    hi[i] = h;
+    const int64_t o = (int64_t)slot * P + j;
+    centre[o] = c;
+    hw[o] = w0 * w_init_frac;
+    lo[o] = l;
+    hi[o] = h;
+}
+
+__global__ void reset_keys_kernel(int n, const SacDev* __restrict__ sacs, uint64_t* keys)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) keys[sacs[i].slot] = ~0ull;
 }
 
 __device__ __forceinline__ void load_box(Box& b, int s, const float* centre, const float* hw,
@@ -146,14 +154,19 @@ __device__ __forceinline__ void refine_one(const SacDev& sd, int s, int r, uint6
     }
 }
 
-__global__ void refine_kernel(int S, const SacDev* __restrict__ sacs, int r, const uint64_t* __restrict__ keys,
-                              float shrink, float* centre, float* hw, const float* lo, const float* hi,
-                              int32_t* status)
+// round >= 0: every saccade is at that round and keys are [round][key_stride];
+// round < 0: each saccade is at its own sd.round and keys are [slot].
+__global__ void refine_kernel(int S, const SacDev* __restrict__ sacs, int round, int key_stride,
+                              const uint64_t* __restrict__ keys, float shrink, float* centre, float* hw,
+                              const float* lo, const float* hi, int32_t* status)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
-    if (status[s] & OPMM_ST_NONFINITE_INPUT) return;
-    refine_one(sacs[s], s, r, keys[(int64_t)r * S + s], shrink, centre, hw, lo, hi, status);
+    const SacDev sd = sacs[s];
+    if (status[sd.slot] & OPMM_ST_NONFINITE_INPUT) return;
+    const int r = round >= 0 ? round : sd.round;
+    refine_one(sd, sd.slot, r, keys[(int64_t)(round >= 0 ? r : 0) * key_stride + sd.slot], shrink, centre, hw, lo,
+               hi, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -234,7 +247,7 @@ __device__ __forceinline__ uint64_t process_tile(TileSmem<TPB, PASSES>& sm, cons
     const int tid = threadIdx.x;
     const int T = sd.T;
     for (int k = tid; k < T; k += TPB) sm.r[k] = (R)proj[sd.proj_off + k];
-    load_box(sm.box, s, centre, hw, lo, hi);
+    load_box(sm.box, sd.slot, centre, hw, lo, hi);
     for (int i = tid; i < NBIN; i += TPB) sm.hist[i] = 0;
     __syncthreads();
 
@@ -326,9 +339,12 @@ __device__ __forceinline__ int find_saccade(const SacDev* __restrict__ sacs, int
     return lo;
 }
 
+// One round over a batch: round >= 0 puts every saccade at that round with keys
+// [round][key_stride]; round < 0 takes each saccade's own round (sd.round) and
+// keys [slot] (saccades admitted at different times, see the server).
 template <int TPB, int PASSES, int UNROLL>
 __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_round_kernel(const SacDev* __restrict__ sacs, int S, int round,
-                                                        float dt, const float* __restrict__ proj,
+                                                        int key_stride, float dt, const float* __restrict__ proj,
                                                         const float* centre, const float* hw,
                                                         const float* lo, const float* hi,
                                                         const int32_t* __restrict__ status,
@@ -340,11 +356,13 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_round_kernel(const Sa
     __syncthreads();
     const int s = s_s;
     const SacDev sd = sacs[s];
-    if (status[s] & OPMM_ST_NONFINITE_INPUT) return;
+    if (status[sd.slot] & OPMM_ST_NONFINITE_INPUT) return;
     const int t = blockIdx.x - sd.tile_base;
-    uint64_t best = process_tile<TPB, PASSES, UNROLL>(sm, sd, s, t, round, dt, proj, centre, hw, lo, hi);
+    const int r = round >= 0 ? round : sd.round;
+    uint64_t best = process_tile<TPB, PASSES, UNROLL>(sm, sd, s, t, r, dt, proj, centre, hw, lo, hi);
     if (threadIdx.x == 0 && best != ~0ull)
-        atomicMin((unsigned long long*)&keys[(int64_t)round * S + s], (unsigned long long)best);
+        atomicMin((unsigned long long*)&keys[(int64_t)(round >= 0 ? r : 0) * key_stride + sd.slot],
+                  (unsigned long long)best);
 }
 
 // Every round of every saccade in one launch: a work queue of (round, tile)
@@ -418,7 +436,7 @@ __global__ void report_kernel(int S, const SacDev* __restrict__ sacs, const floa
     bool act = s < S;
     SacDev sd = sacs[act ? s : 0];
     float p[P];
-    for (int j = 0; j < P; ++j) p[j] = centre[(act ? s : 0) * P + j];
+    for (int j = 0; j < P; ++j) p[j] = centre[(int64_t)sd.slot * P + j];
     Plant pl;
     plant_setup(p, sd.amp, dt, pl);
     R frac;
@@ -426,7 +444,7 @@ __global__ void report_kernel(int S, const SacDev* __restrict__ sacs, const floa
     Cost2dSink sink{pos + sd.pos_off, sd.C, sd.cphi, sd.sphi, 0.0, 0.0};
     run_trajectory<1>(pl, sd.T, (R)dt, k0, frac, k0, k0, sink);
     if (!act) return;
-    const int32_t st = status[s];
+    const int32_t st = status[sd.slot];
     const bool bad = (st & OPMM_ST_NONFINITE_INPUT) != 0;
     const double n = (double)sd.T * sd.C;
     for (int j = 0; j < P; ++j) opc_out[s * P + j] = bad ? __int_as_float(0x7FC00000) : p[j];
@@ -523,10 +541,12 @@ const Shape kShapes[] = {
     {128, 32, 1, "tpb128_pass32_unroll1"},
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+constexpr int kDefaultShape = 5;  // fastest per-round shape on the full-estimation workload (sweep)
 
 struct FitLaunch {
     const SacDev* sacs;
     int S, R, tiles_per_round;
+    int key_stride;
     float dt, shrink;
     const float* proj;
     float *centre, *hw, *lo, *hi;
@@ -545,7 +565,8 @@ hipError_t launch_shape(const FitLaunch& L, bool persistent, int round, hipStrea
                            L.lo, L.hi, L.status, L.keys, L.head, L.done, L.ready, L.errflag);
     } else {
         hipLaunchKernelGGL((fit_round_kernel<TPB, PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(TPB), 0, st,
-                           L.sacs, L.S, round, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status, L.keys);
+                           L.sacs, L.S, round, L.key_stride, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status,
+                           L.keys);
     }
     return hipGetLastError();
 }
@@ -679,7 +700,7 @@ int ensure(opmm_ctx* ctx, DevBuf& b, size_t bytes)
 
 int blocks_for(int64_t n, int tpb) { return (int)((n + tpb - 1) / tpb); }
 
-int validate_saccade(opmm_ctx* ctx, const opmm_saccade& s, int64_t pos_len, int i)
+int validate_saccade_impl(opmm_ctx* ctx, const opmm_saccade& s, int64_t pos_len, int i)
 {
     std::string at = " (saccade " + std::to_string(i) + ")";
     if (s.T < 1 || s.T > OPMM_MAX_T) return fail(ctx, OPMM_EINVAL, "T out of range" + at);
@@ -719,24 +740,13 @@ int upload_saccades(opmm_ctx* ctx, FitScratch& sc, const opmm_saccade* sacs, int
     int64_t toff = 0;
     int64_t tiles = 0;
     for (int i = 0; i < S; ++i) {
-        const opmm_saccade& s = sacs[i];
         SacDev& d = h[i];
-        d.pos_off = s.pos_offset;
+        d = opmm_rt::make_record(sacs[i], prm ? prm->n_cand : 1);
         d.proj_off = toff;
-        double phi = (double)s.dir_deg * (M_PI / 180.0);
-        d.cphi = std::cos(phi);
-        d.sphi = std::sin(phi);
-        if (s.C == 1) { d.cphi = s.dir_deg == 0.0f ? 1.0 : -1.0; d.sphi = 0.0; }
-        d.seed = s.seed;
-        d.T = s.T;
-        d.C = s.C;
-        d.amp = s.amp_deg;
-        d.dur = s.dur_ms;
-        d.n_cand = s.n_cand > 0 ? s.n_cand : (prm ? prm->n_cand : 1);
         d.tiles = (int)((d.n_cand + tile_size - 1) / tile_size);
         d.tile_base = (int)tiles;
-        d.pad = 0;
-        toff += s.T;
+        d.slot = i;
+        toff += sacs[i].T;
         tiles += d.tiles;
     }
     if (tiles > 0x7FFFFFFF / 8) return fail(ctx, OPMM_EINVAL, "too many candidate tiles in one batch");
@@ -793,6 +803,7 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
     L.shrink = prm->shrink; L.proj = proj; L.centre = centre; L.hw = hw; L.lo = lo; L.hi = hi;
     L.status = status; L.keys = keys; L.head = head; L.done = done; L.ready = ready; L.errflag = errflag;
     L.grid_persistent = 0;
+    L.key_stride = S;
     if (tiles_per_round > 0) {
         if (prm->mode == OPMM_FIT_PERSISTENT) {
             // The queue needs no co-residency, so oversubscribe: blocks that start
@@ -805,7 +816,7 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
         } else {
             for (int r = 0; r < R; ++r) {
                 OPMM_HIP(ctx, launch_fit_kernel(shape, L, false, r, st));
-                hipLaunchKernelGGL(refine_kernel, dim3(blocks_for(S, 128)), dim3(128), 0, st, S, d_sacs, r, keys,
+                hipLaunchKernelGGL(refine_kernel, dim3(blocks_for(S, 128)), dim3(128), 0, st, S, d_sacs, r, S, keys,
                                    prm->shrink, centre, hw, lo, hi, status);
                 OPMM_HIP(ctx, hipGetLastError());
             }
@@ -822,7 +833,7 @@ int shape_tile(int shape) { return kShapes[shape].tpb * kShapes[shape].passes; }
 int pick_shape(opmm_ctx* ctx, const opmm_fit_params* prm)
 {
     if (prm->tile >= 0) return prm->tile;
-    return ctx->tuned_shape >= 0 ? ctx->tuned_shape : 0;
+    return ctx->tuned_shape >= 0 ? ctx->tuned_shape : kDefaultShape;
 }
 
 int check_fit_args(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
@@ -835,7 +846,7 @@ int check_fit_args(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_
     if (S > 0 && (!pos || !sacs || !opc_out || !rmse_out)) return fail(ctx, OPMM_EINVAL, "NULL array argument");
     if (pos_len < 0) return fail(ctx, OPMM_EINVAL, "pos_len must be >= 0");
     for (int i = 0; i < S; ++i)
-        if ((rc = validate_saccade(ctx, sacs[i], pos_len, i)) != OPMM_OK) return rc;
+        if ((rc = validate_saccade_impl(ctx, sacs[i], pos_len, i)) != OPMM_OK) return rc;
     return OPMM_OK;
 }
 
@@ -843,12 +854,88 @@ int check_fit_args(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_
 
 namespace opmm_rt {
 
+int validate_saccade(opmm_ctx* ctx, const opmm_saccade& s, int64_t pos_len, int i)
+{
+    return validate_saccade_impl(ctx, s, pos_len, i);
+}
+
+SacDev make_record(const opmm_saccade& s, int n_cand_default)
+{
+    SacDev d;
+    std::memset(&d, 0, sizeof d);
+    d.pos_off = s.pos_offset;
+    double phi = (double)s.dir_deg * (M_PI / 180.0);
+    d.cphi = std::cos(phi);
+    d.sphi = std::sin(phi);
+    if (s.C == 1) { d.cphi = s.dir_deg == 0.0f ? 1.0 : -1.0; d.sphi = 0.0; }
+    d.seed = s.seed;
+    d.T = s.T;
+    d.C = s.C;
+    d.amp = s.amp_deg;
+    d.dur = s.dur_ms;
+    d.n_cand = s.n_cand > 0 ? s.n_cand : n_cand_default;
+    d.tiles = 1;
+    return d;
+}
+
+hipError_t launch_prep(const SacDev* sacs, int n, const float* pos, const SlotState& ss, hipStream_t st)
+{
+    hipLaunchKernelGGL(prep_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, st, n, sacs, pos, ss.proj, ss.qorth,
+                       ss.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(const SacDev* sacs, int n, float box_frac, float w_init_frac, const float* seed_opc,
+                       const SlotState& ss, hipStream_t st)
+{
+    hipLaunchKernelGGL(init_kernel, dim3(blocks_for((int64_t)n * P, 256)), dim3(256), 0, st, n, sacs, box_frac,
+                       w_init_frac, seed_opc, ss.centre, ss.hw, ss.lo, ss.hi, ss.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_keys(const SacDev* sacs, int n, const SlotState& ss, hipStream_t st)
+{
+    hipLaunchKernelGGL(reset_keys_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, st, n, sacs, ss.keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_round(int shape, const SacDev* sacs, int n, int tiles_total, float dt, const SlotState& ss,
+                        hipStream_t st)
+{
+    if (tiles_total <= 0) return hipSuccess;
+    FitLaunch L;
+    std::memset(&L, 0, sizeof L);
+    L.sacs = sacs; L.S = n; L.R = 1; L.tiles_per_round = tiles_total; L.key_stride = 0; L.dt = dt;
+    L.proj = ss.proj; L.centre = ss.centre; L.hw = ss.hw; L.lo = ss.lo; L.hi = ss.hi;
+    L.status = ss.status; L.keys = ss.keys;
+    return launch_fit_kernel(shape, L, false, -1, st);
+}
+
+hipError_t launch_refine(const SacDev* sacs, int n, float shrink, const SlotState& ss, hipStream_t st)
+{
+    hipLaunchKernelGGL(refine_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, st, n, sacs, -1, 0, ss.keys, shrink,
+                       ss.centre, ss.hw, ss.lo, ss.hi, ss.status);
+    return hipGetLastError();
+}
+
+hipError_t launch_report(const SacDev* sacs, int n, const float* pos, float dt, const SlotState& ss, float* opc_out,
+                         float* rmse_out, float* mae_out, int32_t* status_out, hipStream_t st)
+{
+    hipLaunchKernelGGL(report_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, st, n, sacs, pos, dt, ss.centre, opc_out,
+                       rmse_out, mae_out, ss.status, status_out);
+    return hipGetLastError();
+}
+
+int shape_tile(int shape) { return ::shape_tile(shape); }
+
+int default_shape(const opmm_ctx* ctx) { return ctx->tuned_shape >= 0 ? ctx->tuned_shape : kDefaultShape; }
+
 int project_batch(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int S,
                   const SacDev** sacs_dev, const float** proj, hipStream_t st)
 {
     int rc;
     for (int i = 0; i < S; ++i)
-        if ((rc = validate_saccade(ctx, sacs[i], pos_len, i)) != OPMM_OK) return rc;
+        if ((rc = validate_saccade_impl(ctx, sacs[i], pos_len, i)) != OPMM_OK) return rc;
     FitScratch& sc = ctx->aux;
     int64_t total_T;
     int tiles;
@@ -861,6 +948,17 @@ int project_batch(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_s
     OPMM_HIP(ctx, hipGetLastError());
     *sacs_dev = (const SacDev*)sc.sacs.p;
     *proj = (const float*)sc.proj.p;
+    return OPMM_OK;
+}
+
+int project_batch_full(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int S,
+                       const SacDev** sacs_dev, const float** proj, const double** qorth, const int32_t** status,
+                       hipStream_t st)
+{
+    int rc = project_batch(ctx, pos, pos_len, sacs, S, sacs_dev, proj, st);
+    if (rc != OPMM_OK) return rc;
+    *qorth = (const double*)ctx->aux.qorth.p;
+    *status = (const int32_t*)ctx->aux.status.p;
     return OPMM_OK;
 }
 
@@ -970,7 +1068,7 @@ int opmm_score(opmm_ctx* ctx, const float* opc, int64_t n, const float* pos, int
     if (!ctx) return OPMM_EINVAL;
     if (!sac) return fail(ctx, OPMM_EINVAL, "sac is NULL");
     int rc;
-    if ((rc = validate_saccade(ctx, *sac, pos_len, 0)) != OPMM_OK) return rc;
+    if ((rc = validate_saccade_impl(ctx, *sac, pos_len, 0)) != OPMM_OK) return rc;
     if (!(dt_ms > 0.0f && dt_ms <= 1.0f)) return fail(ctx, OPMM_EINVAL, "dt_ms must be in (0, 1]");
     if (n < 0) return fail(ctx, OPMM_EINVAL, "n must be >= 0");
     if (n > 0 && (!opc || !pos || !rmse_out)) return fail(ctx, OPMM_EINVAL, "NULL array argument");
@@ -1085,14 +1183,15 @@ int opmm_autotune(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_s
     if (S == 0) return fail(ctx, OPMM_EINVAL, "autotune needs S >= 1");
     OPMM_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    // sample: every k-th saccade, at most 256, two rounds, persistent mode
+    // sample: every k-th saccade, at most 256
     const int stride = std::max(1, S / 256);
     std::vector<opmm_saccade> sub;
     for (int i = 0; i < S; i += stride) sub.push_back(sacs[i]);
     const int Ss = (int)sub.size();
+    // the caller's mode; enough rounds that the sample sees both the wide early boxes (many
+    // distinct pulse ends per tile) and the narrow later ones
     opmm_fit_params pp = *params;
-    pp.n_rounds = std::min(params->n_rounds, 2);
-    pp.mode = OPMM_FIT_PERSISTENT;
+    pp.n_rounds = std::min(params->n_rounds, 4);
     DevBuf out;
     if ((rc = ensure(ctx, out, sizeof(float) * (size_t)Ss * (P + 1))) != OPMM_OK) return rc;
     float* d_opc = (float*)out.p;

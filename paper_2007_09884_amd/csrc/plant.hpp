@@ -74,6 +74,32 @@ __host__ __device__ inline float nominal_param(int j, float dur_ms)
     }
 }
 
+// Table 1 in FP64 (the decimal values as printed), for methods whose iterates
+// live in FP64 relative to nominal.
+__host__ __device__ inline double nominal_param_f64(int j, double dur_ms)
+{
+    switch (j) {
+    case 0: return 2.5;
+    case 1: return 2.5;
+    case 2: return 1.2;
+    case 3: return 1.2;
+    case 4: return 0.046;
+    case 5: return 0.022;
+    case 6: return 0.06;
+    case 7: return 0.8;
+    case 8: return 0.5;
+    case 9: return 0.000043;
+    case 10: return 11.7;
+    case 11: return 2.4;
+    case 12: return 2.0;
+    case 13: return 1.9;
+    case 14: return 14.0;
+    case 15: return 55.0;
+    case 16: return 0.5;
+    default: return dur_ms - 6.0;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Candidate stream
 // ---------------------------------------------------------------------------

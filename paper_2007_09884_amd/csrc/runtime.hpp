@@ -17,7 +17,10 @@ struct SacDev {
     uint64_t seed;     // candidate-stream key
     int32_t T, C;
     float amp, dur;
-    int32_t n_cand, tiles, tile_base, pad;
+    int32_t n_cand, tiles, tile_base;
+    int32_t slot;      // index of this saccade's search state (box, status, keys)
+    int32_t round;     // current round when a launch serves saccades at different rounds
+    int32_t pad;
 };
 
 int fail(opmm_ctx* ctx, int code, const std::string& msg);
@@ -28,5 +31,37 @@ int ctx_device(const opmm_ctx* ctx);
 // movement direction (ctx-owned scratch, valid until the next call on ctx).
 int project_batch(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int S,
                   const SacDev** sacs_dev, const float** proj, hipStream_t st);
+
+// As project_batch, also returning the orthogonal energies and status words
+// (both indexed by SacDev::slot = position in the batch).
+int project_batch_full(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int S,
+                       const SacDev** sacs_dev, const float** proj, const double** qorth, const int32_t** status,
+                       hipStream_t st);
+
+int validate_saccade(opmm_ctx* ctx, const opmm_saccade& s, int64_t pos_len, int i);
+SacDev make_record(const opmm_saccade& s, int n_cand_default);
+
+// Search state of a set of slots (one saccade each), indexed by SacDev::slot.
+struct SlotState {
+    float *centre, *hw, *lo, *hi;  // [slots][18]
+    int32_t* status;               // [slots]
+    uint64_t* keys;                // [slots]: argmin key of the slot's current round
+    float* proj;                   // projected traces (SacDev::proj_off)
+    double* qorth;                 // [slots]
+};
+
+// Launchers over a compact device list of n records (each names its slot).
+hipError_t launch_prep(const SacDev* sacs, int n, const float* pos, const SlotState& ss, hipStream_t st);
+hipError_t launch_init(const SacDev* sacs, int n, float box_frac, float w_init_frac, const float* seed_opc,
+                       const SlotState& ss, hipStream_t st);
+hipError_t launch_reset_keys(const SacDev* sacs, int n, const SlotState& ss, hipStream_t st);
+// one round for every listed saccade at its own SacDev::round (records carry tile_base/tiles)
+hipError_t launch_round(int shape, const SacDev* sacs, int n, int tiles_total, float dt, const SlotState& ss,
+                        hipStream_t st);
+hipError_t launch_refine(const SacDev* sacs, int n, float shrink, const SlotState& ss, hipStream_t st);
+hipError_t launch_report(const SacDev* sacs, int n, const float* pos, float dt, const SlotState& ss, float* opc_out,
+                         float* rmse_out, float* mae_out, int32_t* status_out, hipStream_t st);
+int shape_tile(int shape);
+int default_shape(const opmm_ctx* ctx);
 
 }  // namespace opmm_rt

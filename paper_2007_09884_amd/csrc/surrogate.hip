@@ -278,7 +278,7 @@ struct GenSink {
     __device__ __forceinline__ void operator()(int k, R dth, R theq) { out[k] = (float)(dth + theq); }
 };
 
-__global__ __launch_bounds__(256) void gen_batch_kernel(int B, uint64_t seed, const uint64_t* __restrict__ counter,
+__global__ __launch_bounds__(64) void gen_batch_kernel(int B, uint64_t seed, const uint64_t* __restrict__ counter,
                                                         float spread, float sigma_max, float* __restrict__ trace,
                                                         uint16_t* __restrict__ feat, float* __restrict__ target)
 {
@@ -339,14 +339,21 @@ __global__ void mse_grad_kernel(int B, const float* __restrict__ out, const floa
     if (threadIdx.x == 0) atomicAdd(loss, red[0] / (float)n);
 }
 
-// Column sums: db[n] = sum_b dY[b][n]
-__global__ void colsum_kernel(int B, int N, const uint16_t* __restrict__ dy, float* __restrict__ db)
+// Column sums: db[n] = sum_b dY[b][n]; one block per column, tree reduction
+__global__ __launch_bounds__(256) void colsum_kernel(int B, int N, const uint16_t* __restrict__ dy,
+                                                     float* __restrict__ db)
 {
-    int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+    __shared__ float red[256];
+    const int n = blockIdx.x;
     float s = 0.0f;
-    for (int b = 0; b < B; ++b) s += bf2f(dy[(int64_t)b * N + n]);
-    db[n] = s;
+    for (int b = threadIdx.x; b < B; b += 256) s += bf2f(dy[(int64_t)b * N + n]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[n] = red[0];
 }
 
 __global__ void adam_kernel(int64_t n, float* __restrict__ w, uint16_t* __restrict__ wb, const float* __restrict__ g,
@@ -475,7 +482,7 @@ int sg_backward(opmm_surrogate* sg, int B, hipStream_t st)
         hipError_t e = gemm<true, false, EPI_F32>(K, N, B, sg->act[l], K, dy, N, sg->g + w_off(l), N, nullptr,
                                                   nullptr, 0, st);
         if (e != hipSuccess) return opmm_rt::hip_fail(sg->ctx, e, "gemm dW");
-        hipLaunchKernelGGL(colsum_kernel, dim3(blocks(N, 256)), dim3(256), 0, st, B, N, dy, sg->g + b_off(l));
+        hipLaunchKernelGGL(colsum_kernel, dim3(N), dim3(256), 0, st, B, N, dy, sg->g + b_off(l));
         if (l > 0) {
             // dX_l = (dY . W_l^T) masked by act[l] > 0   ([B][N] x [N][K])
             e = gemm<false, true, EPI_RELU_MASK_BF16>(B, K, N, dy, N, sg->wb + w_off(l), N, sg->dact[l], K, nullptr,
@@ -617,7 +624,7 @@ int opmm_surrogate_generate(opmm_surrogate* sg, uint64_t data_seed, uint64_t ste
     int rc;
     if ((rc = sg_alloc(sg, B)) != OPMM_OK) return rc;
     SG_HIP(hipMemcpyAsync(sg->counter, &step, sizeof(uint64_t), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(gen_batch_kernel, dim3(blocks(B, 256)), dim3(256), 0, st, B, data_seed, sg->counter, spread,
+    hipLaunchKernelGGL(gen_batch_kernel, dim3(blocks(B, 64)), dim3(64), 0, st, B, data_seed, sg->counter, spread,
                        sigma_max, sg->trace, feat_out, target_out);
     SG_HIP(hipGetLastError());
     SG_HIP(hipStreamSynchronize(st));
@@ -636,7 +643,7 @@ int opmm_surrogate_train(opmm_surrogate* sg, uint64_t data_seed, int32_t B, int3
     const int64_t first = sg->step;
     for (int32_t t = 0; t < n_steps; ++t) {
         hipLaunchKernelGGL(fill_f32_kernel, dim3(1), dim3(64), 0, st, sg->loss, 1, 0.0f);
-        hipLaunchKernelGGL(gen_batch_kernel, dim3(blocks(B, 256)), dim3(256), 0, st, B, data_seed, sg->counter, spread,
+        hipLaunchKernelGGL(gen_batch_kernel, dim3(blocks(B, 64)), dim3(64), 0, st, B, data_seed, sg->counter, spread,
                            sigma_max, sg->trace, sg->act[0], sg->target);
         if ((rc = sg_forward(sg, B, st)) != OPMM_OK) return rc;
         if ((rc = sg_backward(sg, B, st)) != OPMM_OK) return rc;

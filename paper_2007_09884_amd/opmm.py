@@ -32,6 +32,17 @@ class FitParams(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
+class ServeParams(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("max_T", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("plain", FitParams), ("seeded", FitParams), ("fallback_rmse", ctypes.c_float),
+                ("pad", ctypes.c_int32)]
+
+
+class NmParams(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("tol_x", ctypes.c_float), ("tol_f", ctypes.c_float),
+                ("box_frac", ctypes.c_float), ("dt_ms", ctypes.c_float)]
+
+
 class OpmmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("opmm error %d: %s" % (code, msg))
@@ -76,6 +87,19 @@ def _load():
         "opmm_surrogate_features": (ctypes.c_int, [vp, vp, i64, vp, i32, f, vp, vp]),
         "opmm_surrogate_predict": (ctypes.c_int, [vp, vp, i64, vp, i32, f, f, vp, vp]),
         "opmm_surrogate_save": (ctypes.c_int, [vp, ctypes.c_char_p]),
+        "opmm_serve_params_default": (None, [ctypes.POINTER(ServeParams)]),
+        "opmm_nm_params_default": (None, [ctypes.POINTER(NmParams)]),
+        "opmm_fit_nm": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(NmParams), vp, vp, vp, vp, vp, vp,
+                                       vp]),
+        "opmm_server_create": (ctypes.c_int, [vp, vp, ctypes.POINTER(ServeParams), ctypes.POINTER(vp)]),
+        "opmm_server_destroy": (ctypes.c_int, [vp]),
+        "opmm_server_slots": (ctypes.c_int, [vp]),
+        "opmm_server_now": (ctypes.c_double, []),
+        "opmm_server_submit": (ctypes.c_int, [vp, vp, vp, ctypes.c_double, ctypes.POINTER(i64)]),
+        "opmm_server_step": (ctypes.c_int, [vp, ctypes.POINTER(i32)]),
+        "opmm_server_submit_many": (ctypes.c_int, [vp, vp, i64, vp, i32, vp, vp]),
+        "opmm_server_poll": (ctypes.c_int, [vp, i64, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(i64)]),
+        "opmm_server_stats": (ctypes.c_int, [vp, vp]),
         "opmm_fit_learned": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(FitParams),
                                             ctypes.POINTER(FitParams), f, vp, vp, vp, vp, ctypes.POINTER(i32), vp]),
         "opmm_surrogate_load": (ctypes.c_int, [vp, ctypes.c_char_p]),
@@ -96,6 +120,16 @@ def fit_params(**kw) -> FitParams:
     for k, v in kw.items():
         if not hasattr(p, k):
             raise TypeError("unknown fit parameter %r" % k)
+        setattr(p, k, v)
+    return p
+
+
+def nm_params(**kw) -> NmParams:
+    p = NmParams()
+    lib.opmm_nm_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError("unknown Nelder-Mead parameter %r" % k)
         setattr(p, k, v)
     return p
 
@@ -193,6 +227,14 @@ class Context:
                                  recs.shape[0], ctypes.byref(params), _ptr(seed_opc), _ptr(opc_out),
                                  _ptr(rmse_out), _ptr(mae_out), _ptr(status_out), _ptr(round_keys),
                                  _stream(stream)))
+
+    def fit_nm(self, pos, recs, params: NmParams, opc_out, rmse_out, iters_out=None, decisions_out=None,
+               status_out=None, seed_opc=None, stream=None):
+        recs = np.ascontiguousarray(recs, SACCADE_DTYPE)
+        self._check(lib.opmm_fit_nm(self._h, _ptr(pos), pos.numel(), recs.ctypes.data_as(ctypes.c_void_p),
+                                    recs.shape[0], ctypes.byref(params), _ptr(seed_opc), _ptr(opc_out),
+                                    _ptr(rmse_out), _ptr(iters_out), _ptr(decisions_out), _ptr(status_out),
+                                    _stream(stream)))
 
     def autotune(self, pos, recs, params: FitParams, stream=None) -> int:
         recs = np.ascontiguousarray(recs, SACCADE_DTYPE)
@@ -303,6 +345,90 @@ class Surrogate:
 
     def load(self, path):
         self._ctx._check(lib.opmm_surrogate_load(self._h, os.fsencode(path)))
+
+
+def serve_params(**kw) -> ServeParams:
+    p = ServeParams()
+    lib.opmm_serve_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if k in ("plain", "seeded") and isinstance(v, dict):
+            for kk, vv in v.items():
+                setattr(getattr(p, k), kk, vv)
+        else:
+            setattr(p, k, v)
+    return p
+
+
+class Server:
+    """Continuous-batching estimation server (include/opmm.h, 'Continuous-batching server')."""
+
+    def __init__(self, ctx: Context, params: ServeParams, surrogate: "Surrogate" = None):
+        h = ctypes.c_void_p()
+        ctx._check(lib.opmm_server_create(ctx._h, surrogate._h if surrogate else None, ctypes.byref(params),
+                                          ctypes.byref(h)))
+        self._ctx, self._h, self._sg = ctx, h, surrogate
+
+    def close(self):
+        if self._h:
+            lib.opmm_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def now() -> float:
+        return lib.opmm_server_now()
+
+    @property
+    def slots(self) -> int:
+        return lib.opmm_server_slots(self._h)
+
+    def submit(self, trace, rec, t_arrival=None) -> int:
+        trace = np.ascontiguousarray(trace, np.float32)
+        rec = np.ascontiguousarray(rec, SACCADE_DTYPE).reshape(1)
+        rid = ctypes.c_int64()
+        self._ctx._check(lib.opmm_server_submit(self._h, trace.ctypes.data_as(ctypes.c_void_p),
+                                                rec.ctypes.data_as(ctypes.c_void_p),
+                                                self.now() if t_arrival is None else float(t_arrival),
+                                                ctypes.byref(rid)))
+        return rid.value
+
+    def submit_many(self, host_pos, recs, t_arrival) -> np.ndarray:
+        """host_pos: packed float32 traces (numpy), recs: records locating them, t_arrival: [n] seconds."""
+        host_pos = np.ascontiguousarray(host_pos, np.float32)
+        recs = np.ascontiguousarray(recs, SACCADE_DTYPE)
+        ta = np.ascontiguousarray(t_arrival, np.float64)
+        ids = np.zeros(recs.shape[0], np.int64)
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        self._ctx._check(lib.opmm_server_submit_many(self._h, p(host_pos), host_pos.size, p(recs), recs.shape[0],
+                                                     p(ta), p(ids)))
+        return ids
+
+    def step(self) -> int:
+        n = ctypes.c_int32()
+        self._ctx._check(lib.opmm_server_step(self._h, ctypes.byref(n)))
+        return n.value
+
+    def poll(self, max_n=1 << 16) -> dict:
+        ids = np.zeros(max_n, np.int64); opc = np.zeros((max_n, P), np.float32)
+        rm = np.zeros(max_n, np.float32); ma = np.zeros(max_n, np.float32); st = np.zeros(max_n, np.int32)
+        ta = np.zeros(max_n); td = np.zeros(max_n)
+        n = ctypes.c_int64()
+        p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        self._ctx._check(lib.opmm_server_poll(self._h, max_n, p(ids), p(opc), p(rm), p(ma), p(st), p(ta), p(td),
+                                              ctypes.byref(n)))
+        k = n.value
+        return dict(id=ids[:k], opc=opc[:k], rmse=rm[:k], mae=ma[:k], status=st[:k], t_arrival=ta[:k],
+                    t_done=td[:k])
+
+    def stats(self) -> dict:
+        out = np.zeros(7, np.int64)
+        self._ctx._check(lib.opmm_server_stats(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return dict(zip(("pending", "busy", "admitted", "completed", "fallbacks", "steps", "slots"), map(int, out)))
 
 
 class Plan:
