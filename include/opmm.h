@@ -102,9 +102,16 @@ typedef struct {
                             OPMM_FIT_PERSISTENT: one work-queue launch for
                             every round and saccade (uneven batches)         */
     int32_t tile;        /* kernel shape index; -1 = autotuned/default       */
+    int32_t model;       /* 18: the 18-parameter OPMM (Section 2.2.1);
+                            9: the 9-parameter OPMM (Section 2.2.2, Table 2):
+                            one K_SE and one K_LT for both muscles (the
+                            stream's K_SE_ANT := K_SE_AG, K_LT_ANT := K_LT_AG)
+                            and the neural parameters (tau_AC/DE, N_SAC, PW)
+                            held at nominal (half-width 0)                   */
 } opmm_fit_params;
 
-/* Defaults: n_cand 4096, n_rounds 1, box 0.25, w_init 1, shrink 0.5, dt 1 ms. */
+/* Defaults: n_cand 4096, n_rounds 1, box 0.25, w_init 1, shrink 0.5, dt 1 ms,
+ * model 18. */
 void opmm_fit_params_default(opmm_fit_params* p);
 
 /* Nominal OPC for a saccade of duration dur_ms (Table 1; PW = D - 6 ms).
@@ -339,6 +346,27 @@ void opmm_nm_params_default(opmm_nm_params* p);
 int opmm_fit_nm(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
                 const opmm_nm_params* prm, const float* seed_opc, float* opc_out, float* rmse_out, int32_t* iters_out,
                 int8_t* decisions_out, int32_t* status_out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Saccade extraction by velocity threshold (I-VT), the identification step
+ * before estimation (Section 3.1; Section 4 uses I-VT and drops saccades
+ * shorter than 6 ms).  gaze: device [N][2] FP32 positions (deg), sample
+ * period dt_ms.  A sample k >= 1 is fast when |g_k - g_{k-1}| / dt exceeds
+ * vel_thresh_deg_s; a saccade is a maximal run of fast samples, its trace
+ * the run with the preceding (fixation) sample prepended, re-based to that
+ * sample (T = run length + 1, duration (T-1) dt, amplitude and direction of
+ * the last sample).  Runs with duration < min_dur_ms, amplitude <
+ * min_amp_deg or T > max_T are dropped.  Up to max_out saccades, in stream
+ * order: records to sacs_out (HOST [max_out], pos_offset into pos_out,
+ * seed = seed_base + first sample), traces to pos_out (device, pos_cap
+ * floats, [T][2] back to back), src_start_out (HOST, nullable) = index of
+ * each trace's first sample in the stream.  Ready for opmm_fit.  *n_out
+ * (host) = saccades written.  Synchronises the stream.
+ * ------------------------------------------------------------------------ */
+int opmm_ivt_extract(opmm_ctx* ctx, const float* gaze, int64_t N, float dt_ms, float vel_thresh_deg_s,
+                     float min_dur_ms, float min_amp_deg, int32_t max_T, uint64_t seed_base, int32_t max_out,
+                     opmm_saccade* sacs_out, float* pos_out, int64_t pos_cap, int64_t* src_start_out,
+                     int32_t* n_out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -57,8 +57,10 @@ def lib():
         L.oracle_initial_box.argtypes = [d, f, P, P, P, P]
         L.oracle_score.argtypes = [P, i64, P, i, i, d, d, d, i, i, P, P]
         L.oracle_score.restype = i
-        L.oracle_fit.argtypes = [P, i, i, d, d, d, d, u64, i64, i, f, f, f, P, i, i,
+        L.oracle_fit.argtypes = [P, i, i, d, d, d, d, u64, i64, i, f, f, f, P, i, i, i,
                                  P, P, P, P, P, P]
+        L.oracle_initial_box_model.argtypes = [d, f, i, P, P, P, P]
+        L.oracle_tie_model9.argtypes = [P]
         L.oracle_fit.restype = i
         L.oracle_nelder_mead.argtypes = [P, i, i, d, d, d, d, P, i, d, d, d, d, i, P, P, P, P, P]
         L.oracle_nelder_mead.restype = i
@@ -136,10 +138,17 @@ def splitmix64(seed: int, n: int) -> int:
     return int(lib().oracle_splitmix64(ctypes.c_uint64(seed), ctypes.c_uint64(n)))
 
 
-def initial_box(dur_ms, frac=0.25):
+def initial_box(dur_ms, frac=0.25, model=18):
     c, w, lo, hi = (np.zeros(NP_, np.float32) for _ in range(4))
-    lib().oracle_initial_box(float(dur_ms), ctypes.c_float(frac), _p(c), _p(w), _p(lo), _p(hi))
+    lib().oracle_initial_box_model(float(dur_ms), ctypes.c_float(frac), int(model), _p(c), _p(w), _p(lo), _p(hi))
     return c, w, lo, hi
+
+
+def tie_model9(p):
+    """The 9-parameter model's ties applied to a candidate (copy)."""
+    q = np.array(p, np.float32)
+    lib().oracle_tie_model9(_p(q))
+    return q
 
 
 def candidate(seed, rnd, idx, c, w, lo, hi) -> np.ndarray:
@@ -149,8 +158,12 @@ def candidate(seed, rnd, idx, c, w, lo, hi) -> np.ndarray:
     return out
 
 
-def candidates(seed, rnd, idxs, c, w, lo, hi) -> np.ndarray:
-    return np.stack([candidate(seed, rnd, int(i), c, w, lo, hi) for i in idxs])
+def candidates(seed, rnd, idxs, c, w, lo, hi, model=18) -> np.ndarray:
+    out = np.stack([candidate(seed, rnd, int(i), c, w, lo, hi) for i in idxs])
+    if model == 9:
+        out[:, 1] = out[:, 0]
+        out[:, 3] = out[:, 2]
+    return out
 
 
 def score(opc, pos, amp, dir_deg, dt_ms=1.0, nsub=NSUB, nthreads=1):
@@ -164,7 +177,7 @@ def score(opc, pos, amp, dir_deg, dt_ms=1.0, nsub=NSUB, nthreads=1):
 
 
 def fit(pos, amp, dir_deg, dur_ms, seed, n_cand, n_rounds, *, dt_ms=1.0, box_frac=0.25,
-        w_init_frac=1.0, shrink=0.5, c_init=None, nsub=NSUB, nthreads=1):
+        w_init_frac=1.0, shrink=0.5, c_init=None, model=18, nsub=NSUB, nthreads=1):
     pos = _f32(pos); T, C = pos.shape
     opc = np.zeros(NP_, np.float32); rm = ctypes.c_double(); ma = ctypes.c_double()
     bi = np.zeros(n_rounds, np.int64); br = np.zeros(n_rounds); cen = np.zeros((n_rounds, NP_), np.float32)
@@ -172,7 +185,7 @@ def fit(pos, amp, dir_deg, dur_ms, seed, n_cand, n_rounds, *, dt_ms=1.0, box_fra
     rc = lib().oracle_fit(_p(pos), T, C, float(amp), float(dir_deg), float(dur_ms), float(dt_ms),
                           ctypes.c_uint64(seed), int(n_cand), int(n_rounds), ctypes.c_float(box_frac),
                           ctypes.c_float(w_init_frac), ctypes.c_float(shrink),
-                          None if ci is None else _p(ci), nsub, int(nthreads), _p(opc),
+                          None if ci is None else _p(ci), int(model), nsub, int(nthreads), _p(opc),
                           ctypes.byref(rm), ctypes.byref(ma), _p(bi), _p(br), _p(cen))
     assert rc == 0
     return dict(opc=opc, rmse=rm.value, mae=ma.value, best_idx=bi, best_rmse=br, centres=cen)
@@ -210,3 +223,39 @@ def nelder_mead(pos, amp, dir_deg, dur_ms, *, x0=None, max_iter=500, tol_x=1e-4,
                                   int(max_iter), float(tol_x), float(tol_f), float(lo), float(hi), int(nsub),
                                   None if fc is None else _p(fc), _p(own), _p(mar), _p(opc), ctypes.byref(f))
     return dict(opc=opc, rmse=f.value, iters=it, own=own[:it], margin=mar[:it])
+
+
+def ivt(gaze, dt_ms=1.0, vel_thresh=30.0, min_dur=6.0, min_amp=0.0, max_T=2048):
+    """I-VT written as plain loops (Section 3.1 / Section 4: velocity-threshold identification, short
+    saccades dropped).  A sample k >= 1 is fast when |g_k - g_(k-1)| / dt > threshold (compared
+    squared, per sample, in FP32 like the stream's own values); a saccade is a maximal run of fast
+    samples plus the fixation sample before it, re-based to that sample.  Returns a list of dicts
+    (start = index of the prepended sample, T, amp, dir, trace [T][2] float32)."""
+    g = np.asarray(gaze, np.float32)
+    N = g.shape[0]
+    v = np.float32(vel_thresh) * np.float32(dt_ms) * np.float32(1e-3)
+    thr2 = v * v
+
+    def fast(k):
+        dx = g[k, 0] - g[k - 1, 0]
+        dy = g[k, 1] - g[k - 1, 1]
+        return dx * dx + dy * dy > thr2
+
+    out = []
+    k = 1
+    while k < N:
+        if fast(k):
+            k0 = k
+            while k + 1 < N and fast(k + 1):
+                k += 1
+            k1 = k
+            T = k1 - k0 + 2
+            d = g[k1] - g[k0 - 1]
+            amp = float(np.sqrt(np.float32(d[0] * d[0] + d[1] * d[1])))
+            ang = float(np.degrees(np.arctan2(float(d[1]), float(d[0]))))
+            if ang < 0:
+                ang += 360.0
+            if (T - 1) * dt_ms >= min_dur and amp >= min_amp and T <= max_T:
+                out.append(dict(start=k0 - 1, T=T, amp=amp, dir=ang, trace=(g[k0 - 1:k1 + 1] - g[k0 - 1])))
+        k += 1
+    return out

@@ -289,18 +289,37 @@ void oracle_candidate(uint64_t seed, uint32_t round, uint32_t idx, const float c
     }
 }
 
+/* The 9-parameter OPMM (Section 2.2.2, Table 2): one series elasticity and
+ * one length-tension value for both muscles, the viscosities, tension slopes,
+ * inertia and tension intercept free; the neuronal-control parameters (the
+ * table lists none) are held at their 18-parameter nominal values. */
+static int model9_fixed(int j) { return (j >= 10 && j <= 13) || j >= 15; }
+
+void oracle_tie_model9(float p[NP])
+{
+    p[1] = p[0]; /* K_SE_ANT = K_SE_AG */
+    p[3] = p[2]; /* K_LT_ANT = K_LT_AG */
+}
+
 /* Round-0 box: centre = nominal rounded to FP32 (PW from the duration),
- * half-width = frac * centre, bounds = centre -/+ half-width in FP32. */
-void oracle_initial_box(double dur_ms, float frac, float c0[NP], float w0[NP], float lo[NP], float hi[NP])
+ * half-width = frac * centre (0 for parameters a model holds fixed),
+ * bounds = centre -/+ half-width in FP32. */
+void oracle_initial_box_model(double dur_ms, float frac, int model, float c0[NP], float w0[NP], float lo[NP],
+                              float hi[NP])
 {
     double nom[NP];
     oracle_nominal(dur_ms, nom);
     for (int j = 0; j < NP; ++j) {
         c0[j] = (float)nom[j];
-        w0[j] = frac * c0[j];
+        w0[j] = (model == 9 && model9_fixed(j)) ? 0.0f : frac * c0[j];
         lo[j] = c0[j] - w0[j];
         hi[j] = c0[j] + w0[j];
     }
+}
+
+void oracle_initial_box(double dur_ms, float frac, float c0[NP], float w0[NP], float lo[NP], float hi[NP])
+{
+    oracle_initial_box_model(dur_ms, frac, 18, c0, w0, lo, hi);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -359,25 +378,28 @@ int oracle_score(const float* opc, int64_t n, const float* pos, int T, int C, do
  * the round was drawn around (centres: [n_rounds][18], nullable). */
 int oracle_fit(const float* pos, int T, int C, double amp, double dir_deg, double dur_ms,
                double dt_ms, uint64_t seed, int64_t n_cand, int n_rounds, float box_frac,
-               float w_init_frac, float shrink, const float* c_init, int nsub, int nthreads,
+               float w_init_frac, float shrink, const float* c_init, int model, int nsub, int nthreads,
                float opc_out[NP], double* rmse_out, double* mae_out,
                int64_t* best_idx, double* best_rmse, float* centres)
 {
     if (n_cand < 1 || n_rounds < 1 || T < 1 || n_cand > 0xFFFFFFFFLL) return -1;
+    if (model != 18 && model != 9) return -1;
     float c[NP], w[NP], lo[NP], hi[NP];
-    oracle_initial_box(dur_ms, box_frac, c, w, lo, hi);
+    oracle_initial_box_model(dur_ms, box_frac, model, c, w, lo, hi);
     for (int j = 0; j < NP; ++j) w[j] = w[j] * w_init_frac;
     if (c_init)
         for (int j = 0; j < NP; ++j) {
-            float v = c_init[j];
+            float v = c_init[(model == 9 && (j == 1 || j == 3)) ? j - 1 : j];
             c[j] = v < lo[j] ? lo[j] : (v > hi[j] ? hi[j] : v);
         }
     float* cand = (float*)malloc(sizeof(float) * NP * n_cand);
     double* cost = (double*)malloc(sizeof(double) * n_cand);
     for (int r = 0; r < n_rounds; ++r) {
         if (centres) memcpy(centres + (size_t)r * NP, c, sizeof c);
-        for (int64_t i = 0; i < n_cand; ++i)
+        for (int64_t i = 0; i < n_cand; ++i) {
             oracle_candidate(seed, (uint32_t)r, (uint32_t)i, c, w, lo, hi, cand + i * NP);
+            if (model == 9) oracle_tie_model9(cand + i * NP);
+        }
         oracle_score(cand, n_cand, pos, T, C, amp, dir_deg, dt_ms, nsub, nthreads, cost, NULL);
         int64_t b = 0;
         for (int64_t i = 1; i < n_cand; ++i)

@@ -94,11 +94,13 @@ __global__ void init_kernel(int S, const SacDev* __restrict__ sacs, float box_fr
     int s = i / P, j = i % P;
     const int slot = sacs[s].slot;
     float c0 = nominal_param(j, sacs[s].dur);
-    float w0 = box_frac * c0;
+    float w0 = (sacs[s].model == 9 && fixed_in_model9(j)) ? 0.0f : box_frac * c0;
     float l = c0 - w0, h = c0 + w0;
     float c = c0;
     if (seed_opc) {
-        float v = seed_opc[i];
+        // 9-parameter model: tied components take the agonist's seed
+        const int js = (sacs[s].model == 9 && (j == 1 || j == 3)) ? j - 1 : j;
+        float v = seed_opc[(int64_t)s * P + js];
         c = (v == v) ? fminf(fmaxf(v, l), h) : c0;
         if (j == 0) status[slot] |= OPMM_ST_SEEDED;
     }
@@ -147,7 +149,7 @@ __device__ __forceinline__ void refine_one(const SacDev& sd, int s, int r, uint6
         idx = 0;
     }
     float p[P];
-    draw_candidate(sd.seed, (uint32_t)r, idx, b, p);
+    draw_candidate(sd.seed, (uint32_t)r, idx, b, p, sd.model);
     for (int j = 0; j < P; ++j) {
         centre[s * P + j] = p[j];
         hw[s * P + j] = b.w[j] * shrink;
@@ -303,7 +305,7 @@ __device__ __forceinline__ uint64_t process_tile(TileSmem<TPB, PASSES>& sm, cons
         const bool valid = (int64_t)idx < sd.n_cand;
         if (!__any(valid)) continue;
         float p[P];
-        draw_candidate(sd.seed, (uint32_t)round, idx, sm.box, p);
+        draw_candidate(sd.seed, (uint32_t)round, idx, sm.box, p, sd.model);
         Plant pl;
         plant_setup(p, sd.amp, dt, pl);
         R frac;
@@ -727,6 +729,7 @@ int validate_params(opmm_ctx* ctx, const opmm_fit_params* p)
     if (!(p->dt_ms > 0.0f && p->dt_ms <= 1.0f)) return fail(ctx, OPMM_EINVAL, "dt_ms must be in (0, 1]");
     if (p->mode != OPMM_FIT_ROUNDS && p->mode != OPMM_FIT_PERSISTENT) return fail(ctx, OPMM_EINVAL, "bad mode");
     if (p->tile < -1 || p->tile >= kNumShapes) return fail(ctx, OPMM_EINVAL, "bad tile index");
+    if (p->model != 18 && p->model != 9) return fail(ctx, OPMM_EINVAL, "model must be 18 or 9");
     return OPMM_OK;
 }
 
@@ -742,6 +745,7 @@ int upload_saccades(opmm_ctx* ctx, FitScratch& sc, const opmm_saccade* sacs, int
     for (int i = 0; i < S; ++i) {
         SacDev& d = h[i];
         d = opmm_rt::make_record(sacs[i], prm ? prm->n_cand : 1);
+        d.model = prm ? prm->model : 18;
         d.proj_off = toff;
         d.tiles = (int)((d.n_cand + tile_size - 1) / tile_size);
         d.tile_base = (int)tiles;
@@ -875,6 +879,7 @@ SacDev make_record(const opmm_saccade& s, int n_cand_default)
     d.dur = s.dur_ms;
     d.n_cand = s.n_cand > 0 ? s.n_cand : n_cand_default;
     d.tiles = 1;
+    d.model = 18;
     return d;
 }
 
@@ -981,6 +986,7 @@ void opmm_fit_params_default(opmm_fit_params* p)
     p->dt_ms = 1.0f;
     p->mode = OPMM_FIT_ROUNDS;
     p->tile = -1;
+    p->model = 18;
 }
 
 void opmm_nominal(float dur_ms, float* out)

@@ -131,9 +131,13 @@ struct Box {
     float c[P], w[P], lo[P], hi[P];
 };
 
+// The 9-parameter model (Table 2) shares one series elasticity and one
+// length-tension value between the muscles.
+__host__ __device__ inline bool fixed_in_model9(int j) { return (j >= 10 && j <= 13) || j >= 15; }
+
 // Full candidate `idx` of round `round` (index 0 is the centre).
 __device__ __forceinline__ void draw_candidate(uint64_t seed, uint32_t round, uint32_t idx,
-                                               const Box& b, float p[P])
+                                               const Box& b, float p[P], int model = 18)
 {
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
@@ -146,6 +150,10 @@ __device__ __forceinline__ void draw_candidate(uint64_t seed, uint32_t round, ui
     if (idx == 0) {
 #pragma unroll
         for (int j = 0; j < P; ++j) p[j] = b.c[j];
+    }
+    if (model == 9) {
+        p[1] = p[0];
+        p[3] = p[2];
     }
 }
 

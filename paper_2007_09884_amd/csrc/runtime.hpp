@@ -20,7 +20,7 @@ struct SacDev {
     int32_t n_cand, tiles, tile_base;
     int32_t slot;      // index of this saccade's search state (box, status, keys)
     int32_t round;     // current round when a launch serves saccades at different rounds
-    int32_t pad;
+    int32_t model;     // 18 or 9 (tied K_SE/K_LT, neural parameters fixed)
 };
 
 int fail(opmm_ctx* ctx, int code, const std::string& msg);

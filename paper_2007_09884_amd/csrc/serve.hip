@@ -117,6 +117,11 @@ int sfail(opmm_server* sv, int code, const std::string& m) { return opmm_rt::fai
         if (_e != hipSuccess) return opmm_rt::hip_fail(sv->ctx, _e, #call); \
     } while (0)
 
+const opmm_fit_params& phase_params(const opmm_server* sv, int phase)
+{
+    return (phase == PH_FIRST && sv->sg) ? sv->prm.seeded : sv->prm.plain;
+}
+
 opmm_saccade slot_saccade(const opmm_server* sv, int k)
 {
     opmm_saccade s = sv->slot[k].sac;
@@ -132,13 +137,11 @@ SacDev slot_record(const opmm_server* sv, int k)
     d.slot = k;
     d.round = sv->slot[k].round;
     d.tiles = (d.n_cand + sv->tile - 1) / sv->tile;
+    d.model = phase_params(sv, sv->slot[k].phase).model;
     return d;
 }
 
-const opmm_fit_params& phase_params(const opmm_server* sv, int phase)
-{
-    return (phase == PH_FIRST && sv->sg) ? sv->prm.seeded : sv->prm.plain;
-}
+
 
 }  // namespace
 
@@ -176,8 +179,9 @@ int opmm_server_create(opmm_ctx* ctx, opmm_surrogate* sg, const opmm_serve_param
             return opmm_rt::fail(ctx, OPMM_EINVAL, "bad search parameters");
     }
     if (prm->plain.dt_ms != prm->seeded.dt_ms || prm->plain.box_frac != prm->seeded.box_frac ||
-        prm->plain.shrink != prm->seeded.shrink)
-        return opmm_rt::fail(ctx, OPMM_EINVAL, "plain and seeded searches must share dt_ms, box_frac and shrink");
+        prm->plain.shrink != prm->seeded.shrink || (prm->plain.model != 18 && prm->plain.model != 9) ||
+        prm->plain.model != prm->seeded.model)
+        return opmm_rt::fail(ctx, OPMM_EINVAL, "plain and seeded searches must share dt_ms, box_frac, shrink and model");
     // slots admitted by memory: what one resident request costs on the device
     const size_t per_slot = sizeof(float) * (3 * (size_t)prm->max_T + 4 * P + P + P + 2) + sizeof(int32_t) * 2 +
                             sizeof(uint64_t) + sizeof(double) + sizeof(SacDev);

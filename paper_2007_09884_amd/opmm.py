@@ -29,7 +29,7 @@ assert SACCADE_DTYPE.itemsize == 40
 class FitParams(ctypes.Structure):
     _fields_ = [("n_cand", ctypes.c_int32), ("n_rounds", ctypes.c_int32), ("box_frac", ctypes.c_float),
                 ("w_init_frac", ctypes.c_float), ("shrink", ctypes.c_float), ("dt_ms", ctypes.c_float),
-                ("mode", ctypes.c_int32), ("tile", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("tile", ctypes.c_int32), ("model", ctypes.c_int32)]
 
 
 class ServeParams(ctypes.Structure):
@@ -89,6 +89,8 @@ def _load():
         "opmm_surrogate_save": (ctypes.c_int, [vp, ctypes.c_char_p]),
         "opmm_serve_params_default": (None, [ctypes.POINTER(ServeParams)]),
         "opmm_nm_params_default": (None, [ctypes.POINTER(NmParams)]),
+        "opmm_ivt_extract": (ctypes.c_int, [vp, vp, i64, f, f, f, f, i32, u64, i32, vp, vp, i64, vp,
+                                            ctypes.POINTER(i32), vp]),
         "opmm_fit_nm": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(NmParams), vp, vp, vp, vp, vp, vp,
                                        vp]),
         "opmm_server_create": (ctypes.c_int, [vp, vp, ctypes.POINTER(ServeParams), ctypes.POINTER(vp)]),
@@ -235,6 +237,20 @@ class Context:
                                     recs.shape[0], ctypes.byref(params), _ptr(seed_opc), _ptr(opc_out),
                                     _ptr(rmse_out), _ptr(iters_out), _ptr(decisions_out), _ptr(status_out),
                                     _stream(stream)))
+
+    def ivt_extract(self, gaze, pos_out, dt_ms=1.0, vel_thresh=30.0, min_dur=6.0, min_amp=0.0, max_T=MAX_T,
+                    seed_base=0, max_out=4096, stream=None):
+        """Saccades of a gaze stream (device [N][2]) -> (records, first-sample indices); traces in pos_out."""
+        recs = np.zeros(max_out, SACCADE_DTYPE)
+        src = np.zeros(max_out, np.int64)
+        n = ctypes.c_int32()
+        self._check(lib.opmm_ivt_extract(self._h, _ptr(gaze), gaze.shape[0], ctypes.c_float(dt_ms),
+                                         ctypes.c_float(vel_thresh), ctypes.c_float(min_dur),
+                                         ctypes.c_float(min_amp), int(max_T), ctypes.c_uint64(seed_base),
+                                         int(max_out), recs.ctypes.data_as(ctypes.c_void_p), _ptr(pos_out),
+                                         pos_out.numel(), src.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n),
+                                         _stream(stream)))
+        return recs[:n.value], src[:n.value]
 
     def autotune(self, pos, recs, params: FitParams, stream=None) -> int:
         recs = np.ascontiguousarray(recs, SACCADE_DTYPE)

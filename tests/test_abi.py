@@ -35,10 +35,11 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     from paper_2007_09884_amd import opmm
     assert opmm.SACCADE_DTYPE.itemsize == 40
-    assert ctypes.sizeof(opmm.FitParams) == 32
+    assert ctypes.sizeof(opmm.FitParams) == 36
+    assert ctypes.sizeof(opmm.ServeParams) == 96 and ctypes.sizeof(opmm.NmParams) == 20
     p = opmm.fit_params()
-    assert (p.n_cand, p.n_rounds, p.box_frac, p.w_init_frac, p.shrink, p.dt_ms, p.mode, p.tile) == \
-        (4096, 1, 0.25, 1.0, 0.5, 1.0, 0, -1)
+    assert (p.n_cand, p.n_rounds, p.box_frac, p.w_init_frac, p.shrink, p.dt_ms, p.mode, p.tile, p.model) == \
+        (4096, 1, 0.25, 1.0, 0.5, 1.0, 0, -1, 18)
 
 
 def test_nominal_is_table1():

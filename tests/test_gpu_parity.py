@@ -58,11 +58,11 @@ def check_argmin(ref, w, where=""):
         assert w == order[0], (where, w, int(order[0]))
 
 
-def run_fit(ctx, opmm, b, traces, n_cand, R, mode=0, tile=-1, n_cand_per=None, seed_opc=None):
+def run_fit(ctx, opmm, b, traces, n_cand, R, mode=0, tile=-1, n_cand_per=None, seed_opc=None, model=18):
     S = b["S"]
     recs = records(b, opmm, n_cand=n_cand_per)
     pos = dev(opmm.pack_traces(traces))
-    prm = opmm.fit_params(n_cand=n_cand, n_rounds=R, mode=mode, tile=tile)
+    prm = opmm.fit_params(n_cand=n_cand, n_rounds=R, mode=mode, tile=tile, model=model)
     opc = torch.zeros(S, 18, device="cuda")
     rmse = torch.zeros(S, device="cuda")
     mae = torch.zeros(S, device="cuda")
@@ -74,13 +74,14 @@ def run_fit(ctx, opmm, b, traces, n_cand, R, mode=0, tile=-1, n_cand_per=None, s
                 status=st.cpu().numpy(), keys=keys.cpu().numpy().view(np.uint64))
 
 
-def centre_chain(b, s, keys, R):
+def centre_chain(b, s, keys, R, model=18):
     """Round centres implied by the GPU's winners, rebuilt with the oracle's candidate rule."""
-    c, w, lo, hi = oracle.initial_box(b["dur_ms"][s])
+    c, w, lo, hi = oracle.initial_box(b["dur_ms"][s], model=model)
     cen = [c]
     for r in range(R):
         idx = int(keys[r, s] & np.uint64(0xFFFFFFFF))
-        cen.append(oracle.candidate(int(b["seed"][s]), r, idx, cen[-1], w * np.float32(0.5 ** r), lo, hi))
+        cen.append(oracle.candidates(int(b["seed"][s]), r, [idx], cen[-1], w * np.float32(0.5 ** r), lo, hi,
+                                     model=model)[0])
     return cen, w, lo, hi
 
 
@@ -196,6 +197,27 @@ def test_fit_replay_rounds(ctx, opmm):
         ref_final, mae_final = oracle.cost(oracle.simulate(cen[R].astype(np.float64), b["amp"][s],
                                                            int(b["T"][s])), traces[s], b["dir_deg"][s])
         assert abs(res["rmse"][s] - ref_final) <= 1e-6 * max(1, ref_final)
+
+
+def test_fit_model9_replay_rounds(ctx, opmm):
+    """The 9-parameter OPMM (Section 2.2.2, Table 2): same replay as above on its tied stream."""
+    full, traces_all = make_batch(6, "full")
+    pick = [1, 4]
+    b = synth.subset(full, pick)
+    traces = [traces_all[i] for i in pick]
+    N, R = 2000, 3
+    res = run_fit(ctx, opmm, b, traces, N, R, model=9)
+    for s in range(b["S"]):
+        cen, w, lo, hi = centre_chain(b, s, res["keys"], R, model=9)
+        for r in range(R):
+            cands = oracle.candidates(int(b["seed"][s]), r, range(N), cen[r], w * np.float32(0.5 ** r), lo, hi,
+                                      model=9)
+            ref, _ = oracle.score(cands, traces[s], b["amp"][s], b["dir_deg"][s], nthreads=NTH)
+            check_argmin(ref, int(res["keys"][r, s] & np.uint64(0xFFFFFFFF)), (s, r))
+        o = res["opc"][s]
+        assert o[1] == o[0] and o[3] == o[2] and np.array_equal(o, cen[R])
+        th = oracle.simulate(o.astype(np.float64), b["amp"][s], int(b["T"][s]))
+        assert abs(oracle.cost(th, traces[s], b["dir_deg"][s])[0] - res["rmse"][s]) <= 1e-6
 
 
 def test_fit_full_size_sampled(ctx, opmm):

@@ -322,3 +322,19 @@ def test_brute_force_grid():
     for i in (0, 17, truth_i, 124):
         th = oracle.simulate(grid[i].astype(np.float64), 10.0, 80)
         assert oracle.cost(th, pos, 0.0)[0] == r[i]
+
+
+def test_model9_stream_and_truth_recovery():
+    """9-parameter model (Section 2.2.2, Table 2): one K_SE and one K_LT for both muscles, the
+    neuronal-control parameters at nominal; a noise-free target made from one of its candidates is
+    recovered exactly."""
+    c, w, lo, hi = oracle.initial_box(43.0, 0.25, model=9)
+    fixed = [10, 11, 12, 13, 15, 16, 17]
+    assert np.all(w[fixed] == 0) and np.all(w[[0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 14]] > 0)
+    X = oracle.candidates(3, 0, range(1, 200), c, w, lo, hi, model=9)
+    assert np.all(X[:, 1] == X[:, 0]) and np.all(X[:, 3] == X[:, 2])
+    assert np.all(X[:, fixed] == c[fixed])
+    truth = oracle.candidates(77, 0, [41], c, w, lo, hi, model=9)[0]
+    pos = oracle.make_target(truth.astype(np.float64), 10.0, 0.0, 80, 1, np.zeros((80, 1)), 0.0)
+    res = oracle.fit(pos, 10.0, 0.0, 43.0, 77, 100, 1, model=9, nthreads=4)
+    assert res["best_idx"][0] == 41 and np.array_equal(res["opc"], truth)
