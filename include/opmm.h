@@ -348,6 +348,63 @@ int opmm_fit_nm(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_sac
                 int8_t* decisions_out, int32_t* status_out, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Forward sensitivities of the plant trajectory: d theta_k / d p_j for every
+ * OPC component j (Table 1 order, per unit of the component), k < T, at the
+ * given candidates.  The plant is linear and time-invariant on each piece of
+ * the pulse-step control (Section 2.1), so the sensitivities are those of the
+ * exact trajectory; PW's column is the effect of moving the pulse end.  This
+ * is the gradient information that the gradient-based estimation the paper
+ * proposes as future work (Section 5) needs.
+ *   sacs      host [S]: only T, amp_deg and dur_ms are read
+ *   opc       device [S][18] FP32
+ *   theta_out device, FP64: saccade s's trajectory at [off_s, off_s + T_s),
+ *             off_s = sum of T over the saccades before s
+ *   jac_out   device, FP64 [sum T][18]: row off_s + k is d theta_k / d p
+ * Synchronises the stream before returning (host records).  Errors:
+ * OPMM_EINVAL (bad record, dt_ms outside (0, 1]); nothing is queued then. */
+int opmm_sensitivity(opmm_ctx* ctx, const opmm_saccade* sacs, int32_t S, const float* opc, float dt_ms,
+                     double* theta_out, double* jac_out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Gradient-based polish of fitted OPC vectors (the estimation alternative of
+ * Section 5, applied after the box search): Levenberg-Marquardt with
+ * Marquardt scaling in coordinates relative to the Table 1 nominal, Jacobian
+ * from the forward sensitivities above.  Each iteration solves the damped
+ * normal equations for 8 damping values at once (lambda * 10^(m-4),
+ * m = 0..7) and takes the best trial point if it lowers the objective
+ * (lambda becomes a tenth of the winner's), else raises lambda by 1e8.
+ * Objective OPMM_OBJ_RMSE is the fit cost of Section 3.4; OPMM_OBJ_MAE is
+ * the mean absolute difference reported as OptErr (Fig. 4), minimised by
+ * iteratively reweighted least squares.  Points stay inside the search box
+ * (nominal +/- box_frac, PW = D - 6 ms); components at a bound whose
+ * gradient points outward are held.  With model 9 only the nine free
+ * components move (K_SE and K_LT tied across muscles, the rest fixed at their
+ * input values).  Stops when an accepted step gains less than tol_f times the
+ * objective, when lambda exceeds 1e30, or after max_iter iterations. */
+enum { OPMM_OBJ_RMSE = 0, OPMM_OBJ_MAE = 1 };
+typedef struct {
+    int32_t max_iter;   /* iteration cap                       [20]    */
+    int32_t objective;  /* OPMM_OBJ_RMSE or OPMM_OBJ_MAE       [RMSE]  */
+    float tol_f;        /* relative gain that ends the polish  [1e-10] */
+    float lambda0;      /* initial damping                     [1e-3]  */
+    float box_frac;     /* search box half-width / nominal     [0.25]  */
+    float dt_ms;        /* sample period, (0, 1]               [1.0]   */
+} opmm_polish_params;
+void opmm_polish_params_default(opmm_polish_params* p);
+/* pos, sacs as for opmm_fit (n_cand and seed unused).  opc_inout: device
+ * [S][18], the start points in, the polished OPC out (never worse in the
+ * objective than the start clamped to the box).  rmse_out (device [S]) and
+ * mae_out (nullable) get both costs of the result; iters_out (nullable) the
+ * iterations taken; decisions_out (nullable, device [S][max_iter]) per
+ * iteration the index m of the accepted damping value or -1 (rejected);
+ * entries past the last iteration are left untouched.  Saccades whose trace
+ * holds NaN/Inf get NaN outputs.  Queued on `stream`; OPMM_EINVAL on bad
+ * parameters or model not 9/18, before anything is queued. */
+int opmm_polish(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
+                const opmm_polish_params* prm, int32_t model, float* opc_inout, float* rmse_out, float* mae_out,
+                int32_t* iters_out, int8_t* decisions_out, void* stream);
+
+/* ------------------------------------------------------------------------
  * Saccade extraction by velocity threshold (I-VT), the identification step
  * before estimation (Section 3.1; Section 4 uses I-VT and drops saccades
  * shorter than 6 ms).  gaze: device [N][2] FP32 positions (deg), sample

@@ -64,6 +64,12 @@ def lib():
         L.oracle_fit.restype = i
         L.oracle_nelder_mead.argtypes = [P, i, i, d, d, d, d, P, i, d, d, d, d, i, P, P, P, P, P]
         L.oracle_nelder_mead.restype = i
+        L.oracle_jacobian.argtypes = [P, d, i, d, i, d, P, P]
+        L.oracle_jacobian.restype = i
+        L.oracle_damped_solve.argtypes = [i, P, P, d, P, P]
+        L.oracle_damped_solve.restype = i
+        L.oracle_polish.argtypes = [P, i, i, d, d, d, d, P, i, i, i, d, d, d, i, P, P, P, P, P, P]
+        L.oracle_polish.restype = i
         _lib = L
     return _lib
 
@@ -223,6 +229,43 @@ def nelder_mead(pos, amp, dir_deg, dur_ms, *, x0=None, max_iter=500, tol_x=1e-4,
                                   int(max_iter), float(tol_x), float(tol_f), float(lo), float(hi), int(nsub),
                                   None if fc is None else _p(fc), _p(own), _p(mar), _p(opc), ctypes.byref(f))
     return dict(opc=opc, rmse=f.value, iters=it, own=own[:it], margin=mar[:it])
+
+
+def jacobian(p, amp, T, dt_ms=1.0, nsub=NSUB, h_rel=3e-5):
+    """(theta [T], d theta / d p [T][18]) by central differences of the RK4 trajectory."""
+    p = np.ascontiguousarray(p, np.float64)
+    th = np.zeros(T); J = np.zeros((T, NP_))
+    rc = lib().oracle_jacobian(_p(p), float(amp), int(T), float(dt_ms), int(nsub), float(h_rel), _p(th), _p(J))
+    assert rc == 0
+    return th, J
+
+
+def damped_solve(H, g, lam, held=None):
+    """delta solving (H + lam diag H) delta = -g (held unknowns: 0), or None if not positive definite."""
+    H = np.ascontiguousarray(H, np.float64); g = np.ascontiguousarray(g, np.float64)
+    n = g.shape[0]
+    hd = np.ascontiguousarray(np.zeros(n, np.int32) if held is None else held, np.int32)
+    dl = np.zeros(n)
+    rc = lib().oracle_damped_solve(n, _p(H), _p(g), float(lam), _p(hd), _p(dl))
+    return None if rc != 0 else dl
+
+
+def polish(pos, amp, dir_deg, dur_ms, x0, *, model=18, objective=0, max_iter=20, tol_f=1e-10, lam0=1e-3,
+           box_frac=0.25, dt_ms=1.0, nsub=NSUB, forced=None):
+    """Levenberg-Marquardt polish (objective 0: sum of squares, 1: sum of absolute differences).
+    Returns dict(opc, f, iters, own, margin, fhist); with forced, exactly len(forced) iterations
+    following those decisions."""
+    pos = _f32(pos); T, C = pos.shape
+    x0 = _f32(x0)
+    n = max_iter if forced is None else len(forced)
+    own = np.full(max(n, 1), -2, np.int8); mar = np.zeros(max(n, 1)); fh = np.zeros(max(n, 1))
+    fc = None if forced is None else np.ascontiguousarray(forced, np.int8)
+    opc = np.zeros(NP_, np.float32); f = ctypes.c_double()
+    it = lib().oracle_polish(_p(pos), T, C, float(amp), float(dir_deg), float(dur_ms), float(dt_ms), _p(x0),
+                             int(model), int(objective), int(n), float(tol_f), float(lam0), float(box_frac),
+                             int(nsub), None if fc is None else _p(fc), _p(own), _p(mar), _p(fh), _p(opc),
+                             ctypes.byref(f))
+    return dict(opc=opc, f=f.value, iters=it, own=own[:it], margin=mar[:it], fhist=fh[:it])
 
 
 def ivt(gaze, dt_ms=1.0, vel_thresh=30.0, min_dur=6.0, min_amp=0.0, max_T=2048):

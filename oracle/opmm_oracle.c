@@ -572,3 +572,243 @@ int oracle_nelder_mead(const float* pos, int T, int C, double amp, double dir_de
     *f_out = f[0];
     return it;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Gradient-based polish (Section 5: gradient methods as future work)         */
+/* ------------------------------------------------------------------------- */
+
+/* Sensitivities d theta_k / d p_j of the RK4 trajectory by central
+ * differences with step h_rel * |p_j| (p in double, not rounded).  theta
+ * (nullable) [T]; jac [T][NP]. */
+int oracle_jacobian(const double p[NP], double amp, int T, double dt_ms, int nsub, double h_rel,
+                    double* theta, double* jac)
+{
+    if (T < 1 || !(h_rel > 0)) return -1;
+    double* tp = (double*)malloc(sizeof(double) * T);
+    double* tm = (double*)malloc(sizeof(double) * T);
+    if (theta) oracle_simulate(p, amp, T, dt_ms, nsub, theta);
+    for (int j = 0; j < NP; ++j) {
+        double q[NP];
+        memcpy(q, p, sizeof q);
+        double h = h_rel * fabs(p[j]);
+        if (!(h > 0)) h = h_rel;
+        q[j] = p[j] + h;
+        double hp = q[j] - p[j];
+        oracle_simulate(q, amp, T, dt_ms, nsub, tp);
+        q[j] = p[j] - h;
+        double hm = p[j] - q[j];
+        oracle_simulate(q, amp, T, dt_ms, nsub, tm);
+        for (int k = 0; k < T; ++k) jac[(int64_t)k * NP + j] = (tp[k] - tm[k]) / (hp + hm);
+    }
+    free(tp);
+    free(tm);
+    return 0;
+}
+
+/* Solve (H + lam diag H) delta = -g over the n unknowns not held (held
+ * unknowns get delta = 0) by a Cholesky factorisation.  H row-major n x n.
+ * Returns 0, or -1 if the damped matrix is not positive definite. */
+int oracle_damped_solve(int n, const double* H, const double* g, double lam, const int* held, double* delta)
+{
+    double A[NP][NP], L[NP][NP], y[NP];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            if (held[i] || held[j]) A[i][j] = (i == j) ? 1.0 : 0.0;
+            else A[i][j] = H[i * n + j] + ((i == j) ? lam * H[i * n + j] : 0.0);
+        }
+    for (int j = 0; j < n; ++j) {
+        double d = A[j][j];
+        for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
+        if (!(d > 0)) return -1;
+        L[j][j] = sqrt(d);
+        for (int i = j + 1; i < n; ++i) {
+            double s = A[i][j];
+            for (int k = 0; k < j; ++k) s -= L[i][k] * L[j][k];
+            L[i][j] = s / L[j][j];
+        }
+    }
+    for (int i = 0; i < n; ++i) { /* L y = -g */
+        double s = held[i] ? 0.0 : -g[i];
+        for (int k = 0; k < i; ++k) s -= L[i][k] * y[k];
+        y[i] = s / L[i][i];
+    }
+    for (int i = n - 1; i >= 0; --i) { /* L^T delta = y */
+        double s = y[i];
+        for (int k = i + 1; k < n; ++k) s -= L[k][i] * delta[k];
+        delta[i] = s / L[i][i];
+    }
+    return 0;
+}
+
+typedef struct {
+    const float* pos; int T, C; double amp, u[2], dt; int nsub, objective;
+    double nom[NP];
+} lm_problem;
+
+/* objective at the FP32-rounded OPC of relative point x: sum of squared or of
+ * absolute differences over all samples and channels */
+static double lm_cost(const lm_problem* pb, const double x[NP], double* sq_out, double* ab_out)
+{
+    double p[NP];
+    for (int j = 0; j < NP; ++j) p[j] = (double)(float)(x[j] * pb->nom[j]);
+    double* th = (double*)malloc(sizeof(double) * pb->T);
+    oracle_simulate(p, pb->amp, pb->T, pb->dt, pb->nsub, th);
+    double sq = 0.0, ab = 0.0;
+    for (int k = 0; k < pb->T; ++k)
+        for (int c = 0; c < pb->C; ++c) {
+            double e = th[k] * pb->u[c] - (double)pb->pos[k * pb->C + c];
+            sq += e * e;
+            ab += fabs(e);
+        }
+    free(th);
+    if (sq_out) *sq_out = sq;
+    if (ab_out) *ab_out = ab;
+    double f = pb->objective == 1 ? ab : sq;
+    return (f >= 0.0 && f <= HUGE_VAL && f == f) ? f : HUGE_VAL;
+}
+
+/* Levenberg-Marquardt with Marquardt scaling on the relative coordinates
+ * x_j = p_j / nominal_j.  Per iteration:
+ *   1. residuals e (per sample and channel) of the FP32-rounded point and
+ *      their Jacobian J with respect to the free coordinates;
+ *   2. weights: 1 for the squared objective; 1/max(|e|, 1e-3) for the
+ *      absolute objective (iteratively reweighted least squares);
+ *      H = J^T W J, g = J^T W e;
+ *   3. a free coordinate is held if H_jj <= 0 or it sits at a bound with
+ *      the gradient pointing out of the box;
+ *   4. for each factor m of {1e-4, ..., 1e3}: delta_m solves
+ *      (H + lam*fac_m diag H) delta = -g, trial point clamp(x + delta_m);
+ *   5. the trial with the smallest objective (first on ties) is taken if it
+ *      is below the current objective: lam <- lam * fac_best / 10; else
+ *      lam <- lam * 1e8 and x stays;
+ *   6. stop when a taken step gained <= tol_f times the new objective, when
+ *      lam > 1e30, or after max_iter iterations.
+ * model 9: free coordinates K_SE (both muscles), K_LT (both), B_AG, B_ANT,
+ * B_P, N_C_AG, N_C_ANT, J and N_C_FIX; the rest keep their input values.
+ * forced (nullable, [max_iter]): take these decisions (index or -1) for
+ * exactly max_iter iterations instead; own/margin (nullable, [max_iter]) get
+ * the oracle's own decision and the smallest gap it rested on; fhist
+ * (nullable, [max_iter]) the objective at the start of each iteration.
+ * Returns the number of iterations; opc_out the result (FP32), *f_out its
+ * objective. */
+int oracle_polish(const float* pos, int T, int C, double amp, double dir_deg, double dur_ms, double dt_ms,
+                  const float* x0_opc, int model, int objective, int max_iter, double tol_f, double lam0,
+                  double box_frac, int nsub, const signed char* forced, signed char* own, double* margin,
+                  double* fhist, float opc_out[NP], double* f_out)
+{
+    static const double fac[8] = {1e-4, 1e-3, 1e-2, 1e-1, 1.0, 1e1, 1e2, 1e3};
+    lm_problem pb;
+    pb.pos = pos; pb.T = T; pb.C = C; pb.amp = amp; pb.dt = dt_ms; pb.nsub = nsub; pb.objective = objective;
+    double phi = dir_deg * (M_PI / 180.0);
+    pb.u[0] = cos(phi);
+    pb.u[1] = sin(phi);
+    if (C == 1) { pb.u[0] = dir_deg == 0.0 ? 1.0 : -1.0; pb.u[1] = 0.0; }
+    oracle_nominal(dur_ms, pb.nom);
+
+    /* free coordinates and the second component each one moves (ties) */
+    int fr[NP], tie[NP], nf = 0;
+    for (int j = 0; j < NP; ++j) {
+        if (model == 9 && (model9_fixed(j) || j == 1 || j == 3)) continue;
+        fr[nf] = j;
+        tie[nf] = (model == 9 && (j == 0 || j == 2)) ? j + 1 : -1;
+        ++nf;
+    }
+    double x[NP], lo[NP], hi[NP];
+    for (int j = 0; j < NP; ++j) x[j] = (double)x0_opc[j] / pb.nom[j];
+    if (model == 9) { /* the antagonist's K_SE and K_LT take the agonist's values */
+        x[1] = (double)(float)(x[0] * pb.nom[0]) / pb.nom[1];
+        x[3] = (double)(float)(x[2] * pb.nom[2]) / pb.nom[3];
+    }
+    for (int j = 0; j < NP; ++j) {
+        int fixed = model == 9 && model9_fixed(j);
+        lo[j] = fixed ? x[j] : 1.0 - box_frac;
+        hi[j] = fixed ? x[j] : 1.0 + box_frac;
+        if (x[j] < lo[j]) x[j] = lo[j];
+        if (x[j] > hi[j]) x[j] = hi[j];
+    }
+    const int nch = T * C;
+    double* th = (double*)malloc(sizeof(double) * T);
+    double* ja = (double*)malloc(sizeof(double) * T * NP);
+    double* jr = (double*)malloc(sizeof(double) * T * NP);
+    double lam = lam0;
+    int it = 0;
+    for (; it < max_iter; ++it) {
+        /* 1-2: normal equations at x */
+        double p[NP];
+        for (int j = 0; j < NP; ++j) p[j] = (double)(float)(x[j] * pb.nom[j]);
+        oracle_jacobian(p, amp, T, dt_ms, nsub, 3e-5, th, ja);
+        for (int k = 0; k < T; ++k)
+            for (int f = 0; f < nf; ++f) {
+                double v = pb.nom[fr[f]] * ja[(int64_t)k * NP + fr[f]];
+                if (tie[f] >= 0) v += pb.nom[tie[f]] * ja[(int64_t)k * NP + tie[f]];
+                jr[(int64_t)k * NP + f] = v;
+            }
+        double H[NP * NP], g[NP], fcur = 0.0;
+        memset(H, 0, sizeof H);
+        memset(g, 0, sizeof g);
+        for (int k = 0; k < T; ++k)
+            for (int c = 0; c < C; ++c) {
+                double e = th[k] * pb.u[c] - (double)pos[k * C + c];
+                double w = objective == 1 ? 1.0 / fmax(fabs(e), 1e-3) : 1.0;
+                fcur += objective == 1 ? fabs(e) : e * e;
+                for (int a = 0; a < nf; ++a) {
+                    double ja_ = jr[(int64_t)k * NP + a] * pb.u[c];
+                    g[a] += w * ja_ * e;
+                    for (int b = 0; b < nf; ++b) H[a * nf + b] += w * ja_ * jr[(int64_t)k * NP + b] * pb.u[c];
+                }
+            }
+        (void)nch;
+        if (fhist) fhist[it] = fcur;
+        /* 3 */
+        int held[NP];
+        for (int f = 0; f < nf; ++f) {
+            int j = fr[f];
+            held[f] = !(H[f * nf + f] > 0.0) || (x[j] <= lo[j] && g[f] > 0.0) || (x[j] >= hi[j] && g[f] < 0.0);
+        }
+        /* 4 */
+        double xt[8][NP], ft[8];
+        for (int m = 0; m < 8; ++m) {
+            double delta[NP];
+            memcpy(xt[m], x, sizeof x);
+            if (oracle_damped_solve(nf, H, g, lam * fac[m], held, delta) != 0) { ft[m] = HUGE_VAL; continue; }
+            for (int f = 0; f < nf; ++f) {
+                int j = fr[f];
+                double v = x[j] + delta[f];
+                if (v < lo[j]) v = lo[j];
+                if (v > hi[j]) v = hi[j];
+                xt[m][j] = v;
+                if (tie[f] >= 0) xt[m][tie[f]] = v;
+            }
+            ft[m] = lm_cost(&pb, xt[m], NULL, NULL);
+        }
+        /* 5 */
+        int best = 0;
+        for (int m = 1; m < 8; ++m)
+            if (ft[m] < ft[best]) best = m;
+        int d = ft[best] < fcur ? best : -1;
+        double mg = fabs(ft[best] - fcur);
+        for (int m = 0; m < 8; ++m)
+            if (m != best && ft[m] < HUGE_VAL) mg = fmin(mg, fabs(ft[m] - ft[best]));
+        if (own) own[it] = (signed char)d;
+        if (margin) margin[it] = mg;
+        if (forced) d = forced[it];
+        int done;
+        if (d >= 0) {
+            double gain = fcur - ft[d];
+            memcpy(x, xt[d], sizeof x);
+            lam = lam * fac[d] * 0.1;
+            done = gain <= tol_f * ft[d];
+        } else {
+            lam *= 1e8;
+            done = !(lam <= 1e30);
+        }
+        if (!forced && done) { ++it; break; }
+    }
+    for (int j = 0; j < NP; ++j) opc_out[j] = (float)(x[j] * pb.nom[j]);
+    double sq;
+    *f_out = lm_cost(&pb, x, &sq, NULL);
+    free(th);
+    free(ja);
+    free(jr);
+    return it;
+}

@@ -7,7 +7,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SRCS = [os.path.join(PKG, "csrc", n) for n in ("opmm.hip", "surrogate.hip", "serve.hip", "nm.hip", "ivt.hip")]
+SRCS = [os.path.join(PKG, "csrc", n) for n in ("opmm.hip", "surrogate.hip", "serve.hip", "nm.hip", "ivt.hip", "polish.hip")]
 DEPS = SRCS + [os.path.join(PKG, "csrc", n) for n in ("plant.hpp", "runtime.hpp")] + \
     [os.path.join(ROOT, "include", "opmm.h")]
 LIB = os.path.join(PKG, "libopmm.so")

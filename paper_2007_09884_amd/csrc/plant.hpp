@@ -1,5 +1,5 @@
 // Device-side model of the 18-parameter oculomotor plant (arXiv 2007.09884,
-// Section 2.1 and Section 2.2.1 / Table 1) for one candidate per lane, FP32.
+// Section 2.1 and Section 2.2.1 / Table 1) for one candidate per lane.
 //
 // Units: time in ms (viscosities scaled by 1e3, inertia by 1e6 from Table 1's
 // second-based units), angles in degrees, forces in grams.
@@ -9,11 +9,12 @@
 // with the activation time constants, step afterwards with the deactivation
 // time constants), so one sample period dt advances the deviation from the
 // piece's equilibrium by a fixed matrix: d_{k+1} = Phi d_k.  Phi = exp(A dt) is
-// formed once per candidate in "D-form" (D = Phi - I, degree-8 Taylor
-// polynomial evaluated by Horner's rule): storing Phi - I keeps the slow modes
-// (|1 - mu| ~ 0.02 per ms) at full relative precision, which is what lets the
-// whole path run in FP32.  The sample that contains the pulse end is split
-// exactly at PW with two Taylor exponential-vector products.
+// formed once per candidate in "D-form" (D = Phi - I, Taylor polynomial by
+// Horner's rule, then squarings): storing Phi - I keeps the slow modes
+// (|1 - mu| ~ 0.02 per ms) at full relative precision.  The recurrence type R
+// is FP64 by default (FP32 stays buildable); candidates are FP32.  The sample
+// that contains the pulse end is split exactly at PW with two Taylor
+// exponential-vector products.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -305,59 +306,89 @@ __device__ __forceinline__ void transition_dform(Plant& pl, R hfull)
     pl.e2[0] = pd[2]; pl.e2[1] = pd[3];
 }
 
-// Coefficients, transition and equilibria of candidate p for a saccade of
-// amplitude amp (deg), sample period dt (ms).  The scalar part (matrix
-// entries, equilibria, deviations) is formed in FP64 and rounded once to FP32:
-// FP32 chains of reciprocals here would shift the equilibria by a few ulps of
-// ~10 deg, i.e. ~1e-6 deg on every sample.  FP64 runs at the FP32 rate on the
-// vector ALU, and this part is a few hundred operations per candidate.
-__device__ __forceinline__ void plant_setup(const float p[P], float amp, float dt, Plant& pl)
+// Continuous-time coefficients (per ms) and the statics of candidate p for a
+// saccade of amplitude amp (deg): the matrix entries of the mechanical block,
+// the force couplings and active-state rates of both pieces, the pulse
+// equilibrium's theta, and the deviations rest - pulse equilibrium and pulse
+// equilibrium - post equilibrium (Section 2.1).  Generic in the scalar so that
+// the sensitivity pass runs the very same formulas on dual numbers.
+template <class S>
+struct PlantScalars {
+    S a10, a11, a12, a13, a20, a22, g2, a30, a33, g3;
+    S q1a, q1n, q2a, q2n;
+    S th1;
+    S d0[6];
+    S sh[6];
+};
+
+template <class S>
+__device__ __forceinline__ void plant_scalars(const S p[P], S amp, PlantScalars<S>& o)
 {
-    const double kse_a = p[0], kse_n = p[1], klt_a = p[2], klt_n = p[3];
-    const double b_a = (double)p[4] * 1e3, b_n = (double)p[5] * 1e3, b_p = (double)p[6] * 1e3;
-    const double nc_a = p[7], nc_n = p[8];
-    const double kp = nc_a + nc_n;            // passive elasticity = sum of tension slopes
-    const double jm = (double)p[9] * 1e6;
-    const double ij = rcp64(jm), iba = rcp64(b_a), ibn = rcp64(b_n);
-    pl.a10 = (R)(-(kse_a + kse_n + kp) * ij);
-    pl.a11 = (R)(-b_p * ij);
-    pl.a12 = (R)(kse_a * ij);
-    pl.a13 = (R)(-kse_n * ij);
-    pl.a20 = (R)(kse_a * iba);
-    pl.a22 = (R)(-(klt_a + kse_a) * iba);
-    pl.g2 = (R)iba;
-    pl.a30 = (R)(-kse_n * ibn);
-    pl.a33 = (R)(-(klt_n + kse_n) * ibn);
-    pl.g3 = (R)ibn;
-    pl.q1a = (R)(-rcp64((double)p[10]));
-    pl.q1n = (R)(-rcp64((double)p[11]));
-    pl.q2a = (R)(-rcp64((double)p[12]));
-    pl.q2n = (R)(-rcp64((double)p[13]));
-    transition_dform(pl, (R)dt);
+    const S kse_a = p[0], kse_n = p[1], klt_a = p[2], klt_n = p[3];
+    const S b_a = p[4] * 1e3, b_n = p[5] * 1e3, b_p = p[6] * 1e3;
+    const S nc_a = p[7], nc_n = p[8];
+    const S kp = nc_a + nc_n;            // passive elasticity = sum of tension slopes
+    const S jm = p[9] * 1e6;
+    const S ij = rcp64(jm), iba = rcp64(b_a), ibn = rcp64(b_n);
+    o.a10 = -(kse_a + kse_n + kp) * ij;
+    o.a11 = -b_p * ij;
+    o.a12 = kse_a * ij;
+    o.a13 = -kse_n * ij;
+    o.a20 = kse_a * iba;
+    o.a22 = -(klt_a + kse_a) * iba;
+    o.g2 = iba;
+    o.a30 = -kse_n * ibn;
+    o.a33 = -(klt_n + kse_n) * ibn;
+    o.g3 = ibn;
+    o.q1a = -rcp64(p[10]);
+    o.q1n = -rcp64(p[11]);
+    o.q2a = -rcp64(p[12]);
+    o.q2n = -rcp64(p[13]);
 
     // statics: c_m = K_SE/(K_SE + K_LT) is the share of the active state the series element carries
-    const double iksa = rcp64(kse_a), iksn = rcp64(kse_n);
-    const double ica = 1.0 + klt_a * iksa, icn = 1.0 + klt_n * iksn;  // 1/c_m
-    const double ca = kse_a * rcp64(kse_a + klt_a), cn = kse_n * rcp64(kse_n + klt_n);
-    const double kt = kp + ca * klt_a + cn * klt_n;
-    const double nfix = p[14], ns_a = p[15], ns_n = p[16], a = amp;
+    const S iksa = rcp64(kse_a), iksn = rcp64(kse_n);
+    const S ica = 1.0 + klt_a * iksa, icn = 1.0 + klt_n * iksn;  // 1/c_m
+    const S ca = kse_a * rcp64(kse_a + klt_a), cn = kse_n * rcp64(kse_n + klt_n);
+    const S kt = kp + ca * klt_a + cn * klt_n;
+    const S nfix = p[14], ns_a = p[15], ns_n = p[16], a = amp;
     // rest: theta = 0, fixation tension N_C_FIX on both muscles
-    const double xa0 = nfix * iksa, xn0 = nfix * iksn;
-    const double fa0 = nfix * ica, fn0 = nfix * icn;
+    const S xa0 = nfix * iksa, xn0 = nfix * iksn;
+    const S fa0 = nfix * ica, fn0 = nfix * icn;
     // pulse piece equilibrium (active states at the pulse heights)
-    const double th1 = (ca * ns_a - cn * ns_n) * rcp64(kt);
-    const double ta1 = ca * (ns_a - klt_a * th1), tn1 = cn * (ns_n + klt_n * th1);
-    const double xa1 = th1 + ta1 * iksa, xn1 = tn1 * iksn - th1;
+    const S th1 = (ca * ns_a - cn * ns_n) * rcp64(kt);
+    const S ta1 = ca * (ns_a - klt_a * th1), tn1 = cn * (ns_n + klt_n * th1);
+    const S xa1 = th1 + ta1 * iksa, xn1 = tn1 * iksn - th1;
     // post piece equilibrium: the step holds the eye at the amplitude
-    const double ta2 = nfix + nc_a * a, tn2 = nfix - nc_n * a;
-    const double xa2 = a + ta2 * iksa, xn2 = tn2 * iksn - a;
-    const double fa2 = ta2 * ica + klt_a * a, fn2 = tn2 * icn - klt_n * a;
-    pl.th1 = (R)th1;
+    const S ta2 = nfix + nc_a * a, tn2 = nfix - nc_n * a;
+    const S xa2 = a + ta2 * iksa, xn2 = tn2 * iksn - a;
+    const S fa2 = ta2 * ica + klt_a * a, fn2 = tn2 * icn - klt_n * a;
+    o.th1 = th1;
+    o.d0[0] = -th1; o.d0[1] = S(0.0); o.d0[2] = xa0 - xa1; o.d0[3] = xn0 - xn1;
+    o.d0[4] = fa0 - ns_a; o.d0[5] = fn0 - ns_n;
+    o.sh[0] = th1 - a; o.sh[1] = S(0.0); o.sh[2] = xa1 - xa2; o.sh[3] = xn1 - xn2;
+    o.sh[4] = ns_a - fa2; o.sh[5] = ns_n - fn2;
+}
+
+// Coefficients, transition and equilibria of candidate p for a saccade of
+// amplitude amp (deg), sample period dt (ms).  The scalar part is formed in
+// FP64 and rounded once to R: FP32 chains of reciprocals here would shift the
+// equilibria by a few ulps of ~10 deg, i.e. ~1e-6 deg on every sample.
+__device__ __forceinline__ void plant_setup(const float p[P], float amp, float dt, Plant& pl)
+{
+    double pd[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) pd[j] = p[j];
+    PlantScalars<double> c;
+    plant_scalars(pd, (double)amp, c);
+    pl.a10 = (R)c.a10; pl.a11 = (R)c.a11; pl.a12 = (R)c.a12; pl.a13 = (R)c.a13;
+    pl.a20 = (R)c.a20; pl.a22 = (R)c.a22; pl.g2 = (R)c.g2;
+    pl.a30 = (R)c.a30; pl.a33 = (R)c.a33; pl.g3 = (R)c.g3;
+    pl.q1a = (R)c.q1a; pl.q1n = (R)c.q1n; pl.q2a = (R)c.q2a; pl.q2n = (R)c.q2n;
+    transition_dform(pl, (R)dt);
+    pl.th1 = (R)c.th1;
     pl.amp = amp;
-    pl.d0[0] = (R)(-th1); pl.d0[1] = R(0); pl.d0[2] = (R)(xa0 - xa1); pl.d0[3] = (R)(xn0 - xn1);
-    pl.d0[4] = (R)(fa0 - ns_a); pl.d0[5] = (R)(fn0 - ns_n);
-    pl.sh[0] = (R)(th1 - a); pl.sh[1] = R(0); pl.sh[2] = (R)(xa1 - xa2); pl.sh[3] = (R)(xn1 - xn2);
-    pl.sh[4] = (R)(ns_a - fa2); pl.sh[5] = (R)(ns_n - fn2);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) { pl.d0[i] = (R)c.d0[i]; pl.sh[i] = (R)c.sh[i]; }
     pl.pw = p[17];
     pl.pwd = (double)p[17] * rcp64((double)dt);
 }

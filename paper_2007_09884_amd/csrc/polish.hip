@@ -1,0 +1,612 @@
+// libopmm: gradient-based estimation -- the alternative to the simplex search
+// that the paper leaves to future work (Section 5) -- as a polish after the
+// box search, with exact forward sensitivities of the plant.
+//
+// Sensitivities.  The plant is linear and time-invariant on each piece of the
+// pulse-step control (Section 2.1), so theta_k is a smooth function of the OPC
+// p (PW included: it moves the switching instant inside its sample).  The
+// derivative d theta_k / d p_j is computed in forward mode: the plant's scalar
+// physics (the same template as the search path), the one-sample transition
+// of each piece, the exact split of the pulse-end sample and the recurrence
+// all run on dual numbers (value, derivative) seeded with the unit direction
+// of parameter j.  One lane per parameter, one wave per saccade.  The
+// discretisation is exact to FP64 truncation (Taylor degree 12 on dt/2 and
+// one squaring; degree 16 for the split), so these are the sensitivities of
+// the exact trajectory to ~1e-13 relative.
+//
+// Polish.  Levenberg-Marquardt on the fit cost with Marquardt's diagonal
+// scaling, in coordinates relative to the Table 1 nominal.  Every iteration
+// forms J^T W J and J^T W e from the sensitivity pass (cross-lane shuffles),
+// then 8 lanes solve the damped system for 8 damping values at once
+// (lambda_c * 10^(m-4), m = 0..7; Cholesky per lane) and evaluate their trial
+// points; the best trial is taken if it lowers the cost (lambda_c becomes a
+// tenth of its lambda), otherwise lambda_c grows by 1e8 and the point stays.
+// Objectives: the RMSE of Section 3.4 (Gauss-Newton on squared residuals) or
+// the mean absolute difference the paper reports as OptErr (Fig. 4), by
+// iteratively reweighted least squares (weights 1/max(|e|, 1e-3 deg)).
+// Parameters at a bound whose gradient points outward are held; trial points
+// are clamped to the search box and rounded to FP32, the candidate format.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/opmm.h"
+#include "plant.hpp"
+#include "runtime.hpp"
+
+namespace opmm {
+
+// Forward-mode dual number: value and derivative along one direction.  Value
+// parts follow exactly the double operations of the plain path.
+struct Dual {
+    double v, d;
+    Dual() = default;
+    __device__ constexpr Dual(double x) : v(x), d(0.0) {}
+    __device__ constexpr Dual(double x, double dx) : v(x), d(dx) {}
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, __fma_rn(a.v, b.d, a.d * b.v)); }
+__device__ __forceinline__ Dual operator*(Dual a, double b) { return Dual(a.v * b, a.d * b); }
+__device__ __forceinline__ Dual operator*(double a, Dual b) { return Dual(a * b.v, a * b.d); }
+__device__ __forceinline__ Dual operator+(double a, Dual b) { return Dual(a + b.v, b.d); }
+__device__ __forceinline__ Dual fmr(Dual a, Dual b, Dual c)
+{
+    return Dual(__fma_rn(a.v, b.v, c.v), __fma_rn(a.v, b.d, __fma_rn(a.d, b.v, c.d)));
+}
+__device__ __forceinline__ Dual rcp64(Dual a)
+{
+    const double r = rcp64(a.v);
+    return Dual(r, -a.d * r * r);
+}
+__device__ __forceinline__ double val(double a) { return a; }
+__device__ __forceinline__ double val(Dual a) { return a.v; }
+
+}  // namespace opmm
+
+using namespace opmm;
+using opmm_rt::SacDev;
+
+namespace {
+
+constexpr int NLAM = 8;             // damping values tried per iteration
+constexpr int PTRI = P * (P + 1) / 2;
+constexpr double IRLS_EPS = 1e-3;   // deg: floor of |e| in the L1 weights
+constexpr int DF_M = 12;            // Taylor degree of the transition (on dt/2)
+constexpr int EX_M = 16;            // Taylor degree of the split exponential
+// damping factors of the 8 trial lanes, relative to the current lambda
+__constant__ double LAM_FAC[NLAM] = {1e-4, 1e-3, 1e-2, 1e-1, 1.0, 1e1, 1e2, 1e3};
+
+// D-form transition of one piece: mechanical block, coupling to (F_ag, F_ant),
+// active-state factors minus one.
+template <class S>
+struct Piece {
+    S m[4][4], x[4][2], e[2];
+};
+
+// rows of Mc * V for the mechanical block Mc (theta' = omega is row 0)
+template <class S>
+__device__ __forceinline__ void mech_rows(const PlantScalars<S>& c, const S v[4], S o[4])
+{
+    o[0] = v[1];
+    o[1] = fmr(c.a13, v[3], fmr(c.a12, v[2], fmr(c.a11, v[1], c.a10 * v[0])));
+    o[2] = fmr(c.a22, v[2], c.a20 * v[0]);
+    o[3] = fmr(c.a33, v[3], c.a30 * v[0]);
+}
+
+// D = exp(dt A) - I of the piece with active-state rates (qa, qn): Horner
+// evaluation of the Taylor polynomial on h = dt/2 in block form
+// A = [[Mc, G], [0, diag(q)]], then one squaring D_2h = D_h^2 + 2 D_h.
+template <class S>
+__device__ void lti_dform(const PlantScalars<S>& c, S qa, S qn, double dt, Piece<S>& o)
+{
+    const double h = 0.5 * dt;
+    const S q[2] = {qa, qn};
+    S qm[4][4], qx[4][2], qd[2];
+    for (int i = 0; i < 4; ++i) {
+        for (int j = 0; j < 4; ++j) qm[i][j] = S(i == j ? 1.0 : 0.0);
+        qx[i][0] = S(0.0); qx[i][1] = S(0.0);
+    }
+    qd[0] = S(1.0); qd[1] = S(1.0);
+    for (int k = DF_M; k >= 1; --k) {
+        // Q <- I + (h/k) A Q  (k >= 2);  D = h A Q  (k == 1)
+        const double s = h / (double)k;
+        S am[4][4], ax[4][2], ad[2];
+        for (int col = 0; col < 4; ++col) {
+            S v[4] = {qm[0][col], qm[1][col], qm[2][col], qm[3][col]}, r[4];
+            mech_rows(c, v, r);
+            for (int i = 0; i < 4; ++i) am[i][col] = r[i];
+        }
+        for (int col = 0; col < 2; ++col) {
+            S v[4] = {qx[0][col], qx[1][col], qx[2][col], qx[3][col]}, r[4];
+            mech_rows(c, v, r);
+            for (int i = 0; i < 4; ++i) ax[i][col] = r[i];
+        }
+        ax[2][0] = fmr(c.g2, qd[0], ax[2][0]);
+        ax[3][1] = fmr(c.g3, qd[1], ax[3][1]);
+        ad[0] = q[0] * qd[0];
+        ad[1] = q[1] * qd[1];
+        const double one = k >= 2 ? 1.0 : 0.0;
+        for (int i = 0; i < 4; ++i) {
+            for (int j = 0; j < 4; ++j) qm[i][j] = fmr(S(s), am[i][j], S(i == j ? one : 0.0));
+            qx[i][0] = S(s) * ax[i][0];
+            qx[i][1] = S(s) * ax[i][1];
+        }
+        qd[0] = fmr(S(s), ad[0], S(one));
+        qd[1] = fmr(S(s), ad[1], S(one));
+    }
+    // one squaring in D-form
+    for (int i = 0; i < 4; ++i) {
+        for (int j = 0; j < 4; ++j) {
+            S a = qm[i][j] + qm[i][j];
+            for (int k = 0; k < 4; ++k) a = fmr(qm[i][k], qm[k][j], a);
+            o.m[i][j] = a;
+        }
+        for (int j = 0; j < 2; ++j) {
+            S b = qx[i][j] * (qd[j] + S(2.0));
+            for (int k = 0; k < 4; ++k) b = fmr(qm[i][k], qx[k][j], b);
+            o.x[i][j] = b;
+        }
+    }
+    o.e[0] = qd[0] * (qd[0] + S(2.0));
+    o.e[1] = qd[1] * (qd[1] + S(2.0));
+}
+
+template <class S>
+__device__ __forceinline__ void piece_step(const Piece<S>& pc, S d[6])
+{
+    S n[4];
+    for (int i = 0; i < 4; ++i) {
+        S a = d[i];
+        for (int j = 0; j < 4; ++j) a = fmr(pc.m[i][j], d[j], a);
+        a = fmr(pc.x[i][0], d[4], a);
+        n[i] = fmr(pc.x[i][1], d[5], a);
+    }
+    d[4] = fmr(pc.e[0], d[4], d[4]);
+    d[5] = fmr(pc.e[1], d[5], d[5]);
+    for (int i = 0; i < 4; ++i) d[i] = n[i];
+}
+
+// v <- exp(t A) v by the Taylor polynomial of degree EX_M (|t| <= dt)
+template <class S>
+__device__ void expmv_t(const PlantScalars<S>& c, S qa, S qn, S t, S v[6])
+{
+    S w[6];
+    for (int i = 0; i < 6; ++i) w[i] = v[i];
+    for (int k = EX_M; k >= 1; --k) {
+        const S s = t * (1.0 / (double)k);
+        S mv[4], aw[6];
+        S w4[4] = {w[0], w[1], w[2], w[3]};
+        mech_rows(c, w4, mv);
+        aw[0] = mv[0];
+        aw[1] = mv[1];
+        aw[2] = fmr(c.g2, w[4], mv[2]);
+        aw[3] = fmr(c.g3, w[5], mv[3]);
+        aw[4] = qa * w[4];
+        aw[5] = qn * w[5];
+        for (int i = 0; i < 6; ++i) w[i] = fmr(s, aw[i], v[i]);
+    }
+    for (int i = 0; i < 6; ++i) v[i] = w[i];
+}
+
+// theta_k, k = 0..T-1, of OPC p (deg), handed to sink(k, theta_k).  Control
+// flow depends on value parts only, so every lane of a Dual pass at one point
+// takes the same path.
+template <class S, class Sink>
+__device__ void simulate_s(const S p[P], double amp, double dt, int T, Sink& sink)
+{
+    PlantScalars<S> c;
+    plant_scalars(p, S(amp), c);
+    Piece<S> pul, pos;
+    lti_dform(c, c.q1a, c.q1n, dt, pul);
+    lti_dform(c, c.q2a, c.q2n, dt, pos);
+    const S pwd = p[17] * rcp64(dt);
+    const double fl = floor(val(pwd));
+    int k0;
+    S frac(0.0);
+    if (!(val(pwd) > 0.0)) k0 = -1;
+    else if (fl >= (double)T) k0 = T;
+    else { k0 = (int)fl; frac = pwd - S(fl); }
+    S d[6];
+    for (int i = 0; i < 6; ++i) d[i] = c.d0[i];
+    S theq = c.th1;
+    if (k0 < 0) {
+        for (int i = 0; i < 6; ++i) d[i] = d[i] + c.sh[i];
+        theq = S(amp);
+    }
+    for (int k = 0; k < T; ++k) {
+        sink(k, d[0] + theq);
+        if (k < k0) {
+            piece_step(pul, d);
+        } else if (k == k0) {
+            expmv_t(c, c.q1a, c.q1n, frac * dt, d);
+            for (int i = 0; i < 6; ++i) d[i] = d[i] + c.sh[i];
+            expmv_t(c, c.q2a, c.q2n, (S(1.0) - frac) * dt, d);
+            theq = S(amp);
+        } else {
+            piece_step(pos, d);
+        }
+    }
+}
+
+// ---- sinks ----------------------------------------------------------------
+
+struct JacSink {  // theta and d theta / d p_lane
+    double* theta;
+    double* jac;  // [T][P] row-major
+    int lane;
+    __device__ void operator()(int k, Dual th)
+    {
+        if (lane == 0) theta[k] = th.v;
+        if (lane < P) jac[(int64_t)k * P + lane] = th.d;
+    }
+};
+
+struct Residual {
+    const float* X;
+    const float* Y;
+    double cphi, sphi;
+    int C;
+    __device__ __forceinline__ void operator()(int k, double th, double& ex, double& ey) const
+    {
+        ex = th * cphi - (double)X[k];
+        ey = C == 2 ? th * sphi - (double)Y[k] : 0.0;
+    }
+};
+
+struct CostSink {  // objective value only (trial points, reports)
+    Residual res;
+    int objective;
+    double sq, ab;
+    __device__ void operator()(int k, double th)
+    {
+        double ex, ey;
+        res(k, th, ex, ey);
+        sq = __fma_rn(ex, ex, sq);
+        ab += fabs(ex);
+        if (res.C == 2) {
+            sq = __fma_rn(ey, ey, sq);
+            ab += fabs(ey);
+        }
+    }
+    __device__ double f() const { return objective == OPMM_OBJ_MAE ? ab : sq; }
+};
+
+// Normal equations of the linearised problem.  Lane j holds column j of J
+// (the dual part); its row of J^T W J needs the other lanes' columns, taken
+// by shuffles.  Every lane of the wave calls it (wave-uniform control flow).
+struct NormalSink {
+    CostSink cost;
+    int nf;
+    double g;
+    double h[P];
+    __device__ void operator()(int k, Dual th)
+    {
+        double ex, ey;
+        cost.res(k, th.v, ex, ey);
+        cost(k, th.v);
+        double wx = 1.0, wy = 1.0;
+        if (cost.objective == OPMM_OBJ_MAE) {
+            wx = 1.0 / fmax(fabs(ex), IRLS_EPS);
+            wy = 1.0 / fmax(fabs(ey), IRLS_EPS);
+        }
+        const double cp = cost.res.cphi, sp = cost.res.sphi;
+        double a = wx * cp * cp, b = wx * cp * ex;
+        if (cost.res.C == 2) {
+            a = __fma_rn(wy * sp, sp, a);
+            b = __fma_rn(wy * sp, ey, b);
+        }
+        const double jd = th.d;
+        g = __fma_rn(jd, b, g);
+        const double aj = a * jd;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const double ji = __shfl(jd, i);
+            if (i < nf) h[i] = __fma_rn(aj, ji, h[i]);
+        }
+    }
+};
+
+// ---- sensitivity entry point ------------------------------------------------
+
+__global__ __launch_bounds__(64) void sensitivity_kernel(int S, const SacDev* __restrict__ sacs,
+                                                         const int64_t* __restrict__ out_off,
+                                                         const float* __restrict__ opc, double dt,
+                                                         double* __restrict__ theta, double* __restrict__ jac)
+{
+    const int s = blockIdx.x, lane = threadIdx.x;
+    const SacDev sd = sacs[s];
+    Dual p[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) p[j] = Dual((double)opc[(int64_t)s * P + j], j == lane ? 1.0 : 0.0);
+    JacSink sink{theta + out_off[s], jac + out_off[s] * P, lane};
+    simulate_s(p, (double)sd.amp, dt, sd.T, sink);
+}
+
+// ---- polish -------------------------------------------------------------------
+
+struct PolishSmem {
+    float X[OPMM_MAX_T], Y[OPMM_MAX_T];
+    double H[P][P];
+    double g[P];
+    double xt[NLAM][P];
+    double ft[NLAM];
+    double L[NLAM][PTRI];
+    double x[P], nom[P], lo[P], hi[P];
+    int opc_of[P];   // free parameter -> its (first) OPC index
+    int tied[P];     // free parameter -> second OPC index it moves, or -1
+    int nf;
+    double fcur, lam;
+    int ok[NLAM];
+    int done;
+};
+
+// OPC of relative point x, rounded to FP32 (the candidate format)
+__device__ __forceinline__ double opc_value(const PolishSmem& sm, const double* x, int i)
+{
+    return (double)(float)(x[i] * sm.nom[i]);
+}
+
+// Cholesky solve of (H + lam diag H) delta = -g over the free, unheld
+// parameters (packed lower factor in L).  Returns false if not positive definite.
+__device__ bool damped_solve(const PolishSmem& sm, double* Lp, double lam, const bool* held, double* delta)
+{
+    const int n = sm.nf;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double a;
+            if (held[i] || held[j]) a = (i == j) ? 1.0 : 0.0;
+            else a = (i == j) ? sm.H[i][i] * (1.0 + lam) : sm.H[i][j];
+            for (int k = 0; k < j; ++k) a -= Lp[i * (i + 1) / 2 + k] * Lp[j * (j + 1) / 2 + k];
+            if (i == j) {
+                if (!(a > 0.0)) return false;
+                Lp[i * (i + 1) / 2 + i] = sqrt(a);
+            } else {
+                Lp[i * (i + 1) / 2 + j] = a / Lp[j * (j + 1) / 2 + j];
+            }
+        }
+    }
+    double y[P];
+    for (int i = 0; i < n; ++i) {
+        double a = held[i] ? 0.0 : -sm.g[i];
+        for (int k = 0; k < i; ++k) a -= Lp[i * (i + 1) / 2 + k] * y[k];
+        y[i] = a / Lp[i * (i + 1) / 2 + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double a = y[i];
+        for (int k = i + 1; k < n; ++k) a -= Lp[k * (k + 1) / 2 + i] * delta[k];
+        delta[i] = a / Lp[i * (i + 1) / 2 + i];
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(64) void polish_kernel(int S, const SacDev* __restrict__ sacs,
+                                                    const float* __restrict__ pos, const int32_t* __restrict__ status_in,
+                                                    int model, int max_iter, int objective, double tol_f, double lam0,
+                                                    double box_frac, double dt, float* __restrict__ opc,
+                                                    float* __restrict__ rmse_out, float* __restrict__ mae_out,
+                                                    int32_t* __restrict__ iters_out, int8_t* __restrict__ dec_out)
+{
+    __shared__ PolishSmem sm;
+    const int s = blockIdx.x, lane = threadIdx.x;
+    const SacDev sd = sacs[s];
+    const int T = sd.T;
+    if (status_in[sd.slot] & OPMM_ST_NONFINITE_INPUT) {
+        if (lane < P) opc[(int64_t)s * P + lane] = __int_as_float(0x7FC00000);
+        if (lane == 0) {
+            rmse_out[s] = __int_as_float(0x7FC00000);
+            if (mae_out) mae_out[s] = __int_as_float(0x7FC00000);
+            if (iters_out) iters_out[s] = 0;
+        }
+        return;
+    }
+    for (int k = lane; k < T; k += 64) {
+        sm.X[k] = pos[sd.pos_off + (int64_t)k * sd.C];
+        sm.Y[k] = sd.C == 2 ? pos[sd.pos_off + (int64_t)k * sd.C + 1] : 0.0f;
+    }
+    if (lane < P) {
+        const double nm = nominal_param_f64(lane, (double)sd.dur);
+        const double v = (double)opc[(int64_t)s * P + lane];
+        sm.nom[lane] = nm;
+        sm.x[lane] = v / nm;
+        const bool fixed = model == 9 && fixed_in_model9(lane);
+        sm.lo[lane] = fixed ? sm.x[lane] : 1.0 - box_frac;
+        sm.hi[lane] = fixed ? sm.x[lane] : 1.0 + box_frac;
+    }
+    if (lane == 0) {
+        int n = 0;
+        for (int i = 0; i < P; ++i) {
+            if (model == 9 && (fixed_in_model9(i) || i == 1 || i == 3)) continue;
+            sm.opc_of[n] = i;
+            sm.tied[n] = (model == 9 && (i == 0 || i == 2)) ? i + 1 : -1;
+            ++n;
+        }
+        sm.nf = n;
+        sm.lam = lam0;
+        sm.done = 0;
+    }
+    __syncthreads();
+    if (lane < P) {
+        // 9-parameter model: the antagonist's K_SE and K_LT follow the agonist's
+        const int src = (model == 9 && (lane == 1 || lane == 3)) ? lane - 1 : lane;
+        const double v = opc_value(sm, sm.x, src) / sm.nom[lane];
+        sm.x[lane] = fmin(fmax(model == 9 ? v : sm.x[lane], sm.lo[lane]), sm.hi[lane]);
+    }
+    __syncthreads();
+    const int nf = sm.nf;
+    const Residual res{sm.X, sm.Y, sd.cphi, sd.sphi, sd.C};
+    int it = 0;
+    for (; it < max_iter; ++it) {
+        // A: sensitivities and normal equations at x (lane j: free parameter j)
+        {
+            Dual p[P];
+            const int i0 = lane < nf ? sm.opc_of[lane] : -1;
+            const int i1 = lane < nf ? sm.tied[lane] : -1;
+            for (int i = 0; i < P; ++i)
+                p[i] = Dual(opc_value(sm, sm.x, i), (i == i0 || i == i1) ? sm.nom[i] : 0.0);
+            NormalSink ns{CostSink{res, objective, 0.0, 0.0}, nf, 0.0, {}};
+            for (int i = 0; i < P; ++i) ns.h[i] = 0.0;
+            simulate_s(p, (double)sd.amp, dt, T, ns);
+            if (lane < nf) {
+                for (int i = 0; i < nf; ++i) sm.H[lane][i] = ns.h[i];
+                sm.g[lane] = ns.g;
+            }
+            if (lane == 0) sm.fcur = ns.cost.f();
+        }
+        __syncthreads();
+        // B: damped solves, one damping value per lane
+        if (lane < NLAM) {
+            const double lam = sm.lam * LAM_FAC[lane];
+            bool held[P];
+            for (int j = 0; j < nf; ++j) {
+                const int i = sm.opc_of[j];
+                held[j] = !(sm.H[j][j] > 0.0) || (sm.x[i] <= sm.lo[i] && sm.g[j] > 0.0) ||
+                          (sm.x[i] >= sm.hi[i] && sm.g[j] < 0.0);
+            }
+            double delta[P];
+            const bool ok = damped_solve(sm, sm.L[lane], lam, held, delta);
+            for (int i = 0; i < P; ++i) sm.xt[lane][i] = sm.x[i];
+            if (ok) {
+                for (int j = 0; j < nf; ++j) {
+                    const int i = sm.opc_of[j];
+                    const double v = fmin(fmax(sm.x[i] + delta[j], sm.lo[i]), sm.hi[i]);
+                    sm.xt[lane][i] = v;
+                    if (sm.tied[j] >= 0) sm.xt[lane][sm.tied[j]] = v;
+                }
+            }
+            sm.ok[lane] = ok;
+            sm.ft[lane] = INFINITY;
+        }
+        __syncthreads();
+        // C: trial costs
+        if (lane < NLAM && sm.ok[lane]) {
+            double p[P];
+            for (int i = 0; i < P; ++i) p[i] = opc_value(sm, sm.xt[lane], i);
+            CostSink cs{res, objective, 0.0, 0.0};
+            simulate_s(p, (double)sd.amp, dt, T, cs);
+            const double f = cs.f();
+            sm.ft[lane] = (f >= 0.0 && f <= 1.7976931348623157e308) ? f : INFINITY;
+        }
+        __syncthreads();
+        // D: decision
+        if (lane == 0) {
+            int best = 0;
+            for (int m = 1; m < NLAM; ++m)
+                if (sm.ft[m] < sm.ft[best]) best = m;
+            int dec;
+            if (sm.ft[best] < sm.fcur) {
+                dec = best;
+                const double gain = sm.fcur - sm.ft[best];
+                for (int i = 0; i < P; ++i) sm.x[i] = sm.xt[best][i];
+                sm.lam = sm.lam * LAM_FAC[best] * 0.1;
+                sm.done = gain <= tol_f * sm.ft[best];
+            } else {
+                dec = -1;
+                sm.lam *= 1e8;
+                sm.done = !(sm.lam <= 1e30);
+            }
+            if (dec_out) dec_out[(int64_t)s * max_iter + it] = (int8_t)dec;
+        }
+        __syncthreads();
+        if (sm.done) { ++it; break; }
+    }
+    if (lane < P) opc[(int64_t)s * P + lane] = (float)opc_value(sm, sm.x, lane);
+    if (lane == 0) {
+        double p[P];
+        for (int i = 0; i < P; ++i) p[i] = opc_value(sm, sm.x, i);
+        CostSink cs{res, objective, 0.0, 0.0};
+        simulate_s(p, (double)sd.amp, dt, T, cs);
+        const double n = (double)T * sd.C;
+        rmse_out[s] = (float)sqrt(cs.sq / n);
+        if (mae_out) mae_out[s] = (float)(cs.ab / n);
+        if (iters_out) iters_out[s] = it;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void opmm_polish_params_default(opmm_polish_params* p)
+{
+    if (!p) return;
+    p->max_iter = 20;
+    p->objective = OPMM_OBJ_RMSE;
+    p->tol_f = 1e-10f;
+    p->lambda0 = 1e-3f;
+    p->box_frac = 0.25f;
+    p->dt_ms = 1.0f;
+}
+
+int opmm_sensitivity(opmm_ctx* ctx, const opmm_saccade* sacs, int32_t S, const float* opc, float dt_ms,
+                     double* theta_out, double* jac_out, void* stream)
+{
+    if (!ctx) return OPMM_EINVAL;
+    if (S < 0 || (S > 0 && (!sacs || !opc || !theta_out || !jac_out)) || !(dt_ms > 0 && dt_ms <= 1))
+        return opmm_rt::fail(ctx, OPMM_EINVAL, "bad sensitivity arguments");
+    if (S == 0) return OPMM_OK;
+    std::vector<SacDev> hs(S);
+    std::vector<int64_t> off(S);
+    int64_t acc = 0;
+    for (int i = 0; i < S; ++i) {
+        if (sacs[i].T < 1 || sacs[i].T > OPMM_MAX_T || !std::isfinite(sacs[i].amp_deg) ||
+            !(sacs[i].dur_ms > 0))
+            return opmm_rt::fail(ctx, OPMM_EINVAL, "bad saccade record " + std::to_string(i));
+        hs[i] = opmm_rt::make_record(sacs[i], 1);
+        off[i] = acc;
+        acc += sacs[i].T;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    SacDev* d_sacs = nullptr;
+    int64_t* d_off = nullptr;
+    int rc = OPMM_OK;
+    auto ok = [&](hipError_t e, const char* w) { if (rc == OPMM_OK && e != hipSuccess) rc = opmm_rt::hip_fail(ctx, e, w); };
+    ok(hipMallocAsync((void**)&d_sacs, sizeof(SacDev) * S, st), "alloc");
+    ok(hipMallocAsync((void**)&d_off, sizeof(int64_t) * S, st), "alloc");
+    ok(hipMemcpyAsync(d_sacs, hs.data(), sizeof(SacDev) * S, hipMemcpyHostToDevice, st), "copy");
+    ok(hipMemcpyAsync(d_off, off.data(), sizeof(int64_t) * S, hipMemcpyHostToDevice, st), "copy");
+    if (rc == OPMM_OK) {
+        hipLaunchKernelGGL(sensitivity_kernel, dim3(S), dim3(64), 0, st, S, d_sacs, d_off, opc, (double)dt_ms,
+                           theta_out, jac_out);
+        ok(hipGetLastError(), "sensitivity_kernel");
+    }
+    // the host arrays are released when this call returns: wait for the copies
+    ok(hipStreamSynchronize(st), "sync");
+    if (d_sacs) (void)hipFreeAsync(d_sacs, st);
+    if (d_off) (void)hipFreeAsync(d_off, st);
+    return rc;
+}
+
+int opmm_polish(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
+                const opmm_polish_params* prm, int32_t model, float* opc_inout, float* rmse_out, float* mae_out,
+                int32_t* iters_out, int8_t* decisions_out, void* stream)
+{
+    if (!ctx) return OPMM_EINVAL;
+    if (!prm || prm->max_iter < 0 || prm->max_iter > 10000 ||
+        (prm->objective != OPMM_OBJ_RMSE && prm->objective != OPMM_OBJ_MAE) || !(prm->tol_f >= 0) ||
+        !(prm->lambda0 > 0) || !(prm->box_frac > 0 && prm->box_frac < 1) || !(prm->dt_ms > 0 && prm->dt_ms <= 1) ||
+        (model != 9 && model != 18))
+        return opmm_rt::fail(ctx, OPMM_EINVAL, "bad polish parameters");
+    if (S < 0 || (S > 0 && (!pos || !sacs || !opc_inout || !rmse_out)))
+        return opmm_rt::fail(ctx, OPMM_EINVAL, "bad arguments");
+    if (S == 0) return OPMM_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const SacDev* d_sacs;
+    const float* proj;
+    const double* qorth;
+    const int32_t* status;
+    int rc = opmm_rt::project_batch_full(ctx, pos, pos_len, sacs, S, &d_sacs, &proj, &qorth, &status, st);
+    if (rc != OPMM_OK) return rc;
+    hipLaunchKernelGGL(polish_kernel, dim3(S), dim3(64), 0, st, S, d_sacs, pos, status, (int)model, prm->max_iter,
+                       prm->objective, (double)prm->tol_f, (double)prm->lambda0, (double)prm->box_frac,
+                       (double)prm->dt_ms, opc_inout, rmse_out, mae_out, iters_out, decisions_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return opmm_rt::hip_fail(ctx, e, "polish_kernel");
+    return OPMM_OK;
+}
+
+}  // extern "C"

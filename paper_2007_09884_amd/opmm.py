@@ -43,6 +43,14 @@ class NmParams(ctypes.Structure):
                 ("box_frac", ctypes.c_float), ("dt_ms", ctypes.c_float)]
 
 
+class PolishParams(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("objective", ctypes.c_int32), ("tol_f", ctypes.c_float),
+                ("lambda0", ctypes.c_float), ("box_frac", ctypes.c_float), ("dt_ms", ctypes.c_float)]
+
+
+OBJ_RMSE, OBJ_MAE = 0, 1
+
+
 class OpmmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("opmm error %d: %s" % (code, msg))
@@ -105,6 +113,10 @@ def _load():
         "opmm_fit_learned": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(FitParams),
                                             ctypes.POINTER(FitParams), f, vp, vp, vp, vp, ctypes.POINTER(i32), vp]),
         "opmm_surrogate_load": (ctypes.c_int, [vp, ctypes.c_char_p]),
+        "opmm_polish_params_default": (None, [ctypes.POINTER(PolishParams)]),
+        "opmm_sensitivity": (ctypes.c_int, [vp, vp, i32, vp, f, vp, vp, vp]),
+        "opmm_polish": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(PolishParams), i32, vp, vp, vp, vp,
+                                       vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -122,6 +134,16 @@ def fit_params(**kw) -> FitParams:
     for k, v in kw.items():
         if not hasattr(p, k):
             raise TypeError("unknown fit parameter %r" % k)
+        setattr(p, k, v)
+    return p
+
+
+def polish_params(**kw) -> PolishParams:
+    p = PolishParams()
+    lib.opmm_polish_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError("unknown polish parameter %r" % k)
         setattr(p, k, v)
     return p
 
@@ -236,6 +258,20 @@ class Context:
         self._check(lib.opmm_fit_nm(self._h, _ptr(pos), pos.numel(), recs.ctypes.data_as(ctypes.c_void_p),
                                     recs.shape[0], ctypes.byref(params), _ptr(seed_opc), _ptr(opc_out),
                                     _ptr(rmse_out), _ptr(iters_out), _ptr(decisions_out), _ptr(status_out),
+                                    _stream(stream)))
+
+    def sensitivity(self, recs, opc, theta_out, jac_out, dt_ms=1.0, stream=None):
+        """Trajectories (FP64 [sum T]) and d theta / d p (FP64 [sum T][18]) at opc (device [S][18])."""
+        recs = np.ascontiguousarray(recs, SACCADE_DTYPE)
+        self._check(lib.opmm_sensitivity(self._h, recs.ctypes.data_as(ctypes.c_void_p), recs.shape[0], _ptr(opc),
+                                         ctypes.c_float(dt_ms), _ptr(theta_out), _ptr(jac_out), _stream(stream)))
+
+    def polish(self, pos, recs, params: PolishParams, opc_inout, rmse_out, mae_out=None, iters_out=None,
+               decisions_out=None, model=18, stream=None):
+        recs = np.ascontiguousarray(recs, SACCADE_DTYPE)
+        self._check(lib.opmm_polish(self._h, _ptr(pos), pos.numel(), recs.ctypes.data_as(ctypes.c_void_p),
+                                    recs.shape[0], ctypes.byref(params), int(model), _ptr(opc_inout),
+                                    _ptr(rmse_out), _ptr(mae_out), _ptr(iters_out), _ptr(decisions_out),
                                     _stream(stream)))
 
     def ivt_extract(self, gaze, pos_out, dt_ms=1.0, vel_thresh=30.0, min_dur=6.0, min_amp=0.0, max_T=MAX_T,

@@ -37,6 +37,9 @@ def test_struct_layouts_match_header():
     assert opmm.SACCADE_DTYPE.itemsize == 40
     assert ctypes.sizeof(opmm.FitParams) == 36
     assert ctypes.sizeof(opmm.ServeParams) == 96 and ctypes.sizeof(opmm.NmParams) == 20
+    assert ctypes.sizeof(opmm.PolishParams) == 24
+    q = opmm.polish_params()
+    assert (q.max_iter, q.objective, q.lambda0, q.box_frac, q.dt_ms) == (20, 0, np.float32(1e-3), 0.25, 1.0)
     p = opmm.fit_params()
     assert (p.n_cand, p.n_rounds, p.box_frac, p.w_init_frac, p.shrink, p.dt_ms, p.mode, p.tile, p.model) == \
         (4096, 1, 0.25, 1.0, 0.5, 1.0, 0, -1, 18)

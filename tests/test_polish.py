@@ -1,0 +1,366 @@
+"""Gradient-based polish (the gradient estimation of Section 5, after the box search).
+
+CPU: the oracle's sensitivities (central differences of the RK4 trajectory) and its Levenberg-Marquardt
+are pinned to what the mathematics fixes -- the force-scale gauge of the plant, the affine dependence of
+the trajectory on N_C_FIX and the pulse heights, the Frechet derivative of the matrix exponential for a
+pure-pulse window, the damped normal equations solved by numpy, and recovery of a noise-free truth.
+GPU: exact forward sensitivities (dual numbers through the exact discretisation) against the oracle's,
+and the GPU polish replayed decision by decision against the oracle's."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from paper_2007_09884_amd import synth
+from workload import make_batch, records
+
+FORCE = [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 14, 15, 16]   # components measured in grams (force units)
+
+
+def _p(seed, dur=43.0):
+    rng = np.random.default_rng(seed)
+    return oracle.nominal(dur) * rng.uniform(0.8, 1.2, 18)
+
+
+# --------------------------------------------------------------------------- CPU pins
+
+def test_jacobian_gauge_direction_is_null():
+    """Scaling every force-unit component by (1 + eps) leaves theta unchanged: sum_j p_j dtheta/dp_j = 0."""
+    for seed in range(3):
+        p = _p(seed)
+        _, J = oracle.jacobian(p, 12.0, 70)
+        terms = J[:, FORCE] * p[FORCE]
+        assert np.abs(terms.sum(1)).max() <= 1e-6 * np.abs(terms).sum(1).max()
+        assert np.abs(terms).max() > 1.0   # the individual terms are not small
+
+
+def test_jacobian_affine_columns():
+    """theta is affine in N_C_FIX and both pulse heights: the derivative equals a large finite difference."""
+    p = _p(7)
+    th, J = oracle.jacobian(p, 15.0, 80)
+    for j in (14, 15, 16):
+        d = 0.2 * p[j]
+        q1, q2 = p.copy(), p.copy()
+        q1[j] += d
+        q2[j] -= d
+        fd = (oracle.simulate(q1, 15.0, 80) - oracle.simulate(q2, 15.0, 80)) / (2 * d)
+        fwd = (oracle.simulate(q1, 15.0, 80) - th) / d
+        scale = np.abs(fd).max()
+        assert np.abs(J[:, j] - fd).max() <= 1e-7 * scale, j
+        assert np.abs(fwd - fd).max() <= 1e-9 * scale * 1e3, j   # affine: one-sided == central
+
+
+def test_jacobian_matches_expm_frechet_in_the_pulse():
+    """With the pulse covering the window, theta(t) = e1 . [x1 + expm(A t)(x0 - x1)] and B_P, J enter A
+    only, so d theta / dp = e1 . L_expm(A t, (dA/dp) t)(x0 - x1) (scipy's Frechet derivative)."""
+    p = _p(11)
+    p[17] = 500.0                         # pulse longer than the window
+    T, amp = 40, 10.0
+    _, J = oracle.jacobian(p, amp, T)
+    lv = oracle.control_levels(p, amp)
+    tau_a, tau_n = p[10] * 1e-3, p[11] * 1e-3
+    A = np.stack([oracle.rhs(p, np.eye(6)[i], 0.0, 0.0, tau_a, tau_n) for i in range(6)], 1)
+    x0 = oracle.equilibrium(p, lv[0], lv[1])
+    x1 = oracle.equilibrium(p, lv[2], lv[3])
+    dA = {6: np.zeros((6, 6)), 9: np.zeros((6, 6))}
+    dA[6][1, 1] = -1.0 / p[9]             # omega' = (... - B_P omega ...) / J
+    dA[9][1, :] = -A[1, :] / p[9]
+    for j, E in dA.items():
+        ref = np.array([0.0] + [
+            (scipy.linalg.expm_frechet(A * k * 1e-3, E * k * 1e-3, compute_expm=False) @ (x0 - x1))[0]
+            for k in range(1, T)])
+        assert np.abs(J[:, j] - ref).max() <= 1e-6 * np.abs(ref).max() + 1e-12, j
+
+
+def test_damped_solve_matches_numpy():
+    rng = np.random.default_rng(5)
+    n = 18
+    M = rng.standard_normal((40, n))
+    H = M.T @ M
+    g = rng.standard_normal(n)
+    held = np.zeros(n, np.int32)
+    held[[3, 11]] = 1
+    lam = 0.37
+    d = oracle.damped_solve(H, g, lam, held)
+    free = np.nonzero(held == 0)[0]
+    Hf = H[np.ix_(free, free)] + lam * np.diag(np.diag(H)[free])
+    ref = np.zeros(n)
+    ref[free] = np.linalg.solve(Hf, -g[free])
+    assert np.allclose(d, ref, rtol=1e-10, atol=1e-12)
+    assert oracle.damped_solve(-np.eye(3), np.ones(3), 0.0) is None
+
+
+def test_polish_recovers_noise_free_truth():
+    """Noise-free target from a known OPC, start 2% away: the polish drives the RMSE to ~0 and never
+    raises the objective."""
+    rng = np.random.default_rng(9)
+    p_true = _p(21)
+    T, amp = 80, 10.0
+    pos = oracle.simulate(p_true, amp, T).astype(np.float32)[:, None]
+    x0 = (p_true * (1 + 0.02 * rng.uniform(-1, 1, 18))).astype(np.float32)
+    r = oracle.polish(pos, amp, 0.0, 43.0, x0, max_iter=40, tol_f=0.0)
+    th0 = oracle.simulate(x0.astype(np.float64), amp, T)
+    rmse0 = np.sqrt(np.mean((th0 - pos[:, 0]) ** 2))
+    rmse = np.sqrt(r["f"] / T)
+    assert rmse0 > 1e-2 and rmse < 1e-5, (rmse0, rmse)
+    assert np.all(np.diff(r["fhist"]) <= 0)
+
+
+@pytest.mark.parametrize("model", [18, 9])
+def test_polish_converges_quadratically(model):
+    """Gauss-Newton on a zero-residual problem converges quadratically: from 1% away, a few iterations
+    take the objective down by >= 1e8, to the FP32 rounding floor of the OPC (a Jacobian off by a factor anywhere only converges linearly).
+    2-D trace at an oblique direction, so both channels enter."""
+    rng = np.random.default_rng(31 + model)
+    p_true = _p(41, dur=50.0)
+    if model == 9:
+        p_true[1], p_true[3] = p_true[0], p_true[2]
+        fixed = [10, 11, 12, 13, 15, 16, 17]
+        p_true[fixed] = oracle.nominal(50.0)[fixed]
+    p_true = p_true.astype(np.float32).astype(np.float64)
+    T, amp, phi = 90, 14.0, 37.0
+    th = oracle.simulate(p_true, amp, T)
+    u = np.array([np.cos(np.deg2rad(phi)), np.sin(np.deg2rad(phi))])
+    pos = (th[:, None] * u[None, :]).astype(np.float32)
+    x0 = p_true * (1 + 0.01 * rng.uniform(-1, 1, 18))
+    if model == 9:
+        x0[1], x0[3] = x0[0], x0[2]
+        x0[fixed] = p_true[fixed]
+    r = oracle.polish(pos, amp, phi, 50.0, x0.astype(np.float32), model=model, max_iter=4, tol_f=0.0)
+    assert r["f"] < 1e-8 * r["fhist"][0], (r["f"], r["fhist"])
+
+
+def test_polish_rejected_steps_do_not_move():
+    """Near the minimum some iterations find no better trial: those keep the point (the next iteration
+    starts from the same objective) and the objective never rises."""
+    p_true = _p(43).astype(np.float32)
+    pos = oracle.simulate(p_true.astype(np.float64), 10.0, 80).astype(np.float32)[:, None]
+    r = oracle.polish(pos, 10.0, 0.0, 43.0, p_true, max_iter=12, tol_f=0.0)
+    rej = np.nonzero(r["own"][:-1] == -1)[0]
+    assert rej.size >= 1
+    assert np.all(r["fhist"][rej + 1] == r["fhist"][rej])
+    assert np.all(np.diff(r["fhist"]) <= 0)
+
+
+def test_polish_absolute_objective_and_model9():
+    b, traces = make_batch(2, "full", seed=synth.BASE_SEED + 301)
+    s = 0
+    pos = traces[s].copy()
+    pos[10:13] += 2.0                    # a few outlying samples
+    nom = oracle.nominal(b["dur_ms"][s])
+    x0 = nom.astype(np.float32)
+    l2 = oracle.polish(pos, b["amp"][s], b["dir_deg"][s], b["dur_ms"][s], x0, max_iter=15)
+    l1 = oracle.polish(pos, b["amp"][s], b["dir_deg"][s], b["dur_ms"][s], l2["opc"], objective=1, max_iter=15)
+
+    def mae(opc):
+        th = oracle.simulate(opc.astype(np.float64), b["amp"][s], pos.shape[0])
+        return oracle.cost(th, pos, b["dir_deg"][s])[1]
+    assert mae(l1["opc"]) < mae(l2["opc"]) < mae(x0)
+    m9 = oracle.polish(pos, b["amp"][s], b["dir_deg"][s], b["dur_ms"][s], x0, model=9, max_iter=10)
+    o = m9["opc"]
+    assert o[1] == o[0] and o[3] == o[2]
+    fixed = [10, 11, 12, 13, 15, 16, 17]
+    assert np.array_equal(o[fixed], x0[fixed])
+    assert m9["f"] < l2["fhist"][0]
+
+
+@pytest.mark.parametrize("scale", [1.4, 0.6])
+def test_polish_stays_in_the_box(scale):
+    """Truth with PW and tau_DE_AG outside the +/-25% box: the result sits on the box face, never beyond."""
+    p_true = oracle.nominal(43.0)
+    p_true[[12, 17]] *= scale
+    pos = oracle.simulate(p_true, 10.0, 80).astype(np.float32)[:, None]
+    r = oracle.polish(pos, 10.0, 0.0, 43.0, oracle.nominal(43.0).astype(np.float32), max_iter=15)
+    rel = r["opc"] / oracle.nominal(43.0)
+    assert np.all(rel >= 0.75 * (1 - 1e-7)) and np.all(rel <= 1.25 * (1 + 1e-7))
+    face = 1.25 if scale > 1 else 0.75
+    assert np.any(np.abs(rel - face) < 1e-6)   # the bound is active
+    assert np.all(np.diff(r["fhist"]) <= 0)
+
+
+def test_polish_reaches_a_stationary_point():
+    """On a noisy 2-D trace the polish ends where the objective's own gradient (central differences of
+    the RK4 cost, independent of the Jacobian the polish uses) has all but vanished."""
+    b, traces = make_batch(1, "full", seed=synth.BASE_SEED + 303)
+    amp, phi, dur = b["amp"][0], b["dir_deg"][0], b["dur_ms"][0]
+    pos = traces[0]
+    nom = oracle.nominal(dur)
+
+    def grad(opc):
+        g = np.zeros(18)
+        for j in range(18):
+            h = 1e-6 * opc[j]
+            q1, q2 = opc.astype(np.float64), opc.astype(np.float64)
+            q1[j] += h
+            q2[j] -= h
+            f1 = oracle.cost(oracle.simulate(q1, amp, pos.shape[0]), pos, phi)[0] ** 2
+            f2 = oracle.cost(oracle.simulate(q2, amp, pos.shape[0]), pos, phi)[0] ** 2
+            g[j] = (f1 - f2) / (2 * h) * nom[j]
+        return g
+    x0 = (nom * np.random.default_rng(2).uniform(0.9, 1.1, 18)).astype(np.float32)
+    r = oracle.polish(pos, amp, phi, dur, x0, max_iter=40, tol_f=0.0)
+    rel = r["opc"] / nom
+    inside = (rel > 0.75 + 1e-4) & (rel < 1.25 - 1e-4)
+    g0, g1 = grad(x0), grad(r["opc"])
+    assert np.abs(g1[inside]).max() <= 1e-3 * np.abs(g0).max(), (g1, g0)
+
+
+# --------------------------------------------------------------------------- GPU
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def opmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_09884_amd import opmm as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(opmm):
+    c = opmm.Context(0)
+    yield c
+    c.close()
+
+
+def _box_points(b, n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(b["S"]):
+        nom = oracle.nominal(b["dur_ms"][s])
+        out.append((nom * rng.uniform(0.75, 1.25, (n, 18))).astype(np.float32))
+    return out
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("kind", ["tiny", "full"])
+def test_sensitivity_matches_oracle(ctx, opmm, kind):
+    b, _ = make_batch(3, kind, seed=synth.BASE_SEED + 311)
+    pts = _box_points(b, 2, 3)
+    recs = np.concatenate([records(b, opmm)] * 2)
+    opc = np.concatenate([pts[s][i:i + 1] for i in range(2) for s in range(3)])
+    Ts = recs["T"].astype(np.int64)
+    th = torch.zeros(int(Ts.sum()), dtype=torch.float64, device="cuda")
+    jac = torch.zeros(int(Ts.sum()), 18, dtype=torch.float64, device="cuda")
+    ctx.sensitivity(recs, torch.from_numpy(opc).cuda(), th, jac)
+    th, jac = th.cpu().numpy(), jac.cpu().numpy()
+    off = 0
+    for i, r in enumerate(recs):
+        T = int(r["T"])
+        t_ref, J_ref = oracle.jacobian(opc[i].astype(np.float64), float(r["amp_deg"]), T)
+        assert np.abs(th[off:off + T] - t_ref).max() <= 1e-8, i
+        scale = np.abs(J_ref).max(0) + 1e-30
+        err = np.abs(jac[off:off + T] - J_ref).max(0) / scale
+        assert err.max() <= 1e-6, (i, err)
+        off += T
+
+
+@pytest.mark.gpu
+def test_sensitivity_gauge_at_full_size(ctx, opmm):
+    """At the full configuration's size (256 saccades, at their true OPC) the exact sensitivities satisfy
+    the force-scale gauge identity to rounding."""
+    b, _ = make_batch(256, "full", seed=synth.BASE_SEED + 313)
+    recs = records(b, opmm)
+    opc = np.stack([oracle.true_opc(b["mult"][s], b["dur_ms"][s]) for s in range(256)]).astype(np.float32)
+    Ts = recs["T"].astype(np.int64)
+    th = torch.zeros(int(Ts.sum()), dtype=torch.float64, device="cuda")
+    jac = torch.zeros(int(Ts.sum()), 18, dtype=torch.float64, device="cuda")
+    ctx.sensitivity(recs, torch.from_numpy(opc).cuda(), th, jac)
+    jac = jac.cpu().numpy()
+    s_of_row = np.repeat(np.arange(256), Ts)
+    terms = jac[:, FORCE] * opc[s_of_row][:, FORCE]
+    assert np.abs(terms.sum(1)).max() <= 1e-9 * np.abs(terms).sum(1).max()
+
+
+def _polish(ctx, opmm, b, traces, prm, start, model=18):
+    S = b["S"]
+    recs = records(b, opmm)
+    pos = torch.from_numpy(opmm.pack_traces(traces)).cuda()
+    opc = torch.from_numpy(np.ascontiguousarray(start, np.float32)).cuda()
+    rm = torch.zeros(S, device="cuda"); ma = torch.zeros(S, device="cuda")
+    it = torch.zeros(S, dtype=torch.int32, device="cuda")
+    dec = torch.full((S, max(prm.max_iter, 1)), -2, dtype=torch.int8, device="cuda")
+    ctx.polish(pos, recs, prm, opc, rm, ma, it, dec, model=model)
+    torch.cuda.synchronize()
+    return opc.cpu().numpy(), rm.cpu().numpy(), ma.cpu().numpy(), it.cpu().numpy(), dec.cpu().numpy()
+
+
+def _fit(ctx, opmm, b, traces, n_cand, rounds, model=18):
+    S = b["S"]
+    recs = records(b, opmm)
+    pos = torch.from_numpy(opmm.pack_traces(traces)).cuda()
+    opc = torch.zeros(S, 18, device="cuda"); rm = torch.zeros(S, device="cuda")
+    ctx.fit(pos, recs, opmm.fit_params(n_cand=n_cand, n_rounds=rounds, model=model), opc, rm)
+    torch.cuda.synchronize()
+    return opc.cpu().numpy(), rm.cpu().numpy()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("kind,objective", [("tiny", 0), ("full", 0), ("full", 1)])
+def test_polish_replays_against_oracle(ctx, opmm, kind, objective):
+    b, traces = make_batch(3, kind, seed=synth.BASE_SEED + 321)
+    start, _ = _fit(ctx, opmm, b, traces, 4096, 2)
+    n = 6
+    prm = opmm.polish_params(max_iter=n, tol_f=0.0, objective=objective)
+    opc, rm, ma, it, dec = _polish(ctx, opmm, b, traces, prm, start)
+    assert np.all(it == n)
+    for s in range(b["S"]):
+        r = oracle.polish(traces[s], b["amp"][s], b["dir_deg"][s], b["dur_ms"][s], start[s],
+                          objective=objective, forced=dec[s, :n])
+        f0 = r["fhist"][0]
+        differ = r["own"] != dec[s, :n]
+        assert np.all(r["margin"][differ] < 1e-6 * f0), (s, np.nonzero(differ), r["margin"][differ])
+        T, C = traces[s].shape
+        if objective == 0:
+            assert abs(np.sqrt(r["f"] / (T * C)) - rm[s]) <= 1e-6 * rm[s], s
+        else:
+            assert abs(r["f"] / (T * C) - ma[s]) <= 1e-6 * ma[s], s
+        assert np.abs(r["opc"].astype(np.float64) / opc[s] - 1).max() <= 1e-3, s
+
+
+@pytest.mark.gpu
+def test_polish_improves_the_box_search(ctx, opmm):
+    b, traces = make_batch(16, "full", seed=synth.BASE_SEED + 331)
+    start, rm0 = _fit(ctx, opmm, b, traces, 4096, 4)
+    _, rm_big = _fit(ctx, opmm, b, traces, 65536, 10)
+    opc, rm, ma, it, dec = _polish(ctx, opmm, b, traces, opmm.polish_params(), start)
+    assert np.all(rm <= rm0 * (1 + 1e-7))
+    assert rm.mean() < rm0.mean() and rm.mean() <= rm_big.mean() * (1 + 1e-4), (rm.mean(), rm0.mean(), rm_big.mean())
+    assert np.all((it >= 1) & (it <= 20))
+
+
+@pytest.mark.gpu
+def test_polish_model9_and_mae(ctx, opmm):
+    b, traces = make_batch(4, "full", seed=synth.BASE_SEED + 341)
+    start, _ = _fit(ctx, opmm, b, traces, 4096, 3, model=9)
+    opc, rm, ma, it, _ = _polish(ctx, opmm, b, traces, opmm.polish_params(max_iter=10), start, model=9)
+    fixed = [10, 11, 12, 13, 15, 16, 17]
+    assert np.array_equal(opc[:, fixed], start[:, fixed])
+    assert np.array_equal(opc[:, 1], opc[:, 0]) and np.array_equal(opc[:, 3], opc[:, 2])
+    start18, _ = _fit(ctx, opmm, b, traces, 4096, 3)
+    _, rm1, ma1, _, _ = _polish(ctx, opmm, b, traces, opmm.polish_params(max_iter=0), start18)
+    _, rm2, ma2, _, _ = _polish(ctx, opmm, b, traces, opmm.polish_params(objective=1), start18)
+    assert np.all(ma2 <= ma1 * (1 + 1e-7)) and ma2.mean() < ma1.mean()
+
+
+@pytest.mark.gpu
+def test_polish_edges(ctx, opmm):
+    b, traces = make_batch(2, "full", seed=synth.BASE_SEED + 351)
+    start = np.stack([oracle.nominal(d) * 1.3 for d in b["dur_ms"]]).astype(np.float32)  # outside the box
+    opc, rm, ma, it, dec = _polish(ctx, opmm, b, traces, opmm.polish_params(max_iter=0), start)
+    nom = np.stack([oracle.nominal(d) for d in b["dur_ms"]])
+    assert np.allclose(opc / nom, 1.25, rtol=1e-6) and np.all(it == 0)
+    for s in range(2):
+        th = oracle.simulate(opc[s].astype(np.float64), b["amp"][s], traces[s].shape[0])
+        r, m = oracle.cost(th, traces[s], b["dir_deg"][s])
+        assert abs(r - rm[s]) <= 1e-6 * r and abs(m - ma[s]) <= 1e-6 * m
+    bad = [t.copy() for t in traces]
+    bad[1][5, 0] = np.nan
+    opc, rm, ma, it, dec = _polish(ctx, opmm, b, bad, opmm.polish_params(max_iter=3), start)
+    assert np.isnan(rm[1]) and np.all(np.isnan(opc[1])) and np.isfinite(rm[0])
+    with pytest.raises(opmm.OpmmError):
+        _polish(ctx, opmm, b, traces, opmm.polish_params(objective=7), start)
+    with pytest.raises(opmm.OpmmError):
+        _polish(ctx, opmm, b, traces, opmm.polish_params(), start, model=5)
