@@ -6,8 +6,10 @@ sequence D = 2.2 ms/deg * A + 21 ms sampled at 1 kHz (T = ceil(D)), traces made
 from true OPCs = nominal * U[0.8, 1.2] plus N(0, 0.05^2) deg noise.  A step is
 one whole estimation of the batch: 65536 candidates per saccade per round, 10
 rounds with the box halving each round, argmin, final report -- the fused
-kernels of libopmm, launched as one captured HIP graph (persistent work-queue
-kernel).  Inputs are resident in HBM before timing starts.
+kernels of libopmm, launched as one captured HIP graph.  By default the tile
+shape is autotuned for both launch modes (one kernel per round, or one
+persistent work-queue kernel for all rounds) and the faster is timed.  Inputs
+are resident in HBM before timing starts.
 
 Prints one JSON line.  value = candidate simulations per second for the whole
 job; saccades fitted per second is reported beside it.
@@ -37,9 +39,12 @@ def parse():
     ap.add_argument("--saccades", type=int, default=256)
     ap.add_argument("--n-cand", type=int, default=65536)
     ap.add_argument("--rounds", type=int, default=10)
-    ap.add_argument("--mode", choices=["persistent", "rounds"], default="persistent")
+    ap.add_argument("--mode", choices=["auto", "persistent", "rounds"], default="rounds",
+                    help="auto: autotune the tile for both launch modes and keep the faster")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--tile", type=int, default=-2, help="kernel shape index; -1 default, -2 autotune")
+    ap.add_argument("--tile", type=int, default=-1, help="kernel shape index; -1 library default, -2 autotune")
+    ap.add_argument("--no-autotune-leg", action="store_true",
+                    help="skip the side leg that autotunes both launch modes and times their picks")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
@@ -48,6 +53,7 @@ def parse():
     ap.add_argument("--seed-cand", type=int, default=1024)
     ap.add_argument("--seed-rounds", type=int, default=3)
     ap.add_argument("--seed-width", type=float, default=0.25, help="round-0 half-width / box half-width")
+    ap.add_argument("--polish-iter", type=int, default=4, help="Levenberg-Marquardt iterations after the seeded refine")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-nm", action="store_true")
     ap.add_argument("--nm-iter", type=int, default=2000)
@@ -56,6 +62,34 @@ def parse():
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000")
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="arrival window per rate")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ("paper_2007_09884_amd/csrc/plant.hpp", "paper_2007_09884_amd/csrc/opmm.hip",
+                  "paper_2007_09884_amd/csrc/runtime.hpp")
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(mode, tile_name):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading), if that summary was taken on
+    the same launch mode and tile shape from the current kernel sources; else None."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
+        for line in open(path):
+            if line.startswith("traffic_per_launch_bytes"):
+                kv = dict(t.split("=", 1) for t in line.split()[1:])
+                if (kv.get("mode") == mode and kv.get("tile") == tile_name
+                        and kv.get("sources_sha256") == sources_digest()):
+                    return int(line.split()[0].split("=")[1])
+    return None
 
 
 def gpu_targets(ctx, opmm, torch, b):
@@ -114,6 +148,25 @@ def surrogate_leg(a, ctx, opmm, torch, synth, keep=False):
     torch.cuda.synchronize()
     seed_s = time.perf_counter() - t0
     rp, rs = rm_plain.cpu().numpy(), rm_seed.cpu().numpy()
+    # gradient polish (exact sensitivities + Levenberg-Marquardt) after the seeded refine, and after the
+    # plain search for reference
+    pprm = opmm.polish_params(max_iter=a.polish_iter)
+    opc_p = opc.clone()
+    rm_sp = torch.zeros(S, device="cuda")
+    its = torch.zeros(S, dtype=torch.int32, device="cuda")
+    ctx.polish(pos, recs, pprm, opc_p, rm_sp, iters_out=its)  # warm-up
+    opc_p.copy_(opc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.polish(pos, recs, pprm, opc_p, rm_sp, iters_out=its)
+    torch.cuda.synchronize()
+    pol_s = time.perf_counter() - t0
+    rsp, itn = rm_sp.cpu().numpy(), its.cpu().numpy()
+    opc_pp = torch.zeros(S, 18, device="cuda")
+    ctx.fit(pos, recs, plain, opc_pp, rm_plain)
+    rm_pp = torch.zeros(S, device="cuda")
+    ctx.polish(pos, recs, pprm, opc_pp, rm_pp)
+    rpp = rm_pp.cpu().numpy()
     if not keep:
         sg.close()
         sg = None
@@ -126,8 +179,16 @@ def surrogate_leg(a, ctx, opmm, torch, synth, keep=False):
                           "fallback_rmse_deg": 1.5 * synth.SIGMA, "fallbacks": int(n_fb),
                           "saccades_fitted_per_s": S / seed_s, "mean_rmse_deg": float(rs.mean()),
                           "median_rmse_deg": float(np.median(rs))},
-            "speedup_saccades_per_s": plain_s / seed_s,
-            "rmse_ratio_surrogate_over_plain": float(rs.mean() / rp.mean())}
+            "surrogate_polished": {"polish_max_iter": a.polish_iter, "mean_polish_iters": float(itn.mean()),
+                                   "saccades_fitted_per_s": S / (seed_s + pol_s),
+                                   "polish_seconds": pol_s, "mean_rmse_deg": float(rsp.mean()),
+                                   "median_rmse_deg": float(np.median(rsp)),
+                                   "not_worse_than_plain": float(np.mean(rsp <= rp * (1 + 1e-6)))},
+            "plain_polished": {"mean_rmse_deg": float(rpp.mean()), "median_rmse_deg": float(np.median(rpp))},
+            "speedup_saccades_per_s": plain_s / (seed_s + pol_s),
+            "rmse_ratio_surrogate_over_plain": float(rsp.mean() / rp.mean()),
+            "refine_only": {"speedup_saccades_per_s": plain_s / seed_s,
+                            "rmse_ratio_surrogate_over_plain": float(rs.mean() / rp.mean())}}
 
 
 def nm_leg(a, ctx, opmm, torch, pos, recs, rm_box, box_s):
@@ -239,15 +300,44 @@ def main():
     pos = gpu_targets(ctx, opmm, torch, b)
     recs = opmm.saccade_records(b["T"], 2, b["amp"], b["dir_deg"], b["dur_ms"], b["seed"])
     S, N, R = a.saccades, a.n_cand, a.rounds
-    mode = opmm.FIT_PERSISTENT if a.mode == "persistent" else opmm.FIT_ROUNDS
-    prm = opmm.fit_params(n_cand=N, n_rounds=R, mode=mode)
-    if a.tile == -2:
-        prm.tile = ctx.autotune(pos, recs, prm)
-    else:
-        prm.tile = a.tile
     opc = torch.zeros(S, 18, device="cuda")
     rmse = torch.zeros(S, device="cuda")
     status = torch.zeros(S, dtype=torch.int32, device="cuda")
+    modes = {"persistent": opmm.FIT_PERSISTENT, "rounds": opmm.FIT_ROUNDS}
+
+    def time_plan(p, reps=2):
+        """ms of one captured step with fit parameters p, after a warm-up launch"""
+        pl = ctx.plan(pos, recs, p, opc, rmse, None, status)
+        pl.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            pl.launch()
+        torch.cuda.synchronize()
+        pl.close()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    def autotuned(name):
+        p = opmm.fit_params(n_cand=N, n_rounds=R, mode=modes[name])
+        p.tile = ctx.autotune(pos, recs, p)
+        return p
+
+    tuned = {}
+    if a.mode == "auto" or not a.no_autotune_leg:
+        # the project's autotuner on both launch modes, each pick timed on a whole step
+        for name in ("persistent", "rounds"):
+            p = autotuned(name)
+            tuned[name] = {"tile": opmm.tile_names()[p.tile], "ms_per_step": time_plan(p), "params": p}
+    if a.mode == "auto":
+        a.mode = min(tuned, key=lambda k: tuned[k]["ms_per_step"])
+        prm = tuned[a.mode]["params"]
+    else:
+        prm = opmm.fit_params(n_cand=N, n_rounds=R, mode=modes[a.mode])
+        prm.tile = autotuned(a.mode).tile if a.tile == -2 else a.tile
+    if prm.tile < 0:
+        prm.tile = opmm.lib.opmm_tile_default()
+    for v in tuned.values():
+        del v["params"]
     torch.cuda.synchronize()
 
     if a.no_graph:
@@ -278,6 +368,9 @@ def main():
     value = sims * a.steps / wall
     sum_T = int(np.sum(b["T"]))
     flop = FLOP_PER_CAND_SAMPLE * N * R * sum_T
+    # one kernel per round (rounds mode) or one for the whole step (persistent); the HIP events bracket
+    # the captured step, so the per-launch time includes the small kernels' ~1 %
+    n_launch = R if a.mode == "rounds" else 1
     achieved = flop / (launch_ms * 1e-3) / 1e12
     st = status.cpu().numpy()
     rm = rmse.cpu().numpy()
@@ -298,16 +391,22 @@ def main():
         "config": {"workload": "full estimation: %d 2-D saccades (A~U[2,30] deg, D=2.2A+21 ms, 1 kHz), "
                                "%d candidates x %d halving rounds, plain box search" % (S, N, R),
                    "saccades": S, "n_cand": N, "rounds": R, "mean_T": float(np.mean(b["T"])),
-                   "mode": a.mode, "graph": not a.no_graph, "tile": opmm.tile_names()[prm.tile] if prm.tile >= 0 else "default"},
+                   "mode": a.mode, "graph": not a.no_graph, "tile": opmm.tile_names()[prm.tile]},
         "saccades_fitted_per_s": S * a.steps / wall,
         "mean_final_rmse_deg": float(np.mean(rm)),
         "status_nonzero": int(np.count_nonzero(st)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "fit_persistent_kernel (one launch per step; prep/init/report kernels add <1%)",
-                     "launch_ms": launch_ms, "algorithmic_flop_per_launch": flop,
+                     "frac": achieved / ALU_PEAK_TFLOPS,
+                     "traffic": profiled_traffic(a.mode, opmm.tile_names()[prm.tile]),
+                     "kernel": ("fit_persistent_kernel (one launch per step" if a.mode == "persistent" else
+                                "fit_round_kernel (%d launches per step" % R) +
+                               "; launch_ms is the whole captured step: prep/init/refine/report kernels add ~1%)",
+                     "launch_ms": launch_ms / n_launch, "launches_per_step": n_launch,
+                     "algorithmic_flop_per_launch": flop // n_launch,
                      "frac_of_published_fp32_157": achieved / PUBLISHED_FP32_PEAK},
     }
+    if tuned:
+        out["autotune"] = tuned
     if not a.no_nm:
         out["nelder_mead"] = nm_leg(a, ctx, opmm, torch, pos, recs, rm, ms_per_step * 1e-3)
     if not a.no_surrogate:

@@ -190,9 +190,12 @@ int opmm_plan_destroy(opmm_plan* plan);
  * Writes the chosen shape index to *tile_out (host, nullable). */
 int opmm_autotune(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs,
                   int32_t S, const opmm_fit_params* params, int32_t* tile_out, void* stream);
-/* Number of kernel shapes and a description of shape i (host string). */
+/* Number of kernel shapes, a description of shape i (host string), and the
+ * shape used for tile = -1 on a context that has not been autotuned (the
+ * fastest per-round shape of a sweep on the full-estimation workload). */
 int opmm_tile_count(void);
 const char* opmm_tile_name(int i);
+int opmm_tile_default(void);
 
 
 /* ------------------------------------------------------------------------

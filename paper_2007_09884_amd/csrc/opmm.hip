@@ -541,9 +541,13 @@ const Shape kShapes[] = {
     {64, 16, 1, "tpb64_pass16_unroll1"},
     {256, 16, 1, "tpb256_pass16_unroll1"},
     {128, 32, 1, "tpb128_pass32_unroll1"},
+    {256, 8, 4, "tpb256_pass8_unroll4"},
+    {256, 4, 8, "tpb256_pass4_unroll8"},
+    {64, 16, 4, "tpb64_pass16_unroll4"},
+    {128, 8, 4, "tpb128_pass8_unroll4"},
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
-constexpr int kDefaultShape = 5;  // fastest per-round shape on the full-estimation workload (sweep)
+constexpr int kDefaultShape = 9;  // fastest per-round shape on the full-estimation workload (sweep)
 
 struct FitLaunch {
     const SacDev* sacs;
@@ -584,7 +588,11 @@ hipError_t launch_fit_kernel(int shape, const FitLaunch& L, bool persistent, int
     case 5: return launch_shape<256, 4, 4>(L, persistent, round, st);
     case 6: return launch_shape<64, 16, 1>(L, persistent, round, st);
     case 7: return launch_shape<256, 16, 1>(L, persistent, round, st);
-    default: return launch_shape<128, 32, 1>(L, persistent, round, st);
+    case 8: return launch_shape<128, 32, 1>(L, persistent, round, st);
+    case 9: return launch_shape<256, 8, 4>(L, persistent, round, st);
+    case 10: return launch_shape<256, 4, 8>(L, persistent, round, st);
+    case 11: return launch_shape<64, 16, 4>(L, persistent, round, st);
+    default: return launch_shape<128, 8, 4>(L, persistent, round, st);
     }
 }
 
@@ -609,7 +617,11 @@ int shape_blocks_per_cu(int shape)
     case 5: return persistent_blocks_per_cu<256, 4, 4>();
     case 6: return persistent_blocks_per_cu<64, 16, 1>();
     case 7: return persistent_blocks_per_cu<256, 16, 1>();
-    default: return persistent_blocks_per_cu<128, 32, 1>();
+    case 8: return persistent_blocks_per_cu<128, 32, 1>();
+    case 9: return persistent_blocks_per_cu<256, 8, 4>();
+    case 10: return persistent_blocks_per_cu<256, 4, 8>();
+    case 11: return persistent_blocks_per_cu<64, 16, 4>();
+    default: return persistent_blocks_per_cu<128, 8, 4>();
     }
 }
 
@@ -1029,6 +1041,7 @@ int opmm_destroy(opmm_ctx* ctx)
 const char* opmm_last_error(const opmm_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
 
 int opmm_tile_count(void) { return kNumShapes; }
+int opmm_tile_default(void) { return kDefaultShape; }
 
 const char* opmm_tile_name(int i) { return (i >= 0 && i < kNumShapes) ? kShapes[i].name : ""; }
 

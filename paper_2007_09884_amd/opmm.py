@@ -81,6 +81,7 @@ def _load():
         "opmm_autotune": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(FitParams),
                                          ctypes.POINTER(i32), vp]),
         "opmm_tile_count": (ctypes.c_int, []),
+        "opmm_tile_default": (ctypes.c_int, []),
         "opmm_tile_name": (ctypes.c_char_p, [ctypes.c_int]),
         "opmm_surrogate_create": (ctypes.c_int, [vp, u64, ctypes.POINTER(vp)]),
         "opmm_surrogate_destroy": (ctypes.c_int, [vp]),
