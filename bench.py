@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--seed-width", type=float, default=0.25, help="round-0 half-width / box half-width")
     ap.add_argument("--polish-iter", type=int, default=4, help="Levenberg-Marquardt iterations after the seeded refine")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the batched-uneven (persistent launch) leg")
     ap.add_argument("--no-nm", action="store_true")
     ap.add_argument("--nm-iter", type=int, default=2000)
     ap.add_argument("--copy-probe", action="store_true",
@@ -191,6 +192,35 @@ def surrogate_leg(a, ctx, opmm, torch, synth, keep=False):
                             "rmse_ratio_surrogate_over_plain": float(rs.mean() / rp.mean())}}
 
 
+def uneven_leg(a, ctx, opmm, torch, synth):
+    """Batched uneven saccades: 4096 saccades of 20-150 samples, per-saccade candidate counts from
+    {4096, 16384, 65536}, every round of every saccade in one persistent launch captured in a graph,
+    shape picked by the autotuner; the per-round launches of the default shape beside it."""
+    b = synth.draw_saccades(4096, "uneven", seed=synth.BASE_SEED + 2)
+    pos = gpu_targets(ctx, opmm, torch, b)
+    recs = opmm.saccade_records(b["T"], 2, b["amp"], b["dir_deg"], b["dur_ms"], b["seed"], n_cand=b["n_cand"])
+    S, R = 4096, a.rounds
+    sims = int(np.sum(b["n_cand"].astype(np.int64))) * R
+    opc = torch.zeros(S, 18, device="cuda")
+    rm = torch.zeros(S, device="cuda")
+    out = {"saccades": S, "rounds": R, "candidate_sims_per_step": sims, "mean_T": float(np.mean(b["T"]))}
+    for name, mode in (("persistent", opmm.FIT_PERSISTENT), ("rounds", opmm.FIT_ROUNDS)):
+        p = opmm.fit_params(n_cand=4096, n_rounds=R, mode=mode)
+        p.tile = ctx.autotune(pos, recs, p) if name == "persistent" else opmm.lib.opmm_tile_default()
+        pl = ctx.plan(pos, recs, p, opc, rm)
+        pl.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            pl.launch()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 3
+        pl.close()
+        out[name] = {"tile": opmm.tile_names()[p.tile], "ms_per_step": dt * 1e3, "candidate_sims_per_s": sims / dt,
+                     "saccades_fitted_per_s": S / dt}
+    return out
+
+
 def nm_leg(a, ctx, opmm, torch, pos, recs, rm_box, box_s):
     """The paper's estimator (parallel Nelder-Mead, one task per saccade, all transforms of an
     iteration at once) on the same batch, from the nominal OPC, against the box search."""
@@ -258,7 +288,7 @@ def cpu_baseline(b, pos_host, seconds):
     """The FP64 oracle's own box search (candidate draw + RK4 simulation + RMSE + argmin), one round,
     on a bounded sample of the same workload, all host cores."""
     import oracle
-    cores = os.cpu_count() or 1
+    cores = min(16, len(os.sched_getaffinity(0)))  # the host share of one GPU
     s = 0
     T = int(b["T"][s])
     amp, phi, dur = (float(np.float32(b[k][s])) for k in ("amp", "dir_deg", "dur_ms"))
@@ -407,6 +437,8 @@ def main():
     }
     if tuned:
         out["autotune"] = tuned
+    if not a.no_uneven:
+        out["batched_uneven"] = uneven_leg(a, ctx, opmm, torch, synth)
     if not a.no_nm:
         out["nelder_mead"] = nm_leg(a, ctx, opmm, torch, pos, recs, rm, ms_per_step * 1e-3)
     if not a.no_surrogate:

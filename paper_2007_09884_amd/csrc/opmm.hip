@@ -330,13 +330,21 @@ __device__ __forceinline__ uint64_t process_tile(TileSmem<TPB, PASSES>& sm, cons
     return best;
 }
 
-__device__ __forceinline__ int find_saccade(const SacDev* __restrict__ sacs, int S, int b)
+// Last s with sacs[s].tile_base <= b (tile bases increase from 0), by one
+// whole wave: each level probes 64 evenly spaced records at once and keeps the
+// segment after the last probe that is <= b, so S = 4096 takes 2 dependent
+// loads instead of 12.  Every lane of the wave must call it.
+__device__ __forceinline__ int find_saccade_wave(const SacDev* __restrict__ sacs, int S, int b)
 {
-    int lo = 0, hi = S - 1;  // last s with tile_base <= b
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (sacs[mid].tile_base <= b) lo = mid;
-        else hi = mid - 1;
+    const int lane = threadIdx.x & 63;
+    int lo = 0, n = S;
+    while (n > 1) {
+        const int step = (n + 63) / 64;
+        const bool le = lane * step < n && sacs[lo + lane * step].tile_base <= b;
+        const uint64_t m = __ballot(le);  // lane 0 always set: sacs[lo].tile_base <= b
+        const int last = 63 - __clzll((long long)m);
+        lo += last * step;
+        n = min(step, n - last * step);
     }
     return lo;
 }
@@ -354,7 +362,10 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_round_kernel(const Sa
 {
     __shared__ TileSmem<TPB, PASSES> sm;
     __shared__ int s_s;
-    if (threadIdx.x == 0) s_s = find_saccade(sacs, S, blockIdx.x);
+    if (threadIdx.x < 64) {
+        const int sw = find_saccade_wave(sacs, S, blockIdx.x);
+        if (threadIdx.x == 0) s_s = sw;
+    }
     __syncthreads();
     const int s = s_s;
     const SacDev sd = sacs[s];
@@ -379,7 +390,7 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_persistent_kernel(
     int32_t* status, uint64_t* keys, uint32_t* head, uint32_t* done, uint32_t* ready, uint32_t* errflag)
 {
     __shared__ TileSmem<TPB, PASSES> sm;
-    __shared__ int s_item;
+    __shared__ int s_item, s_sac;
     const int64_t total = (int64_t)R * tiles_per_round;
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(head, 1u);
@@ -388,7 +399,12 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_persistent_kernel(
         if (item >= total) break;
         const int r = (int)(item / tiles_per_round);
         const int b = (int)(item % tiles_per_round);
-        const int s = find_saccade(sacs, S, b);
+        if (threadIdx.x < 64) {
+            const int sw = find_saccade_wave(sacs, S, b);
+            if (threadIdx.x == 0) s_sac = sw;
+        }
+        __syncthreads();
+        const int s = s_sac;
         const SacDev sd = sacs[s];
         const int t = b - sd.tile_base;
         const bool skip = (status[s] & OPMM_ST_NONFINITE_INPUT) != 0;

@@ -125,7 +125,7 @@ __device__ __forceinline__ float box_draw(uint32_t u, float c, float w, float lo
 {
     float s = __fmaf_rn((float)u, 0x1p-23f, -1.0f);
     float v = __fmaf_rn(w, s, c);
-    return fminf(fmaxf(v, lo), hi);
+    return __builtin_amdgcn_fmed3f(v, lo, hi);  // = clamp to [lo, hi] (lo <= hi, v finite)
 }
 
 struct Box {

@@ -201,9 +201,6 @@ __device__ void simulate_s(const S p[P], double amp, double dt, int T, Sink& sin
 {
     PlantScalars<S> c;
     plant_scalars(p, S(amp), c);
-    Piece<S> pul, pos;
-    lti_dform(c, c.q1a, c.q1n, dt, pul);
-    lti_dform(c, c.q2a, c.q2n, dt, pos);
     const S pwd = p[17] * rcp64(dt);
     const double fl = floor(val(pwd));
     int k0;
@@ -214,22 +211,31 @@ __device__ void simulate_s(const S p[P], double amp, double dt, int T, Sink& sin
     S d[6];
     for (int i = 0; i < 6; ++i) d[i] = c.d0[i];
     S theq = c.th1;
+    // one piece's transition at a time (the post piece is formed when the pulse ends), which
+    // keeps the dual pass within the register file
+    Piece<S> pc;
+    int k = 0;
     if (k0 < 0) {
         for (int i = 0; i < 6; ++i) d[i] = d[i] + c.sh[i];
         theq = S(amp);
-    }
-    for (int k = 0; k < T; ++k) {
-        sink(k, d[0] + theq);
-        if (k < k0) {
-            piece_step(pul, d);
-        } else if (k == k0) {
-            expmv_t(c, c.q1a, c.q1n, frac * dt, d);
-            for (int i = 0; i < 6; ++i) d[i] = d[i] + c.sh[i];
-            expmv_t(c, c.q2a, c.q2n, (S(1.0) - frac) * dt, d);
-            theq = S(amp);
-        } else {
-            piece_step(pos, d);
+    } else {
+        lti_dform(c, c.q1a, c.q1n, dt, pc);
+        for (; k < k0 && k < T; ++k) {
+            sink(k, d[0] + theq);
+            piece_step(pc, d);
         }
+        if (k0 >= T) return;
+        sink(k, d[0] + theq);
+        expmv_t(c, c.q1a, c.q1n, frac * dt, d);
+        for (int i = 0; i < 6; ++i) d[i] = d[i] + c.sh[i];
+        expmv_t(c, c.q2a, c.q2n, (S(1.0) - frac) * dt, d);
+        theq = S(amp);
+        ++k;
+    }
+    lti_dform(c, c.q2a, c.q2n, dt, pc);
+    for (; k < T; ++k) {
+        sink(k, d[0] + theq);
+        piece_step(pc, d);
     }
 }
 
@@ -335,7 +341,6 @@ struct PolishSmem {
     double g[P];
     double xt[NLAM][P];
     double ft[NLAM];
-    double L[NLAM][PTRI];
     double x[P], nom[P], lo[P], hi[P];
     int opc_of[P];   // free parameter -> its (first) OPC index
     int tied[P];     // free parameter -> second OPC index it moves, or -1
@@ -351,35 +356,45 @@ __device__ __forceinline__ double opc_value(const PolishSmem& sm, const double* 
     return (double)(float)(x[i] * sm.nom[i]);
 }
 
-// Cholesky solve of (H + lam diag H) delta = -g over the free, unheld
-// parameters (packed lower factor in L).  Returns false if not positive definite.
-__device__ bool damped_solve(const PolishSmem& sm, double* Lp, double lam, const bool* held, double* delta)
+// Cholesky solve of (H + lam diag H) delta = -g with the factor in registers
+// (fully unrolled, 18 unknowns).  Unknowns flagged in `held` (held parameters
+// and those past the free count) take an identity row, so their delta is 0.
+// The diagonal of the packed factor stores 1/L_jj.  Returns false if the
+// damped matrix is not positive definite.
+__device__ __forceinline__ bool damped_solve(const PolishSmem& sm, double lam, uint32_t held, double delta[P])
 {
-    const int n = sm.nf;
-    for (int i = 0; i < n; ++i) {
-        for (int j = 0; j <= i; ++j) {
-            double a;
-            if (held[i] || held[j]) a = (i == j) ? 1.0 : 0.0;
-            else a = (i == j) ? sm.H[i][i] * (1.0 + lam) : sm.H[i][j];
-            for (int k = 0; k < j; ++k) a -= Lp[i * (i + 1) / 2 + k] * Lp[j * (j + 1) / 2 + k];
-            if (i == j) {
-                if (!(a > 0.0)) return false;
-                Lp[i * (i + 1) / 2 + i] = sqrt(a);
-            } else {
-                Lp[i * (i + 1) / 2 + j] = a / Lp[j * (j + 1) / 2 + j];
-            }
+    double L[PTRI];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const bool uj = !((held >> j) & 1u);
+        double d = uj ? sm.H[j][j] * (1.0 + lam) : 1.0;
+#pragma unroll
+        for (int k = 0; k < j; ++k) d = __fma_rn(-L[j * (j + 1) / 2 + k], L[j * (j + 1) / 2 + k], d);
+        if (!(d > 0.0)) return false;
+        const double rj = 1.0 / sqrt(d);
+        L[j * (j + 1) / 2 + j] = rj;
+#pragma unroll
+        for (int i = j + 1; i < P; ++i) {
+            const bool ui = !((held >> i) & 1u);
+            double a = (ui && uj) ? sm.H[i][j] : 0.0;
+#pragma unroll
+            for (int k = 0; k < j; ++k) a = __fma_rn(-L[i * (i + 1) / 2 + k], L[j * (j + 1) / 2 + k], a);
+            L[i * (i + 1) / 2 + j] = a * rj;
         }
     }
-    double y[P];
-    for (int i = 0; i < n; ++i) {
-        double a = held[i] ? 0.0 : -sm.g[i];
-        for (int k = 0; k < i; ++k) a -= Lp[i * (i + 1) / 2 + k] * y[k];
-        y[i] = a / Lp[i * (i + 1) / 2 + i];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {  // L y = -g
+        double a = ((held >> i) & 1u) ? 0.0 : -sm.g[i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) a = __fma_rn(-L[i * (i + 1) / 2 + k], delta[k], a);
+        delta[i] = a * L[i * (i + 1) / 2 + i];
     }
-    for (int i = n - 1; i >= 0; --i) {
-        double a = y[i];
-        for (int k = i + 1; k < n; ++k) a -= Lp[k * (k + 1) / 2 + i] * delta[k];
-        delta[i] = a / Lp[i * (i + 1) / 2 + i];
+#pragma unroll
+    for (int i = P - 1; i >= 0; --i) {  // L^T delta = y
+        double a = delta[i];
+#pragma unroll
+        for (int k = i + 1; k < P; ++k) a = __fma_rn(-L[k * (k + 1) / 2 + i], delta[k], a);
+        delta[i] = a * L[i * (i + 1) / 2 + i];
     }
     return true;
 }
@@ -461,14 +476,18 @@ __global__ __launch_bounds__(64) void polish_kernel(int S, const SacDev* __restr
         // B: damped solves, one damping value per lane
         if (lane < NLAM) {
             const double lam = sm.lam * LAM_FAC[lane];
-            bool held[P];
-            for (int j = 0; j < nf; ++j) {
-                const int i = sm.opc_of[j];
-                held[j] = !(sm.H[j][j] > 0.0) || (sm.x[i] <= sm.lo[i] && sm.g[j] > 0.0) ||
-                          (sm.x[i] >= sm.hi[i] && sm.g[j] < 0.0);
+            uint32_t held = 0;
+            for (int j = 0; j < P; ++j) {
+                bool h = true;
+                if (j < nf) {
+                    const int i = sm.opc_of[j];
+                    h = !(sm.H[j][j] > 0.0) || (sm.x[i] <= sm.lo[i] && sm.g[j] > 0.0) ||
+                        (sm.x[i] >= sm.hi[i] && sm.g[j] < 0.0);
+                }
+                held |= (uint32_t)h << j;
             }
             double delta[P];
-            const bool ok = damped_solve(sm, sm.L[lane], lam, held, delta);
+            const bool ok = damped_solve(sm, lam, held, delta);
             for (int i = 0; i < P; ++i) sm.xt[lane][i] = sm.x[i];
             if (ok) {
                 for (int j = 0; j < nf; ++j) {

@@ -56,7 +56,7 @@ template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A, int lda,
                                                         const uint16_t* __restrict__ B, int ldb, void* C, int ldc,
                                                         const float* __restrict__ bias,
-                                                        const uint16_t* __restrict__ mask, int ldm)
+                                                        const uint16_t* __restrict__ mask, int ldm, int kchunk)
 {
     __shared__ __attribute__((aligned(16))) uint16_t As[GBM][GBK + GPAD];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[GBN][GBK + GPAD];
@@ -64,7 +64,11 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
     const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     floatx16 acc = {};
-    for (int k0 = 0; k0 < K; k0 += GBK) {
+    // split K: block z covers [z kchunk, (z+1) kchunk); with EPI_F32 it writes slice z of C
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    if (EPI == EPI_F32) C = (float*)C + (int64_t)blockIdx.z * M * ldc;
+    for (int k0 = kbeg; k0 < kend; k0 += GBK) {
         // stage A tile (64 x 32): 2048 elements, 8 per thread
         {
             if (!TA) {
@@ -72,14 +76,14 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const int m = m0 + r, k = k0 + kc + i;
-                    As[r][kc + i] = (m < M && k < K) ? A[(int64_t)m * lda + k] : (uint16_t)0;
+                    As[r][kc + i] = (m < M && k < kend) ? A[(int64_t)m * lda + k] : (uint16_t)0;
                 }
             } else {
                 const int kk = tid >> 3, mc = (tid & 7) * 8;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const int m = m0 + mc + i, k = k0 + kk;
-                    As[mc + i][kk] = (m < M && k < K) ? A[(int64_t)k * lda + m] : (uint16_t)0;
+                    As[mc + i][kk] = (m < M && k < kend) ? A[(int64_t)k * lda + m] : (uint16_t)0;
                 }
             }
         }
@@ -90,14 +94,14 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const int n = n0 + r, k = k0 + kc + i;
-                    Bs[r][kc + i] = (n < N && k < K) ? B[(int64_t)n * ldb + k] : (uint16_t)0;
+                    Bs[r][kc + i] = (n < N && k < kend) ? B[(int64_t)n * ldb + k] : (uint16_t)0;
                 }
             } else {
                 const int kk = tid >> 3, nc = (tid & 7) * 8;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const int n = n0 + nc + i, k = k0 + kk;
-                    Bs[nc + i][kk] = (n < N && k < K) ? B[(int64_t)k * ldb + n] : (uint16_t)0;
+                    Bs[nc + i][kk] = (n < N && k < kend) ? B[(int64_t)k * ldb + n] : (uint16_t)0;
                 }
             }
         }
@@ -132,15 +136,30 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
     }
 }
 
+// nsplit > 1 (EPI_F32 only): C holds nsplit slices [M][ldc] of partial sums over K
 template <bool TA, bool TB, int EPI>
 hipError_t gemm(int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb, void* C, int ldc,
-                const float* bias, const uint16_t* mask, int ldm, hipStream_t st)
+                const float* bias, const uint16_t* mask, int ldm, hipStream_t st, int nsplit = 1)
 {
-    dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM);
+    const int kchunk = (((K + nsplit - 1) / nsplit) + GBK - 1) / GBK * GBK;
+    dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM, nsplit);
     hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, bias,
-                       mask, ldm);
+                       mask, ldm, kchunk);
     return hipGetLastError();
 }
+
+// out[i] = sum over z of parts[z * n + i], z in order (deterministic split-K reduction)
+__global__ void splitk_sum_kernel(int64_t n, int nsplit, const float* __restrict__ parts, float* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float a = 0.0f;
+    for (int z = 0; z < nsplit; ++z) a += parts[(int64_t)z * n + i];
+    out[i] = a;
+}
+
+constexpr int SPLITK_ROWS = 512;  // batch rows per split of the weight-gradient GEMM
+constexpr int SPLITK_MAX = 16;
 
 // ---------------------------------------------------------------------------
 // Network state
@@ -192,6 +211,7 @@ struct opmm_surrogate {
     int32_t* tlen = nullptr;  // [B]
     float* dur = nullptr;     // [B]
     uint64_t* counter = nullptr;  // device step counter for data generation (graph-replay safe)
+    float* gpart = nullptr;       // split-K partial weight gradients [SPLITK_MAX][512 x 512]
 };
 
 namespace {
@@ -447,6 +467,7 @@ int sg_alloc(opmm_surrogate* sg, int batch)
     SG_HIP(hipMalloc(&sg->trace, sizeof(float) * (size_t)batch * MAX_T_GEN));
     SG_HIP(hipMalloc(&sg->tlen, sizeof(int32_t) * (size_t)batch));
     SG_HIP(hipMalloc(&sg->dur, sizeof(float) * (size_t)batch));
+    if (!sg->gpart) SG_HIP(hipMalloc(&sg->gpart, sizeof(float) * (size_t)SPLITK_MAX * 512 * 512));
     sg->cap_batch = batch;
     return OPMM_OK;
 }
@@ -478,10 +499,15 @@ int sg_backward(opmm_surrogate* sg, int B, hipStream_t st)
     for (int l = NL - 1; l >= 0; --l) {
         const int K = WIDTH[l], N = WIDTH[l + 1];
         const uint16_t* dy = (l == NL - 1) ? sg->dact[0] : sg->dact[l + 1];
-        // dW_l = act[l]^T . dY   ([K][B] x [B][N])
-        hipError_t e = gemm<true, false, EPI_F32>(K, N, B, sg->act[l], K, dy, N, sg->g + w_off(l), N, nullptr,
-                                                  nullptr, 0, st);
+        // dW_l = act[l]^T . dY   ([K][B] x [B][N]): the batch is the long contraction, split it so
+        // that a 512 x 512 gradient fills the chip, then sum the slices in a fixed order
+        const int nsplit = std::min(SPLITK_MAX, std::max(1, (B + SPLITK_ROWS - 1) / SPLITK_ROWS));
+        hipError_t e = gemm<true, false, EPI_F32>(K, N, B, sg->act[l], K, dy, N, nsplit > 1 ? sg->gpart : sg->g + w_off(l),
+                                                  N, nullptr, nullptr, 0, st, nsplit);
         if (e != hipSuccess) return opmm_rt::hip_fail(sg->ctx, e, "gemm dW");
+        if (nsplit > 1)
+            hipLaunchKernelGGL(splitk_sum_kernel, dim3(blocks((int64_t)K * N, 256)), dim3(256), 0, st, (int64_t)K * N,
+                               nsplit, sg->gpart, sg->g + w_off(l));
         hipLaunchKernelGGL(colsum_kernel, dim3(N), dim3(256), 0, st, B, N, dy, sg->g + b_off(l));
         if (l > 0) {
             // dX_l = (dY . W_l^T) masked by act[l] > 0   ([B][N] x [N][K])
@@ -551,7 +577,7 @@ int opmm_surrogate_destroy(opmm_surrogate* sg)
     }
     for (void* p : {(void*)sg->w, (void*)sg->wb, (void*)sg->g, (void*)sg->m1, (void*)sg->m2, (void*)sg->out,
                     (void*)sg->target, (void*)sg->loss, (void*)sg->trace, (void*)sg->tlen, (void*)sg->dur,
-                    (void*)sg->counter})
+                    (void*)sg->counter, (void*)sg->gpart})
         if (p) (void)hipFree(p);
     delete sg;
     return OPMM_OK;

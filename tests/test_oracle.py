@@ -338,3 +338,100 @@ def test_model9_stream_and_truth_recovery():
     pos = oracle.make_target(truth.astype(np.float64), 10.0, 0.0, 80, 1, np.zeros((80, 1)), 0.0)
     res = oracle.fit(pos, 10.0, 0.0, 43.0, 77, 100, 1, model=9, nthreads=4)
     assert res["best_idx"][0] == 41 and np.array_equal(res["opc"], truth)
+
+
+# --- the paper's estimator: Nelder-Mead (Section 3.3) ---------------------------------------------
+
+def _nm_problem(seed=5, noise=0.0):
+    rng = np.random.default_rng(seed)
+    dur, amp = 43.0, 10.0
+    p_true = oracle.nominal(dur) * rng.uniform(0.95, 1.05, 18)
+    T = 80
+    th = oracle.simulate(p_true, amp, T)
+    pos = (th + noise * rng.standard_normal(T)).astype(np.float32)[:, None]
+    return pos, amp, dur
+
+
+def _rmse_at(x_rel, pos, amp, dur, lo=0.75, hi=1.25):
+    p = np.float32(np.clip(x_rel, lo, hi) * oracle.nominal(dur)).astype(np.float64)
+    return oracle.cost(oracle.simulate(p, amp, pos.shape[0]), pos, 0.0)[0]
+
+
+def test_nelder_mead_exit_needs_both_tolerances():
+    """The initial simplex (x0 and x0 with one coordinate scaled by 1.05) spreads 0.05 in x and some
+    amount in f: loose tolerances on both stop at once, one tight tolerance keeps it going."""
+    pos, amp, dur = _nm_problem()
+    assert oracle.nelder_mead(pos, amp, 0.0, dur, max_iter=50, tol_x=1.0, tol_f=1.0)["iters"] == 0
+    assert oracle.nelder_mead(pos, amp, 0.0, dur, max_iter=50, tol_x=1.0, tol_f=1e-12)["iters"] > 0
+    assert oracle.nelder_mead(pos, amp, 0.0, dur, max_iter=50, tol_x=0.01, tol_f=1.0)["iters"] > 0
+
+
+def test_nelder_mead_initial_simplex_best_vertex():
+    """Stopped before the first iteration, the result is the best of the 19 initial vertices."""
+    pos, amp, dur = _nm_problem()
+    r = oracle.nelder_mead(pos, amp, 0.0, dur, max_iter=0)
+    verts = [np.ones(18)] + [np.where(np.arange(18) == j, 1.05, 1.0) for j in range(18)]
+    costs = [_rmse_at(v, pos, amp, dur) for v in verts]
+    best = int(np.argmin(costs))
+    assert np.array_equal(r["opc"], np.float32(verts[best] * oracle.nominal(dur)))
+    assert abs(r["rmse"] - costs[best]) <= 1e-12
+
+
+def test_nelder_mead_descends_and_replays_itself():
+    """On a noise-free target 5% from nominal the simplex search lowers the RMSE by orders of
+    magnitude, its best value never rises, and replaying its own decisions reproduces it exactly."""
+    pos, amp, dur = _nm_problem()
+    r0 = _rmse_at(np.ones(18), pos, amp, dur)
+    r = oracle.nelder_mead(pos, amp, 0.0, dur, max_iter=1500, tol_x=0.0, tol_f=0.0)
+    assert r["rmse"] < 1e-2 * r0, (r["rmse"], r0)
+    assert set(np.unique(r["own"])) <= {0, 1, 2, 3, 4}
+    short = [oracle.nelder_mead(pos, amp, 0.0, dur, max_iter=n, tol_x=0.0, tol_f=0.0)["rmse"] for n in (50, 200, 800)]
+    assert short[0] >= short[1] >= short[2] >= r["rmse"]
+    again = oracle.nelder_mead(pos, amp, 0.0, dur, max_iter=1500, tol_x=0.0, tol_f=0.0, forced=r["own"])
+    assert np.array_equal(again["opc"], r["opc"]) and again["rmse"] == r["rmse"]
+
+
+def test_nelder_mead_steps_follow_lagarias():
+    """The first iterations, rebuilt here from the transformation's definition (Lagarias et al.
+    1998: reflection 1, expansion 2, contractions 1/2, shrink 1/2, the simplex sorted stably after
+    each step): every decision and the best vertex agree, and the runs exercise every kind of step
+    (the last case is one whose 263rd step is a shrink)."""
+    seen = set()
+    for seed, noise, n_it in ((0, 0.05, 40), (1, 0.05, 40), (2, 0.05, 40), (3, 0.05, 40), (9, 0.5, 300)):
+        pos, amp, dur = _nm_problem(seed=seed, noise=noise)
+        cache = {}
+
+        def f(x):
+            k = tuple(np.round(x, 15))
+            if k not in cache:
+                cache[k] = _rmse_at(x, pos, amp, dur)
+            return cache[k]
+        V = [np.ones(18)] + [np.where(np.arange(18) == j, 1.05, 1.0) for j in range(18)]
+        F = [f(v) for v in V]
+        r = oracle.nelder_mead(pos, amp, 0.0, dur, max_iter=n_it, tol_x=0.0, tol_f=0.0)
+        for it in range(n_it):
+            order = np.argsort(F, kind="stable")
+            V = [V[i] for i in order]
+            F = [F[i] for i in order]
+            xb = np.mean(V[:18], axis=0)
+            w = V[18]
+            pt = [xb + (xb - w), xb + 2 * (xb - w), xb + 0.5 * (xb - w), xb - 0.5 * (xb - w)]
+            fr = f(pt[0])
+            if fr < F[0]:
+                d = 1 if f(pt[1]) < fr else 0
+            elif fr < F[17]:
+                d = 0
+            elif fr < F[18]:
+                d = 2 if f(pt[2]) <= fr else 4
+            else:
+                d = 3 if f(pt[3]) < F[18] else 4
+            assert r["own"][it] == d, (seed, it, r["own"][it], d)
+            seen.add(d)
+            if d < 4:
+                V[18], F[18] = pt[d], f(pt[d])
+            else:
+                V = [V[0]] + [V[0] + 0.5 * (v - V[0]) for v in V[1:]]
+                F = [F[0]] + [f(v) for v in V[1:]]
+        best = V[int(np.argsort(F, kind="stable")[0])]
+        assert np.array_equal(r["opc"], np.float32(np.clip(best, 0.75, 1.25) * oracle.nominal(dur))), seed
+    assert seen >= {0, 1, 2, 3, 4}, seen
