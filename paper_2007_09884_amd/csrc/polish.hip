@@ -10,13 +10,14 @@
 // of each piece, the exact split of the pulse-end sample and the recurrence
 // all run on dual numbers (value, derivative) seeded with the unit direction
 // of parameter j.  One lane per parameter, one wave per saccade.  The
-// discretisation is exact to FP64 truncation (Taylor degree 12 on dt/2 and
-// one squaring; degree 16 for the split), so these are the sensitivities of
-// the exact trajectory to ~1e-13 relative.
+// discretisation (Taylor degree 12 on dt/4 and two squarings; degree 20 for
+// the split) truncates below 1e-11 relative even for the fastest mechanical
+// mode in a +/-25% box (~2.6 per ms), so these are the sensitivities of the
+// exact trajectory to that accuracy.
 //
 // Polish.  Levenberg-Marquardt on the fit cost with Marquardt's diagonal
 // scaling, in coordinates relative to the Table 1 nominal.  Every iteration
-// forms J^T W J and J^T W e from the sensitivity pass (cross-lane shuffles),
+// forms J^T W J and J^T W e from the sensitivity pass (lane reads into SGPRs),
 // then 8 lanes solve the damped system for 8 damping values at once
 // (lambda_c * 10^(m-4), m = 0..7; Cholesky per lane) and evaluate their trial
 // points; the best trial is taken if it lowers the cost (lambda_c becomes a
@@ -76,8 +77,9 @@ namespace {
 constexpr int NLAM = 8;             // damping values tried per iteration
 constexpr int PTRI = P * (P + 1) / 2;
 constexpr double IRLS_EPS = 1e-3;   // deg: floor of |e| in the L1 weights
-constexpr int DF_M = 12;            // Taylor degree of the transition (on dt/2)
-constexpr int EX_M = 16;            // Taylor degree of the split exponential
+constexpr int DF_M = 12;            // Taylor degree of the transition (on dt/4)
+constexpr int DF_SQ = 2;            // squarings of the transition
+constexpr int EX_M = 20;            // Taylor degree of the split exponential
 // damping factors of the 8 trial lanes, relative to the current lambda
 __constant__ double LAM_FAC[NLAM] = {1e-4, 1e-3, 1e-2, 1e-1, 1.0, 1e1, 1e2, 1e3};
 
@@ -99,12 +101,12 @@ __device__ __forceinline__ void mech_rows(const PlantScalars<S>& c, const S v[4]
 }
 
 // D = exp(dt A) - I of the piece with active-state rates (qa, qn): Horner
-// evaluation of the Taylor polynomial on h = dt/2 in block form
-// A = [[Mc, G], [0, diag(q)]], then one squaring D_2h = D_h^2 + 2 D_h.
+// evaluation of the Taylor polynomial on h = dt / 2^DF_SQ in block form
+// A = [[Mc, G], [0, diag(q)]], then DF_SQ squarings D_2h = D_h^2 + 2 D_h.
 template <class S>
 __device__ void lti_dform(const PlantScalars<S>& c, S qa, S qn, double dt, Piece<S>& o)
 {
-    const double h = 0.5 * dt;
+    const double h = dt / (double)(1 << DF_SQ);
     const S q[2] = {qa, qn};
     S qm[4][4], qx[4][2], qd[2];
     for (int i = 0; i < 4; ++i) {
@@ -139,21 +141,36 @@ __device__ void lti_dform(const PlantScalars<S>& c, S qa, S qn, double dt, Piece
         qd[0] = fmr(S(s), ad[0], S(one));
         qd[1] = fmr(S(s), ad[1], S(one));
     }
-    // one squaring in D-form
-    for (int i = 0; i < 4; ++i) {
-        for (int j = 0; j < 4; ++j) {
-            S a = qm[i][j] + qm[i][j];
-            for (int k = 0; k < 4; ++k) a = fmr(qm[i][k], qm[k][j], a);
-            o.m[i][j] = a;
+    // squarings in D-form
+    for (int q = 0; q < DF_SQ; ++q) {
+        S nm[4][4], nx[4][2];
+        for (int i = 0; i < 4; ++i) {
+            for (int j = 0; j < 4; ++j) {
+                S a = qm[i][j] + qm[i][j];
+                for (int k = 0; k < 4; ++k) a = fmr(qm[i][k], qm[k][j], a);
+                nm[i][j] = a;
+            }
+            for (int j = 0; j < 2; ++j) {
+                S b = qx[i][j] * (qd[j] + S(2.0));
+                for (int k = 0; k < 4; ++k) b = fmr(qm[i][k], qx[k][j], b);
+                nx[i][j] = b;
+            }
         }
-        for (int j = 0; j < 2; ++j) {
-            S b = qx[i][j] * (qd[j] + S(2.0));
-            for (int k = 0; k < 4; ++k) b = fmr(qm[i][k], qx[k][j], b);
-            o.x[i][j] = b;
+        for (int i = 0; i < 4; ++i) {
+            for (int j = 0; j < 4; ++j) qm[i][j] = nm[i][j];
+            qx[i][0] = nx[i][0];
+            qx[i][1] = nx[i][1];
         }
+        qd[0] = qd[0] * (qd[0] + S(2.0));
+        qd[1] = qd[1] * (qd[1] + S(2.0));
     }
-    o.e[0] = qd[0] * (qd[0] + S(2.0));
-    o.e[1] = qd[1] * (qd[1] + S(2.0));
+    for (int i = 0; i < 4; ++i) {
+        for (int j = 0; j < 4; ++j) o.m[i][j] = qm[i][j];
+        o.x[i][0] = qx[i][0];
+        o.x[i][1] = qx[i][1];
+    }
+    o.e[0] = qd[0];
+    o.e[1] = qd[1];
 }
 
 template <class S>
@@ -282,9 +299,20 @@ struct CostSink {  // objective value only (trial points, reports)
     __device__ double f() const { return objective == OPMM_OBJ_MAE ? ab : sq; }
 };
 
+// The value of v held by lane `lane` (a compile-time lane index), for every
+// lane: two scalar reads, no LDS round trip.
+__device__ __forceinline__ double lane_value(double v, int lane)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // Normal equations of the linearised problem.  Lane j holds column j of J
-// (the dual part); its row of J^T W J needs the other lanes' columns, taken
-// by shuffles.  Every lane of the wave calls it (wave-uniform control flow).
+// (the dual part); its row of J^T W J needs the other lanes' columns, read
+// lane by lane into scalar registers.  Every lane of the wave calls it
+// (wave-uniform control flow).
 struct NormalSink {
     CostSink cost;
     int nf;
@@ -311,7 +339,7 @@ struct NormalSink {
         const double aj = a * jd;
 #pragma unroll
         for (int i = 0; i < P; ++i) {
-            const double ji = __shfl(jd, i);
+            const double ji = lane_value(jd, i);
             if (i < nf) h[i] = __fma_rn(aj, ji, h[i]);
         }
     }

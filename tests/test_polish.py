@@ -339,6 +339,21 @@ def test_polish_improves_the_box_search(ctx, opmm):
 
 
 @pytest.mark.gpu
+def test_polish_alone_equals_in_batch(ctx, opmm):
+    """Each saccade's polish is its own wave: its result does not depend on the rest of the batch
+    (bit-exact alone and in the batch)."""
+    b, traces = make_batch(7, "uneven", seed=synth.BASE_SEED + 361)
+    start, _ = _fit(ctx, opmm, b, traces, 2048, 2)
+    prm = opmm.polish_params(max_iter=5)
+    opc, rm, ma, it, dec = _polish(ctx, opmm, b, traces, prm, start)
+    for s in (0, 3, 6):
+        o1, r1, m1, i1, d1 = _polish(ctx, opmm, synth.subset(b, [s]), [traces[s]], prm, start[s:s + 1])
+        assert np.array_equal(o1[0].view(np.uint32), opc[s].view(np.uint32)), s
+        assert r1[0] == rm[s] and m1[0] == ma[s] and i1[0] == it[s], s
+        assert np.array_equal(d1[0], dec[s]), s
+
+
+@pytest.mark.gpu
 def test_polish_model9_and_mae(ctx, opmm):
     b, traces = make_batch(4, "full", seed=synth.BASE_SEED + 341)
     start, _ = _fit(ctx, opmm, b, traces, 4096, 3, model=9)
