@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--tile", type=int, default=-1, help="kernel shape index; -1 library default, -2 autotune")
     ap.add_argument("--no-autotune-leg", action="store_true",
                     help="skip the side leg that autotunes both launch modes and times their picks")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=16.0, help="target length of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--train-saccades", type=int, default=10_000_000)
@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy 3 times (calibrates HBM byte counters)")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000")
+    ap.add_argument("--serve-polish", type=int, default=4,
+                    help="polish iterations per served request in the extra polished-serving line (0: skip it)")
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="arrival window per rate")
     return ap.parse_args()
 
@@ -129,9 +131,9 @@ def surrogate_leg(a, ctx, opmm, torch, synth, keep=False):
     pos = gpu_targets(ctx, opmm, torch, b)
     recs = opmm.saccade_records(b["T"], 2, b["amp"], b["dir_deg"], b["dur_ms"], b["seed"])
     S = a.heldout
-    plain = opmm.fit_params(n_cand=a.n_cand, n_rounds=a.rounds, mode=opmm.FIT_ROUNDS, tile=4)
+    plain = opmm.fit_params(n_cand=a.n_cand, n_rounds=a.rounds, mode=opmm.FIT_ROUNDS)
     seeded = opmm.fit_params(n_cand=a.seed_cand, n_rounds=a.seed_rounds, w_init_frac=a.seed_width,
-                             mode=opmm.FIT_ROUNDS, tile=4)
+                             mode=opmm.FIT_ROUNDS)
     opc = torch.zeros(S, 18, device="cuda")
     rm_plain = torch.zeros(S, device="cuda")
     rm_seed = torch.zeros(S, device="cuda")
@@ -242,11 +244,12 @@ def nm_leg(a, ctx, opmm, torch, pos, recs, rm_box, box_s):
             "box_search_saccades_fitted_per_s": S / box_s, "box_search_mean_rmse_deg": float(rm_box.mean())}
 
 
-def serve_leg(a, ctx, opmm, torch, synth, sg):
+def serve_leg(a, ctx, opmm, torch, synth, sg, rates=None, polish_iter=0):
     """Continuous batching: saccades of the full-estimation distributions arrive as a Poisson stream;
-    the server admits them into device slots, seeds them from the learned network and advances every
-    resident request by one round per step.  Latency = arrival to result on the host."""
-    rates = [float(r) for r in a.serve_rates.split(",") if r]
+    the server admits them into device slots, seeds them from the learned network, advances every
+    resident request by one round per step (and, with polish_iter, polishes each finished search).
+    Latency = arrival to result on the host."""
+    rates = rates or [float(r) for r in a.serve_rates.split(",") if r]
     out = []
     for lam in rates:
         n = max(16, int(lam * a.serve_seconds))
@@ -255,7 +258,8 @@ def serve_leg(a, ctx, opmm, torch, synth, sg):
         recs = opmm.saccade_records(b["T"], 2, b["amp"], b["dir_deg"], b["dur_ms"], b["seed"])
         rng = np.random.default_rng(int(lam))
         arrive = np.cumsum(rng.exponential(1.0 / lam, n))
-        prm = opmm.serve_params(max_slots=65536, hbm_budget_bytes=1 << 30, fallback_rmse=1.5 * synth.SIGMA)
+        prm = opmm.serve_params(max_slots=65536, hbm_budget_bytes=1 << 30, fallback_rmse=1.5 * synth.SIGMA,
+                                polish_iter=polish_iter)
         prm.seeded.n_cand, prm.seeded.n_rounds, prm.seeded.w_init_frac = a.seed_cand, a.seed_rounds, a.seed_width
         prm.plain.n_cand, prm.plain.n_rounds = 16384, 10
         sv = opmm.Server(ctx, prm, sg)
@@ -280,7 +284,7 @@ def serve_leg(a, ctx, opmm, torch, synth, sg):
         out.append({"rate_per_s": lam, "requests": n, "p50_ms": float(np.percentile(lat, 50)),
                     "p99_ms": float(np.percentile(lat, 99)), "sustained_per_s": n / span,
                     "mean_rmse_deg": float(np.concatenate(rm).mean()), "fallbacks": fb, "steps": st["steps"],
-                    "slots": st["slots"]})
+                    "slots": st["slots"], "polish_iter": polish_iter})
     return out
 
 
@@ -296,7 +300,7 @@ def cpu_baseline(b, pos_host, seconds):
     t0 = time.perf_counter()
     oracle.fit(pos_host[0], amp, phi, dur, int(b["seed"][s]), probe, 1, nthreads=cores)
     rate = probe / (time.perf_counter() - t0)
-    n = int(max(probe, min(rate * seconds, 2_000_000)))
+    n = int(max(probe, min(rate * seconds, 8_000_000)))
     t0 = time.perf_counter()
     oracle.fit(pos_host[0], amp, phi, dur, int(b["seed"][s]), n, 1, nthreads=cores)
     dt = time.perf_counter() - t0
@@ -445,6 +449,9 @@ def main():
         sg, out["surrogate_vs_plain"] = surrogate_leg(a, ctx, opmm, torch, synth, keep=not a.no_serve)
         if not a.no_serve:
             out["serving"] = serve_leg(a, ctx, opmm, torch, synth, sg)
+            if a.serve_polish > 0:
+                out["serving_polished"] = serve_leg(a, ctx, opmm, torch, synth, sg, rates=[20000.0],
+                                                    polish_iter=a.serve_polish)
             sg.close()
     if not a.no_cpu_baseline:
         pos_host = []

@@ -278,6 +278,9 @@ int opmm_surrogate_load(opmm_surrogate* sg, const char* path);
  * With a surrogate, requests start from the learned seed (`seeded`) and fall
  * back to `plain` when the seeded RMSE exceeds fallback_rmse (the lower-RMSE
  * result is kept, status gets OPMM_ST_FALLBACK); without, they run `plain`.
+ * With polish_iter > 0, every finished search is polished (opmm_polish with
+ * that many iterations, the RMSE objective, the searches' box and dt) before
+ * the fallback rule and the result are taken.
  * The server owns its stream; calls on one server must not overlap.
  * ------------------------------------------------------------------------ */
 typedef struct opmm_server opmm_server;
@@ -288,12 +291,12 @@ typedef struct {
     opmm_fit_params plain;    /* search from the nominal OPC (and fallback)  */
     opmm_fit_params seeded;   /* search from the learned seed                */
     float fallback_rmse;      /* deg; e.g. 1.5 x the noise floor             */
-    int32_t pad;
+    int32_t polish_iter;      /* polish iterations per finished search, 0-100 */
 } opmm_serve_params;
 
 /* Defaults: 4096 slots, max_T 160, 1 GiB; plain 4096 x 10, seeded 1024 x 3
- * with w_init_frac 0.25; fallback 0.075 deg.  plain and seeded must share
- * dt_ms, box_frac and shrink. */
+ * with w_init_frac 0.25; fallback 0.075 deg; no polish.  plain and seeded
+ * must share dt_ms, box_frac and shrink. */
 void opmm_serve_params_default(opmm_serve_params* p);
 /* sg nullable (no learned seed).  The server keeps ctx and sg. */
 int opmm_server_create(opmm_ctx* ctx, opmm_surrogate* sg, const opmm_serve_params* prm, opmm_server** out);

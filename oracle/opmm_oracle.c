@@ -13,8 +13,8 @@
  * printed, angles in degrees, forces in grams.  (The GPU path works in ms; the
  * two were written independently.)
  *
- * What the paper fixes and what is a reading (each reading is listed in the
- * design notes):
+ * What the paper fixes and what is a reading (each reading is restated at the
+ * function that uses it):
  *   - Parameter set, order and nominal values: Section 2.2.1, Table 1.
  *   - Component semantics (series elasticity, length-tension, force-velocity,
  *     tension slope/intercept, inertia, passive viscosity; pulse-step control
@@ -33,6 +33,24 @@
  * Integrator: classical fixed-step RK4, nsub substeps per sample, the sample
  * that contains the pulse end split exactly at PW.  Pinned in the tests
  * against the matrix-exponential solution of the piecewise-LTI plant.
+ *
+ * Contents and what pins each part (tests under tests/):
+ *   - plant, controls, integrator, cost: the closed form above, equilibria
+ *     and force balance, linearity, the force-scale and time-scale
+ *     invariances, the onset derivative, hand-computed costs;
+ *   - candidate stream (SplitMix64) and box rule: the generator's published
+ *     test vectors, exact rational arithmetic, uniform fill;
+ *   - box search and the 9-parameter subspace: truth recovery, monotone
+ *     cost, brute force on small grids, ties and fixed components;
+ *   - Nelder-Mead (Section 3.3, Algorithm 1): the exit rule, the initial
+ *     simplex, every step of several runs against the Lagarias definition
+ *     (all five kinds of step occur), descent;
+ *   - sensitivities and the Levenberg-Marquardt polish (the gradient method
+ *     of Section 5): the gauge null vector, affine columns, the Frechet
+ *     derivative of expm, numpy's solve, quadratic convergence, box faces,
+ *     stationarity.
+ * The I-VT extraction reference is plain Python in __init__.py, pinned on
+ * hand-built streams and planted saccades.
  */
 #define _GNU_SOURCE
 #include <math.h>

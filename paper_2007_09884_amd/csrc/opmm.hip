@@ -862,10 +862,30 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
 
 int shape_tile(int shape) { return kShapes[shape].tpb * kShapes[shape].passes; }
 
-int pick_shape(opmm_ctx* ctx, const opmm_fit_params* prm)
+// Shapes in the order of a sweep on the full-estimation workload (fastest first).
+constexpr int kShapePreference[] = {9, 10, 11, 5, 12, 4, 6, 2, 7, 3, 0, 1, 8};
+
+// The tuned (else default) shape, unless its tile holds more candidates than
+// a saccade has: then the fastest shape whose tile fits (empty lanes do no
+// work but hold their SIMD slot), else the smallest tile.
+int shape_for(const opmm_ctx* ctx, int64_t n_cand)
+{
+    const int base = ctx->tuned_shape >= 0 ? ctx->tuned_shape : kDefaultShape;
+    if (shape_tile(base) <= n_cand) return base;
+    int smallest = base;
+    for (int sh : kShapePreference) {
+        if (shape_tile(sh) <= n_cand) return sh;
+        if (shape_tile(sh) < shape_tile(smallest)) smallest = sh;
+    }
+    return smallest;
+}
+
+int pick_shape(opmm_ctx* ctx, const opmm_fit_params* prm, const opmm_saccade* sacs, int S)
 {
     if (prm->tile >= 0) return prm->tile;
-    return ctx->tuned_shape >= 0 ? ctx->tuned_shape : kDefaultShape;
+    int64_t most = 0;
+    for (int i = 0; i < S; ++i) most = std::max<int64_t>(most, sacs[i].n_cand > 0 ? sacs[i].n_cand : prm->n_cand);
+    return shape_for(ctx, most);
 }
 
 int check_fit_args(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
@@ -962,6 +982,7 @@ hipError_t launch_report(const SacDev* sacs, int n, const float* pos, float dt, 
 int shape_tile(int shape) { return ::shape_tile(shape); }
 
 int default_shape(const opmm_ctx* ctx) { return ctx->tuned_shape >= 0 ? ctx->tuned_shape : kDefaultShape; }
+int shape_for_candidates(const opmm_ctx* ctx, int64_t n_cand) { return ::shape_for(ctx, n_cand); }
 
 int project_batch(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int S,
                   const SacDev** sacs_dev, const float** proj, hipStream_t st)
@@ -1134,7 +1155,7 @@ int opmm_fit(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccad
     if (S == 0) return OPMM_OK;
     OPMM_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    const int shape = pick_shape(ctx, params);
+    const int shape = pick_shape(ctx, params, sacs, S);
     int64_t total_T;
     int tiles;
     if ((rc = upload_saccades(ctx, ctx->scratch, sacs, S, params, shape_tile(shape), &total_T, &tiles, st)) != OPMM_OK)
@@ -1156,7 +1177,7 @@ int opmm_fit_plan_create(opmm_ctx* ctx, const float* pos, int64_t pos_len, const
     opmm_plan* pl = new (std::nothrow) opmm_plan();
     if (!pl) return fail(ctx, OPMM_ENOMEM, "plan allocation failed");
     pl->ctx = ctx;
-    const int shape = pick_shape(ctx, params);
+    const int shape = pick_shape(ctx, params, sacs, S);
     int64_t total_T;
     int tiles;
     hipStream_t cs = ctx->cap_stream;

@@ -576,6 +576,20 @@ __global__ __launch_bounds__(64) void polish_kernel(int S, const SacDev* __restr
 
 }  // namespace
 
+namespace opmm_rt {
+
+hipError_t launch_polish(const SacDev* sacs, int n, const float* pos, const int32_t* status, int model,
+                         const opmm_polish_params& prm, float* opc, float* rmse, float* mae, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(polish_kernel, dim3(n), dim3(64), 0, st, n, sacs, pos, status, model, prm.max_iter,
+                       prm.objective, (double)prm.tol_f, (double)prm.lambda0, (double)prm.box_frac,
+                       (double)prm.dt_ms, opc, rmse, mae, (int32_t*)nullptr, (int8_t*)nullptr);
+    return hipGetLastError();
+}
+
+}  // namespace opmm_rt
+
 extern "C" {
 
 void opmm_polish_params_default(opmm_polish_params* p)

@@ -63,5 +63,12 @@ hipError_t launch_report(const SacDev* sacs, int n, const float* pos, float dt, 
                          float* rmse_out, float* mae_out, int32_t* status_out, hipStream_t st);
 int shape_tile(int shape);
 int default_shape(const opmm_ctx* ctx);
+// default_shape, or a smaller-tile shape when a saccade has fewer candidates than its tile
+int shape_for_candidates(const opmm_ctx* ctx, int64_t n_cand);
+
+// Gradient polish of n listed saccades (one wave each): opc [n][18] in/out,
+// rmse/mae [n] out, status indexed by SacDev::slot.
+hipError_t launch_polish(const SacDev* sacs, int n, const float* pos, const int32_t* status, int model,
+                         const opmm_polish_params& prm, float* opc, float* rmse, float* mae, hipStream_t st);
 
 }  // namespace opmm_rt

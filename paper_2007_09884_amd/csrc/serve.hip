@@ -182,6 +182,8 @@ int opmm_server_create(opmm_ctx* ctx, opmm_surrogate* sg, const opmm_serve_param
         prm->plain.shrink != prm->seeded.shrink || (prm->plain.model != 18 && prm->plain.model != 9) ||
         prm->plain.model != prm->seeded.model)
         return opmm_rt::fail(ctx, OPMM_EINVAL, "plain and seeded searches must share dt_ms, box_frac, shrink and model");
+    if (prm->polish_iter < 0 || prm->polish_iter > 100)
+        return opmm_rt::fail(ctx, OPMM_EINVAL, "polish_iter must be in 0..100");
     // slots admitted by memory: what one resident request costs on the device
     const size_t per_slot = sizeof(float) * (3 * (size_t)prm->max_T + 4 * P + P + P + 2) + sizeof(int32_t) * 2 +
                             sizeof(uint64_t) + sizeof(double) + sizeof(SacDev);
@@ -196,7 +198,8 @@ int opmm_server_create(opmm_ctx* ctx, opmm_surrogate* sg, const opmm_serve_param
     sv->device = opmm_rt::ctx_device(ctx);
     sv->slots = slots;
     sv->max_T = prm->max_T;
-    sv->shape = opmm_rt::default_shape(ctx);
+    sv->shape = opmm_rt::shape_for_candidates(
+        ctx, sg ? std::min(prm->seeded.n_cand, prm->plain.n_cand) : prm->plain.n_cand);
     sv->tile = opmm_rt::shape_tile(sv->shape);
     int rc = OPMM_OK;
     if (hipSetDevice(sv->device) != hipSuccess || hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking) != hipSuccess)
@@ -384,6 +387,15 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
         float* rm = sv->d_out + (size_t)P * sv->slots;
         float* ma = rm + sv->slots;
         SV_HIP(opmm_rt::launch_report(sv->d_list, nf, sv->d_pos, dt, sv->ss, opc, rm, ma, sv->d_st, st));
+        if (sv->prm.polish_iter > 0) {
+            opmm_polish_params pp;
+            opmm_polish_params_default(&pp);
+            pp.max_iter = sv->prm.polish_iter;
+            pp.box_frac = sv->prm.plain.box_frac;
+            pp.dt_ms = dt;
+            SV_HIP(opmm_rt::launch_polish(sv->d_list, nf, sv->d_pos, sv->ss.status, sv->prm.plain.model, pp, opc, rm,
+                                          ma, st));
+        }
         SV_HIP(hipMemcpyAsync(sv->h_out, opc, sizeof(float) * P * nf, hipMemcpyDeviceToHost, st));
         SV_HIP(hipMemcpyAsync(sv->h_out + (size_t)P * sv->slots, rm, sizeof(float) * nf, hipMemcpyDeviceToHost, st));
         SV_HIP(hipMemcpyAsync(sv->h_out + (size_t)P * sv->slots + sv->slots, ma, sizeof(float) * nf,

@@ -71,6 +71,34 @@ def test_plain_server_results_equal_fit_alone(ctx, opmm):
     sv.close()
 
 
+def test_polished_server_results_equal_fit_and_polish_alone(ctx, opmm):
+    """With polish_iter > 0 every finished search is polished in the server's harvest launch: the
+    result equals opmm_fit followed by opmm_polish on that saccade alone."""
+    b, traces = make_batch(9, "full", seed=synth.BASE_SEED + 35)
+    recs = records(b, opmm)
+    recs["pos_offset"] = 0
+    prm = opmm.serve_params(max_slots=4, polish_iter=3)
+    prm.plain.n_cand = 2048
+    prm.plain.n_rounds = 3
+    sv = opmm.Server(ctx, prm)
+    res = stream_through(sv, b, traces, recs, waves=(3, 2))
+    assert len(res["id"]) == b["S"]
+    fp = opmm.fit_params(n_cand=2048, n_rounds=3)
+    pp = opmm.polish_params(max_iter=3)
+    for s in range(b["S"]):
+        pos = torch.from_numpy(traces[s].reshape(-1)).cuda()
+        opc = torch.zeros(1, 18, device="cuda"); rm = torch.zeros(1, device="cuda")
+        ctx.fit(pos, recs[s:s + 1], fp, opc, rm)
+        rm0 = float(rm.cpu()[0])
+        ctx.polish(pos, recs[s:s + 1], pp, opc, rm)
+        torch.cuda.synchronize()
+        assert np.array_equal(opc.cpu().numpy()[0].view(np.uint32), res["opc"][s].view(np.uint32)), s
+        assert rm.cpu().numpy()[0] == res["rmse"][s] and res["rmse"][s] <= rm0 * (1 + 1e-6)
+    sv.close()
+    with pytest.raises(opmm.OpmmError):
+        opmm.Server(ctx, opmm.serve_params(polish_iter=-1))
+
+
 def test_learned_server_results_equal_learned_fit_alone(ctx, opmm):
     sg = opmm.Surrogate(ctx, init_seed=9)
     sg.train(data_seed=5, batch=2048, n_steps=150)

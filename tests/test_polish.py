@@ -258,6 +258,29 @@ def test_sensitivity_matches_oracle(ctx, opmm, kind):
 
 
 @pytest.mark.gpu
+def test_sensitivity_edge_pulse_widths(ctx, opmm):
+    """PW past the window (no switch: its column is zero), inside the first sample, and on a sample
+    boundary (theta is C1 in PW there), against the oracle's differences."""
+    b, _ = make_batch(1, "tiny", seed=synth.BASE_SEED + 315)
+    recs = np.concatenate([records(b, opmm)] * 3)
+    T = int(recs["T"][0])
+    nom = oracle.nominal(float(b["dur_ms"][0]))
+    opc = np.stack([nom] * 3).astype(np.float32)
+    opc[:, 17] = [T + 15.0, 0.4, 20.0]
+    th = torch.zeros(3 * T, dtype=torch.float64, device="cuda")
+    jac = torch.zeros(3 * T, 18, dtype=torch.float64, device="cuda")
+    ctx.sensitivity(recs, torch.from_numpy(opc).cuda(), th, jac)
+    th, jac = th.cpu().numpy(), jac.cpu().numpy()
+    for i in range(3):
+        t_ref, J_ref = oracle.jacobian(opc[i].astype(np.float64), float(recs["amp_deg"][i]), T)
+        got = jac[i * T:(i + 1) * T]
+        assert np.abs(th[i * T:(i + 1) * T] - t_ref).max() <= 1e-8, i
+        scale = np.abs(J_ref).max(0) + 1e-30
+        assert (np.abs(got - J_ref).max(0) <= 1e-6 * scale + 1e-12).all(), (i, np.abs(got - J_ref).max(0) / scale)
+    assert np.all(jac[:T, 17] == 0.0)
+
+
+@pytest.mark.gpu
 def test_sensitivity_gauge_at_full_size(ctx, opmm):
     """At the full configuration's size (256 saccades, at their true OPC) the exact sensitivities satisfy
     the force-scale gauge identity to rounding."""
