@@ -29,6 +29,7 @@ using opmm_rt::SlotState;
 namespace {
 
 constexpr int P = OPMM_P;
+constexpr int kMaxAdmitPerStep = 4096;
 
 struct Request {
     int64_t id;
@@ -79,6 +80,7 @@ struct opmm_server {
     int max_T = 0;
     int shape = 0;
     int tile = 1;
+    int max_admit = 1;  // requests admitted per step (bounds a step's work and its scratch)
     hipStream_t stream = nullptr;
     // device
     float* d_pos = nullptr;   // [slots][max_T * 2]
@@ -220,6 +222,12 @@ int opmm_server_create(opmm_ctx* ctx, opmm_surrogate* sg, const opmm_serve_param
     hm((void**)&sv->h_out, sizeof(float) * (P + 2) * (size_t)slots);
     hm((void**)&sv->h_st, sizeof(int32_t) * slots);
     hm((void**)&sv->h_trace, sizeof(float) * (size_t)slots * sv->max_T * 2);
+    // a step admits at most max_admit requests; size the per-call scratch for that now, so no step
+    // reallocates (which would synchronise the device) when a burst arrives
+    sv->max_admit = std::min(slots, kMaxAdmitPerStep);
+    if (rc == OPMM_OK)
+        rc = opmm_rt::reserve_batch(ctx, sv->max_admit, (int64_t)sv->max_admit * sv->max_T);
+    if (rc == OPMM_OK && sg) rc = opmm_rt::surrogate_reserve(sg, sv->max_admit);
     if (rc != OPMM_OK) {
         opmm_server_destroy(sv);
         return opmm_rt::fail(ctx, rc, "server allocation failed");
@@ -315,7 +323,7 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
     }
     // 2. admission: pending requests into free slots
     std::vector<int> adm;
-    while (!sv->free_slots.empty() && !sv->pending.empty()) {
+    while (!sv->free_slots.empty() && !sv->pending.empty() && (int)adm.size() < sv->max_admit) {
         const int k = sv->free_slots.back();
         sv->free_slots.pop_back();
         Request& r = sv->pending.front();

@@ -472,6 +472,14 @@ int sg_alloc(opmm_surrogate* sg, int batch)
     return OPMM_OK;
 }
 
+}  // namespace
+
+namespace opmm_rt {
+int surrogate_reserve(opmm_surrogate* sg, int batch) { return sg_alloc(sg, batch); }
+}  // namespace opmm_rt
+
+namespace {
+
 // forward pass over B rows of act[0]; output in sg->out
 int sg_forward(opmm_surrogate* sg, int B, hipStream_t st)
 {
