@@ -15,6 +15,7 @@ Prints one JSON line.  value = candidate simulations per second for the whole
 job; saccades fitted per second is reported beside it.
 """
 import argparse
+import gc
 import json
 import math
 import os
@@ -263,6 +264,8 @@ def serve_leg(a, ctx, opmm, torch, synth, sg, rates=None, polish_iter=0):
         prm.seeded.n_cand, prm.seeded.n_rounds, prm.seeded.w_init_frac = a.seed_cand, a.seed_rounds, a.seed_width
         prm.plain.n_cand, prm.plain.n_rounds = 16384, 10
         sv = opmm.Server(ctx, prm, sg)
+        gc.collect()
+        gc.disable()  # a collector pass inside the arrival loop would show up as request latency
         t0 = sv.now()
         nxt, done, lat, rm, fb = 0, 0, [], [], 0
         while done < n:
@@ -278,6 +281,7 @@ def serve_leg(a, ctx, opmm, torch, synth, sg, rates=None, polish_iter=0):
             rm.append(r["rmse"])
             fb += int(np.count_nonzero(r["status"] & opmm.ST_FALLBACK))
         span = sv.now() - t0
+        gc.enable()
         st = sv.stats()
         sv.close()
         lat = np.concatenate(lat) * 1e3

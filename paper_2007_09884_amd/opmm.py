@@ -466,17 +466,31 @@ class Server:
         self._ctx._check(lib.opmm_server_step(self._h, ctypes.byref(n)))
         return n.value
 
-    def poll(self, max_n=1 << 16) -> dict:
-        ids = np.zeros(max_n, np.int64); opc = np.zeros((max_n, P), np.float32)
-        rm = np.zeros(max_n, np.float32); ma = np.zeros(max_n, np.float32); st = np.zeros(max_n, np.int32)
-        ta = np.zeros(max_n); td = np.zeros(max_n)
+    _POLL_CHUNK = 4096
+
+    def poll(self, max_n=1 << 30) -> dict:
+        """Every finished result (up to max_n), oldest first.  Results are read in chunks through
+        buffers kept on the server object, so a poll in a serving loop allocates only its output."""
+        if not hasattr(self, "_pbuf"):
+            c = self._POLL_CHUNK
+            self._pbuf = (np.empty(c, np.int64), np.empty((c, P), np.float32), np.empty(c, np.float32),
+                          np.empty(c, np.float32), np.empty(c, np.int32), np.empty(c), np.empty(c))
+        ids, opc, rm, ma, st, ta, td = self._pbuf
         n = ctypes.c_int64()
         p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
-        self._ctx._check(lib.opmm_server_poll(self._h, max_n, p(ids), p(opc), p(rm), p(ma), p(st), p(ta), p(td),
-                                              ctypes.byref(n)))
-        k = n.value
-        return dict(id=ids[:k], opc=opc[:k], rmse=rm[:k], mae=ma[:k], status=st[:k], t_arrival=ta[:k],
-                    t_done=td[:k])
+        parts, got = [], 0
+        while got < max_n:
+            want = int(min(self._POLL_CHUNK, max_n - got))
+            self._ctx._check(lib.opmm_server_poll(self._h, want, p(ids), p(opc), p(rm), p(ma), p(st), p(ta), p(td),
+                                                  ctypes.byref(n)))
+            k = n.value
+            parts.append([a[:k].copy() for a in (ids, opc, rm, ma, st, ta, td)])
+            got += k
+            if k < want:
+                break
+        cols = [np.concatenate([q[i] for q in parts]) for i in range(7)]
+        return dict(id=cols[0], opc=cols[1], rmse=cols[2], mae=cols[3], status=cols[4], t_arrival=cols[5],
+                    t_done=cols[6])
 
     def stats(self) -> dict:
         out = np.zeros(7, np.int64)
