@@ -419,8 +419,10 @@ int opmm_polish(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_sac
  * the run with the preceding (fixation) sample prepended, re-based to that
  * sample (T = run length + 1, duration (T-1) dt, amplitude and direction of
  * the last sample).  Runs with duration < min_dur_ms, amplitude <
- * min_amp_deg or T > max_T are dropped.  Up to max_out saccades, in stream
- * order: records to sacs_out (HOST [max_out], pos_offset into pos_out,
+ * min_amp_deg or T > max_T are dropped.  The output is the stream's first
+ * saccades, in order, up to max_out records and pos_cap floats of trace (it
+ * stops at the first saccade that does not fit): records to sacs_out
+ * (HOST [max_out], pos_offset into pos_out,
  * seed = seed_base + first sample), traces to pos_out (device, pos_cap
  * floats, [T][2] back to back), src_start_out (HOST, nullable) = index of
  * each trace's first sample in the stream.  Ready for opmm_fit.  *n_out

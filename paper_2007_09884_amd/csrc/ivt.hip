@@ -188,14 +188,16 @@ int opmm_ivt_extract(opmm_ctx* ctx, const float* gaze, int64_t N, float dt_ms, f
         ok(hipMemcpyAsync(hT.data(), Ts, sizeof(int32_t) * n_runs, hipMemcpyDeviceToHost, st), "copy");
         ok(hipStreamSynchronize(st), "sync");
         if (rc == OPMM_OK) {
-            // output slot and trace offset of the kept runs, in stream order, up to max_out
-            // records and pos_cap floats of trace
+            // output slot and trace offset of the kept runs, in stream order; output stops at the
+            // first kept run past max_out records or pos_cap floats of trace (a prefix of the stream)
             std::vector<int32_t> ho(n_runs, 0), hs(n_runs, 0);
             int64_t acc = 0;
             int32_t emitted = 0;
+            bool full = false;
             for (int i = 0; i < n_runs; ++i) {
                 if (!hk[i]) continue;
-                if (emitted >= max_out || 2 * (acc + hT[i]) > pos_cap) { hk[i] = 0; continue; }
+                full = full || emitted >= max_out || 2 * (acc + hT[i]) > pos_cap;
+                if (full) { hk[i] = 0; continue; }
                 ho[i] = (int32_t)acc;
                 hs[i] = emitted;
                 acc += hT[i];

@@ -85,3 +85,31 @@ def test_ivt_gpu_matches_reference():
     torch.cuda.synchronize()
     assert np.all(np.isfinite(rm.cpu().numpy()))
     ctx.close()
+
+
+@pytest.mark.gpu
+def test_ivt_gpu_truncation_and_edges():
+    """max_out and the trace capacity cut the output in stream order; a stream with no fast sample
+    or shorter than two samples gives nothing; bad arguments are rejected."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_09884_amd import opmm
+    ctx = opmm.Context(0)
+    rng = np.random.default_rng(6)
+    g, planted = synthetic_stream(rng, n_sacc=10)
+    ref = oracle.ivt(g, vel_thresh=30.0, min_dur=6.0)
+    d = torch.from_numpy(g).cuda()
+    pos = torch.zeros(100000, device="cuda")
+    recs, src = ctx.ivt_extract(d, pos, max_out=4)
+    assert len(recs) == 4 and list(src) == [r["start"] for r in ref[:4]]
+    cap = 2 * sum(r["T"] for r in ref[:3]) + 1          # room for three traces, not four
+    small = torch.zeros(cap, device="cuda")
+    recs, src = ctx.ivt_extract(d, small, max_out=100)
+    assert len(recs) == 3 and list(src) == [r["start"] for r in ref[:3]]
+    still = torch.zeros(500, 2, device="cuda")
+    assert len(ctx.ivt_extract(still, pos)[0]) == 0
+    assert len(ctx.ivt_extract(still[:1], pos)[0]) == 0
+    with pytest.raises(opmm.OpmmError):
+        ctx.ivt_extract(d, pos, dt_ms=0.0)
+    ctx.close()
