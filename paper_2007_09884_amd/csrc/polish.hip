@@ -10,18 +10,20 @@
 // of each piece, the exact split of the pulse-end sample and the recurrence
 // all run on dual numbers (value, derivative) seeded with the unit direction
 // of parameter j.  One lane per parameter, one wave per saccade.  The
-// discretisation (Taylor degree 12 on dt/4 and two squarings; degree 20 for
-// the split) truncates below 1e-11 relative even for the fastest mechanical
-// mode in a +/-25% box (~2.6 per ms), so these are the sensitivities of the
-// exact trajectory to that accuracy.
+// sensitivity entry point's discretisation (Taylor degree 12 on dt/4 and two
+// squarings; degree 20 for the split) truncates below 1e-11 relative even for
+// the fastest mechanical mode in a +/-25% box (~2.6 per ms), so these are the
+// sensitivities of the exact trajectory to that accuracy.
 //
 // Polish.  Levenberg-Marquardt on the fit cost with Marquardt's diagonal
 // scaling, in coordinates relative to the Table 1 nominal.  Every iteration
-// forms J^T W J and J^T W e from the sensitivity pass (lane reads into SGPRs),
-// then 8 lanes solve the damped system for 8 damping values at once
-// (lambda_c * 10^(m-4), m = 0..7; Cholesky per lane) and evaluate their trial
-// points; the best trial is taken if it lowers the cost (lambda_c becomes a
-// tenth of its lambda), otherwise lambda_c grows by 1e8 and the point stays.
+// forms J^T W J and J^T W e from a sensitivity pass on the search path's
+// discretisation (it only shapes the step), then 8 lanes solve the damped
+// system for 8 damping values at once (lambda_c * 10^(m-4), m = 0..7;
+// Cholesky per lane) and evaluate their trial points, and a ninth lane the
+// cost at the current point, all on the exact discretisation; the best trial
+// is taken if it lowers the cost (lambda_c becomes a tenth of its lambda),
+// otherwise lambda_c grows by 1e8 and the point stays.
 // Objectives: the RMSE of Section 3.4 (Gauss-Newton on squared residuals) or
 // the mean absolute difference the paper reports as OptErr (Fig. 4), by
 // iteratively reweighted least squares (weights 1/max(|e|, 1e-3 deg)).
@@ -77,9 +79,14 @@ namespace {
 constexpr int NLAM = 8;             // damping values tried per iteration
 constexpr int PTRI = P * (P + 1) / 2;
 constexpr double IRLS_EPS = 1e-3;   // deg: floor of |e| in the L1 weights
-constexpr int DF_M = 12;            // Taylor degree of the transition (on dt/4)
-constexpr int DF_SQ = 2;            // squarings of the transition
-constexpr int EX_M = 20;            // Taylor degree of the split exponential
+constexpr int NCH = 64;             // samples of Jacobian rows staged in LDS per normal-equation pass
+// Discretisations of the plant: Taylor degree M and squarings SQ of the
+// one-sample transition (on dt / 2^SQ), Taylor degree EXM of the split
+// sample's exponentials.  Exact: truncation below 1e-11 relative for the
+// fastest mechanical mode of a +/-25% box (~2.6 per ms).  Fast: the search
+// path's (~1e-8 deg on trajectories), enough for a Gauss-Newton model.
+struct DiscExact { static constexpr int M = 12, SQ = 2, EXM = 20; };
+struct DiscFast { static constexpr int M = 6, SQ = 2, EXM = 11; };
 // damping factors of the 8 trial lanes, relative to the current lambda
 __constant__ double LAM_FAC[NLAM] = {1e-4, 1e-3, 1e-2, 1e-1, 1.0, 1e1, 1e2, 1e3};
 
@@ -101,12 +108,12 @@ __device__ __forceinline__ void mech_rows(const PlantScalars<S>& c, const S v[4]
 }
 
 // D = exp(dt A) - I of the piece with active-state rates (qa, qn): Horner
-// evaluation of the Taylor polynomial on h = dt / 2^DF_SQ in block form
-// A = [[Mc, G], [0, diag(q)]], then DF_SQ squarings D_2h = D_h^2 + 2 D_h.
-template <class S>
+// evaluation of the degree-M Taylor polynomial on h = dt / 2^SQ in block form
+// A = [[Mc, G], [0, diag(q)]], then SQ squarings D_2h = D_h^2 + 2 D_h.
+template <int M, int SQ, class S>
 __device__ void lti_dform(const PlantScalars<S>& c, S qa, S qn, double dt, Piece<S>& o)
 {
-    const double h = dt / (double)(1 << DF_SQ);
+    const double h = dt / (double)(1 << SQ);
     const S q[2] = {qa, qn};
     S qm[4][4], qx[4][2], qd[2];
     for (int i = 0; i < 4; ++i) {
@@ -114,7 +121,7 @@ __device__ void lti_dform(const PlantScalars<S>& c, S qa, S qn, double dt, Piece
         qx[i][0] = S(0.0); qx[i][1] = S(0.0);
     }
     qd[0] = S(1.0); qd[1] = S(1.0);
-    for (int k = DF_M; k >= 1; --k) {
+    for (int k = M; k >= 1; --k) {
         // Q <- I + (h/k) A Q  (k >= 2);  D = h A Q  (k == 1)
         const double s = h / (double)k;
         S am[4][4], ax[4][2], ad[2];
@@ -142,7 +149,7 @@ __device__ void lti_dform(const PlantScalars<S>& c, S qa, S qn, double dt, Piece
         qd[1] = fmr(S(s), ad[1], S(one));
     }
     // squarings in D-form
-    for (int q = 0; q < DF_SQ; ++q) {
+    for (int q = 0; q < SQ; ++q) {
         S nm[4][4], nx[4][2];
         for (int i = 0; i < 4; ++i) {
             for (int j = 0; j < 4; ++j) {
@@ -188,13 +195,13 @@ __device__ __forceinline__ void piece_step(const Piece<S>& pc, S d[6])
     for (int i = 0; i < 4; ++i) d[i] = n[i];
 }
 
-// v <- exp(t A) v by the Taylor polynomial of degree EX_M (|t| <= dt)
-template <class S>
+// v <- exp(t A) v by the Taylor polynomial of degree EXM (|t| <= dt)
+template <int EXM, class S>
 __device__ void expmv_t(const PlantScalars<S>& c, S qa, S qn, S t, S v[6])
 {
     S w[6];
     for (int i = 0; i < 6; ++i) w[i] = v[i];
-    for (int k = EX_M; k >= 1; --k) {
+    for (int k = EXM; k >= 1; --k) {
         const S s = t * (1.0 / (double)k);
         S mv[4], aw[6];
         S w4[4] = {w[0], w[1], w[2], w[3]};
@@ -210,10 +217,10 @@ __device__ void expmv_t(const PlantScalars<S>& c, S qa, S qn, S t, S v[6])
     for (int i = 0; i < 6; ++i) v[i] = w[i];
 }
 
-// theta_k, k = 0..T-1, of OPC p (deg), handed to sink(k, theta_k).  Control
-// flow depends on value parts only, so every lane of a Dual pass at one point
-// takes the same path.
-template <class S, class Sink>
+// theta_k, k = 0..T-1, of OPC p (deg), handed to sink(k, theta_k), with the
+// discretisation Disc.  Control flow depends on value parts only, so every
+// lane of a Dual pass at one point takes the same path.
+template <class Disc, class S, class Sink>
 __device__ void simulate_s(const S p[P], double amp, double dt, int T, Sink& sink)
 {
     PlantScalars<S> c;
@@ -236,20 +243,20 @@ __device__ void simulate_s(const S p[P], double amp, double dt, int T, Sink& sin
         for (int i = 0; i < 6; ++i) d[i] = d[i] + c.sh[i];
         theq = S(amp);
     } else {
-        lti_dform(c, c.q1a, c.q1n, dt, pc);
+        lti_dform<Disc::M, Disc::SQ>(c, c.q1a, c.q1n, dt, pc);
         for (; k < k0 && k < T; ++k) {
             sink(k, d[0] + theq);
             piece_step(pc, d);
         }
         if (k0 >= T) return;
         sink(k, d[0] + theq);
-        expmv_t(c, c.q1a, c.q1n, frac * dt, d);
+        expmv_t<Disc::EXM>(c, c.q1a, c.q1n, frac * dt, d);
         for (int i = 0; i < 6; ++i) d[i] = d[i] + c.sh[i];
-        expmv_t(c, c.q2a, c.q2n, (S(1.0) - frac) * dt, d);
+        expmv_t<Disc::EXM>(c, c.q2a, c.q2n, (S(1.0) - frac) * dt, d);
         theq = S(amp);
         ++k;
     }
-    lti_dform(c, c.q2a, c.q2n, dt, pc);
+    lti_dform<Disc::M, Disc::SQ>(c, c.q2a, c.q2n, dt, pc);
     for (; k < T; ++k) {
         sink(k, d[0] + theq);
         piece_step(pc, d);
@@ -299,49 +306,67 @@ struct CostSink {  // objective value only (trial points, reports)
     __device__ double f() const { return objective == OPMM_OBJ_MAE ? ab : sq; }
 };
 
-// The value of v held by lane `lane` (a compile-time lane index), for every
-// lane: two scalar reads, no LDS round trip.
-__device__ __forceinline__ double lane_value(double v, int lane)
-{
-    const uint64_t u = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, lane);
-    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-// Normal equations of the linearised problem.  Lane j holds column j of J
-// (the dual part); its row of J^T W J needs the other lanes' columns, read
-// lane by lane into scalar registers.  Every lane of the wave calls it
-// (wave-uniform control flow).
+// Normal equations of the linearised problem.  Lane j carries column j of J
+// (the dual part) and accumulates g_j; the rows of J are staged in LDS NCH
+// samples at a time, and each lane then accumulates up to three entries
+// (i >= j) of the lower triangle of J^T W J, h_ij += (w_k J_ki) J_kj in sample
+// order.  Every lane of the wave calls it (wave-uniform control flow).
 struct NormalSink {
-    CostSink cost;
-    int nf;
+    Residual res;
+    int objective;
+    double* jst;  // LDS [NCH][P]: staged rows of J
+    double* ast;  // LDS [NCH]: per-sample weight of the normal matrix
+    int nk;       // samples staged
     double g;
-    double h[P];
+    int ei[3], ej[3];  // this lane's entries (row, column); row -1: none
+    double h[3];
+    __device__ void init(int nf)
+    {
+        nk = 0;
+        g = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int e = (int)threadIdx.x + 64 * q;
+            int i = 0;
+            while ((i + 1) * (i + 2) / 2 <= e) ++i;
+            const bool use = e < PTRI && i < nf;
+            ei[q] = use ? i : -1;
+            ej[q] = use ? e - i * (i + 1) / 2 : 0;
+            h[q] = 0.0;
+        }
+    }
     __device__ void operator()(int k, Dual th)
     {
         double ex, ey;
-        cost.res(k, th.v, ex, ey);
-        cost(k, th.v);
+        res(k, th.v, ex, ey);
         double wx = 1.0, wy = 1.0;
-        if (cost.objective == OPMM_OBJ_MAE) {
+        if (objective == OPMM_OBJ_MAE) {
             wx = 1.0 / fmax(fabs(ex), IRLS_EPS);
             wy = 1.0 / fmax(fabs(ey), IRLS_EPS);
         }
-        const double cp = cost.res.cphi, sp = cost.res.sphi;
+        const double cp = res.cphi, sp = res.sphi;
         double a = wx * cp * cp, b = wx * cp * ex;
-        if (cost.res.C == 2) {
+        if (res.C == 2) {
             a = __fma_rn(wy * sp, sp, a);
             b = __fma_rn(wy * sp, ey, b);
         }
-        const double jd = th.d;
-        g = __fma_rn(jd, b, g);
-        const double aj = a * jd;
+        g = __fma_rn(th.d, b, g);
+        const int lane = threadIdx.x;
+        if (lane < P) jst[nk * P + lane] = th.d;
+        if (lane == 0) ast[nk] = a;
+        if (++nk == NCH) flush();
+    }
+    __device__ void flush()
+    {
+        __syncthreads();
+        for (int kk = 0; kk < nk; ++kk) {
+            const double ak = ast[kk];
 #pragma unroll
-        for (int i = 0; i < P; ++i) {
-            const double ji = lane_value(jd, i);
-            if (i < nf) h[i] = __fma_rn(aj, ji, h[i]);
+            for (int q = 0; q < 3; ++q)
+                if (ei[q] >= 0) h[q] = __fma_rn(ak * jst[kk * P + ei[q]], jst[kk * P + ej[q]], h[q]);
         }
+        __syncthreads();
+        nk = 0;
     }
 };
 
@@ -358,7 +383,7 @@ __global__ __launch_bounds__(64) void sensitivity_kernel(int S, const SacDev* __
 #pragma unroll
     for (int j = 0; j < P; ++j) p[j] = Dual((double)opc[(int64_t)s * P + j], j == lane ? 1.0 : 0.0);
     JacSink sink{theta + out_off[s], jac + out_off[s] * P, lane};
-    simulate_s(p, (double)sd.amp, dt, sd.T, sink);
+    simulate_s<DiscExact>(p, (double)sd.amp, dt, sd.T, sink);
 }
 
 // ---- polish -------------------------------------------------------------------
@@ -370,6 +395,8 @@ struct PolishSmem {
     double xt[NLAM][P];
     double ft[NLAM];
     double x[P], nom[P], lo[P], hi[P];
+    double jst[NCH][P];
+    double ast[NCH];
     int opc_of[P];   // free parameter -> its (first) OPC index
     int tied[P];     // free parameter -> second OPC index it moves, or -1
     int nf;
@@ -484,21 +511,22 @@ __global__ __launch_bounds__(64) void polish_kernel(int S, const SacDev* __restr
     const Residual res{sm.X, sm.Y, sd.cphi, sd.sphi, sd.C};
     int it = 0;
     for (; it < max_iter; ++it) {
-        // A: sensitivities and normal equations at x (lane j: free parameter j)
+        // A: sensitivities and normal equations at x (lane j: free parameter j), on the
+        // fast discretisation: it only shapes the step; costs below are exact
         {
             Dual p[P];
             const int i0 = lane < nf ? sm.opc_of[lane] : -1;
             const int i1 = lane < nf ? sm.tied[lane] : -1;
             for (int i = 0; i < P; ++i)
                 p[i] = Dual(opc_value(sm, sm.x, i), (i == i0 || i == i1) ? sm.nom[i] : 0.0);
-            NormalSink ns{CostSink{res, objective, 0.0, 0.0}, nf, 0.0, {}};
-            for (int i = 0; i < P; ++i) ns.h[i] = 0.0;
-            simulate_s(p, (double)sd.amp, dt, T, ns);
-            if (lane < nf) {
-                for (int i = 0; i < nf; ++i) sm.H[lane][i] = ns.h[i];
-                sm.g[lane] = ns.g;
-            }
-            if (lane == 0) sm.fcur = ns.cost.f();
+            NormalSink ns{res, objective, &sm.jst[0][0], sm.ast};
+            ns.init(nf);
+            simulate_s<DiscFast>(p, (double)sd.amp, dt, T, ns);
+            ns.flush();
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if (ns.ei[q] >= 0) sm.H[ns.ei[q]][ns.ej[q]] = ns.h[q];
+            if (lane < nf) sm.g[lane] = ns.g;
         }
         __syncthreads();
         // B: damped solves, one damping value per lane
@@ -529,14 +557,16 @@ __global__ __launch_bounds__(64) void polish_kernel(int S, const SacDev* __restr
             sm.ft[lane] = INFINITY;
         }
         __syncthreads();
-        // C: trial costs
-        if (lane < NLAM && sm.ok[lane]) {
+        // C: trial costs, and the cost at the current point (lane NLAM)
+        if ((lane < NLAM && sm.ok[lane]) || lane == NLAM) {
+            const double* xp = lane < NLAM ? sm.xt[lane] : sm.x;
             double p[P];
-            for (int i = 0; i < P; ++i) p[i] = opc_value(sm, sm.xt[lane], i);
+            for (int i = 0; i < P; ++i) p[i] = opc_value(sm, xp, i);
             CostSink cs{res, objective, 0.0, 0.0};
-            simulate_s(p, (double)sd.amp, dt, T, cs);
+            simulate_s<DiscExact>(p, (double)sd.amp, dt, T, cs);
             const double f = cs.f();
-            sm.ft[lane] = (f >= 0.0 && f <= 1.7976931348623157e308) ? f : INFINITY;
+            if (lane < NLAM) sm.ft[lane] = (f >= 0.0 && f <= 1.7976931348623157e308) ? f : INFINITY;
+            else sm.fcur = f;
         }
         __syncthreads();
         // D: decision
@@ -566,7 +596,7 @@ __global__ __launch_bounds__(64) void polish_kernel(int S, const SacDev* __restr
         double p[P];
         for (int i = 0; i < P; ++i) p[i] = opc_value(sm, sm.x, i);
         CostSink cs{res, objective, 0.0, 0.0};
-        simulate_s(p, (double)sd.amp, dt, T, cs);
+        simulate_s<DiscExact>(p, (double)sd.amp, dt, T, cs);
         const double n = (double)T * sd.C;
         rmse_out[s] = (float)sqrt(cs.sq / n);
         if (mae_out) mae_out[s] = (float)(cs.ab / n);
