@@ -375,9 +375,11 @@ int opmm_sensitivity(opmm_ctx* ctx, const opmm_saccade* sacs, int32_t S, const f
  * Gradient-based polish of fitted OPC vectors (the estimation alternative of
  * Section 5, applied after the box search): Levenberg-Marquardt with
  * Marquardt scaling in coordinates relative to the Table 1 nominal, Jacobian
- * from the forward sensitivities above.  Each iteration solves the damped
- * normal equations for 8 damping values at once (lambda * 10^(m-4),
- * m = 0..7) and takes the best trial point if it lowers the objective
+ * from the forward sensitivities above taken on the search path's coarser
+ * discretisation (it only shapes the step; the objective values that accept
+ * or reject a step use the finer one of opmm_sensitivity).  Each iteration
+ * solves the damped normal equations for 8 damping values at once
+ * (lambda * 10^(m-4), m = 0..7) and takes the best trial point if it lowers the objective
  * (lambda becomes a tenth of the winner's), else raises lambda by 1e8.
  * Objective OPMM_OBJ_RMSE is the fit cost of Section 3.4; OPMM_OBJ_MAE is
  * the mean absolute difference reported as OptErr (Fig. 4), minimised by
