@@ -68,6 +68,18 @@ def parse():
     return ap.parse_args()
 
 
+# The paper's own figures (Section 4.2 and its performance table; hardware from the test-system
+# figure): its parallel Nelder-Mead on a private recorded dataset, so context, not a target.
+PAPER_FIGURES = {
+    "source": "Section 4.2, performance table; test-system figure",
+    "workload": "about 60,000 saccade simulations by the paper's Nelder-Mead estimator on recorded saccades",
+    "matlab_serial": {"runtime_s": 832.8, "throughput_per_s": 9.22,
+                      "hardware": "Intel Xeon Silver 4116 @ 2.10 GHz (Dell R740), MATLAB"},
+    "cuda": {"runtime_s": 42.6, "throughput_per_s": 464.61,
+             "hardware": "NVIDIA Tesla T4 (named TU102 in the text), CUDA 10.1"},
+    "unit": "simulations/s as printed (the text also calls them samples/second)",
+}
+
 KERNEL_SOURCES = ("paper_2007_09884_amd/csrc/plant.hpp", "paper_2007_09884_amd/csrc/opmm.hip",
                   "paper_2007_09884_amd/csrc/runtime.hpp")
 
@@ -465,6 +477,7 @@ def main():
             T = int(b["T"][s])
             pos_host.append(ph[off:off + 2 * T].reshape(T, 2))
         out["cpu_baseline"] = cpu_baseline(b, pos_host, a.cpu_seconds)
+    out["paper_figures"] = PAPER_FIGURES
     print(json.dumps(out), flush=True)
 
 
