@@ -80,6 +80,12 @@ PAPER_FIGURES = {
     "unit": "simulations/s as printed (the text also calls them samples/second)",
 }
 
+# multiply-adds per sample of the 256-512-512-256-18 network: all four layers (forward, weight
+# gradients) and the input gradients of layers 1-3
+MLP_MACS = 256 * 512 + 512 * 512 + 512 * 256 + 256 * 18
+MLP_DX_MACS = 512 * 512 + 512 * 256 + 256 * 18
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
+
 KERNEL_SOURCES = ("paper_2007_09884_amd/csrc/plant.hpp", "paper_2007_09884_amd/csrc/opmm.hip",
                   "paper_2007_09884_amd/csrc/runtime.hpp")
 
@@ -140,6 +146,25 @@ def surrogate_leg(a, ctx, opmm, torch, synth, keep=False):
     t0 = time.perf_counter()
     loss = sg.train(data_seed=1, batch=B, n_steps=steps, lr0=2e-3, lr_min=2e-5)
     train_s = time.perf_counter() - t0
+    # the training GEMMs' share of the BF16 MFMA peak: forward + backward of one generated batch (4 forward,
+    # 4 weight-gradient and 3 input-gradient GEMMs plus their small reductions), timed with HIP events
+    feat = torch.empty(B, 256, dtype=torch.int16, device="cuda")
+    target = torch.empty(B, 18, dtype=torch.float32, device="cuda")
+    sg.generate(1, 0, feat, target)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        sg.backward(feat, target, want_loss=False)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record(stream)
+    for _ in range(reps):
+        sg.backward(feat, target, want_loss=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fb_ms = e0.elapsed_time(e1) / reps
+    fb_flop = 2.0 * B * (2 * MLP_MACS + MLP_DX_MACS)
+    fb = {"batch": B, "ms": fb_ms, "flop": fb_flop, "tflops": fb_flop / (fb_ms * 1e-3) / 1e12,
+          "mfma_frac": fb_flop / (fb_ms * 1e-3) / 1e12 / BF16_MFMA_PEAK_TFLOPS}
     b = synth.draw_saccades(a.heldout, "full", seed=synth.BASE_SEED + 1)
     pos = gpu_targets(ctx, opmm, torch, b)
     recs = opmm.saccade_records(b["T"], 2, b["amp"], b["dir_deg"], b["dur_ms"], b["seed"])
@@ -187,7 +212,8 @@ def surrogate_leg(a, ctx, opmm, torch, synth, keep=False):
         sg.close()
         sg = None
     return sg, {"train": {"saccades": steps * B, "steps": steps, "batch": B, "seconds": train_s,
-                      "loss_first": float(loss[:10].mean()), "loss_last": float(loss[-10:].mean())},
+                      "loss_first": float(loss[:10].mean()), "loss_last": float(loss[-10:].mean()),
+                      "forward_backward": fb},
             "heldout_saccades": S,
             "plain": {"n_cand": a.n_cand, "rounds": a.rounds, "saccades_fitted_per_s": S / plain_s,
                       "mean_rmse_deg": float(rp.mean()), "median_rmse_deg": float(np.median(rp))},

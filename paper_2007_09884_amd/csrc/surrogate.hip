@@ -43,23 +43,84 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 // BF16 MFMA GEMM: C[M][N] = sum_k A(m,k) B(k,n), FP32 accumulate.
 //   TA = false: A stored [M][K] (row stride lda); true: stored [K][M].
 //   TB = false: B stored [K][N] (row stride ldb); true: stored [N][K].
-// Tile 64 x 64 x 32 per 256-thread block; each wave owns a 32 x 32 sub-tile
-// and issues two v_mfma_f32_32x32x16_bf16 per K step.  Operands are staged
-// through LDS with k contiguous so every fragment is one 16-byte LDS read.
+// Tile 64 x 64 x GBK per 256-thread block; each wave owns a 32 x 32 sub-tile
+// and issues GBK / 16 v_mfma_f32_32x32x16_bf16 per K step.  Operands are staged
+// through LDS with k contiguous, so every MFMA fragment is one 16-byte LDS
+// read; two LDS buffers let the global loads of step i+1 (16 bytes per
+// thread and load, into registers) overlap the MFMAs of step i, with one
+// barrier per step.  A k-contiguous operand goes to LDS as 16-byte rows; an
+// operand contiguous along m or n is transposed on the way (eight 2-byte
+// LDS writes per load).
 // ---------------------------------------------------------------------------
 
+#ifndef OPMM_GEMM_BK
+#define OPMM_GEMM_BK 64
+#endif
 enum Epi { EPI_F32 = 0, EPI_BIAS_RELU_BF16 = 1, EPI_BIAS_F32 = 2, EPI_RELU_MASK_BF16 = 3 };
 
-constexpr int GBM = 64, GBN = 64, GBK = 32, GPAD = 8;
+constexpr int GBM = 64, GBN = 64, GBK = OPMM_GEMM_BK, GPAD = 8;
+constexpr int GROW = GBK + GPAD;  // LDS row length (elements), a multiple of 8 (16 bytes)
+constexpr int GCH = GBK / 32;     // 16-byte chunks per thread of one 64 x GBK operand tile
+
+typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+
+// GCH 16-byte chunks per thread of a 64 (outer) x GBK (k) operand tile.  KC:
+// the operand is k-contiguous (rows = outer index); else rows are k.  Chunks
+// that leave the matrix, or all chunks when the rows are not 16-byte aligned
+// (vec false), are read element by element with zero fill.
+template <bool KC>
+__device__ __forceinline__ void tile_load(const uint16_t* __restrict__ X, int ld, int o0, int O, int k0, int kend,
+                                          bool vec, u32x4 v[GCH])
+{
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < GCH; ++j) {
+        const int c = tid + 256 * j;
+        // KC: GBK / 8 chunks per outer row; else 8 chunks per k row
+        const int r = KC ? c / (GBK / 8) : c >> 3, q = (KC ? c % (GBK / 8) : c & 7) * 8;
+        // KC: element i is (outer o0 + r, k k0 + q + i); else (k k0 + r, outer o0 + q + i)
+        const int ro = KC ? o0 + r : k0 + r;             // storage row
+        const int co = KC ? k0 + q : o0 + q;             // storage column of element 0
+        const int rlim = KC ? O : kend, clim = KC ? kend : O;
+        if (vec && ro < rlim && co + 8 <= clim) {
+            v[j] = *reinterpret_cast<const u32x4*>(X + (int64_t)ro * ld + co);
+        } else {
+            uint16_t e[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) e[i] = (ro < rlim && co + i < clim) ? X[(int64_t)ro * ld + co + i] : (uint16_t)0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) v[j][w] = (uint32_t)e[2 * w] | ((uint32_t)e[2 * w + 1] << 16);
+        }
+    }
+}
+
+// Writes the chunks of tile_load into S[outer][k].
+template <bool KC>
+__device__ __forceinline__ void tile_store(uint16_t (*S)[GROW], const u32x4 v[GCH])
+{
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < GCH; ++j) {
+        const int c = tid + 256 * j;
+        const int r = KC ? c / (GBK / 8) : c >> 3, q = (KC ? c % (GBK / 8) : c & 7) * 8;
+        if (KC) {
+            *reinterpret_cast<u32x4*>(&S[r][q]) = v[j];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) S[q + i][r] = (uint16_t)(v[j][i >> 1] >> (16 * (i & 1)));
+        }
+    }
+}
 
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A, int lda,
                                                         const uint16_t* __restrict__ B, int ldb, void* C, int ldc,
                                                         const float* __restrict__ bias,
-                                                        const uint16_t* __restrict__ mask, int ldm, int kchunk)
+                                                        const uint16_t* __restrict__ mask, int ldm, int kchunk,
+                                                        float* __restrict__ colsum)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t As[GBM][GBK + GPAD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[GBN][GBK + GPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][GBM][GROW];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][GBN][GROW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -68,53 +129,50 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(K, kbeg + kchunk);
     if (EPI == EPI_F32) C = (float*)C + (int64_t)blockIdx.z * M * ldc;
+    const bool va = (lda % 8 == 0) && (((uintptr_t)A & 15) == 0);
+    const bool vb = (ldb % 8 == 0) && (((uintptr_t)B & 15) == 0);
+    u32x4 ra[GCH], rb[GCH];
+    // colsum (non-null): the first row of blocks also sums its B tiles over k, i.e. the column sums of
+    // B over this block's K range (the bias gradient when B is the output gradient)
+    const bool csum = colsum != nullptr && blockIdx.y == 0 && tid < 64;
+    float cs = 0.0f;
+    if (kbeg < kend) {
+        tile_load<!TA>(A, lda, m0, M, kbeg, kend, va, ra);
+        tile_load<TB>(B, ldb, n0, N, kbeg, kend, vb, rb);
+        tile_store<!TA>(As[0], ra);
+        tile_store<TB>(Bs[0], rb);
+    }
+    __syncthreads();
+    int cur = 0;
     for (int k0 = kbeg; k0 < kend; k0 += GBK) {
-        // stage A tile (64 x 32): 2048 elements, 8 per thread
-        {
-            if (!TA) {
-                const int r = tid >> 2, kc = (tid & 3) * 8;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int m = m0 + r, k = k0 + kc + i;
-                    As[r][kc + i] = (m < M && k < kend) ? A[(int64_t)m * lda + k] : (uint16_t)0;
-                }
-            } else {
-                const int kk = tid >> 3, mc = (tid & 7) * 8;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int m = m0 + mc + i, k = k0 + kk;
-                    As[mc + i][kk] = (m < M && k < kend) ? A[(int64_t)k * lda + m] : (uint16_t)0;
-                }
-            }
+        const bool more = k0 + GBK < kend;
+        if (more) {
+            tile_load<!TA>(A, lda, m0, M, k0 + GBK, kend, va, ra);
+            tile_load<TB>(B, ldb, n0, N, k0 + GBK, kend, vb, rb);
         }
-        // stage B tile (32 x 64) as Bs[n][k]
-        {
-            if (TB) {
-                const int r = tid >> 2, kc = (tid & 3) * 8;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int n = n0 + r, k = k0 + kc + i;
-                    Bs[r][kc + i] = (n < N && k < kend) ? B[(int64_t)n * ldb + k] : (uint16_t)0;
-                }
-            } else {
-                const int kk = tid >> 3, nc = (tid & 7) * 8;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int n = n0 + nc + i, k = k0 + kk;
-                    Bs[nc + i][kk] = (n < N && k < kend) ? B[(int64_t)k * ldb + n] : (uint16_t)0;
-                }
-            }
-        }
-        __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < GBK; ks += 16) {
             // lane l: A row (l % 32), k = 8 (l / 32) + 0..7; B col (l % 32), same k
-            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[wm + (lane & 31)][ks + 8 * (lane >> 5)]);
-            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[wn + (lane & 31)][ks + 8 * (lane >> 5)]);
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[cur][wm + (lane & 31)][ks + 8 * (lane >> 5)]);
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn + (lane & 31)][ks + 8 * (lane >> 5)]);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
         }
+        if (csum) {
+#pragma unroll
+            for (int kq = 0; kq < GBK; kq += 8) {
+                const u32x4 w = *reinterpret_cast<const u32x4*>(&Bs[cur][tid][kq]);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) cs += bf2f((uint16_t)(w[i >> 1] >> (16 * (i & 1))));
+            }
+        }
+        if (more) {
+            tile_store<!TA>(As[cur ^ 1], ra);
+            tile_store<TB>(Bs[cur ^ 1], rb);
+        }
         __syncthreads();
+        cur ^= 1;
     }
+    if (csum && n0 + tid < N) colsum[(int64_t)blockIdx.z * N + n0 + tid] = cs;
     // accumulator j of lane l holds row 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
@@ -136,25 +194,33 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, con
     }
 }
 
-// nsplit > 1 (EPI_F32 only): C holds nsplit slices [M][ldc] of partial sums over K
+// nsplit > 1 (EPI_F32 only): C holds nsplit slices [M][ldc] of partial sums over K.  colsum (nullable,
+// B stored [K][N]): [nsplit][N] column sums of B over each slice's K range.
 template <bool TA, bool TB, int EPI>
 hipError_t gemm(int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb, void* C, int ldc,
-                const float* bias, const uint16_t* mask, int ldm, hipStream_t st, int nsplit = 1)
+                const float* bias, const uint16_t* mask, int ldm, hipStream_t st, int nsplit = 1,
+                float* colsum = nullptr)
 {
     const int kchunk = (((K + nsplit - 1) / nsplit) + GBK - 1) / GBK * GBK;
     dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM, nsplit);
     hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, bias,
-                       mask, ldm, kchunk);
+                       mask, ldm, kchunk, colsum);
     return hipGetLastError();
 }
 
-// out[i] = sum over z of parts[z * n + i], z in order (deterministic split-K reduction)
-__global__ void splitk_sum_kernel(int64_t n, int nsplit, const float* __restrict__ parts, float* __restrict__ out)
+// Deterministic split-K reduction of a layer's gradients, slices summed in z order:
+// out[i] = sum_z wparts[z][i] for i < nw (weights), out[nw + j] = sum_z bparts[z][j] for
+// j < nb (the bias, stored right after the weights).
+__global__ void splitk_sum_kernel(int64_t nw, int nb, int nsplit, const float* __restrict__ wparts,
+                                  const float* __restrict__ bparts, float* __restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= nw + nb) return;
+    const bool w = i < nw;
+    const float* src = w ? wparts + i : bparts + (i - nw);
+    const int64_t stride = w ? nw : nb;
     float a = 0.0f;
-    for (int z = 0; z < nsplit; ++z) a += parts[(int64_t)z * n + i];
+    for (int z = 0; z < nsplit; ++z) a += src[(int64_t)z * stride];
     out[i] = a;
 }
 
@@ -212,6 +278,7 @@ struct opmm_surrogate {
     float* dur = nullptr;     // [B]
     uint64_t* counter = nullptr;  // device step counter for data generation (graph-replay safe)
     float* gpart = nullptr;       // split-K partial weight gradients [SPLITK_MAX][512 x 512]
+    float* cpart = nullptr;       // split-K partial bias gradients [SPLITK_MAX][512]
 };
 
 namespace {
@@ -360,21 +427,6 @@ __global__ void mse_grad_kernel(int B, const float* __restrict__ out, const floa
 }
 
 // Column sums: db[n] = sum_b dY[b][n]; one block per column, tree reduction
-__global__ __launch_bounds__(256) void colsum_kernel(int B, int N, const uint16_t* __restrict__ dy,
-                                                     float* __restrict__ db)
-{
-    __shared__ float red[256];
-    const int n = blockIdx.x;
-    float s = 0.0f;
-    for (int b = threadIdx.x; b < B; b += 256) s += bf2f(dy[(int64_t)b * N + n]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) db[n] = red[0];
-}
 
 __global__ void adam_kernel(int64_t n, float* __restrict__ w, uint16_t* __restrict__ wb, const float* __restrict__ g,
                             float* __restrict__ m1, float* __restrict__ m2, float lr, float b1, float b2, float eps,
@@ -468,6 +520,7 @@ int sg_alloc(opmm_surrogate* sg, int batch)
     SG_HIP(hipMalloc(&sg->tlen, sizeof(int32_t) * (size_t)batch));
     SG_HIP(hipMalloc(&sg->dur, sizeof(float) * (size_t)batch));
     if (!sg->gpart) SG_HIP(hipMalloc(&sg->gpart, sizeof(float) * (size_t)SPLITK_MAX * 512 * 512));
+    if (!sg->cpart) SG_HIP(hipMalloc(&sg->cpart, sizeof(float) * (size_t)SPLITK_MAX * 512));
     sg->cap_batch = batch;
     return OPMM_OK;
 }
@@ -499,24 +552,26 @@ int sg_forward(opmm_surrogate* sg, int B, hipStream_t st)
 }
 
 // backward pass: needs sg->out and sg->target; gradients into sg->g
-int sg_backward(opmm_surrogate* sg, int B, hipStream_t st)
+// loss: device scalar the MSE is accumulated into (zeroed by the caller)
+int sg_backward(opmm_surrogate* sg, int B, float* loss, hipStream_t st)
 {
     const int NO = WIDTH[NL];
     hipLaunchKernelGGL(mse_grad_kernel, dim3(blocks((int64_t)B * NO, 256)), dim3(256), 0, st, B, sg->out, sg->target,
-                       sg->dact[0], sg->loss);
+                       sg->dact[0], loss);
     for (int l = NL - 1; l >= 0; --l) {
         const int K = WIDTH[l], N = WIDTH[l + 1];
         const uint16_t* dy = (l == NL - 1) ? sg->dact[0] : sg->dact[l + 1];
         // dW_l = act[l]^T . dY   ([K][B] x [B][N]): the batch is the long contraction, split it so
         // that a 512 x 512 gradient fills the chip, then sum the slices in a fixed order
         const int nsplit = std::min(SPLITK_MAX, std::max(1, (B + SPLITK_ROWS - 1) / SPLITK_ROWS));
+        // the bias gradient (column sums of dY) comes out of the same GEMM
         hipError_t e = gemm<true, false, EPI_F32>(K, N, B, sg->act[l], K, dy, N, nsplit > 1 ? sg->gpart : sg->g + w_off(l),
-                                                  N, nullptr, nullptr, 0, st, nsplit);
+                                                  N, nullptr, nullptr, 0, st, nsplit,
+                                                  nsplit > 1 ? sg->cpart : sg->g + b_off(l));
         if (e != hipSuccess) return opmm_rt::hip_fail(sg->ctx, e, "gemm dW");
         if (nsplit > 1)
-            hipLaunchKernelGGL(splitk_sum_kernel, dim3(blocks((int64_t)K * N, 256)), dim3(256), 0, st, (int64_t)K * N,
-                               nsplit, sg->gpart, sg->g + w_off(l));
-        hipLaunchKernelGGL(colsum_kernel, dim3(N), dim3(256), 0, st, B, N, dy, sg->g + b_off(l));
+            hipLaunchKernelGGL(splitk_sum_kernel, dim3(blocks((int64_t)K * N + N, 256)), dim3(256), 0, st,
+                               (int64_t)K * N, N, nsplit, sg->gpart, sg->cpart, sg->g + w_off(l));
         if (l > 0) {
             // dX_l = (dY . W_l^T) masked by act[l] > 0   ([B][N] x [N][K])
             e = gemm<false, true, EPI_RELU_MASK_BF16>(B, K, N, dy, N, sg->wb + w_off(l), N, sg->dact[l], K, nullptr,
@@ -585,7 +640,7 @@ int opmm_surrogate_destroy(opmm_surrogate* sg)
     }
     for (void* p : {(void*)sg->w, (void*)sg->wb, (void*)sg->g, (void*)sg->m1, (void*)sg->m2, (void*)sg->out,
                     (void*)sg->target, (void*)sg->loss, (void*)sg->trace, (void*)sg->tlen, (void*)sg->dur,
-                    (void*)sg->counter, (void*)sg->gpart})
+                    (void*)sg->counter, (void*)sg->gpart, (void*)sg->cpart})
         if (p) (void)hipFree(p);
     delete sg;
     return OPMM_OK;
@@ -641,7 +696,7 @@ int opmm_surrogate_backward(opmm_surrogate* sg, const uint16_t* feat, const floa
     SG_HIP(hipMemcpyAsync(sg->target, target, sizeof(float) * (size_t)B * WIDTH[NL], hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(fill_f32_kernel, dim3(1), dim3(64), 0, st, sg->loss, 1, 0.0f);
     if ((rc = sg_forward(sg, B, st)) != OPMM_OK) return rc;
-    if ((rc = sg_backward(sg, B, st)) != OPMM_OK) return rc;
+    if ((rc = sg_backward(sg, B, sg->loss, st)) != OPMM_OK) return rc;
     if (loss_out) {
         SG_HIP(hipMemcpyAsync(loss_out, sg->loss, sizeof(float), hipMemcpyDeviceToHost, st));
         SG_HIP(hipStreamSynchronize(st));
@@ -673,23 +728,29 @@ int opmm_surrogate_train(opmm_surrogate* sg, uint64_t data_seed, int32_t B, int3
     hipStream_t st = (hipStream_t)stream;
     int rc;
     if ((rc = sg_alloc(sg, B)) != OPMM_OK) return rc;
-    const int64_t total = sg->step + n_steps;
-    const int64_t first = sg->step;
-    for (int32_t t = 0; t < n_steps; ++t) {
-        hipLaunchKernelGGL(fill_f32_kernel, dim3(1), dim3(64), 0, st, sg->loss, 1, 0.0f);
+    // per-step losses stay on the device until the end: no host round trip inside the loop
+    float* hist = nullptr;
+    if (n_steps > 0) {
+        SG_HIP(hipMallocAsync((void**)&hist, sizeof(float) * (size_t)n_steps, st));
+        hipLaunchKernelGGL(fill_f32_kernel, dim3(blocks(n_steps, 256)), dim3(256), 0, st, hist, (int64_t)n_steps, 0.0f);
+    }
+    for (int32_t t = 0; t < n_steps && rc == OPMM_OK; ++t) {
         hipLaunchKernelGGL(gen_batch_kernel, dim3(blocks(B, 64)), dim3(64), 0, st, B, data_seed, sg->counter, spread,
                            sigma_max, sg->trace, sg->act[0], sg->target);
-        if ((rc = sg_forward(sg, B, st)) != OPMM_OK) return rc;
-        if ((rc = sg_backward(sg, B, st)) != OPMM_OK) return rc;
+        if ((rc = sg_forward(sg, B, st)) != OPMM_OK) break;
+        if ((rc = sg_backward(sg, B, hist + t, st)) != OPMM_OK) break;
         // cosine decay from lr0 to lr_min over this call's steps
         const double ph = n_steps > 1 ? (double)t / (double)(n_steps - 1) : 1.0;
         const float lr = (float)(lr_min + 0.5 * (lr0 - lr_min) * (1.0 + std::cos(M_PI * ph)));
-        if ((rc = sg_adam(sg, lr, st)) != OPMM_OK) return rc;
+        if ((rc = sg_adam(sg, lr, st)) != OPMM_OK) break;
         hipLaunchKernelGGL(bump_kernel, dim3(1), dim3(64), 0, st, sg->counter);
-        if (loss_out) SG_HIP(hipMemcpyAsync(loss_out + t, sg->loss, sizeof(float), hipMemcpyDeviceToHost, st));
     }
-    (void)total;
-    (void)first;
+    if (rc == OPMM_OK && loss_out && n_steps > 0)
+        rc = hipMemcpyAsync(loss_out, hist, sizeof(float) * (size_t)n_steps, hipMemcpyDeviceToHost, st) == hipSuccess
+                 ? OPMM_OK
+                 : opmm_rt::fail(sg->ctx, OPMM_EDEVICE, "loss copy failed");
+    if (hist) (void)hipFreeAsync(hist, st);
+    if (rc != OPMM_OK) return rc;
     SG_HIP(hipGetLastError());
     SG_HIP(hipStreamSynchronize(st));
     return OPMM_OK;

@@ -346,11 +346,12 @@ class Surrogate:
     def forward(self, feat, out, stream=None):
         self._ctx._check(lib.opmm_surrogate_forward(self._h, _ptr(feat), feat.shape[0], _ptr(out), _stream(stream)))
 
-    def backward(self, feat, target, stream=None) -> float:
+    def backward(self, feat, target, stream=None, want_loss=True):
+        """Forward + backward on one batch; returns the loss (which synchronises) or None."""
         loss = ctypes.c_float()
         self._ctx._check(lib.opmm_surrogate_backward(self._h, _ptr(feat), _ptr(target), feat.shape[0],
-                                                     ctypes.byref(loss), _stream(stream)))
-        return loss.value
+                                                     ctypes.byref(loss) if want_loss else None, _stream(stream)))
+        return loss.value if want_loss else None
 
     def adam_step(self, lr, stream=None):
         self._ctx._check(lib.opmm_surrogate_adam_step(self._h, ctypes.c_float(lr), _stream(stream)))
