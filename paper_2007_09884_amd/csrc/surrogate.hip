@@ -279,11 +279,17 @@ struct opmm_surrogate {
     uint64_t* counter = nullptr;  // device step counter for data generation (graph-replay safe)
     float* gpart = nullptr;       // split-K partial weight gradients [SPLITK_MAX][512 x 512]
     float* cpart = nullptr;       // split-K partial bias gradients [SPLITK_MAX][512]
+    // training data ring: GEN_BATCHES consecutive batches generated in one launch
+    uint16_t* ring_feat = nullptr;  // [GEN_BATCHES][ring_cap][256]
+    float* ring_tgt = nullptr;      // [GEN_BATCHES][ring_cap][18]
+    float* ring_trace = nullptr;    // [GEN_BATCHES][ring_cap][MAX_T_GEN]
+    int ring_cap = 0;
 };
 
 namespace {
 
 constexpr int MAX_T_GEN = 160;
+constexpr int GEN_BATCHES = 16;  // training batches generated per launch (one lane per saccade each)
 
 __global__ void fill_f32_kernel(float* p, int64_t n, float v)
 {
@@ -372,7 +378,11 @@ __global__ __launch_bounds__(64) void gen_batch_kernel(int B, uint64_t seed, con
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     bool valid = i < B;
     int ii = valid ? i : 0;
-    const uint64_t step = *counter;
+    // grid y: consecutive batches of the data stream, batch j keyed by step counter + j
+    const uint64_t step = *counter + blockIdx.y;
+    trace += (int64_t)blockIdx.y * B * MAX_T_GEN;
+    feat += (int64_t)blockIdx.y * B * (2 * NPTS);
+    target += (int64_t)blockIdx.y * B * P;
     auto uni = [&](uint32_t k) {
         uint64_t z = splitmix64(seed, 1 + ((step << 40) | ((uint64_t)ii << 8) | k));
         return (float)(z >> 40) * 0x1p-24f;  // [0, 1)
@@ -425,8 +435,6 @@ __global__ void mse_grad_kernel(int B, const float* __restrict__ out, const floa
     }
     if (threadIdx.x == 0) atomicAdd(loss, red[0] / (float)n);
 }
-
-// Column sums: db[n] = sum_b dY[b][n]; one block per column, tree reduction
 
 __global__ void adam_kernel(int64_t n, float* __restrict__ w, uint16_t* __restrict__ wb, const float* __restrict__ g,
                             float* __restrict__ m1, float* __restrict__ m2, float lr, float b1, float b2, float eps,
@@ -533,8 +541,8 @@ int surrogate_reserve(opmm_surrogate* sg, int batch) { return sg_alloc(sg, batch
 
 namespace {
 
-// forward pass over B rows of act[0]; output in sg->out
-int sg_forward(opmm_surrogate* sg, int B, hipStream_t st)
+// forward pass over the B rows of x0 (features); output in sg->out
+int sg_forward(opmm_surrogate* sg, int B, const uint16_t* x0, hipStream_t st)
 {
     for (int l = 0; l < NL; ++l) {
         const uint16_t* W = sg->wb + w_off(l);
@@ -542,21 +550,22 @@ int sg_forward(opmm_surrogate* sg, int B, hipStream_t st)
         const int K = WIDTH[l], N = WIDTH[l + 1];
         hipError_t e;
         if (l < NL - 1)
-            e = gemm<false, false, EPI_BIAS_RELU_BF16>(B, N, K, sg->act[l], K, W, N, sg->act[l + 1], N, bias, nullptr,
-                                                       0, st);
+            e = gemm<false, false, EPI_BIAS_RELU_BF16>(B, N, K, l == 0 ? x0 : sg->act[l], K, W, N, sg->act[l + 1], N,
+                                                       bias, nullptr, 0, st);
         else
-            e = gemm<false, false, EPI_BIAS_F32>(B, N, K, sg->act[l], K, W, N, sg->out, N, bias, nullptr, 0, st);
+            e = gemm<false, false, EPI_BIAS_F32>(B, N, K, l == 0 ? x0 : sg->act[l], K, W, N, sg->out, N, bias, nullptr,
+                                                 0, st);
         if (e != hipSuccess) return opmm_rt::hip_fail(sg->ctx, e, "gemm forward");
     }
     return OPMM_OK;
 }
 
-// backward pass: needs sg->out and sg->target; gradients into sg->g
+// backward pass after sg_forward on x0, against tgt [B][18]; gradients into sg->g
 // loss: device scalar the MSE is accumulated into (zeroed by the caller)
-int sg_backward(opmm_surrogate* sg, int B, float* loss, hipStream_t st)
+int sg_backward(opmm_surrogate* sg, int B, const uint16_t* x0, const float* tgt, float* loss, hipStream_t st)
 {
     const int NO = WIDTH[NL];
-    hipLaunchKernelGGL(mse_grad_kernel, dim3(blocks((int64_t)B * NO, 256)), dim3(256), 0, st, B, sg->out, sg->target,
+    hipLaunchKernelGGL(mse_grad_kernel, dim3(blocks((int64_t)B * NO, 256)), dim3(256), 0, st, B, sg->out, tgt,
                        sg->dact[0], loss);
     for (int l = NL - 1; l >= 0; --l) {
         const int K = WIDTH[l], N = WIDTH[l + 1];
@@ -565,7 +574,8 @@ int sg_backward(opmm_surrogate* sg, int B, float* loss, hipStream_t st)
         // that a 512 x 512 gradient fills the chip, then sum the slices in a fixed order
         const int nsplit = std::min(SPLITK_MAX, std::max(1, (B + SPLITK_ROWS - 1) / SPLITK_ROWS));
         // the bias gradient (column sums of dY) comes out of the same GEMM
-        hipError_t e = gemm<true, false, EPI_F32>(K, N, B, sg->act[l], K, dy, N, nsplit > 1 ? sg->gpart : sg->g + w_off(l),
+        hipError_t e = gemm<true, false, EPI_F32>(K, N, B, l == 0 ? x0 : sg->act[l], K, dy, N,
+                                                  nsplit > 1 ? sg->gpart : sg->g + w_off(l),
                                                   N, nullptr, nullptr, 0, st, nsplit,
                                                   nsplit > 1 ? sg->cpart : sg->g + b_off(l));
         if (e != hipSuccess) return opmm_rt::hip_fail(sg->ctx, e, "gemm dW");
@@ -640,7 +650,8 @@ int opmm_surrogate_destroy(opmm_surrogate* sg)
     }
     for (void* p : {(void*)sg->w, (void*)sg->wb, (void*)sg->g, (void*)sg->m1, (void*)sg->m2, (void*)sg->out,
                     (void*)sg->target, (void*)sg->loss, (void*)sg->trace, (void*)sg->tlen, (void*)sg->dur,
-                    (void*)sg->counter, (void*)sg->gpart, (void*)sg->cpart})
+                    (void*)sg->counter, (void*)sg->gpart, (void*)sg->cpart, (void*)sg->ring_feat,
+                    (void*)sg->ring_tgt, (void*)sg->ring_trace})
         if (p) (void)hipFree(p);
     delete sg;
     return OPMM_OK;
@@ -679,7 +690,7 @@ int opmm_surrogate_forward(opmm_surrogate* sg, const uint16_t* feat, int32_t B, 
     int rc;
     if ((rc = sg_alloc(sg, B)) != OPMM_OK) return rc;
     SG_HIP(hipMemcpyAsync(sg->act[0], feat, sizeof(uint16_t) * (size_t)B * WIDTH[0], hipMemcpyDeviceToDevice, st));
-    if ((rc = sg_forward(sg, B, st)) != OPMM_OK) return rc;
+    if ((rc = sg_forward(sg, B, sg->act[0], st)) != OPMM_OK) return rc;
     SG_HIP(hipMemcpyAsync(out, sg->out, sizeof(float) * (size_t)B * WIDTH[NL], hipMemcpyDeviceToDevice, st));
     return OPMM_OK;
 }
@@ -695,8 +706,8 @@ int opmm_surrogate_backward(opmm_surrogate* sg, const uint16_t* feat, const floa
     SG_HIP(hipMemcpyAsync(sg->act[0], feat, sizeof(uint16_t) * (size_t)B * WIDTH[0], hipMemcpyDeviceToDevice, st));
     SG_HIP(hipMemcpyAsync(sg->target, target, sizeof(float) * (size_t)B * WIDTH[NL], hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(fill_f32_kernel, dim3(1), dim3(64), 0, st, sg->loss, 1, 0.0f);
-    if ((rc = sg_forward(sg, B, st)) != OPMM_OK) return rc;
-    if ((rc = sg_backward(sg, B, sg->loss, st)) != OPMM_OK) return rc;
+    if ((rc = sg_forward(sg, B, sg->act[0], st)) != OPMM_OK) return rc;
+    if ((rc = sg_backward(sg, B, sg->act[0], sg->target, sg->loss, st)) != OPMM_OK) return rc;
     if (loss_out) {
         SG_HIP(hipMemcpyAsync(loss_out, sg->loss, sizeof(float), hipMemcpyDeviceToHost, st));
         SG_HIP(hipStreamSynchronize(st));
@@ -728,6 +739,18 @@ int opmm_surrogate_train(opmm_surrogate* sg, uint64_t data_seed, int32_t B, int3
     hipStream_t st = (hipStream_t)stream;
     int rc;
     if ((rc = sg_alloc(sg, B)) != OPMM_OK) return rc;
+    if (sg->ring_cap < B) {
+        SG_HIP(hipDeviceSynchronize());
+        for (void* p : {(void*)sg->ring_feat, (void*)sg->ring_tgt, (void*)sg->ring_trace})
+            if (p) (void)hipFree(p);
+        sg->ring_feat = nullptr;
+        sg->ring_tgt = sg->ring_trace = nullptr;
+        sg->ring_cap = 0;
+        SG_HIP(hipMalloc(&sg->ring_feat, sizeof(uint16_t) * (size_t)GEN_BATCHES * B * WIDTH[0]));
+        SG_HIP(hipMalloc(&sg->ring_tgt, sizeof(float) * (size_t)GEN_BATCHES * B * WIDTH[NL]));
+        SG_HIP(hipMalloc(&sg->ring_trace, sizeof(float) * (size_t)GEN_BATCHES * B * MAX_T_GEN));
+        sg->ring_cap = B;
+    }
     // per-step losses stay on the device until the end: no host round trip inside the loop
     float* hist = nullptr;
     if (n_steps > 0) {
@@ -735,10 +758,17 @@ int opmm_surrogate_train(opmm_surrogate* sg, uint64_t data_seed, int32_t B, int3
         hipLaunchKernelGGL(fill_f32_kernel, dim3(blocks(n_steps, 256)), dim3(256), 0, st, hist, (int64_t)n_steps, 0.0f);
     }
     for (int32_t t = 0; t < n_steps && rc == OPMM_OK; ++t) {
-        hipLaunchKernelGGL(gen_batch_kernel, dim3(blocks(B, 64)), dim3(64), 0, st, B, data_seed, sg->counter, spread,
-                           sigma_max, sg->trace, sg->act[0], sg->target);
-        if ((rc = sg_forward(sg, B, st)) != OPMM_OK) break;
-        if ((rc = sg_backward(sg, B, hist + t, st)) != OPMM_OK) break;
+        // the next GEN_BATCHES batches of the data stream in one launch (keyed by the step counter, so
+        // batch t is the same as when generated alone)
+        const int j = t % GEN_BATCHES;
+        if (j == 0)
+            hipLaunchKernelGGL(gen_batch_kernel, dim3(blocks(B, 64), std::min(GEN_BATCHES, n_steps - t)), dim3(64), 0,
+                               st, B, data_seed, sg->counter, spread, sigma_max, sg->ring_trace, sg->ring_feat,
+                               sg->ring_tgt);
+        const uint16_t* x0 = sg->ring_feat + (size_t)j * B * WIDTH[0];
+        const float* tgt = sg->ring_tgt + (size_t)j * B * WIDTH[NL];
+        if ((rc = sg_forward(sg, B, x0, st)) != OPMM_OK) break;
+        if ((rc = sg_backward(sg, B, x0, tgt, hist + t, st)) != OPMM_OK) break;
         // cosine decay from lr0 to lr_min over this call's steps
         const double ph = n_steps > 1 ? (double)t / (double)(n_steps - 1) : 1.0;
         const float lr = (float)(lr_min + 0.5 * (lr0 - lr_min) * (1.0 + std::cos(M_PI * ph)));
@@ -779,7 +809,7 @@ int opmm_surrogate_predict(opmm_surrogate* sg, const float* pos, int64_t pos_len
     if ((rc = opmm_rt::project_batch(ctx, pos, pos_len, sacs, S, &sd, &proj, st)) != OPMM_OK) return rc;
     if ((rc = sg_alloc(sg, S)) != OPMM_OK) return rc;
     hipLaunchKernelGGL(features_kernel, dim3(blocks(S, 128)), dim3(128), 0, st, S, sd, proj, dt_ms, sg->act[0]);
-    if ((rc = sg_forward(sg, S, st)) != OPMM_OK) return rc;
+    if ((rc = sg_forward(sg, S, sg->act[0], st)) != OPMM_OK) return rc;
     hipLaunchKernelGGL(denorm_kernel, dim3(blocks((int64_t)S * P, 256)), dim3(256), 0, st, S, sg->out, sd, box_frac,
                        opc_out);
     SG_HIP(hipGetLastError());
