@@ -93,8 +93,10 @@ def test_forward_matches_reference(ctx, opmm):
     sg.close()
 
 
-def test_gradients_match_reference(ctx, opmm):
-    B = 256
+@pytest.mark.parametrize("B", [256, 1500])
+def test_gradients_match_reference(ctx, opmm, B):
+    """B = 1500 splits the weight-gradient contraction into three batch slices (the last one ragged),
+    with the bias gradient summed per slice inside the same GEMM."""
     w, x, t = random_problem(B, 2)
     sg = opmm.Surrogate(ctx)
     sg.set_params(w)
