@@ -58,16 +58,18 @@ __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v)
 // Project each trace on the movement direction: r_k = h cos + v sin, and the
 // energy orthogonal to it, Q = sum (v cos - h sin)^2.  Then
 // sum_k sum_c (pos - theta u)^2 = sum_k (r_k - theta_k)^2 + Q for every theta.
-__global__ void prep_kernel(int S, const SacDev* __restrict__ sacs, const float* __restrict__ pos,
-                            float* __restrict__ proj, double* __restrict__ qorth,
-                            int32_t* __restrict__ status)
+// One wave per saccade (block s): lanes take every 64th sample, then the
+// wave combines Q and the finiteness flag.
+__global__ __launch_bounds__(64) void prep_kernel(int S, const SacDev* __restrict__ sacs, const float* __restrict__ pos,
+                                                  float* __restrict__ proj, double* __restrict__ qorth,
+                                                  int32_t* __restrict__ status)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.x;
     if (s >= S) return;
     const SacDev sd = sacs[s];
     bool ok = true;
     double q = 0.0;
-    for (int k = 0; k < sd.T; ++k) {
+    for (int k = threadIdx.x; k < sd.T; k += 64) {
         double h = pos[sd.pos_off + (int64_t)k * sd.C];
         double v = sd.C == 2 ? (double)pos[sd.pos_off + (int64_t)k * sd.C + 1] : 0.0;
         ok = ok && isfinite(h) && isfinite(v);
@@ -78,8 +80,13 @@ __global__ void prep_kernel(int S, const SacDev* __restrict__ sacs, const float*
         }
         proj[sd.proj_off + k] = (float)r;
     }
-    qorth[sd.slot] = q;
-    status[sd.slot] = ok ? OPMM_ST_OK : OPMM_ST_NONFINITE_INPUT;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) q += __shfl_xor(q, o);
+    ok = __all(ok);
+    if (threadIdx.x == 0) {
+        qorth[sd.slot] = q;
+        status[sd.slot] = ok ? OPMM_ST_OK : OPMM_ST_NONFINITE_INPUT;
+    }
 }
 
 // Round-0 box: centre = nominal (PW = D - 6), w = box_frac * centre, bounds
@@ -446,22 +453,28 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_persistent_kernel(
 
 // Final report: re-simulate each saccade's winner and score it on the full
 // 2-channel trace (RMSE and mean absolute difference), FP64 accumulation.
-__global__ void report_kernel(int S, const SacDev* __restrict__ sacs, const float* __restrict__ pos,
-                              float dt, const float* __restrict__ centre, float* opc_out, float* rmse_out,
-                              float* mae_out, const int32_t* __restrict__ status, int32_t* status_out)
+// One wave per saccade (block s): the wave stages the trace in LDS, every
+// lane runs the same simulation and lane 0 writes the results.
+__global__ __launch_bounds__(64) void report_kernel(int S, const SacDev* __restrict__ sacs, const float* __restrict__ pos,
+                                                    float dt, const float* __restrict__ centre, float* opc_out,
+                                                    float* rmse_out, float* mae_out, const int32_t* __restrict__ status,
+                                                    int32_t* status_out)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    bool act = s < S;
-    SacDev sd = sacs[act ? s : 0];
+    __shared__ float tr[2 * OPMM_MAX_T];
+    const int s = blockIdx.x;
+    if (s >= S) return;
+    const SacDev sd = sacs[s];
+    for (int i = threadIdx.x; i < sd.T * sd.C; i += 64) tr[i] = pos[sd.pos_off + i];
+    __syncthreads();
     float p[P];
     for (int j = 0; j < P; ++j) p[j] = centre[(int64_t)sd.slot * P + j];
     Plant pl;
     plant_setup(p, sd.amp, dt, pl);
     R frac;
     int k0 = pulse_end_sample(pl.pwd, sd.T, frac);
-    Cost2dSink sink{pos + sd.pos_off, sd.C, sd.cphi, sd.sphi, 0.0, 0.0};
+    Cost2dSink sink{tr, sd.C, sd.cphi, sd.sphi, 0.0, 0.0};
     run_trajectory<1>(pl, sd.T, (R)dt, k0, frac, k0, k0, sink);
-    if (!act) return;
+    if (threadIdx.x != 0) return;
     const int32_t st = status[sd.slot];
     const bool bad = (st & OPMM_ST_NONFINITE_INPUT) != 0;
     const double n = (double)sd.T * sd.C;
@@ -821,7 +834,7 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
     uint32_t* head = ready + S;
     uint32_t* errflag = head + 1;
 
-    hipLaunchKernelGGL(prep_kernel, dim3(blocks_for(S, 128)), dim3(128), 0, st, S, d_sacs, pos, proj, qorth, status);
+    hipLaunchKernelGGL(prep_kernel, dim3(S), dim3(64), 0, st, S, d_sacs, pos, proj, qorth, status);
     hipLaunchKernelGGL(init_kernel, dim3(blocks_for((int64_t)S * P, 256)), dim3(256), 0, st, S, d_sacs, prm->box_frac,
                        prm->w_init_frac, seed_opc, centre, hw, lo, hi, status);
     hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for((int64_t)R * S, 256)), dim3(256), 0, st, keys,
@@ -854,7 +867,7 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
             }
         }
     }
-    hipLaunchKernelGGL(report_kernel, dim3(blocks_for(S, 64)), dim3(64), 0, st, S, d_sacs, pos, prm->dt_ms, centre,
+    hipLaunchKernelGGL(report_kernel, dim3(S), dim3(64), 0, st, S, d_sacs, pos, prm->dt_ms, centre,
                        opc_out, rmse_out, mae_out, status, status_out);
     OPMM_HIP(ctx, hipGetLastError());
     return OPMM_OK;
@@ -933,7 +946,8 @@ SacDev make_record(const opmm_saccade& s, int n_cand_default)
 
 hipError_t launch_prep(const SacDev* sacs, int n, const float* pos, const SlotState& ss, hipStream_t st)
 {
-    hipLaunchKernelGGL(prep_kernel, dim3(blocks_for(n, 128)), dim3(128), 0, st, n, sacs, pos, ss.proj, ss.qorth,
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(prep_kernel, dim3(n), dim3(64), 0, st, n, sacs, pos, ss.proj, ss.qorth,
                        ss.status);
     return hipGetLastError();
 }
@@ -974,7 +988,8 @@ hipError_t launch_refine(const SacDev* sacs, int n, float shrink, const SlotStat
 hipError_t launch_report(const SacDev* sacs, int n, const float* pos, float dt, const SlotState& ss, float* opc_out,
                          float* rmse_out, float* mae_out, int32_t* status_out, hipStream_t st)
 {
-    hipLaunchKernelGGL(report_kernel, dim3(blocks_for(n, 64)), dim3(64), 0, st, n, sacs, pos, dt, ss.centre, opc_out,
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(report_kernel, dim3(n), dim3(64), 0, st, n, sacs, pos, dt, ss.centre, opc_out,
                        rmse_out, mae_out, ss.status, status_out);
     return hipGetLastError();
 }
@@ -997,8 +1012,10 @@ int project_batch(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_s
     if ((rc = ensure(ctx, sc.proj, sizeof(float) * total_T)) != OPMM_OK) return rc;
     if ((rc = ensure(ctx, sc.qorth, sizeof(double) * S)) != OPMM_OK) return rc;
     if ((rc = ensure(ctx, sc.status, sizeof(int32_t) * S)) != OPMM_OK) return rc;
-    hipLaunchKernelGGL(prep_kernel, dim3(blocks_for(S, 128)), dim3(128), 0, st, S, (const SacDev*)sc.sacs.p, pos,
-                       (float*)sc.proj.p, (double*)sc.qorth.p, (int32_t*)sc.status.p);
+    if (S > 0) {
+        hipLaunchKernelGGL(prep_kernel, dim3(S), dim3(64), 0, st, S, (const SacDev*)sc.sacs.p, pos,
+                           (float*)sc.proj.p, (double*)sc.qorth.p, (int32_t*)sc.status.p);
+    }
     OPMM_HIP(ctx, hipGetLastError());
     *sacs_dev = (const SacDev*)sc.sacs.p;
     *proj = (const float*)sc.proj.p;
@@ -1148,7 +1165,7 @@ int opmm_score(opmm_ctx* ctx, const float* opc, int64_t n, const float* pos, int
     if ((rc = ensure(ctx, sc.proj, sizeof(float) * total_T)) != OPMM_OK) return rc;
     if ((rc = ensure(ctx, sc.qorth, sizeof(double))) != OPMM_OK) return rc;
     if ((rc = ensure(ctx, sc.status, sizeof(int32_t))) != OPMM_OK) return rc;
-    hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(128), 0, st, 1, (const SacDev*)sc.sacs.p, pos, (float*)sc.proj.p,
+    hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(64), 0, st, 1, (const SacDev*)sc.sacs.p, pos, (float*)sc.proj.p,
                        (double*)sc.qorth.p, (int32_t*)sc.status.p);
     hipLaunchKernelGGL(score_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, opc, (const float*)sc.proj.p,
                        sac->T, sac->C, (const double*)sc.qorth.p, sac->amp_deg, dt_ms, rmse_out);
