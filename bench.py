@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the batched-uneven (persistent launch) leg")
     ap.add_argument("--no-nm", action="store_true")
+    ap.add_argument("--no-ivt", action="store_true", help="skip the I-VT leg (gaze stream -> saccades -> fit)")
+    ap.add_argument("--ivt-saccades", type=int, default=2000)
+    ap.add_argument("--no-model9", action="store_true", help="skip the 9-parameter model leg")
     ap.add_argument("--nm-iter", type=int, default=2000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy 3 times (calibrates HBM byte counters)")
@@ -259,6 +262,45 @@ def uneven_leg(a, ctx, opmm, torch, synth):
         pl.close()
         out[name] = {"tile": opmm.tile_names()[p.tile], "ms_per_step": dt * 1e3, "candidate_sims_per_s": sims / dt,
                      "saccades_fitted_per_s": S / dt}
+    return out
+
+
+def ivt_leg(a, ctx, opmm, torch, synth):
+    """I-VT on a synthetic 1 kHz gaze stream: fixations of 100-300 ms (0.003 deg noise) joined by
+    plant-simulated saccades with the full configuration's amplitude, direction and duration draws
+    (true OPC = nominal x U[0.8, 1.2]).  Timed: one extraction call, records back on the host."""
+    rng = np.random.default_rng(synth.BASE_SEED + 5)
+    n = a.ivt_saccades
+    amp = rng.uniform(2.0, 30.0, n)
+    phi = np.radians(rng.uniform(0.0, 360.0, n))
+    dur = 2.2 * amp + 21.0
+    T = np.ceil(dur).astype(np.int64) + 30           # the saccade and its settling
+    fix = rng.integers(100, 301, n)
+    true = np.stack([opmm.nominal(float(d)) for d in dur]) * rng.uniform(0.8, 1.2, (n, 18)).astype(np.float32)
+    Tmax = int(T.max())
+    theta = torch.zeros(n, Tmax, device="cuda")
+    ctx.simulate(torch.from_numpy(true.astype(np.float32)).cuda(), torch.from_numpy(amp.astype(np.float32)).cuda(),
+                 Tmax, theta)
+    th = theta.cpu().numpy()
+    parts, p = [], np.zeros(2)
+    for i in range(n):
+        u = np.array([math.cos(phi[i]), math.sin(phi[i])])
+        parts.append(np.tile(p, (int(fix[i]), 1)))
+        parts.append(p + th[i, :T[i], None] * u[None, :])
+        p = p + amp[i] * u
+    parts.append(np.tile(p, (200, 1)))
+    g = np.concatenate(parts)
+    g = (g + 0.003 * rng.standard_normal(g.shape)).astype(np.float32)
+    gaze = torch.from_numpy(g).cuda()
+    pos_out = torch.empty(2 * g.shape[0], device="cuda")
+    ctx.ivt_extract(gaze, pos_out, max_out=n + 64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs, src = ctx.ivt_extract(gaze, pos_out, max_out=n + 64)
+    ivt_s = time.perf_counter() - t0
+    out = {"stream_samples": int(g.shape[0]), "stream_seconds": g.shape[0] * 1e-3, "planted": n,
+           "extracted": int(len(recs)), "seconds": ivt_s, "samples_per_s": g.shape[0] / ivt_s,
+           "realtime_factor": g.shape[0] * 1e-3 / ivt_s}
     return out
 
 
@@ -485,6 +527,14 @@ def main():
         out["autotune"] = tuned
     if not a.no_uneven:
         out["batched_uneven"] = uneven_leg(a, ctx, opmm, torch, synth)
+    if not a.no_model9:
+        # the 9-parameter model (Table 2) on the same batch and launch
+        p9 = opmm.fit_params(n_cand=N, n_rounds=R, mode=modes[a.mode], tile=prm.tile, model=9)
+        ms9 = time_plan(p9, reps=3)
+        out["model9"] = {"ms_per_step": ms9, "candidate_sims_per_s": sims / (ms9 * 1e-3),
+                         "mean_final_rmse_deg": float(rmse.mean().item())}
+    if not a.no_ivt:
+        out["ivt"] = ivt_leg(a, ctx, opmm, torch, synth)
     if not a.no_nm:
         out["nelder_mead"] = nm_leg(a, ctx, opmm, torch, pos, recs, rm, ms_per_step * 1e-3)
     if not a.no_surrogate:
