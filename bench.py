@@ -102,14 +102,28 @@ def sources_digest():
     return h.hexdigest()
 
 
+def executed_fig(flop_per_launch, launch_ms):
+    """Executed FP64 FLOP/s (the VALU's own count from the profile, over this run's launch time)."""
+    if flop_per_launch is None:
+        return None
+    t = flop_per_launch / (launch_ms * 1e-3) / 1e12
+    return {"flop_per_launch": flop_per_launch, "tflops": t, "frac": t / ALU_PEAK_TFLOPS,
+            "source": "SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes x active-lane share (rocprofv3 summary in profiles/)"}
+
+
 def profiled_traffic(mode, tile_name):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary
-    (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading), if that summary was taken on
-    the same launch mode and tile shape from the current kernel sources; else None."""
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading)."""
+    return profiled_value("traffic_per_launch_bytes", mode, tile_name)
+
+
+def profiled_value(key, mode, tile_name):
+    """A per-launch figure of the dominant kernel from the committed rocprofv3 counter summary
+    (a `key=value mode=.. tile=.. sources_sha256=..` line), if that summary was taken on the same
+    launch mode and tile shape from the current kernel sources; else None."""
     import glob
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
         for line in open(path):
-            if line.startswith("traffic_per_launch_bytes"):
+            if line.startswith(key + "="):
                 kv = dict(t.split("=", 1) for t in line.split()[1:])
                 if (kv.get("mode") == mode and kv.get("tile") == tile_name
                         and kv.get("sources_sha256") == sources_digest()):
@@ -521,6 +535,8 @@ def main():
                                "; launch_ms is the whole captured step: prep/init/refine/report kernels add ~1%)",
                      "launch_ms": launch_ms / n_launch, "launches_per_step": n_launch,
                      "algorithmic_flop_per_launch": flop // n_launch,
+                     "executed": executed_fig(profiled_value("executed_flop_per_launch", a.mode,
+                                                             opmm.tile_names()[prm.tile]), launch_ms / n_launch),
                      "frac_of_published_fp32_157": achieved / PUBLISHED_FP32_PEAK},
     }
     if tuned:
