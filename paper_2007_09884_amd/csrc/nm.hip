@@ -7,8 +7,9 @@
 // FP64, relative to the Table 1 nominal) and the projected trace live in LDS.
 // Every iteration lanes 0..21 build and evaluate reflection, expansion, outside
 // and inside contraction and the 18 shrink vertices at once; lane 0 takes the
-// Lagarias decision (reflection 1, expansion 2, contraction 1/2, shrink 1/2)
-// and keeps the simplex sorted (stable).  Each evaluation is the same plant
+// Lagarias decision (reflection 1, expansion 2, contraction 1/2, shrink 1/2);
+// the exit test, the vertex update and the stable re-sort run one coordinate
+// or one vertex per lane.  Each evaluation is the same plant
 // simulation and RMSE as the box search (points clamped to the search box and
 // rounded to FP32, the candidate format).
 #include <hip/hip_runtime.h>
@@ -37,7 +38,11 @@ struct NmSmem {
     double fp[NPT];
     double xb[P];
     double nom[P];
+    double tv[NV][P];  // sort staging
+    double tf[NV];
+    double dxc[P];     // per-coordinate spread of the simplex
     int flag;
+    int dec;
 };
 
 struct SseSinkNm {
@@ -74,20 +79,25 @@ __device__ double nm_eval(const NmSmem& sm, const double* x, bool valid, const S
     return (rm >= 0.0 && rm <= 1.7976931348623157e308) ? rm : INFINITY;
 }
 
+// Stable sort of the simplex by value, in parallel: vertex i goes to rank
+// #{k : f_k < f_i} + #{k < i : f_k == f_i} (the order a stable insertion sort
+// gives), each lane moves one row.  Every lane of the wave calls it.
 __device__ void nm_sort(NmSmem& sm)
 {
-    for (int i = 1; i < NV; ++i) {
-        double fi = sm.f[i], vi[P];
-        for (int j = 0; j < P; ++j) vi[j] = sm.v[i][j];
-        int k = i - 1;
-        while (k >= 0 && sm.f[k] > fi) {
-            sm.f[k + 1] = sm.f[k];
-            for (int j = 0; j < P; ++j) sm.v[k + 1][j] = sm.v[k][j];
-            --k;
-        }
-        sm.f[k + 1] = fi;
-        for (int j = 0; j < P; ++j) sm.v[k + 1][j] = vi[j];
+    const int lane = threadIdx.x;
+    if (lane < NV) {
+        const double fi = sm.f[lane];
+        int rank = 0;
+        for (int k = 0; k < NV; ++k) rank += (sm.f[k] < fi) || (k < lane && sm.f[k] == fi);
+        for (int j = 0; j < P; ++j) sm.tv[rank][j] = sm.v[lane][j];
+        sm.tf[rank] = fi;
     }
+    __syncthreads();
+    if (lane < NV) {
+        for (int j = 0; j < P; ++j) sm.v[lane][j] = sm.tv[lane][j];
+        sm.f[lane] = sm.tf[lane];
+    }
+    __syncthreads();
 }
 
 __global__ __launch_bounds__(64) void nm_kernel(int S, const SacDev* __restrict__ sacs, const float* __restrict__ proj,
@@ -125,22 +135,24 @@ __global__ __launch_bounds__(64) void nm_kernel(int S, const SacDev* __restrict_
         if (lane < NV) sm.f[lane] = fv;
     }
     __syncthreads();
-    if (lane == 0) nm_sort(sm);
-    __syncthreads();
+    nm_sort(sm);
     int it = 0;
     for (; it < max_iter; ++it) {
+        // exit test (max over vertices and coordinates; fmax is exact, so the order does not matter)
+        // and the centroid of the best P vertices, one coordinate per lane
+        if (lane < P) {
+            double dx = 0.0, acc = 0.0;
+            for (int i = 1; i < NV; ++i) dx = fmax(dx, fabs(sm.v[i][lane] - sm.v[0][lane]));
+            for (int i = 0; i < P; ++i) acc += sm.v[i][lane];
+            sm.dxc[lane] = dx;
+            sm.xb[lane] = acc / (double)P;
+        }
+        __syncthreads();
         if (lane == 0) {
             double dx = 0.0, df = 0.0;
-            for (int i = 1; i < NV; ++i) {
-                df = fmax(df, fabs(sm.f[i] - sm.f[0]));
-                for (int j = 0; j < P; ++j) dx = fmax(dx, fabs(sm.v[i][j] - sm.v[0][j]));
-            }
+            for (int i = 1; i < NV; ++i) df = fmax(df, fabs(sm.f[i] - sm.f[0]));
+            for (int j = 0; j < P; ++j) dx = fmax(dx, sm.dxc[j]);
             sm.flag = (dx <= tol_x && df <= tol_f) ? 1 : 0;
-        }
-        if (lane < P) {
-            double acc = 0.0;
-            for (int i = 0; i < P; ++i) acc += sm.v[i][lane];
-            sm.xb[lane] = acc / (double)P;
         }
         __syncthreads();
         if (sm.flag) break;
@@ -169,19 +181,27 @@ __global__ __launch_bounds__(64) void nm_kernel(int S, const SacDev* __restrict_
             else if (fr < sm.f[NV - 2]) d = 0;
             else if (fr < sm.f[NV - 1]) d = sm.fp[2] <= fr ? 2 : 4;
             else d = sm.fp[3] < sm.f[NV - 1] ? 3 : 4;
-            if (d < 4) {
-                for (int j = 0; j < P; ++j) sm.v[NV - 1][j] = sm.pt[d][j];
-                sm.f[NV - 1] = sm.fp[d];
-            } else {
-                for (int i = 1; i < NV; ++i) {
-                    for (int j = 0; j < P; ++j) sm.v[i][j] = sm.pt[3 + i][j];
-                    sm.f[i] = sm.fp[3 + i];
-                }
-            }
+            sm.dec = d;
             if (dec_out) dec_out[(int64_t)s * max_iter + it] = (int8_t)d;
-            nm_sort(sm);
         }
         __syncthreads();
+        {
+            // the accepted point replaces the worst vertex, or the shrink replaces all but the best;
+            // one coordinate per lane
+            const int d = sm.dec;
+            if (lane < P) {
+                if (d < 4) sm.v[NV - 1][lane] = sm.pt[d][lane];
+                else
+                    for (int i = 1; i < NV; ++i) sm.v[i][lane] = sm.pt[3 + i][lane];
+            }
+            if (lane == 0) {
+                if (d < 4) sm.f[NV - 1] = sm.fp[d];
+                else
+                    for (int i = 1; i < NV; ++i) sm.f[i] = sm.fp[3 + i];
+            }
+        }
+        __syncthreads();
+        nm_sort(sm);
     }
     if (lane < P) {
         double x = fmin(fmax(sm.v[0][lane], lo), hi);
