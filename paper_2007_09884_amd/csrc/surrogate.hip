@@ -330,10 +330,12 @@ __global__ void init_params_kernel(float* w, uint64_t seed)
 // Resample a trace (length T, period dt) to NPTS points over its own duration
 // and write (position, velocity) features; velocity is the central difference
 // (one-sided at the ends) interpolated the same way.
-__device__ void trace_features(const float* r, int T, float dt, uint16_t* feat)
+// Feature point j of a trace r[T]: position and velocity (central difference)
+// linearly interpolated at t = j (T - 1) / (NPTS - 1).
+__device__ __forceinline__ void trace_feature_point(const float* r, int T, float dt, int j, uint16_t* feat)
 {
     const float span = (float)(T - 1);
-    for (int j = 0; j < NPTS; ++j) {
+    {
         float t = span * (float)j / (float)(NPTS - 1);
         int k = (int)floorf(t);
         if (k > T - 2) k = T - 2;
@@ -353,13 +355,22 @@ __device__ void trace_features(const float* r, int T, float dt, uint16_t* feat)
     }
 }
 
-// Features of the saccades of a fit batch, from the projected traces.
-__global__ void features_kernel(int S, const opmm_rt::SacDev* __restrict__ sacs, const float* __restrict__ proj,
-                                float dt, uint16_t* __restrict__ feat)
+__device__ void trace_features(const float* r, int T, float dt, uint16_t* feat)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int j = 0; j < NPTS; ++j) trace_feature_point(r, T, dt, j, feat);
+}
+
+// Features of the saccades of a fit batch, from the projected traces: one wave
+// per saccade (block s), lanes take every 64th feature point.
+__global__ __launch_bounds__(64) void features_kernel(int S, const opmm_rt::SacDev* __restrict__ sacs,
+                                                      const float* __restrict__ proj, float dt,
+                                                      uint16_t* __restrict__ feat)
+{
+    const int s = blockIdx.x;
     if (s >= S) return;
-    trace_features(proj + sacs[s].proj_off, sacs[s].T, dt, feat + (int64_t)s * (2 * NPTS));
+    const float* r = proj + sacs[s].proj_off;
+    const int T = sacs[s].T;
+    for (int j = threadIdx.x; j < NPTS; j += 64) trace_feature_point(r, T, dt, j, feat + (int64_t)s * (2 * NPTS));
 }
 
 // Training data: draw a true OPC (nominal x U[1 - 0.3, 1 + 0.3]), amplitude
@@ -808,7 +819,7 @@ int opmm_surrogate_predict(opmm_surrogate* sg, const float* pos, int64_t pos_len
     const float* proj;
     if ((rc = opmm_rt::project_batch(ctx, pos, pos_len, sacs, S, &sd, &proj, st)) != OPMM_OK) return rc;
     if ((rc = sg_alloc(sg, S)) != OPMM_OK) return rc;
-    hipLaunchKernelGGL(features_kernel, dim3(blocks(S, 128)), dim3(128), 0, st, S, sd, proj, dt_ms, sg->act[0]);
+    hipLaunchKernelGGL(features_kernel, dim3(S), dim3(64), 0, st, S, sd, proj, dt_ms, sg->act[0]);
     if ((rc = sg_forward(sg, S, sg->act[0], st)) != OPMM_OK) return rc;
     hipLaunchKernelGGL(denorm_kernel, dim3(blocks((int64_t)S * P, 256)), dim3(256), 0, st, S, sg->out, sd, box_frac,
                        opc_out);
@@ -828,7 +839,7 @@ int opmm_surrogate_features(opmm_surrogate* sg, const float* pos, int64_t pos_le
     const float* proj;
     int rc;
     if ((rc = opmm_rt::project_batch(ctx, pos, pos_len, sacs, S, &sd, &proj, st)) != OPMM_OK) return rc;
-    hipLaunchKernelGGL(features_kernel, dim3(blocks(S, 128)), dim3(128), 0, st, S, sd, proj, dt_ms, feat_out);
+    hipLaunchKernelGGL(features_kernel, dim3(S), dim3(64), 0, st, S, sd, proj, dt_ms, feat_out);
     SG_HIP(hipGetLastError());
     return OPMM_OK;
 }
