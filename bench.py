@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--no-ivt", action="store_true", help="skip the I-VT leg (gaze stream -> saccades -> fit)")
     ap.add_argument("--ivt-saccades", type=int, default=2000)
     ap.add_argument("--no-model9", action="store_true", help="skip the 9-parameter model leg")
+    ap.add_argument("--report-csv", default=None,
+                    help="also write the batch's results in the paper's output format (Fig. 4) to this path")
     ap.add_argument("--nm-iter", type=int, default=2000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 512 MiB device-to-device copy 3 times (calibrates HBM byte counters)")
@@ -539,6 +541,13 @@ def main():
                                                              opmm.tile_names()[prm.tile]), launch_ms / n_launch),
                      "frac_of_published_fp32_157": achieved / PUBLISHED_FP32_PEAK},
     }
+    if a.report_csv:
+        # one more fit (untimed) for the mean absolute difference, the paper's OptErr; the serial
+        # re-check column (CPU_check) is left empty here
+        from paper_2007_09884_amd import report
+        mae = torch.zeros(S, device="cuda")
+        ctx.fit(pos, recs, prm, opc, rmse, mae, status)
+        report.write_csv(a.report_csv, opc.cpu().numpy(), mae.cpu().numpy())
     if tuned:
         out["autotune"] = tuned
     if not a.no_uneven:

@@ -69,3 +69,28 @@ def test_create_without_gpu_fails_cleanly():
     from paper_2007_09884_amd import opmm
     with pytest.raises(opmm.OpmmError):
         opmm.Context(0)
+
+
+def test_result_file_matches_the_papers_format(tmp_path):
+    """The result writer reproduces the column set of the paper's example output (Fig. 4), reads the
+    printed rows back into Table 1 order, and writes them again digit for digit."""
+    from paper_2007_09884_amd import report
+    lines = [l for l in open(os.path.join(os.path.dirname(__file__), "golden", "fig4_output.txt"))
+             if not l.startswith("#")]
+    assert lines[0].strip().split(",") == report.COLUMNS
+    src = tmp_path / "fig4.csv"
+    src.write_text("".join(lines))
+    opc, err, chk = report.read_csv(str(src))
+    assert opc.shape == (2, 18)
+    # Table 1 positions: K_SE_AG, N_C_AG (tension slope), B_P (passive viscosity), J (inertia), PW
+    assert opc[0, 0] == 25.0 and opc[0, 7] == 8.0 and opc[0, 6] == 0.006063 and opc[0, 9] == 0.000043
+    assert opc[1, 17] == 7.316801 and opc[1, 15] == 126.041275
+    assert list(err) == [10.701933, 1.115680] and list(chk) == [10.701933, 1.115681]
+    out = tmp_path / "again.csv"
+    report.write_csv(str(out), opc, err, chk)
+    again = out.read_text().splitlines()
+    assert again[0] == lines[0].strip()
+    assert again[2] == lines[2].strip()   # every printed value has six decimals in row 2
+    # a result without the serial re-check leaves that column empty
+    report.write_csv(str(out), opc[:1], err[:1])
+    assert out.read_text().splitlines()[1].split(",")[2] == ""

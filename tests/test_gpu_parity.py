@@ -173,6 +173,26 @@ def test_fit_tiny_single_pass(ctx, opmm):
     assert res["status"][0] == 0
 
 
+def test_result_file_with_serial_check(ctx, opmm, tmp_path):
+    """The paper's result file (Fig. 4): OptErr from the GPU fit, CPU_check recomputed serially by
+    the oracle from the fitted OPC; the two agree to the file's six decimals, as in the figure."""
+    from paper_2007_09884_amd import report
+    full, traces_all = make_batch(8, "full")
+    pick = [1, 4, 6]
+    b = synth.subset(full, pick)
+    traces = [traces_all[i] for i in pick]
+    res = run_fit(ctx, opmm, b, traces, 3000, 3)
+    chk = []
+    for s in range(b["S"]):
+        th = oracle.simulate(res["opc"][s].astype(np.float64), b["amp"][s], int(b["T"][s]))
+        chk.append(oracle.cost(th, traces[s], b["dir_deg"][s])[1])   # mean absolute difference
+    path = str(tmp_path / "result.csv")
+    report.write_csv(path, res["opc"], res["mae"], chk)
+    opc, err, cpu = report.read_csv(path)
+    assert np.all(np.abs(err - cpu) <= 1.5e-6), (err, cpu)
+    assert np.all(np.abs(opc - res["opc"]) <= 5e-7 * np.maximum(1.0, np.abs(res["opc"])))
+
+
 def test_fit_replay_rounds(ctx, opmm):
     """Full-estimation saccades (2-D, main-sequence durations), ragged candidate count, 4 rounds:
     every round's winner checked against the oracle on the round's whole candidate set."""
