@@ -135,7 +135,8 @@ def profiled_value(key, mode, tile_name):
 
 def gpu_targets(ctx, opmm, torch, b):
     """Synthetic recorded traces: the plant (opmm_simulate) driven by the true OPC, projected on the
-    direction, plus the drawn noise; FP32, packed [T_i][2] back to back on the device."""
+    direction, plus the drawn noise; FP32, packed [T_i][C] back to back on the device (C = 1: the
+    horizontal channel only)."""
     S = b["S"]
     amp = np.asarray(b["amp"], np.float32)
     dur = np.asarray(b["dur_ms"], np.float32)
@@ -147,7 +148,7 @@ def gpu_targets(ctx, opmm, torch, b):
     parts = []
     for s in range(S):
         T = int(b["T"][s])
-        u = torch.tensor([math.cos(phi[s]), math.sin(phi[s])], dtype=torch.float32, device="cuda")
+        u = torch.tensor([math.cos(phi[s]), math.sin(phi[s])][:b["C"]], dtype=torch.float32, device="cuda")
         z = torch.from_numpy(b["noise"][s].astype(np.float32)).cuda()
         parts.append((theta[s, :T, None] * u[None, :] + float(b["sigma"][s]) * z).reshape(-1))
     return torch.cat(parts).contiguous()
@@ -279,6 +280,29 @@ def uneven_leg(a, ctx, opmm, torch, synth):
         out[name] = {"tile": opmm.tile_names()[p.tile], "ms_per_step": dt * 1e3, "candidate_sims_per_s": sims / dt,
                      "saccades_fitted_per_s": S / dt}
     return out
+
+
+def tiny_leg(a, ctx, opmm, torch, synth):
+    """The tiny configuration: one horizontal 10 deg saccade (T = 80, one channel), 4096 candidates,
+    one argmin pass; latency of one captured fit, launch to synchronise."""
+    b = synth.draw_saccades(1, "tiny")
+    pos = gpu_targets(ctx, opmm, torch, b)
+    recs = opmm.saccade_records(b["T"], 1, b["amp"], b["dir_deg"], b["dur_ms"], b["seed"])
+    opc = torch.zeros(1, 18, device="cuda")
+    rm = torch.zeros(1, device="cuda")
+    pl = ctx.plan(pos, recs, opmm.fit_params(n_cand=4096, n_rounds=1), opc, rm)
+    for _ in range(5):
+        pl.launch()
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(100):
+        t0 = time.perf_counter()
+        pl.launch()
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t0) * 1e3)
+    pl.close()
+    return {"n_cand": 4096, "rounds": 1, "latency_ms_p50": float(np.percentile(lat, 50)),
+            "latency_ms_p99": float(np.percentile(lat, 99)), "rmse_deg": float(rm.item())}
 
 
 def ivt_leg(a, ctx, opmm, torch, synth):
@@ -566,6 +590,7 @@ def main():
                          "mean_final_rmse_deg": float(rmse.mean().item())}
     if not a.no_ivt:
         out["ivt"] = ivt_leg(a, ctx, opmm, torch, synth)
+    out["tiny"] = tiny_leg(a, ctx, opmm, torch, synth)
     if not a.no_nm:
         out["nelder_mead"] = nm_leg(a, ctx, opmm, torch, pos, recs, rm, ms_per_step * 1e-3)
     if not a.no_surrogate:
