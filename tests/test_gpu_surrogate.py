@@ -11,6 +11,7 @@ Tolerances:
     masks, hence the looser bound there;
   * features: within one BF16 ulp of the FP64 resampling.
 """
+import math
 import os
 import tempfile
 
@@ -239,3 +240,28 @@ def test_learned_seed_gains_over_the_plain_search(ctx, opmm):
         th = oracle.simulate(o[i].astype(np.float64), b["amp"][i], int(b["T"][i]))
         assert abs(oracle.cost(th, traces[i], b["dir_deg"][i])[0] - rm0.cpu().numpy()[i]) <= 1e-6
     sg.close()
+
+
+def test_training_loop_equals_step_by_step(ctx, opmm):
+    """opmm_surrogate_train (16 batches generated per launch into a device ring, losses kept on the
+    device) gives bit for bit the weights of the same steps taken one call at a time: generate batch
+    t, forward + backward, Adam with the cosine learning rate of step t.  Batch 1000 is ragged."""
+    B, n, lr0, lr_min = 1000, 20, 2e-3, 1e-4
+    sa = opmm.Surrogate(ctx, init_seed=3)
+    sa.train(data_seed=11, batch=B, n_steps=n, lr0=lr0, lr_min=lr_min)
+    sb = opmm.Surrogate(ctx, init_seed=3)
+    feat = torch.zeros(B, 256, dtype=torch.int16, device="cuda")
+    tgt = torch.zeros(B, 18, device="cuda")
+    # the library's schedule: lr_min + (lr0 - lr_min) (1 + cos(pi t / (n - 1))) / 2, the difference
+    # taken in FP32 (both arguments are FP32), the rest in FP64, rounded once to FP32
+    l1 = float(np.float32(lr_min))
+    d = float(np.float32(np.float32(lr0) - np.float32(lr_min)))
+    for t in range(n):
+        sb.generate(11, t, feat, tgt)
+        sb.backward(feat, tgt, want_loss=False)
+        lr = np.float32(l1 + 0.5 * d * (1.0 + math.cos(math.pi * (t / (n - 1)))))
+        sb.adam_step(float(lr))
+    torch.cuda.synchronize()
+    assert np.array_equal(sa.params(0).view(np.uint32), sb.params(0).view(np.uint32))
+    sa.close()
+    sb.close()
