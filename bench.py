@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--no-ivt", action="store_true", help="skip the I-VT leg (gaze stream -> saccades -> fit)")
     ap.add_argument("--ivt-saccades", type=int, default=2000)
     ap.add_argument("--no-model9", action="store_true", help="skip the 9-parameter model leg")
+    ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-configuration latency leg")
     ap.add_argument("--report-csv", default=None,
                     help="also write the batch's results in the paper's output format (Fig. 4) to this path")
     ap.add_argument("--nm-iter", type=int, default=2000)
@@ -590,7 +591,8 @@ def main():
                          "mean_final_rmse_deg": float(rmse.mean().item())}
     if not a.no_ivt:
         out["ivt"] = ivt_leg(a, ctx, opmm, torch, synth)
-    out["tiny"] = tiny_leg(a, ctx, opmm, torch, synth)
+    if not a.no_tiny:
+        out["tiny"] = tiny_leg(a, ctx, opmm, torch, synth)
     if not a.no_nm:
         out["nelder_mead"] = nm_leg(a, ctx, opmm, torch, pos, recs, rm, ms_per_step * 1e-3)
     if not a.no_surrogate:

@@ -356,6 +356,33 @@ __device__ __forceinline__ int find_saccade_wave(const SacDev* __restrict__ sacs
     return lo;
 }
 
+// Last k with base[k] <= b over a non-decreasing int array (base[0] = 0), by one
+// whole wave, as find_saccade_wave.
+__device__ __forceinline__ int find_index_wave(const int* __restrict__ base, int S, int b)
+{
+    const int lane = threadIdx.x & 63;
+    int lo = 0, n = S;
+    while (n > 1) {
+        const int step = (n + 63) / 64;
+        const bool le = lane * step < n && base[lo + lane * step] <= b;
+        const uint64_t m = __ballot(le);
+        const int last = 63 - __clzll((long long)m);
+        lo += last * step;
+        n = min(step, n - last * step);
+    }
+    return lo;
+}
+
+// Saccade of tile b.  ord (nullable): saccades in dispatch order (longest trace
+// first, so the last blocks of a launch are short ones), obase their tile bases;
+// without it, tiles follow the record order.  Every lane of the wave calls it.
+__device__ __forceinline__ int saccade_of_tile(const SacDev* __restrict__ sacs, const int* __restrict__ ord,
+                                               const int* __restrict__ obase, int S, int b)
+{
+    if (ord) return ord[find_index_wave(obase, S, b)];
+    return find_saccade_wave(sacs, S, b);
+}
+
 // One round over a batch: round >= 0 puts every saccade at that round with keys
 // [round][key_stride]; round < 0 takes each saccade's own round (sd.round) and
 // keys [slot] (saccades admitted at different times, see the server).
@@ -365,12 +392,13 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_round_kernel(const Sa
                                                         const float* centre, const float* hw,
                                                         const float* lo, const float* hi,
                                                         const int32_t* __restrict__ status,
-                                                        uint64_t* keys)
+                                                        uint64_t* keys, const int* __restrict__ ord,
+                                                        const int* __restrict__ obase)
 {
     __shared__ TileSmem<TPB, PASSES> sm;
     __shared__ int s_s;
     if (threadIdx.x < 64) {
-        const int sw = find_saccade_wave(sacs, S, blockIdx.x);
+        const int sw = saccade_of_tile(sacs, ord, obase, S, blockIdx.x);
         if (threadIdx.x == 0) s_s = sw;
     }
     __syncthreads();
@@ -394,7 +422,8 @@ template <int TPB, int PASSES, int UNROLL>
 __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_persistent_kernel(
     const SacDev* __restrict__ sacs, int S, int R, int tiles_per_round, float dt, float shrink,
     const float* __restrict__ proj, float* centre, float* hw, const float* lo, const float* hi,
-    int32_t* status, uint64_t* keys, uint32_t* head, uint32_t* done, uint32_t* ready, uint32_t* errflag)
+    int32_t* status, uint64_t* keys, uint32_t* head, uint32_t* done, uint32_t* ready, uint32_t* errflag,
+    const int* __restrict__ ord, const int* __restrict__ obase)
 {
     __shared__ TileSmem<TPB, PASSES> sm;
     __shared__ int s_item, s_sac;
@@ -407,7 +436,7 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_persistent_kernel(
         const int r = (int)(item / tiles_per_round);
         const int b = (int)(item % tiles_per_round);
         if (threadIdx.x < 64) {
-            const int sw = find_saccade_wave(sacs, S, b);
+            const int sw = saccade_of_tile(sacs, ord, obase, S, b);
             if (threadIdx.x == 0) s_sac = sw;
         }
         __syncthreads();
@@ -589,6 +618,7 @@ struct FitLaunch {
     uint64_t* keys;
     uint32_t *head, *done, *ready, *errflag;
     int grid_persistent;
+    const int *ord, *obase;  // dispatch order (nullable: record order)
 };
 
 template <int TPB, int PASSES, int UNROLL>
@@ -597,11 +627,11 @@ hipError_t launch_shape(const FitLaunch& L, bool persistent, int round, hipStrea
     if (persistent) {
         hipLaunchKernelGGL((fit_persistent_kernel<TPB, PASSES, UNROLL>), dim3(L.grid_persistent), dim3(TPB), 0,
                            st, L.sacs, L.S, L.R, L.tiles_per_round, L.dt, L.shrink, L.proj, L.centre, L.hw,
-                           L.lo, L.hi, L.status, L.keys, L.head, L.done, L.ready, L.errflag);
+                           L.lo, L.hi, L.status, L.keys, L.head, L.done, L.ready, L.errflag, L.ord, L.obase);
     } else {
         hipLaunchKernelGGL((fit_round_kernel<TPB, PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(TPB), 0, st,
                            L.sacs, L.S, round, L.key_stride, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status,
-                           L.keys);
+                           L.keys, L.ord, L.obase);
     }
     return hipGetLastError();
 }
@@ -664,10 +694,10 @@ struct DevBuf {
 };
 
 struct FitScratch {
-    DevBuf sacs, proj, qorth, box, keys, status, counters;
+    DevBuf sacs, proj, qorth, box, keys, status, counters, order;
     ~FitScratch()
     {
-        for (DevBuf* b : {&sacs, &proj, &qorth, &box, &keys, &status, &counters})
+        for (DevBuf* b : {&sacs, &proj, &qorth, &box, &keys, &status, &counters, &order})
             if (b->p) (void)hipFree(b->p);
     }
 };
@@ -782,22 +812,35 @@ int upload_saccades(opmm_ctx* ctx, FitScratch& sc, const opmm_saccade* sacs, int
 {
     std::vector<SacDev> h(S);
     int64_t toff = 0;
-    int64_t tiles = 0;
     for (int i = 0; i < S; ++i) {
         SacDev& d = h[i];
         d = opmm_rt::make_record(sacs[i], prm ? prm->n_cand : 1);
         d.model = prm ? prm->model : 18;
         d.proj_off = toff;
         d.tiles = (int)((d.n_cand + tile_size - 1) / tile_size);
-        d.tile_base = (int)tiles;
         d.slot = i;
         toff += sacs[i].T;
+    }
+    // Tiles are dispatched longest trace first (a tile's time grows with T), so a launch ends on
+    // short blocks; ord[k] is the k-th saccade in that order and obase[k] its first tile.  The
+    // order changes only which block takes a tile, never a result.
+    std::vector<int> ord(S), ob(2 * (size_t)S);
+    for (int i = 0; i < S; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return sacs[x].T > sacs[y].T; });
+    int64_t tiles = 0;
+    for (int k = 0; k < S; ++k) {
+        SacDev& d = h[ord[k]];
+        d.tile_base = (int)tiles;
+        ob[k] = ord[k];
+        ob[S + k] = (int)tiles;
         tiles += d.tiles;
     }
     if (tiles > 0x7FFFFFFF / 8) return fail(ctx, OPMM_EINVAL, "too many candidate tiles in one batch");
     int rc;
     if ((rc = ensure(ctx, sc.sacs, sizeof(SacDev) * S)) != OPMM_OK) return rc;
+    if ((rc = ensure(ctx, sc.order, sizeof(int) * 2 * (size_t)S)) != OPMM_OK) return rc;
     OPMM_HIP(ctx, hipMemcpyAsync(sc.sacs.p, h.data(), sizeof(SacDev) * S, hipMemcpyHostToDevice, st));
+    OPMM_HIP(ctx, hipMemcpyAsync(sc.order.p, ob.data(), sizeof(int) * 2 * (size_t)S, hipMemcpyHostToDevice, st));
     OPMM_HIP(ctx, hipStreamSynchronize(st));
     *total_T = toff;
     *tiles_per_round = (int)tiles;
@@ -848,6 +891,8 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
     L.shrink = prm->shrink; L.proj = proj; L.centre = centre; L.hw = hw; L.lo = lo; L.hi = hi;
     L.status = status; L.keys = keys; L.head = head; L.done = done; L.ready = ready; L.errflag = errflag;
     L.grid_persistent = 0;
+    L.ord = (const int*)sc.order.p;
+    L.obase = L.ord + S;
     L.key_stride = S;
     if (tiles_per_round > 0) {
         if (prm->mode == OPMM_FIT_PERSISTENT) {
