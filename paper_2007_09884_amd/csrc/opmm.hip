@@ -695,10 +695,15 @@ struct DevBuf {
 
 struct FitScratch {
     DevBuf sacs, proj, qorth, box, keys, status, counters, order;
+    // Pinned host staging of the record upload (records, then dispatch order and tile bases), kept
+    // between calls: the upload is a direct DMA and no batch pays for fresh pages.
+    DevBuf stage;
+    std::vector<int> h_count;
     ~FitScratch()
     {
         for (DevBuf* b : {&sacs, &proj, &qorth, &box, &keys, &status, &counters, &order})
             if (b->p) (void)hipFree(b->p);
+        if (stage.p) (void)hipHostFree(stage.p);
     }
 };
 
@@ -771,22 +776,47 @@ int ensure(opmm_ctx* ctx, DevBuf& b, size_t bytes)
     return OPMM_OK;
 }
 
+// Grow a pinned host buffer.  Its previous contents are dead: every upload waits for its copies.
+int ensure_host(opmm_ctx* ctx, DevBuf& b, size_t bytes)
+{
+    if (b.cap >= bytes) return OPMM_OK;
+    if (b.p) {
+        OPMM_HIP(ctx, hipHostFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t cap = std::max(bytes, b.cap * 2);
+    if (hipHostMalloc(&b.p, cap, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return fail(ctx, OPMM_ENOMEM, "pinned host allocation of " + std::to_string(cap) + " bytes failed");
+    }
+    b.cap = cap;
+    return OPMM_OK;
+}
+
 int blocks_for(int64_t n, int tpb) { return (int)((n + tpb - 1) / tpb); }
+
+// The reason a record is unusable, or nullptr (no string work on the accepted path: batches of
+// thousands of records are checked on every call).
+const char* saccade_defect(const opmm_saccade& s, int64_t pos_len)
+{
+    if (s.T < 1 || s.T > OPMM_MAX_T) return "T out of range";
+    if (s.C != 1 && s.C != 2) return "C must be 1 or 2";
+    if (s.C == 1 && !(s.dir_deg == 0.0f || s.dir_deg == 180.0f)) return "C = 1 needs dir_deg 0 or 180";
+    if (!std::isfinite(s.amp_deg) || s.amp_deg < 0.0f) return "amp_deg must be finite and >= 0";
+    if (!std::isfinite(s.dir_deg)) return "dir_deg must be finite";
+    if (!std::isfinite(s.dur_ms) || !(s.dur_ms > 6.0f)) return "dur_ms must be > 6";
+    if (s.pos_offset < 0 || s.pos_offset + (int64_t)s.T * s.C > pos_len) return "trace lies outside pos[0, pos_len)";
+    if (s.n_cand < 0) return "n_cand must be >= 0";
+    return nullptr;
+}
 
 int validate_saccade_impl(opmm_ctx* ctx, const opmm_saccade& s, int64_t pos_len, int i)
 {
-    std::string at = " (saccade " + std::to_string(i) + ")";
-    if (s.T < 1 || s.T > OPMM_MAX_T) return fail(ctx, OPMM_EINVAL, "T out of range" + at);
-    if (s.C != 1 && s.C != 2) return fail(ctx, OPMM_EINVAL, "C must be 1 or 2" + at);
-    if (s.C == 1 && !(s.dir_deg == 0.0f || s.dir_deg == 180.0f))
-        return fail(ctx, OPMM_EINVAL, "C = 1 needs dir_deg 0 or 180" + at);
-    if (!std::isfinite(s.amp_deg) || s.amp_deg < 0.0f) return fail(ctx, OPMM_EINVAL, "amp_deg must be finite and >= 0" + at);
-    if (!std::isfinite(s.dir_deg)) return fail(ctx, OPMM_EINVAL, "dir_deg must be finite" + at);
-    if (!std::isfinite(s.dur_ms) || !(s.dur_ms > 6.0f)) return fail(ctx, OPMM_EINVAL, "dur_ms must be > 6" + at);
-    if (s.pos_offset < 0 || s.pos_offset + (int64_t)s.T * s.C > pos_len)
-        return fail(ctx, OPMM_EINVAL, "trace lies outside pos[0, pos_len)" + at);
-    if (s.n_cand < 0) return fail(ctx, OPMM_EINVAL, "n_cand must be >= 0" + at);
-    return OPMM_OK;
+    const char* why = saccade_defect(s, pos_len);
+    if (!why) return OPMM_OK;
+    return fail(ctx, OPMM_EINVAL, std::string(why) + " (saccade " + std::to_string(i) + ")");
 }
 
 int validate_params(opmm_ctx* ctx, const opmm_fit_params* p)
@@ -810,7 +840,12 @@ int upload_saccades(opmm_ctx* ctx, FitScratch& sc, const opmm_saccade* sacs, int
                     const opmm_fit_params* prm, int tile_size, int64_t* total_T, int* tiles_per_round,
                     hipStream_t st)
 {
-    std::vector<SacDev> h(S);
+    int rc;
+    const size_t rec_bytes = sizeof(SacDev) * (size_t)S, ord_bytes = sizeof(int) * 2 * (size_t)S;
+    if ((rc = ensure_host(ctx, sc.stage, rec_bytes + ord_bytes)) != OPMM_OK) return rc;
+    static_assert(sizeof(SacDev) % alignof(int) == 0, "the order array follows the records");
+    SacDev* h = (SacDev*)sc.stage.p;
+    int* ob = (int*)((char*)sc.stage.p + rec_bytes);
     int64_t toff = 0;
     for (int i = 0; i < S; ++i) {
         SacDev& d = h[i];
@@ -823,24 +858,29 @@ int upload_saccades(opmm_ctx* ctx, FitScratch& sc, const opmm_saccade* sacs, int
     }
     // Tiles are dispatched longest trace first (a tile's time grows with T), so a launch ends on
     // short blocks; ord[k] is the k-th saccade in that order and obase[k] its first tile.  The
-    // order changes only which block takes a tile, never a result.
-    std::vector<int> ord(S), ob(2 * (size_t)S);
-    for (int i = 0; i < S; ++i) ord[i] = i;
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return sacs[x].T > sacs[y].T; });
+    // order changes only which block takes a tile, never a result.  T is bounded, so a counting
+    // sort on (OPMM_MAX_T - T) gives the order in O(S), ties in batch order.
+    std::vector<int>& cnt = sc.h_count;
+    cnt.assign(OPMM_MAX_T + 1, 0);
+    for (int i = 0; i < S; ++i) cnt[OPMM_MAX_T - sacs[i].T]++;  // T in 1..OPMM_MAX_T (validated)
+    for (int k = 0, run = 0; k <= OPMM_MAX_T; ++k) {
+        const int c = cnt[k];
+        cnt[k] = run;
+        run += c;
+    }
+    for (int i = 0; i < S; ++i) ob[cnt[OPMM_MAX_T - sacs[i].T]++] = i;
     int64_t tiles = 0;
     for (int k = 0; k < S; ++k) {
-        SacDev& d = h[ord[k]];
+        SacDev& d = h[ob[k]];
         d.tile_base = (int)tiles;
-        ob[k] = ord[k];
         ob[S + k] = (int)tiles;
         tiles += d.tiles;
     }
     if (tiles > 0x7FFFFFFF / 8) return fail(ctx, OPMM_EINVAL, "too many candidate tiles in one batch");
-    int rc;
-    if ((rc = ensure(ctx, sc.sacs, sizeof(SacDev) * S)) != OPMM_OK) return rc;
-    if ((rc = ensure(ctx, sc.order, sizeof(int) * 2 * (size_t)S)) != OPMM_OK) return rc;
-    OPMM_HIP(ctx, hipMemcpyAsync(sc.sacs.p, h.data(), sizeof(SacDev) * S, hipMemcpyHostToDevice, st));
-    OPMM_HIP(ctx, hipMemcpyAsync(sc.order.p, ob.data(), sizeof(int) * 2 * (size_t)S, hipMemcpyHostToDevice, st));
+    if ((rc = ensure(ctx, sc.sacs, rec_bytes)) != OPMM_OK) return rc;
+    if ((rc = ensure(ctx, sc.order, ord_bytes)) != OPMM_OK) return rc;
+    OPMM_HIP(ctx, hipMemcpyAsync(sc.sacs.p, h, rec_bytes, hipMemcpyHostToDevice, st));
+    OPMM_HIP(ctx, hipMemcpyAsync(sc.order.p, ob, ord_bytes, hipMemcpyHostToDevice, st));
     OPMM_HIP(ctx, hipStreamSynchronize(st));
     *total_T = toff;
     *tiles_per_round = (int)tiles;
