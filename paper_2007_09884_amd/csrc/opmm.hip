@@ -1107,6 +1107,8 @@ int project_batch(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_s
     return OPMM_OK;
 }
 
+const int* batch_order(const opmm_ctx* ctx) { return (const int*)ctx->aux.order.p; }
+
 int reserve_batch(opmm_ctx* ctx, int S, int64_t total_T)
 {
     FitScratch& sc = ctx->aux;

@@ -24,6 +24,10 @@
 // cost at the current point, all on the exact discretisation; the best trial
 // is taken if it lowers the cost (lambda_c becomes a tenth of its lambda),
 // otherwise lambda_c grows by 1e8 and the point stays.
+// A wave polishes three saccades, one lane group of 21 each (a saccade alone would idle 46 lanes in
+// the Jacobian pass and 55 in the trial pass); each group's arithmetic is exactly that of a wave
+// of its own.  Batches holding a trace longer than 512 samples run one saccade per wave (their
+// staged traces would not leave room for four waves per CU).
 // Objectives: the RMSE of Section 3.4 (Gauss-Newton on squared residuals) or
 // the mean absolute difference the paper reports as OptErr (Fig. 4), by
 // iteratively reweighted least squares (weights 1/max(|e|, 1e-3 deg)).
@@ -31,6 +35,7 @@
 // are clamped to the search box and rounded to FP32, the candidate format.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -79,7 +84,14 @@ namespace {
 constexpr int NLAM = 8;             // damping values tried per iteration
 constexpr int PTRI = P * (P + 1) / 2;
 constexpr double IRLS_EPS = 1e-3;   // deg: floor of |e| in the L1 weights
-constexpr int NCH = 64;             // samples of Jacobian rows staged in LDS per normal-equation pass
+constexpr int NCH = 32;             // samples of Jacobian rows staged in LDS per normal-equation pass
+// Lane groups: a wave polishes several saccades, GL lanes each (P sensitivity directions in
+// the Jacobian pass, NLAM + 1 cost lanes in the trial pass).
+constexpr int GL = 21;
+constexpr int NENT = (PTRI + GL - 1) / GL;  // lower-triangle entries accumulated per lane
+static_assert(GL >= P && GL >= NLAM + 1 && 3 * GL <= 64, "lane groups");
+// traces up to this length: three saccades per wave (their LDS fits four waves per CU)
+constexpr int GROUPED_MAX_T = 512;
 // Discretisations of the plant: Taylor degree M and squarings SQ of the
 // one-sample transition (on dt / 2^SQ), Taylor degree EXM of the split
 // sample's exponentials.  Exact: truncation below 1e-11 relative for the
@@ -306,32 +318,41 @@ struct CostSink {  // objective value only (trial points, reports)
     __device__ double f() const { return objective == OPMM_OBJ_MAE ? ab : sq; }
 };
 
-// Normal equations of the linearised problem.  Lane j carries column j of J
-// (the dual part) and accumulates g_j; the rows of J are staged in LDS NCH
-// samples at a time, and each lane then accumulates up to three entries
-// (i >= j) of the lower triangle of J^T W J, h_ij += (w_k J_ki) J_kj in sample
-// order.  Every lane of the wave calls it (wave-uniform control flow).
+// Orders LDS accesses among the lanes of the wave (a block is one wave).  Lane groups flush at
+// different samples, so no block barrier may be used there.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Normal equations of the linearised problem.  Lane r of the saccade's group carries column r of
+// J (the dual part) and accumulates g_r; the rows of J are staged in LDS NCH samples at a time,
+// and each lane of the group then accumulates up to NENT entries (i >= j) of the lower triangle
+// of J^T W J, h_ij += (w_k J_ki) J_kj in sample order.  Every lane of the group calls it (the
+// group's control flow is uniform).
 struct NormalSink {
     Residual res;
     int objective;
     double* jst;  // LDS [NCH][P]: staged rows of J
     double* ast;  // LDS [NCH]: per-sample weight of the normal matrix
+    int r;        // lane within the group
     int nk;       // samples staged
     double g;
-    int ei[3], ej[3];  // this lane's entries (row, column); row -1: none
-    double h[3];
+    int eij[NENT];  // this lane's entries, (row << 8) | column; -1: none
+    double h[NENT];
     __device__ void init(int nf)
     {
         nk = 0;
         g = 0.0;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const int e = (int)threadIdx.x + 64 * q;
+        for (int q = 0; q < NENT; ++q) {
+            const int e = r + GL * q;
             int i = 0;
             while ((i + 1) * (i + 2) / 2 <= e) ++i;
             const bool use = e < PTRI && i < nf;
-            ei[q] = use ? i : -1;
-            ej[q] = use ? e - i * (i + 1) / 2 : 0;
+            eij[q] = use ? (i << 8) | (e - i * (i + 1) / 2) : -1;
             h[q] = 0.0;
         }
     }
@@ -351,21 +372,21 @@ struct NormalSink {
             b = __fma_rn(wy * sp, ey, b);
         }
         g = __fma_rn(th.d, b, g);
-        const int lane = threadIdx.x;
-        if (lane < P) jst[nk * P + lane] = th.d;
-        if (lane == 0) ast[nk] = a;
+        if (r < P) jst[nk * P + r] = th.d;
+        if (r == 0) ast[nk] = a;
         if (++nk == NCH) flush();
     }
     __device__ void flush()
     {
-        __syncthreads();
+        wave_sync();
         for (int kk = 0; kk < nk; ++kk) {
             const double ak = ast[kk];
 #pragma unroll
-            for (int q = 0; q < 3; ++q)
-                if (ei[q] >= 0) h[q] = __fma_rn(ak * jst[kk * P + ei[q]], jst[kk * P + ej[q]], h[q]);
+            for (int q = 0; q < NENT; ++q)
+                if (eij[q] >= 0)
+                    h[q] = __fma_rn(ak * jst[kk * P + (eij[q] >> 8)], jst[kk * P + (eij[q] & 255)], h[q]);
         }
-        __syncthreads();
+        wave_sync();
         nk = 0;
     }
 };
@@ -388,8 +409,8 @@ __global__ __launch_bounds__(64) void sensitivity_kernel(int S, const SacDev* __
 
 // ---- polish -------------------------------------------------------------------
 
-struct PolishSmem {
-    float X[OPMM_MAX_T], Y[OPMM_MAX_T];
+// State of one saccade's polish (one lane group).
+struct PolishSlot {
     double H[P][P];
     double g[P];
     double xt[NLAM][P];
@@ -402,13 +423,14 @@ struct PolishSmem {
     int nf;
     double fcur, lam;
     int ok[NLAM];
-    int done;
+    int done;        // no further iterations (converged, stopped, or no saccade in the group)
+    int it;          // iterations taken
 };
 
 // OPC of relative point x, rounded to FP32 (the candidate format)
-__device__ __forceinline__ double opc_value(const PolishSmem& sm, const double* x, int i)
+__device__ __forceinline__ double opc_value(const PolishSlot& sl, const double* x, int i)
 {
-    return (double)(float)(x[i] * sm.nom[i]);
+    return (double)(float)(x[i] * sl.nom[i]);
 }
 
 // Cholesky solve of (H + lam diag H) delta = -g with the factor in registers
@@ -416,13 +438,13 @@ __device__ __forceinline__ double opc_value(const PolishSmem& sm, const double* 
 // and those past the free count) take an identity row, so their delta is 0.
 // The diagonal of the packed factor stores 1/L_jj.  Returns false if the
 // damped matrix is not positive definite.
-__device__ __forceinline__ bool damped_solve(const PolishSmem& sm, double lam, uint32_t held, double delta[P])
+__device__ __forceinline__ bool damped_solve(const PolishSlot& sl, double lam, uint32_t held, double delta[P])
 {
     double L[PTRI];
 #pragma unroll
     for (int j = 0; j < P; ++j) {
         const bool uj = !((held >> j) & 1u);
-        double d = uj ? sm.H[j][j] * (1.0 + lam) : 1.0;
+        double d = uj ? sl.H[j][j] * (1.0 + lam) : 1.0;
 #pragma unroll
         for (int k = 0; k < j; ++k) d = __fma_rn(-L[j * (j + 1) / 2 + k], L[j * (j + 1) / 2 + k], d);
         if (!(d > 0.0)) return false;
@@ -431,7 +453,7 @@ __device__ __forceinline__ bool damped_solve(const PolishSmem& sm, double lam, u
 #pragma unroll
         for (int i = j + 1; i < P; ++i) {
             const bool ui = !((held >> i) & 1u);
-            double a = (ui && uj) ? sm.H[i][j] : 0.0;
+            double a = (ui && uj) ? sl.H[i][j] : 0.0;
 #pragma unroll
             for (int k = 0; k < j; ++k) a = __fma_rn(-L[i * (i + 1) / 2 + k], L[j * (j + 1) / 2 + k], a);
             L[i * (i + 1) / 2 + j] = a * rj;
@@ -439,7 +461,7 @@ __device__ __forceinline__ bool damped_solve(const PolishSmem& sm, double lam, u
     }
 #pragma unroll
     for (int i = 0; i < P; ++i) {  // L y = -g
-        double a = ((held >> i) & 1u) ? 0.0 : -sm.g[i];
+        double a = ((held >> i) & 1u) ? 0.0 : -sl.g[i];
 #pragma unroll
         for (int k = 0; k < i; ++k) a = __fma_rn(-L[i * (i + 1) / 2 + k], delta[k], a);
         delta[i] = a * L[i * (i + 1) / 2 + i];
@@ -454,168 +476,205 @@ __device__ __forceinline__ bool damped_solve(const PolishSmem& sm, double lam, u
     return true;
 }
 
+// PG saccades per wave: lane group g = lane / GL polishes saccade order[blockIdx.x * PG + g]
+// (order: the batch sorted by T, so a wave's saccades run loops of similar length; NULL: batch
+// order).  A group's arithmetic is that of a wave of its own, so results do not depend on the
+// grouping.  Traces are staged in dynamic LDS, [PG][2][max_T] floats; max_T bounds every T.
+template <int PG>
 __global__ __launch_bounds__(64) void polish_kernel(int S, const SacDev* __restrict__ sacs,
-                                                    const float* __restrict__ pos, const int32_t* __restrict__ status_in,
-                                                    int model, int max_iter, int objective, double tol_f, double lam0,
+                                                    const int* __restrict__ order, const float* __restrict__ pos,
+                                                    const int32_t* __restrict__ status_in, int max_T, int model,
+                                                    int max_iter, int objective, double tol_f, double lam0,
                                                     double box_frac, double dt, float* __restrict__ opc,
                                                     float* __restrict__ rmse_out, float* __restrict__ mae_out,
                                                     int32_t* __restrict__ iters_out, int8_t* __restrict__ dec_out)
 {
-    __shared__ PolishSmem sm;
-    const int s = blockIdx.x, lane = threadIdx.x;
-    const SacDev sd = sacs[s];
+    __shared__ PolishSlot slots[PG];
+    extern __shared__ float traces[];
+    const int lane = threadIdx.x;
+    const bool member = lane < PG * GL;
+    const int g = member ? lane / GL : 0;
+    const int r = lane - g * GL;  // lanes past the groups have r >= GL and no role
+    const int idx = blockIdx.x * PG + g;
+    const bool has = member && idx < S;
+    const int s = has ? (order ? order[idx] : idx) : 0;
+    PolishSlot& sl = slots[g];
+    float* X = traces + (size_t)g * 2 * max_T;
+    float* Y = X + max_T;
+    const SacDev sd = has ? sacs[s] : SacDev{};
     const int T = sd.T;
-    if (status_in[sd.slot] & OPMM_ST_NONFINITE_INPUT) {
-        if (lane < P) opc[(int64_t)s * P + lane] = __int_as_float(0x7FC00000);
-        if (lane == 0) {
+    bool live = has;
+    if (has && ((status_in[sd.slot] & OPMM_ST_NONFINITE_INPUT) || T > max_T)) {
+        if (r < P) opc[(int64_t)s * P + r] = __int_as_float(0x7FC00000);
+        if (r == 0) {
             rmse_out[s] = __int_as_float(0x7FC00000);
             if (mae_out) mae_out[s] = __int_as_float(0x7FC00000);
             if (iters_out) iters_out[s] = 0;
         }
-        return;
+        live = false;
     }
-    for (int k = lane; k < T; k += 64) {
-        sm.X[k] = pos[sd.pos_off + (int64_t)k * sd.C];
-        sm.Y[k] = sd.C == 2 ? pos[sd.pos_off + (int64_t)k * sd.C + 1] : 0.0f;
+    if (live) {
+        for (int k = r; k < T; k += GL) {
+            X[k] = pos[sd.pos_off + (int64_t)k * sd.C];
+            Y[k] = sd.C == 2 ? pos[sd.pos_off + (int64_t)k * sd.C + 1] : 0.0f;
+        }
+        if (r < P) {
+            const double nm = nominal_param_f64(r, (double)sd.dur);
+            const double v = (double)opc[(int64_t)s * P + r];
+            sl.nom[r] = nm;
+            sl.x[r] = v / nm;
+            const bool fixed = model == 9 && fixed_in_model9(r);
+            sl.lo[r] = fixed ? sl.x[r] : 1.0 - box_frac;
+            sl.hi[r] = fixed ? sl.x[r] : 1.0 + box_frac;
+        }
     }
-    if (lane < P) {
-        const double nm = nominal_param_f64(lane, (double)sd.dur);
-        const double v = (double)opc[(int64_t)s * P + lane];
-        sm.nom[lane] = nm;
-        sm.x[lane] = v / nm;
-        const bool fixed = model == 9 && fixed_in_model9(lane);
-        sm.lo[lane] = fixed ? sm.x[lane] : 1.0 - box_frac;
-        sm.hi[lane] = fixed ? sm.x[lane] : 1.0 + box_frac;
-    }
-    if (lane == 0) {
+    if (member && r == 0) {
         int n = 0;
-        for (int i = 0; i < P; ++i) {
+        for (int i = 0; i < P && live; ++i) {
             if (model == 9 && (fixed_in_model9(i) || i == 1 || i == 3)) continue;
-            sm.opc_of[n] = i;
-            sm.tied[n] = (model == 9 && (i == 0 || i == 2)) ? i + 1 : -1;
+            sl.opc_of[n] = i;
+            sl.tied[n] = (model == 9 && (i == 0 || i == 2)) ? i + 1 : -1;
             ++n;
         }
-        sm.nf = n;
-        sm.lam = lam0;
-        sm.done = 0;
+        sl.nf = n;
+        sl.lam = lam0;
+        sl.done = live ? 0 : 1;
+        sl.it = live ? max_iter : 0;
     }
     __syncthreads();
-    if (lane < P) {
+    if (live && r < P) {
         // 9-parameter model: the antagonist's K_SE and K_LT follow the agonist's
-        const int src = (model == 9 && (lane == 1 || lane == 3)) ? lane - 1 : lane;
-        const double v = opc_value(sm, sm.x, src) / sm.nom[lane];
-        sm.x[lane] = fmin(fmax(model == 9 ? v : sm.x[lane], sm.lo[lane]), sm.hi[lane]);
+        const int src = (model == 9 && (r == 1 || r == 3)) ? r - 1 : r;
+        const double v = opc_value(sl, sl.x, src) / sl.nom[r];
+        sl.x[r] = fmin(fmax(model == 9 ? v : sl.x[r], sl.lo[r]), sl.hi[r]);
     }
     __syncthreads();
-    const int nf = sm.nf;
-    const Residual res{sm.X, sm.Y, sd.cphi, sd.sphi, sd.C};
-    int it = 0;
-    for (; it < max_iter; ++it) {
-        // A: sensitivities and normal equations at x (lane j: free parameter j), on the
-        // fast discretisation: it only shapes the step; costs below are exact
-        {
+    const int nf = sl.nf;
+    const Residual res{X, Y, sd.cphi, sd.sphi, sd.C};
+    for (int it = 0; it < max_iter; ++it) {
+        bool all_done = true;
+        for (int q = 0; q < PG; ++q) all_done = all_done && slots[q].done;
+        if (all_done) break;
+        const bool run = live && !sl.done;
+        // A: sensitivities and normal equations at x (lane r: free parameter r), on the fast
+        // discretisation: it only shapes the step; costs below are exact
+        if (run) {
             Dual p[P];
-            const int i0 = lane < nf ? sm.opc_of[lane] : -1;
-            const int i1 = lane < nf ? sm.tied[lane] : -1;
+            const int i0 = r < nf ? sl.opc_of[r] : -1;
+            const int i1 = r < nf ? sl.tied[r] : -1;
             for (int i = 0; i < P; ++i)
-                p[i] = Dual(opc_value(sm, sm.x, i), (i == i0 || i == i1) ? sm.nom[i] : 0.0);
-            NormalSink ns{res, objective, &sm.jst[0][0], sm.ast};
+                p[i] = Dual(opc_value(sl, sl.x, i), (i == i0 || i == i1) ? sl.nom[i] : 0.0);
+            NormalSink ns{res, objective, &sl.jst[0][0], sl.ast, r};
             ns.init(nf);
             simulate_s<DiscFast>(p, (double)sd.amp, dt, T, ns);
             ns.flush();
 #pragma unroll
-            for (int q = 0; q < 3; ++q)
-                if (ns.ei[q] >= 0) sm.H[ns.ei[q]][ns.ej[q]] = ns.h[q];
-            if (lane < nf) sm.g[lane] = ns.g;
+            for (int q = 0; q < NENT; ++q)
+                if (ns.eij[q] >= 0) sl.H[ns.eij[q] >> 8][ns.eij[q] & 255] = ns.h[q];
+            if (r < nf) sl.g[r] = ns.g;
         }
         __syncthreads();
         // B: damped solves, one damping value per lane
-        if (lane < NLAM) {
-            const double lam = sm.lam * LAM_FAC[lane];
+        if (run && r < NLAM) {
+            const double lam = sl.lam * LAM_FAC[r];
             uint32_t held = 0;
             for (int j = 0; j < P; ++j) {
                 bool h = true;
                 if (j < nf) {
-                    const int i = sm.opc_of[j];
-                    h = !(sm.H[j][j] > 0.0) || (sm.x[i] <= sm.lo[i] && sm.g[j] > 0.0) ||
-                        (sm.x[i] >= sm.hi[i] && sm.g[j] < 0.0);
+                    const int i = sl.opc_of[j];
+                    h = !(sl.H[j][j] > 0.0) || (sl.x[i] <= sl.lo[i] && sl.g[j] > 0.0) ||
+                        (sl.x[i] >= sl.hi[i] && sl.g[j] < 0.0);
                 }
                 held |= (uint32_t)h << j;
             }
             double delta[P];
-            const bool ok = damped_solve(sm, lam, held, delta);
-            for (int i = 0; i < P; ++i) sm.xt[lane][i] = sm.x[i];
+            const bool ok = damped_solve(sl, lam, held, delta);
+            for (int i = 0; i < P; ++i) sl.xt[r][i] = sl.x[i];
             if (ok) {
                 for (int j = 0; j < nf; ++j) {
-                    const int i = sm.opc_of[j];
-                    const double v = fmin(fmax(sm.x[i] + delta[j], sm.lo[i]), sm.hi[i]);
-                    sm.xt[lane][i] = v;
-                    if (sm.tied[j] >= 0) sm.xt[lane][sm.tied[j]] = v;
+                    const int i = sl.opc_of[j];
+                    const double v = fmin(fmax(sl.x[i] + delta[j], sl.lo[i]), sl.hi[i]);
+                    sl.xt[r][i] = v;
+                    if (sl.tied[j] >= 0) sl.xt[r][sl.tied[j]] = v;
                 }
             }
-            sm.ok[lane] = ok;
-            sm.ft[lane] = INFINITY;
+            sl.ok[r] = ok;
+            sl.ft[r] = INFINITY;
         }
         __syncthreads();
         // C: trial costs, and the cost at the current point (lane NLAM)
-        if ((lane < NLAM && sm.ok[lane]) || lane == NLAM) {
-            const double* xp = lane < NLAM ? sm.xt[lane] : sm.x;
+        if (run && ((r < NLAM && sl.ok[r]) || r == NLAM)) {
+            const double* xp = r < NLAM ? sl.xt[r] : sl.x;
             double p[P];
-            for (int i = 0; i < P; ++i) p[i] = opc_value(sm, xp, i);
+            for (int i = 0; i < P; ++i) p[i] = opc_value(sl, xp, i);
             CostSink cs{res, objective, 0.0, 0.0};
             simulate_s<DiscExact>(p, (double)sd.amp, dt, T, cs);
             const double f = cs.f();
-            if (lane < NLAM) sm.ft[lane] = (f >= 0.0 && f <= 1.7976931348623157e308) ? f : INFINITY;
-            else sm.fcur = f;
+            if (r < NLAM) sl.ft[r] = (f >= 0.0 && f <= 1.7976931348623157e308) ? f : INFINITY;
+            else sl.fcur = f;
         }
         __syncthreads();
         // D: decision
-        if (lane == 0) {
+        if (run && r == 0) {
             int best = 0;
             for (int m = 1; m < NLAM; ++m)
-                if (sm.ft[m] < sm.ft[best]) best = m;
+                if (sl.ft[m] < sl.ft[best]) best = m;
             int dec;
-            if (sm.ft[best] < sm.fcur) {
+            if (sl.ft[best] < sl.fcur) {
                 dec = best;
-                const double gain = sm.fcur - sm.ft[best];
-                for (int i = 0; i < P; ++i) sm.x[i] = sm.xt[best][i];
-                sm.lam = sm.lam * LAM_FAC[best] * 0.1;
-                sm.done = gain <= tol_f * sm.ft[best];
+                const double gain = sl.fcur - sl.ft[best];
+                for (int i = 0; i < P; ++i) sl.x[i] = sl.xt[best][i];
+                sl.lam = sl.lam * LAM_FAC[best] * 0.1;
+                sl.done = gain <= tol_f * sl.ft[best];
             } else {
                 dec = -1;
-                sm.lam *= 1e8;
-                sm.done = !(sm.lam <= 1e30);
+                sl.lam *= 1e8;
+                sl.done = !(sl.lam <= 1e30);
             }
+            if (sl.done) sl.it = it + 1;
             if (dec_out) dec_out[(int64_t)s * max_iter + it] = (int8_t)dec;
         }
         __syncthreads();
-        if (sm.done) { ++it; break; }
     }
-    if (lane < P) opc[(int64_t)s * P + lane] = (float)opc_value(sm, sm.x, lane);
-    if (lane == 0) {
+    if (live && r < P) opc[(int64_t)s * P + r] = (float)opc_value(sl, sl.x, r);
+    if (live && r == 0) {
         double p[P];
-        for (int i = 0; i < P; ++i) p[i] = opc_value(sm, sm.x, i);
+        for (int i = 0; i < P; ++i) p[i] = opc_value(sl, sl.x, i);
         CostSink cs{res, objective, 0.0, 0.0};
         simulate_s<DiscExact>(p, (double)sd.amp, dt, T, cs);
         const double n = (double)T * sd.C;
         rmse_out[s] = (float)sqrt(cs.sq / n);
         if (mae_out) mae_out[s] = (float)(cs.ab / n);
-        if (iters_out) iters_out[s] = it;
+        if (iters_out) iters_out[s] = sl.it;
     }
+}
+
+hipError_t launch_polish_kernel(const SacDev* sacs, const int* order, int n, int max_T, const float* pos,
+                                const int32_t* status, int model, const opmm_polish_params& prm, float* opc,
+                                float* rmse, float* mae, int32_t* iters, int8_t* dec, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (max_T < 1 || max_T > OPMM_MAX_T) return hipErrorInvalidValue;
+    if (max_T <= GROUPED_MAX_T)
+        hipLaunchKernelGGL(polish_kernel<3>, dim3((n + 2) / 3), dim3(64), sizeof(float) * 2 * 3 * (size_t)max_T, st,
+                           n, sacs, order, pos, status, max_T, model, prm.max_iter, prm.objective, (double)prm.tol_f,
+                           (double)prm.lambda0, (double)prm.box_frac, (double)prm.dt_ms, opc, rmse, mae, iters, dec);
+    else
+        hipLaunchKernelGGL(polish_kernel<1>, dim3(n), dim3(64), sizeof(float) * 2 * (size_t)max_T, st, n, sacs,
+                           order, pos, status, max_T, model, prm.max_iter, prm.objective, (double)prm.tol_f,
+                           (double)prm.lambda0, (double)prm.box_frac, (double)prm.dt_ms, opc, rmse, mae, iters, dec);
+    return hipGetLastError();
 }
 
 }  // namespace
 
 namespace opmm_rt {
 
-hipError_t launch_polish(const SacDev* sacs, int n, const float* pos, const int32_t* status, int model,
+hipError_t launch_polish(const SacDev* sacs, int n, int max_T, const float* pos, const int32_t* status, int model,
                          const opmm_polish_params& prm, float* opc, float* rmse, float* mae, hipStream_t st)
 {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(polish_kernel, dim3(n), dim3(64), 0, st, n, sacs, pos, status, model, prm.max_iter,
-                       prm.objective, (double)prm.tol_f, (double)prm.lambda0, (double)prm.box_frac,
-                       (double)prm.dt_ms, opc, rmse, mae, (int32_t*)nullptr, (int8_t*)nullptr);
-    return hipGetLastError();
+    return launch_polish_kernel(sacs, nullptr, n, max_T, pos, status, model, prm, opc, rmse, mae, nullptr, nullptr,
+                                st);
 }
 
 }  // namespace opmm_rt
@@ -692,10 +751,10 @@ int opmm_polish(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_sac
     const int32_t* status;
     int rc = opmm_rt::project_batch_full(ctx, pos, pos_len, sacs, S, &d_sacs, &proj, &qorth, &status, st);
     if (rc != OPMM_OK) return rc;
-    hipLaunchKernelGGL(polish_kernel, dim3(S), dim3(64), 0, st, S, d_sacs, pos, status, (int)model, prm->max_iter,
-                       prm->objective, (double)prm->tol_f, (double)prm->lambda0, (double)prm->box_frac,
-                       (double)prm->dt_ms, opc_inout, rmse_out, mae_out, iters_out, decisions_out);
-    hipError_t e = hipGetLastError();
+    int max_T = 1;
+    for (int i = 0; i < S; ++i) max_T = std::max(max_T, (int)sacs[i].T);
+    hipError_t e = launch_polish_kernel(d_sacs, opmm_rt::batch_order(ctx), S, max_T, pos, status, (int)model, *prm,
+                                        opc_inout, rmse_out, mae_out, iters_out, decisions_out, st);
     if (e != hipSuccess) return opmm_rt::hip_fail(ctx, e, "polish_kernel");
     return OPMM_OK;
 }

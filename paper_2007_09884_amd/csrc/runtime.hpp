@@ -32,6 +32,10 @@ int ctx_device(const opmm_ctx* ctx);
 int project_batch(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int S,
                   const SacDev** sacs_dev, const float** proj, hipStream_t st);
 
+// Device array [S] of the last project_batch: the batch's indices sorted by T, longest first
+// (ties in batch order).
+const int* batch_order(const opmm_ctx* ctx);
+
 // As project_batch, also returning the orthogonal energies and status words
 // (both indexed by SacDev::slot = position in the batch).
 int project_batch_full(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int S,
@@ -72,9 +76,9 @@ int default_shape(const opmm_ctx* ctx);
 // default_shape, or a smaller-tile shape when a saccade has fewer candidates than its tile
 int shape_for_candidates(const opmm_ctx* ctx, int64_t n_cand);
 
-// Gradient polish of n listed saccades (one wave each): opc [n][18] in/out,
+// Gradient polish of n listed saccades (a lane group each, T <= max_T): opc [n][18] in/out,
 // rmse/mae [n] out, status indexed by SacDev::slot.
-hipError_t launch_polish(const SacDev* sacs, int n, const float* pos, const int32_t* status, int model,
+hipError_t launch_polish(const SacDev* sacs, int n, int max_T, const float* pos, const int32_t* status, int model,
                          const opmm_polish_params& prm, float* opc, float* rmse, float* mae, hipStream_t st);
 
 }  // namespace opmm_rt

@@ -363,8 +363,8 @@ def test_polish_improves_the_box_search(ctx, opmm):
 
 @pytest.mark.gpu
 def test_polish_alone_equals_in_batch(ctx, opmm):
-    """Each saccade's polish is its own wave: its result does not depend on the rest of the batch
-    (bit-exact alone and in the batch)."""
+    """Each saccade's polish is its own lane group: its result does not depend on the rest of the
+    batch or on which saccades share its wave (bit-exact alone and in the batch)."""
     b, traces = make_batch(7, "uneven", seed=synth.BASE_SEED + 361)
     start, _ = _fit(ctx, opmm, b, traces, 2048, 2)
     prm = opmm.polish_params(max_iter=5)
@@ -375,6 +375,28 @@ def test_polish_alone_equals_in_batch(ctx, opmm):
         assert r1[0] == rm[s] and m1[0] == ma[s] and i1[0] == it[s], s
         assert np.array_equal(d1[0], dec[s]), s
 
+
+
+@pytest.mark.gpu
+def test_polish_long_trace_batch_equals_grouped(ctx, opmm):
+    """A batch holding a trace longer than 512 samples runs one saccade per wave; short batches
+    run three per wave.  The same saccades give bit-identical results either way."""
+    b, traces = make_batch(5, "full", seed=synth.BASE_SEED + 371)
+    T_long = 600
+    p_true = oracle.true_opc(b["mult"][4], b["dur_ms"][4])
+    z = np.random.default_rng(371).standard_normal((T_long, b["C"]))
+    traces[4] = oracle.make_target(p_true, b["amp"][4], b["dir_deg"][4], T_long, b["C"], z, b["sigma"][4])
+    b["T"] = b["T"].copy()
+    b["T"][4] = T_long
+    start, _ = _fit(ctx, opmm, b, traces, 2048, 2)
+    prm = opmm.polish_params(max_iter=4)
+    opc, rm, ma, it, dec = _polish(ctx, opmm, b, traces, prm, start)           # one per wave
+    short = list(range(4))
+    o3, r3, m3, i3, d3 = _polish(ctx, opmm, synth.subset(b, short), traces[:4], prm, start[:4])  # grouped
+    assert np.array_equal(o3.view(np.uint32), opc[:4].view(np.uint32))
+    assert np.array_equal(r3, rm[:4]) and np.array_equal(m3, ma[:4]) and np.array_equal(i3, it[:4])
+    assert np.array_equal(d3, dec[:4])
+    assert np.isfinite(rm[4]) and rm[4] <= np.sqrt(np.mean(traces[4].astype(np.float64) ** 2))
 
 @pytest.mark.gpu
 def test_polish_model9_and_mae(ctx, opmm):
