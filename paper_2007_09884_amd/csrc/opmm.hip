@@ -742,6 +742,7 @@ int hip_fail(opmm_ctx* ctx, hipError_t e, const char* what)
 }
 
 int ctx_device(const opmm_ctx* ctx) { return ctx ? ctx->device : 0; }
+int ctx_cu_count(const opmm_ctx* ctx) { return ctx && ctx->cu_count > 0 ? ctx->cu_count : 256; }
 
 }  // namespace opmm_rt
 
@@ -888,9 +889,10 @@ int upload_saccades(opmm_ctx* ctx, FitScratch& sc, const opmm_saccade* sacs, int
 }
 
 // Queue the whole fit on `st` (no host synchronisation inside: capturable).
+// run_prep = false: the projection of this upload is already queued (fit_stage).
 int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t total_T, int tiles_per_round,
                 const opmm_fit_params* prm, int shape, const float* seed_opc, float* opc_out, float* rmse_out,
-                float* mae_out, int32_t* status_out, uint64_t* round_keys, hipStream_t st)
+                float* mae_out, int32_t* status_out, uint64_t* round_keys, hipStream_t st, bool run_prep = true)
 {
     const int R = prm->n_rounds;
     int rc;
@@ -917,7 +919,7 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
     uint32_t* head = ready + S;
     uint32_t* errflag = head + 1;
 
-    hipLaunchKernelGGL(prep_kernel, dim3(S), dim3(64), 0, st, S, d_sacs, pos, proj, qorth, status);
+    if (run_prep) hipLaunchKernelGGL(prep_kernel, dim3(S), dim3(64), 0, st, S, d_sacs, pos, proj, qorth, status);
     hipLaunchKernelGGL(init_kernel, dim3(blocks_for((int64_t)S * P, 256)), dim3(256), 0, st, S, d_sacs, prm->box_frac,
                        prm->w_init_frac, seed_opc, centre, hw, lo, hi, status);
     hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for((int64_t)R * S, 256)), dim3(256), 0, st, keys,
@@ -1109,6 +1111,37 @@ int project_batch(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_s
 
 const int* batch_order(const opmm_ctx* ctx) { return (const int*)ctx->aux.order.p; }
 
+int fit_stage(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int S,
+              const opmm_fit_params* prm, float* opc_out, float* rmse_out, FitStage* fs, const SacDev** sacs_dev,
+              const float** proj, hipStream_t st)
+{
+    int rc = check_fit_args(ctx, pos, pos_len, sacs, S, prm, opc_out, rmse_out);
+    if (rc != OPMM_OK || S == 0) return rc;
+    OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    FitScratch& sc = ctx->scratch;
+    fs->shape = pick_shape(ctx, prm, sacs, S);
+    if ((rc = upload_saccades(ctx, sc, sacs, S, prm, shape_tile(fs->shape), &fs->total_T, &fs->tiles, st)) != OPMM_OK)
+        return rc;
+    if ((rc = ensure(ctx, sc.proj, sizeof(float) * fs->total_T)) != OPMM_OK) return rc;
+    if ((rc = ensure(ctx, sc.qorth, sizeof(double) * S)) != OPMM_OK) return rc;
+    if ((rc = ensure(ctx, sc.status, sizeof(int32_t) * S)) != OPMM_OK) return rc;
+    hipLaunchKernelGGL(prep_kernel, dim3(S), dim3(64), 0, st, S, (const SacDev*)sc.sacs.p, pos, (float*)sc.proj.p,
+                       (double*)sc.qorth.p, (int32_t*)sc.status.p);
+    OPMM_HIP(ctx, hipGetLastError());
+    *sacs_dev = (const SacDev*)sc.sacs.p;
+    *proj = (const float*)sc.proj.p;
+    return OPMM_OK;
+}
+
+int fit_launch(opmm_ctx* ctx, const float* pos, int S, const FitStage& fs, const opmm_fit_params* prm,
+               const float* seed_opc, float* opc_out, float* rmse_out, float* mae_out, int32_t* status_out,
+               uint64_t* round_keys, hipStream_t st)
+{
+    if (S == 0) return OPMM_OK;
+    return enqueue_fit(ctx, ctx->scratch, pos, S, fs.total_T, fs.tiles, prm, fs.shape, seed_opc, opc_out, rmse_out,
+                       mae_out, status_out, round_keys, st, false);
+}
+
 int reserve_batch(opmm_ctx* ctx, int S, int64_t total_T)
 {
     FitScratch& sc = ctx->aux;
@@ -1264,18 +1297,14 @@ int opmm_fit(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccad
              const opmm_fit_params* params, const float* seed_opc, float* opc_out, float* rmse_out, float* mae_out,
              int32_t* status_out, uint64_t* round_keys, void* stream)
 {
-    int rc = check_fit_args(ctx, pos, pos_len, sacs, S, params, opc_out, rmse_out);
-    if (rc != OPMM_OK) return rc;
-    if (S == 0) return OPMM_OK;
-    OPMM_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
-    const int shape = pick_shape(ctx, params, sacs, S);
-    int64_t total_T;
-    int tiles;
-    if ((rc = upload_saccades(ctx, ctx->scratch, sacs, S, params, shape_tile(shape), &total_T, &tiles, st)) != OPMM_OK)
-        return rc;
-    return enqueue_fit(ctx, ctx->scratch, pos, S, total_T, tiles, params, shape, seed_opc, opc_out, rmse_out, mae_out,
-                       status_out, round_keys, st);
+    opmm_rt::FitStage fs;
+    const SacDev* sd;
+    const float* proj;
+    int rc = opmm_rt::fit_stage(ctx, pos, pos_len, sacs, S, params, opc_out, rmse_out, &fs, &sd, &proj, st);
+    if (rc != OPMM_OK || S == 0) return rc;
+    return opmm_rt::fit_launch(ctx, pos, S, fs, params, seed_opc, opc_out, rmse_out, mae_out, status_out, round_keys,
+                               st);
 }
 
 int opmm_fit_plan_create(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,

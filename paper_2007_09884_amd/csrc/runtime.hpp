@@ -26,11 +26,28 @@ struct SacDev {
 int fail(opmm_ctx* ctx, int code, const std::string& msg);
 int hip_fail(opmm_ctx* ctx, hipError_t e, const char* what);
 int ctx_device(const opmm_ctx* ctx);
+int ctx_cu_count(const opmm_ctx* ctx);  // compute units of the context's device
 
 // Validate and upload saccade records, then project every trace on its
 // movement direction (ctx-owned scratch, valid until the next call on ctx).
 int project_batch(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int S,
                   const SacDev** sacs_dev, const float** proj, hipStream_t st);
+
+// A fit in two halves, for callers that queue work of their own on the batch between the upload
+// and the search (the learned seed reads the projection).  fit_stage validates like opmm_fit,
+// uploads the records into the context's fit scratch and queues the projection; *sacs_dev and
+// *proj stay valid until the next fit on ctx.  fit_launch queues the search of that upload.
+struct FitStage {
+    int shape;
+    int64_t total_T;
+    int tiles;
+};
+int fit_stage(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int S,
+              const opmm_fit_params* prm, float* opc_out, float* rmse_out, FitStage* fs, const SacDev** sacs_dev,
+              const float** proj, hipStream_t st);
+int fit_launch(opmm_ctx* ctx, const float* pos, int S, const FitStage& fs, const opmm_fit_params* prm,
+               const float* seed_opc, float* opc_out, float* rmse_out, float* mae_out, int32_t* status_out,
+               uint64_t* round_keys, hipStream_t st);
 
 // Device array [S] of the last project_batch: the batch's indices sorted by T, longest first
 // (ties in batch order).
@@ -76,9 +93,10 @@ int default_shape(const opmm_ctx* ctx);
 // default_shape, or a smaller-tile shape when a saccade has fewer candidates than its tile
 int shape_for_candidates(const opmm_ctx* ctx, int64_t n_cand);
 
-// Gradient polish of n listed saccades (a lane group each, T <= max_T): opc [n][18] in/out,
+// Gradient polish of n listed saccades (T <= max_T) on ctx's device: opc [n][18] in/out,
 // rmse/mae [n] out, status indexed by SacDev::slot.
-hipError_t launch_polish(const SacDev* sacs, int n, int max_T, const float* pos, const int32_t* status, int model,
-                         const opmm_polish_params& prm, float* opc, float* rmse, float* mae, hipStream_t st);
+hipError_t launch_polish(const opmm_ctx* ctx, const SacDev* sacs, int n, int max_T, const float* pos,
+                         const int32_t* status, int model, const opmm_polish_params& prm, float* opc, float* rmse,
+                         float* mae, hipStream_t st);
 
 }  // namespace opmm_rt

@@ -804,6 +804,21 @@ int opmm_surrogate_adam_step(opmm_surrogate* sg, float lr, void* stream)
     return sg_adam(sg, lr, (hipStream_t)stream);
 }
 
+// Learned OPC of S uploaded and projected saccades: features, network, de-normalisation into the
+// search box.
+static int sg_predict(opmm_surrogate* sg, int32_t S, const opmm_rt::SacDev* sd, const float* proj, float dt_ms,
+                      float box_frac, float* opc_out, hipStream_t st)
+{
+    int rc;
+    if ((rc = sg_alloc(sg, S)) != OPMM_OK) return rc;
+    hipLaunchKernelGGL(features_kernel, dim3(S), dim3(64), 0, st, S, sd, proj, dt_ms, sg->act[0]);
+    if ((rc = sg_forward(sg, S, sg->act[0], st)) != OPMM_OK) return rc;
+    hipLaunchKernelGGL(denorm_kernel, dim3(blocks((int64_t)S * P, 256)), dim3(256), 0, st, S, sg->out, sd, box_frac,
+                       opc_out);
+    SG_HIP(hipGetLastError());
+    return OPMM_OK;
+}
+
 int opmm_surrogate_predict(opmm_surrogate* sg, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
                            float dt_ms, float box_frac, float* opc_out, void* stream)
 {
@@ -818,13 +833,7 @@ int opmm_surrogate_predict(opmm_surrogate* sg, const float* pos, int64_t pos_len
     const opmm_rt::SacDev* sd;
     const float* proj;
     if ((rc = opmm_rt::project_batch(ctx, pos, pos_len, sacs, S, &sd, &proj, st)) != OPMM_OK) return rc;
-    if ((rc = sg_alloc(sg, S)) != OPMM_OK) return rc;
-    hipLaunchKernelGGL(features_kernel, dim3(S), dim3(64), 0, st, S, sd, proj, dt_ms, sg->act[0]);
-    if ((rc = sg_forward(sg, S, sg->act[0], st)) != OPMM_OK) return rc;
-    hipLaunchKernelGGL(denorm_kernel, dim3(blocks((int64_t)S * P, 256)), dim3(256), 0, st, S, sg->out, sd, box_frac,
-                       opc_out);
-    SG_HIP(hipGetLastError());
-    return OPMM_OK;
+    return sg_predict(sg, S, sd, proj, dt_ms, box_frac, opc_out, st);
 }
 
 int opmm_surrogate_features(opmm_surrogate* sg, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
@@ -859,14 +868,18 @@ int opmm_fit_learned(opmm_surrogate* sg, const float* pos, int64_t pos_len, cons
     if (S == 0) return OPMM_OK;
     SG_HIP(hipSetDevice(sg->device));
     hipStream_t st = (hipStream_t)stream;
-    // 1. learned seeds
+    // 1. one upload and projection of the batch serves the learned seeds and the seeded refine
+    opmm_rt::FitStage fs;
+    const opmm_rt::SacDev* sd;
+    const float* proj;
+    int rc = opmm_rt::fit_stage(ctx, pos, pos_len, sacs, S, seeded, opc_out, rmse_out, &fs, &sd, &proj, st);
+    if (rc != OPMM_OK) return rc;
     float* seeds = nullptr;
     SG_HIP(hipMallocAsync((void**)&seeds, sizeof(float) * (size_t)S * P, st));
-    int rc = opmm_surrogate_predict(sg, pos, pos_len, sacs, S, seeded->dt_ms, seeded->box_frac, seeds, stream);
+    rc = sg_predict(sg, S, sd, proj, seeded->dt_ms, seeded->box_frac, seeds, st);
     // 2. seeded refine
     if (rc == OPMM_OK)
-        rc = opmm_fit(ctx, pos, pos_len, sacs, S, seeded, seeds, opc_out, rmse_out, mae_out, status_out, nullptr,
-                      stream);
+        rc = opmm_rt::fit_launch(ctx, pos, S, fs, seeded, seeds, opc_out, rmse_out, mae_out, status_out, nullptr, st);
     // 3. the plain search judges: saccades whose seeded RMSE exceeds the threshold are re-fitted plainly
     std::vector<float> h_rmse(S);
     if (rc == OPMM_OK && hipMemcpyAsync(h_rmse.data(), rmse_out, sizeof(float) * S, hipMemcpyDeviceToHost, st) != hipSuccess)

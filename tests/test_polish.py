@@ -378,25 +378,35 @@ def test_polish_alone_equals_in_batch(ctx, opmm):
 
 
 @pytest.mark.gpu
-def test_polish_long_trace_batch_equals_grouped(ctx, opmm):
-    """A batch holding a trace longer than 512 samples runs one saccade per wave; short batches
-    run three per wave.  The same saccades give bit-identical results either way."""
-    b, traces = make_batch(5, "full", seed=synth.BASE_SEED + 371)
-    T_long = 600
-    p_true = oracle.true_opc(b["mult"][4], b["dur_ms"][4])
-    z = np.random.default_rng(371).standard_normal((T_long, b["C"]))
-    traces[4] = oracle.make_target(p_true, b["amp"][4], b["dir_deg"][4], T_long, b["C"], z, b["sigma"][4])
-    b["T"] = b["T"].copy()
-    b["T"][4] = T_long
+def test_polish_wave_layouts_agree(ctx, opmm):
+    """Batches of more saccades than the device has SIMDs run three saccades per wave; smaller
+    batches, and batches holding a trace longer than 512 samples, one per wave.  Every copy of a
+    saccade gives the same bits in each layout, whatever saccades share its wave."""
+    n = 40
+    b, traces = make_batch(n, "full", seed=synth.BASE_SEED + 371)
     start, _ = _fit(ctx, opmm, b, traces, 2048, 2)
     prm = opmm.polish_params(max_iter=4)
-    opc, rm, ma, it, dec = _polish(ctx, opmm, b, traces, prm, start)           # one per wave
-    short = list(range(4))
-    o3, r3, m3, i3, d3 = _polish(ctx, opmm, synth.subset(b, short), traces[:4], prm, start[:4])  # grouped
-    assert np.array_equal(o3.view(np.uint32), opc[:4].view(np.uint32))
-    assert np.array_equal(r3, rm[:4]) and np.array_equal(m3, ma[:4]) and np.array_equal(i3, it[:4])
-    assert np.array_equal(d3, dec[:4])
-    assert np.isfinite(rm[4]) and rm[4] <= np.sqrt(np.mean(traces[4].astype(np.float64) ** 2))
+    ref = _polish(ctx, opmm, b, traces, prm, start)                       # one saccade per wave
+    idx = [i % n for i in range(3000)]
+    big = synth.subset(b, idx)
+    big_tr = [traces[i] for i in idx]
+    grouped = _polish(ctx, opmm, big, big_tr, prm, start[idx])            # three per wave
+    # the same batch and one 600-sample recording: one per wave again
+    T_long = 600
+    p_true = oracle.true_opc(b["mult"][0], b["dur_ms"][0])
+    z = np.random.default_rng(371).standard_normal((T_long, b["C"]))
+    long_tr = oracle.make_target(p_true, b["amp"][0], b["dir_deg"][0], T_long, b["C"], z, b["sigma"][0])
+    mixed = synth.subset(b, idx + [0])
+    mixed["T"] = mixed["T"].copy()
+    mixed["T"][-1] = T_long
+    single = _polish(ctx, opmm, mixed, big_tr + [long_tr], prm, np.concatenate([start[idx], start[:1]]))
+    for out in (grouped, single):
+        opc, rm, ma, it, dec = (x[:len(idx)] for x in out)
+        assert np.array_equal(opc.view(np.uint32), ref[0][idx].view(np.uint32))
+        assert np.array_equal(rm, ref[1][idx]) and np.array_equal(ma, ref[2][idx])
+        assert np.array_equal(it, ref[3][idx]) and np.array_equal(dec, ref[4][idx])
+    assert np.isfinite(single[1][-1]) and np.all(np.isfinite(single[0][-1]))
+
 
 @pytest.mark.gpu
 def test_polish_model9_and_mae(ctx, opmm):
