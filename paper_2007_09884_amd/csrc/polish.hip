@@ -24,11 +24,12 @@
 // cost at the current point, all on the exact discretisation; the best trial
 // is taken if it lowers the cost (lambda_c becomes a tenth of its lambda),
 // otherwise lambda_c grows by 1e8 and the point stays.
-// A wave polishes three saccades, one lane group of 21 each (a saccade alone would idle 46 lanes in
-// the Jacobian pass and 55 in the trial pass); each group's arithmetic is exactly that of a wave
-// of its own.  Batches with no more saccades than the device has SIMDs, or holding a trace longer
-// than 512 samples (their staged traces would not leave room for four waves per CU), run one
-// saccade per wave.
+// A wave polishes one, two or three saccades, one lane group each (64, 32 or 21 lanes: a saccade
+// alone leaves 46 lanes idle in the Jacobian pass and 55 in the trial pass, but its wave finishes
+// sooner).  Each group's arithmetic is exactly that of a wave of its own.  The launch picks the
+// layout with the least time from the waves per SIMD and the measured relative wave times: large
+// batches share waves, batches that fit one wave per SIMD do not, and so does no batch holding a
+// trace longer than 512 samples (the staged traces would not leave room for four waves per CU).
 // Objectives: the RMSE of Section 3.4 (Gauss-Newton on squared residuals) or
 // the mean absolute difference the paper reports as OptErr (Fig. 4), by
 // iteratively reweighted least squares (weights 1/max(|e|, 1e-3 deg)).
@@ -86,12 +87,11 @@ constexpr int NLAM = 8;             // damping values tried per iteration
 constexpr int PTRI = P * (P + 1) / 2;
 constexpr double IRLS_EPS = 1e-3;   // deg: floor of |e| in the L1 weights
 constexpr int NCH = 32;             // samples of Jacobian rows staged in LDS per normal-equation pass
-// Lane groups: a wave polishes several saccades, GL lanes each (P sensitivity directions in
-// the Jacobian pass, NLAM + 1 cost lanes in the trial pass).
-constexpr int GL = 21;
-constexpr int NENT = (PTRI + GL - 1) / GL;  // lower-triangle entries accumulated per lane
-static_assert(GL >= P && GL >= NLAM + 1 && 3 * GL <= 64, "lane groups");
-// traces up to this length: three saccades per wave (their LDS fits four waves per CU)
+// Lane groups: a wave polishes pg saccades, group_lanes(pg) lanes each (P sensitivity directions
+// in the Jacobian pass, NLAM + 1 cost lanes in the trial pass).
+constexpr int group_lanes(int pg) { return pg == 1 ? 64 : pg == 2 ? 32 : 21; }
+static_assert(group_lanes(3) >= P && group_lanes(3) >= NLAM + 1 && 3 * group_lanes(3) <= 64, "lane groups");
+// traces up to this length may share a wave (three staged traces leave room for four waves per CU)
 constexpr int GROUPED_MAX_T = 512;
 // Discretisations of the plant: Taylor degree M and squarings SQ of the
 // one-sample transition (on dt / 2^SQ), Taylor degree EXM of the split
@@ -333,7 +333,9 @@ __device__ __forceinline__ void wave_sync()
 // and each lane of the group then accumulates up to NENT entries (i >= j) of the lower triangle
 // of J^T W J, h_ij += (w_k J_ki) J_kj in sample order.  Every lane of the group calls it (the
 // group's control flow is uniform).
+template <int GL>
 struct NormalSink {
+    static constexpr int NENT = (PTRI + GL - 1) / GL;  // lower-triangle entries accumulated per lane
     Residual res;
     int objective;
     double* jst;  // LDS [NCH][P]: staged rows of J
@@ -493,6 +495,7 @@ __global__ __launch_bounds__(64) void polish_kernel(int S, const SacDev* __restr
     __shared__ PolishSlot slots[PG];
     extern __shared__ float traces[];
     const int lane = threadIdx.x;
+    constexpr int GL = group_lanes(PG);
     const bool member = lane < PG * GL;
     const int g = member ? lane / GL : 0;
     const int r = lane - g * GL;  // lanes past the groups have r >= GL and no role
@@ -565,12 +568,12 @@ __global__ __launch_bounds__(64) void polish_kernel(int S, const SacDev* __restr
             const int i1 = r < nf ? sl.tied[r] : -1;
             for (int i = 0; i < P; ++i)
                 p[i] = Dual(opc_value(sl, sl.x, i), (i == i0 || i == i1) ? sl.nom[i] : 0.0);
-            NormalSink ns{res, objective, &sl.jst[0][0], sl.ast, r};
+            NormalSink<GL> ns{res, objective, &sl.jst[0][0], sl.ast, r};
             ns.init(nf);
             simulate_s<DiscFast>(p, (double)sd.amp, dt, T, ns);
             ns.flush();
 #pragma unroll
-            for (int q = 0; q < NENT; ++q)
+            for (int q = 0; q < NormalSink<GL>::NENT; ++q)
                 if (ns.eij[q] >= 0) sl.H[ns.eij[q] >> 8][ns.eij[q] & 255] = ns.h[q];
             if (r < nf) sl.g[r] = ns.g;
         }
@@ -650,22 +653,50 @@ __global__ __launch_bounds__(64) void polish_kernel(int S, const SacDev* __restr
     }
 }
 
-// Three saccades per wave pay when the batch has more saccades than the device has SIMDs (waves
-// would queue); a smaller batch gets a wave per saccade, whose wave finishes ~1.3x sooner.
+// Time of one wave polishing pg saccades, relative to a wave with one (measured with one wave per
+// SIMD: the groups' loops run to the longest member, and each lane accumulates more entries of
+// the normal matrix).
+constexpr double WAVE_TIME[4] = {0.0, 1.0, 1.30, 1.51};
+
+// Saccades per wave for n saccades (T <= max_T) on `simds` SIMDs: one wave per SIMD is resident at
+// a time, so a batch takes ceil(waves / simds) wave times.
+int polish_group(int n, int max_T, int simds)
+{
+    if (max_T > GROUPED_MAX_T) return 1;
+    int best = 1;
+    double best_t = 0.0;
+    for (int pg = 1; pg <= 3; ++pg) {
+        const int64_t waves = ((int64_t)n + pg - 1) / pg;
+        const double t = (double)((waves + simds - 1) / simds) * WAVE_TIME[pg];
+        if (pg == 1 || t < best_t) {
+            best = pg;
+            best_t = t;
+        }
+    }
+    return best;
+}
+
+template <int PG>
+void launch_group(const SacDev* sacs, const int* order, int n, int max_T, const float* pos, const int32_t* status,
+                  int model, const opmm_polish_params& prm, float* opc, float* rmse, float* mae, int32_t* iters,
+                  int8_t* dec, hipStream_t st)
+{
+    hipLaunchKernelGGL(polish_kernel<PG>, dim3((n + PG - 1) / PG), dim3(64), sizeof(float) * 2 * PG * (size_t)max_T,
+                       st, n, sacs, order, pos, status, max_T, model, prm.max_iter, prm.objective, (double)prm.tol_f,
+                       (double)prm.lambda0, (double)prm.box_frac, (double)prm.dt_ms, opc, rmse, mae, iters, dec);
+}
+
 hipError_t launch_polish_kernel(const opmm_ctx* ctx, const SacDev* sacs, const int* order, int n, int max_T,
                                 const float* pos, const int32_t* status, int model, const opmm_polish_params& prm,
                                 float* opc, float* rmse, float* mae, int32_t* iters, int8_t* dec, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     if (max_T < 1 || max_T > OPMM_MAX_T) return hipErrorInvalidValue;
-    if (max_T <= GROUPED_MAX_T && n > 4 * opmm_rt::ctx_cu_count(ctx))
-        hipLaunchKernelGGL(polish_kernel<3>, dim3((n + 2) / 3), dim3(64), sizeof(float) * 2 * 3 * (size_t)max_T, st,
-                           n, sacs, order, pos, status, max_T, model, prm.max_iter, prm.objective, (double)prm.tol_f,
-                           (double)prm.lambda0, (double)prm.box_frac, (double)prm.dt_ms, opc, rmse, mae, iters, dec);
-    else
-        hipLaunchKernelGGL(polish_kernel<1>, dim3(n), dim3(64), sizeof(float) * 2 * (size_t)max_T, st, n, sacs,
-                           order, pos, status, max_T, model, prm.max_iter, prm.objective, (double)prm.tol_f,
-                           (double)prm.lambda0, (double)prm.box_frac, (double)prm.dt_ms, opc, rmse, mae, iters, dec);
+    switch (polish_group(n, max_T, 4 * opmm_rt::ctx_cu_count(ctx))) {
+        case 3: launch_group<3>(sacs, order, n, max_T, pos, status, model, prm, opc, rmse, mae, iters, dec, st); break;
+        case 2: launch_group<2>(sacs, order, n, max_T, pos, status, model, prm, opc, rmse, mae, iters, dec, st); break;
+        default: launch_group<1>(sacs, order, n, max_T, pos, status, model, prm, opc, rmse, mae, iters, dec, st);
+    }
     return hipGetLastError();
 }
 

@@ -379,14 +379,16 @@ def test_polish_alone_equals_in_batch(ctx, opmm):
 
 @pytest.mark.gpu
 def test_polish_wave_layouts_agree(ctx, opmm):
-    """Batches of more saccades than the device has SIMDs run three saccades per wave; smaller
-    batches, and batches holding a trace longer than 512 samples, one per wave.  Every copy of a
-    saccade gives the same bits in each layout, whatever saccades share its wave."""
+    """On 1024 SIMDs, 40 saccades run one per wave, 2000 two per wave, 3000 three per wave, and a
+    batch holding a trace longer than 512 samples one per wave.  Every copy of a saccade gives the
+    same bits in each layout, whatever saccades share its wave."""
     n = 40
     b, traces = make_batch(n, "full", seed=synth.BASE_SEED + 371)
     start, _ = _fit(ctx, opmm, b, traces, 2048, 2)
     prm = opmm.polish_params(max_iter=4)
     ref = _polish(ctx, opmm, b, traces, prm, start)                       # one saccade per wave
+    idx2 = [i % n for i in range(2000)]
+    pairs = _polish(ctx, opmm, synth.subset(b, idx2), [traces[i] for i in idx2], prm, start[idx2])  # two per wave
     idx = [i % n for i in range(3000)]
     big = synth.subset(b, idx)
     big_tr = [traces[i] for i in idx]
@@ -400,11 +402,11 @@ def test_polish_wave_layouts_agree(ctx, opmm):
     mixed["T"] = mixed["T"].copy()
     mixed["T"][-1] = T_long
     single = _polish(ctx, opmm, mixed, big_tr + [long_tr], prm, np.concatenate([start[idx], start[:1]]))
-    for out in (grouped, single):
-        opc, rm, ma, it, dec = (x[:len(idx)] for x in out)
-        assert np.array_equal(opc.view(np.uint32), ref[0][idx].view(np.uint32))
-        assert np.array_equal(rm, ref[1][idx]) and np.array_equal(ma, ref[2][idx])
-        assert np.array_equal(it, ref[3][idx]) and np.array_equal(dec, ref[4][idx])
+    for out, ix in ((pairs, idx2), (grouped, idx), (single, idx)):
+        opc, rm, ma, it, dec = (x[:len(ix)] for x in out)
+        assert np.array_equal(opc.view(np.uint32), ref[0][ix].view(np.uint32))
+        assert np.array_equal(rm, ref[1][ix]) and np.array_equal(ma, ref[2][ix])
+        assert np.array_equal(it, ref[3][ix]) and np.array_equal(dec, ref[4][ix])
     assert np.isfinite(single[1][-1]) and np.all(np.isfinite(single[0][-1]))
 
 
