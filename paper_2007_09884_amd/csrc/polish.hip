@@ -28,8 +28,8 @@
 // alone leaves 46 lanes idle in the Jacobian pass and 55 in the trial pass, but its wave finishes
 // sooner).  Each group's arithmetic is exactly that of a wave of its own.  The launch picks the
 // layout with the least time from the waves per SIMD and the measured relative wave times: large
-// batches share waves, batches that fit one wave per SIMD do not, and so does no batch holding a
-// trace longer than 512 samples (the staged traces would not leave room for four waves per CU).
+// batches share waves; batches that fit one wave per SIMD, and batches holding a trace longer than
+// 512 samples (three staged traces would not leave room for four waves per CU), do not.
 // Objectives: the RMSE of Section 3.4 (Gauss-Newton on squared residuals) or
 // the mean absolute difference the paper reports as OptErr (Fig. 4), by
 // iteratively reweighted least squares (weights 1/max(|e|, 1e-3 deg)).
