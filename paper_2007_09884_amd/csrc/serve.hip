@@ -401,8 +401,8 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
             pp.max_iter = sv->prm.polish_iter;
             pp.box_frac = sv->prm.plain.box_frac;
             pp.dt_ms = dt;
-            SV_HIP(opmm_rt::launch_polish(sv->ctx, sv->d_list, nf, sv->max_T, sv->d_pos, sv->ss.status, sv->prm.plain.model, pp, opc, rm,
-                                          ma, st));
+            SV_HIP(opmm_rt::launch_polish(sv->ctx, sv->d_list, nf, sv->max_T, sv->d_pos, sv->ss.status,
+                                          sv->prm.plain.model, pp, opc, rm, ma, st));
         }
         SV_HIP(hipMemcpyAsync(sv->h_out, opc, sizeof(float) * P * nf, hipMemcpyDeviceToHost, st));
         SV_HIP(hipMemcpyAsync(sv->h_out + (size_t)P * sv->slots, rm, sizeof(float) * nf, hipMemcpyDeviceToHost, st));
