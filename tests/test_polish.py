@@ -380,8 +380,8 @@ def test_polish_alone_equals_in_batch(ctx, opmm):
 @pytest.mark.gpu
 def test_polish_wave_layouts_agree(ctx, opmm):
     """On 1024 SIMDs, 40 saccades run one per wave, 2000 two per wave, 3000 three per wave, and a
-    batch holding a trace longer than 512 samples one per wave.  Every copy of a saccade gives the
-    same bits in each layout, whatever saccades share its wave."""
+    batch holding a trace longer than 512 samples (here the 2048-sample maximum) one per wave.
+    Every copy of a saccade gives the same bits in each layout, whatever saccades share its wave."""
     n = 40
     b, traces = make_batch(n, "full", seed=synth.BASE_SEED + 371)
     start, _ = _fit(ctx, opmm, b, traces, 2048, 2)
@@ -393,8 +393,8 @@ def test_polish_wave_layouts_agree(ctx, opmm):
     big = synth.subset(b, idx)
     big_tr = [traces[i] for i in idx]
     grouped = _polish(ctx, opmm, big, big_tr, prm, start[idx])            # three per wave
-    # the same batch and one 600-sample recording: one per wave again
-    T_long = 600
+    # the same batch and one recording of the longest trace the library takes: one per wave again
+    T_long = opmm.MAX_T
     p_true = oracle.true_opc(b["mult"][0], b["dur_ms"][0])
     z = np.random.default_rng(371).standard_normal((T_long, b["C"]))
     long_tr = oracle.make_target(p_true, b["amp"][0], b["dir_deg"][0], T_long, b["C"], z, b["sigma"][0])
