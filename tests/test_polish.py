@@ -378,21 +378,24 @@ def test_polish_alone_equals_in_batch(ctx, opmm):
 
 
 @pytest.mark.gpu
-def test_polish_wave_layouts_agree(ctx, opmm):
+@pytest.mark.parametrize("model,objective", [(18, 0), (9, 1)])
+def test_polish_wave_layouts_agree(ctx, opmm, model, objective):
     """On 1024 SIMDs, 40 saccades run one per wave, 2000 two per wave, 3000 three per wave, and a
     batch holding a trace longer than 512 samples (here the 2048-sample maximum) one per wave.
-    Every copy of a saccade gives the same bits in each layout, whatever saccades share its wave."""
+    Every copy of a saccade gives the same bits in each layout, whatever saccades share its wave
+    (18-parameter RMSE polish, and the 9-parameter model with its 9 free parameters on OptErr)."""
     n = 40
     b, traces = make_batch(n, "full", seed=synth.BASE_SEED + 371)
-    start, _ = _fit(ctx, opmm, b, traces, 2048, 2)
-    prm = opmm.polish_params(max_iter=4)
-    ref = _polish(ctx, opmm, b, traces, prm, start)                       # one saccade per wave
+    start, _ = _fit(ctx, opmm, b, traces, 2048, 2, model=model)
+    prm = opmm.polish_params(max_iter=4, objective=objective)
+    ref = _polish(ctx, opmm, b, traces, prm, start, model)                # one saccade per wave
     idx2 = [i % n for i in range(2000)]
-    pairs = _polish(ctx, opmm, synth.subset(b, idx2), [traces[i] for i in idx2], prm, start[idx2])  # two per wave
+    pairs = _polish(ctx, opmm, synth.subset(b, idx2), [traces[i] for i in idx2], prm, start[idx2],
+                    model)                                                # two per wave
     idx = [i % n for i in range(3000)]
     big = synth.subset(b, idx)
     big_tr = [traces[i] for i in idx]
-    grouped = _polish(ctx, opmm, big, big_tr, prm, start[idx])            # three per wave
+    grouped = _polish(ctx, opmm, big, big_tr, prm, start[idx], model)     # three per wave
     # the same batch and one recording of the longest trace the library takes: one per wave again
     T_long = opmm.MAX_T
     p_true = oracle.true_opc(b["mult"][0], b["dur_ms"][0])
@@ -401,7 +404,7 @@ def test_polish_wave_layouts_agree(ctx, opmm):
     mixed = synth.subset(b, idx + [0])
     mixed["T"] = mixed["T"].copy()
     mixed["T"][-1] = T_long
-    single = _polish(ctx, opmm, mixed, big_tr + [long_tr], prm, np.concatenate([start[idx], start[:1]]))
+    single = _polish(ctx, opmm, mixed, big_tr + [long_tr], prm, np.concatenate([start[idx], start[:1]]), model)
     for out, ix in ((pairs, idx2), (grouped, idx), (single, idx)):
         opc, rm, ma, it, dec = (x[:len(ix)] for x in out)
         assert np.array_equal(opc.view(np.uint32), ref[0][ix].view(np.uint32))
