@@ -64,6 +64,10 @@ int project_batch_full(opmm_ctx* ctx, const float* pos, int64_t pos_len, const o
 int reserve_batch(opmm_ctx* ctx, int S, int64_t total_T);
 // Grow the learned seed's activation buffers to `batch` rows now.
 int surrogate_reserve(opmm_surrogate* sg, int batch);
+// Learned OPC [n][18] of n device records whose traces are already projected (proj at each
+// record's proj_off): features, network, de-normalisation into the search box.
+int surrogate_predict_projected(opmm_surrogate* sg, int n, const SacDev* sacs, const float* proj, float dt_ms,
+                                float box_frac, float* opc_out, hipStream_t st);
 
 int validate_saccade(opmm_ctx* ctx, const opmm_saccade& s, int64_t pos_len, int i);
 SacDev make_record(const opmm_saccade& s, int n_cand_default);

@@ -94,7 +94,7 @@ struct opmm_server {
     float* d_out = nullptr;    // [slots][18 + 2] opc, rmse, mae
     int32_t* d_st = nullptr;   // [slots]
     // pinned host staging
-    SacDev* h_list = nullptr;
+    SacDev* h_list = nullptr;  // 4 x [slots]: restart, admitted, active and finished lists of a step
     float* h_out = nullptr;
     int32_t* h_st = nullptr;
     float* h_trace = nullptr;  // [slots][max_T * 2]
@@ -218,7 +218,7 @@ int opmm_server_create(opmm_ctx* ctx, opmm_surrogate* sg, const opmm_serve_param
     dm((void**)&sv->d_seed, sizeof(float) * P * (size_t)slots);
     dm((void**)&sv->d_out, sizeof(float) * (P + 2) * (size_t)slots);
     dm((void**)&sv->d_st, sizeof(int32_t) * slots);
-    hm((void**)&sv->h_list, sizeof(SacDev) * slots);
+    hm((void**)&sv->h_list, sizeof(SacDev) * 4 * (size_t)slots);
     hm((void**)&sv->h_out, sizeof(float) * (P + 2) * (size_t)slots);
     hm((void**)&sv->h_st, sizeof(int32_t) * slots);
     hm((void**)&sv->h_trace, sizeof(float) * (size_t)slots * sv->max_T * 2);
@@ -312,14 +312,22 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
     const float dt = sv->prm.plain.dt_ms;
     const float box = sv->prm.plain.box_frac;
     int rc;
+    // Each list of the step is staged in its own part of h_list, so no copy has to finish before
+    // the host writes the next list; the device list d_list is reused in stream order.  The step
+    // ends with one synchronisation, after which every part may be rewritten.
+    SacDev* h_re = sv->h_list;
+    SacDev* h_adm = sv->h_list + sv->slots;
+    SacDev* h_act = sv->h_list + 2 * (size_t)sv->slots;
+    SacDev* h_fin = sv->h_list + 3 * (size_t)sv->slots;
+    bool queued = false;
     // 1. slots restarting with the plain search (their seeded result was rejected)
     if (!sv->reinit.empty()) {
         const int n = (int)sv->reinit.size();
-        for (int i = 0; i < n; ++i) sv->h_list[i] = slot_record(sv, sv->reinit[i]);
-        SV_HIP(hipMemcpyAsync(sv->d_list, sv->h_list, sizeof(SacDev) * n, hipMemcpyHostToDevice, st));
+        for (int i = 0; i < n; ++i) h_re[i] = slot_record(sv, sv->reinit[i]);
+        SV_HIP(hipMemcpyAsync(sv->d_list, h_re, sizeof(SacDev) * n, hipMemcpyHostToDevice, st));
         SV_HIP(opmm_rt::launch_init(sv->d_list, n, box, sv->prm.plain.w_init_frac, nullptr, sv->ss, st));
-        SV_HIP(hipStreamSynchronize(st));  // h_list is reused below
         sv->reinit.clear();
+        queued = true;
     }
     // 2. admission: pending requests into free slots
     std::vector<int> adm;
@@ -346,21 +354,19 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
     }
     if (!adm.empty()) {
         const int n = (int)adm.size();
-        for (int i = 0; i < n; ++i) sv->h_list[i] = slot_record(sv, adm[i]);
-        SV_HIP(hipMemcpyAsync(sv->d_list, sv->h_list, sizeof(SacDev) * n, hipMemcpyHostToDevice, st));
+        for (int i = 0; i < n; ++i) h_adm[i] = slot_record(sv, adm[i]);
+        SV_HIP(hipMemcpyAsync(sv->d_list, h_adm, sizeof(SacDev) * n, hipMemcpyHostToDevice, st));
         SV_HIP(opmm_rt::launch_prep(sv->d_list, n, sv->d_pos, sv->ss, st));
         const float* seeds = nullptr;
         if (sv->sg) {
-            std::vector<opmm_saccade> sacs(n);
-            for (int i = 0; i < n; ++i) sacs[i] = slot_saccade(sv, adm[i]);
-            rc = opmm_surrogate_predict(sv->sg, sv->d_pos, (int64_t)sv->slots * sv->max_T * 2, sacs.data(), n, dt,
-                                        box, sv->d_seed, st);
+            // the network reads the projection just queued for the admitted slots
+            rc = opmm_rt::surrogate_predict_projected(sv->sg, n, sv->d_list, sv->d_proj, dt, box, sv->d_seed, st);
             if (rc != OPMM_OK) return rc;
             seeds = sv->d_seed;
         }
         const opmm_fit_params& fp = phase_params(sv, PH_FIRST);
         SV_HIP(opmm_rt::launch_init(sv->d_list, n, box, fp.w_init_frac, seeds, sv->ss, st));
-        SV_HIP(hipStreamSynchronize(st));  // h_list is reused below
+        queued = true;
     }
     // 3. one round for every occupied slot, each at its own round
     std::vector<int> act;
@@ -371,16 +377,17 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
         SacDev d = slot_record(sv, k);
         d.tile_base = tiles;
         tiles += d.tiles;
-        sv->h_list[act.size()] = d;
+        h_act[act.size()] = d;
         act.push_back(k);
     }
     const int na = (int)act.size();
     if (na > 0) {
-        SV_HIP(hipMemcpyAsync(sv->d_list, sv->h_list, sizeof(SacDev) * na, hipMemcpyHostToDevice, st));
+        SV_HIP(hipMemcpyAsync(sv->d_list, h_act, sizeof(SacDev) * na, hipMemcpyHostToDevice, st));
         SV_HIP(opmm_rt::launch_reset_keys(sv->d_list, na, sv->ss, st));
         SV_HIP(opmm_rt::launch_round(sv->shape, sv->d_list, na, tiles, dt, sv->ss, st));
         SV_HIP(opmm_rt::launch_refine(sv->d_list, na, phase_params(sv, PH_FIRST).shrink, sv->ss, st));
         for (int k : act) sv->slot[k].round++;
+        queued = true;
     }
     // 4. harvest slots whose search is complete
     std::vector<int> fin;
@@ -388,9 +395,8 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
         if (sv->slot[k].round >= sv->slot[k].rounds) fin.push_back(k);
     if (!fin.empty()) {
         const int nf = (int)fin.size();
-        SV_HIP(hipStreamSynchronize(st));  // the active list in h_list has been consumed
-        for (int i = 0; i < nf; ++i) sv->h_list[i] = slot_record(sv, fin[i]);
-        SV_HIP(hipMemcpyAsync(sv->d_list, sv->h_list, sizeof(SacDev) * nf, hipMemcpyHostToDevice, st));
+        for (int i = 0; i < nf; ++i) h_fin[i] = slot_record(sv, fin[i]);
+        SV_HIP(hipMemcpyAsync(sv->d_list, h_fin, sizeof(SacDev) * nf, hipMemcpyHostToDevice, st));
         float* opc = sv->d_out;
         float* rm = sv->d_out + (size_t)P * sv->slots;
         float* ma = rm + sv->slots;
@@ -457,7 +463,7 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
             ndone++;
         }
         if (n_done_out) *n_done_out = ndone;
-    } else if (na > 0 || !adm.empty()) {
+    } else if (queued) {
         SV_HIP(hipStreamSynchronize(st));
     }
     sv->n_steps++;

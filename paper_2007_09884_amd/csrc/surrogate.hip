@@ -819,6 +819,19 @@ static int sg_predict(opmm_surrogate* sg, int32_t S, const opmm_rt::SacDev* sd, 
     return OPMM_OK;
 }
 
+}  // extern "C"
+
+namespace opmm_rt {
+int surrogate_predict_projected(opmm_surrogate* sg, int n, const SacDev* sacs, const float* proj, float dt_ms,
+                                float box_frac, float* opc_out, hipStream_t st)
+{
+    if (n <= 0) return OPMM_OK;
+    return sg_predict(sg, n, sacs, proj, dt_ms, box_frac, opc_out, st);
+}
+}  // namespace opmm_rt
+
+extern "C" {
+
 int opmm_surrogate_predict(opmm_surrogate* sg, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
                            float dt_ms, float box_frac, float* opc_out, void* stream)
 {
