@@ -1142,16 +1142,6 @@ int fit_launch(opmm_ctx* ctx, const float* pos, int S, const FitStage& fs, const
                        mae_out, status_out, round_keys, st, false);
 }
 
-int reserve_batch(opmm_ctx* ctx, int S, int64_t total_T)
-{
-    FitScratch& sc = ctx->aux;
-    int rc;
-    if ((rc = ensure(ctx, sc.sacs, sizeof(SacDev) * (size_t)S)) != OPMM_OK) return rc;
-    if ((rc = ensure(ctx, sc.proj, sizeof(float) * (size_t)total_T)) != OPMM_OK) return rc;
-    if ((rc = ensure(ctx, sc.qorth, sizeof(double) * (size_t)S)) != OPMM_OK) return rc;
-    return ensure(ctx, sc.status, sizeof(int32_t) * (size_t)S);
-}
-
 int project_batch_full(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int S,
                        const SacDev** sacs_dev, const float** proj, const double** qorth, const int32_t** status,
                        hipStream_t st)

@@ -59,9 +59,6 @@ int project_batch_full(opmm_ctx* ctx, const float* pos, int64_t pos_len, const o
                        const SacDev** sacs_dev, const float** proj, const double** qorth, const int32_t** status,
                        hipStream_t st);
 
-// Grow the context's batch scratch (used by project_batch) to S records of
-// total_T samples now, so that later calls up to that size allocate nothing.
-int reserve_batch(opmm_ctx* ctx, int S, int64_t total_T);
 // Grow the learned seed's activation buffers to `batch` rows now.
 int surrogate_reserve(opmm_surrogate* sg, int batch);
 // Learned OPC [n][18] of n device records whose traces are already projected (proj at each

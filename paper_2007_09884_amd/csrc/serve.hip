@@ -63,6 +63,18 @@ struct Done {
     double t_arrival, t_done;
 };
 
+// Admitted traces, staged contiguously (one copy per step), into their slots' rows of pos.
+// Record i's trace is T * C <= stride floats (T <= max_T was checked at submission).
+__global__ void scatter_traces_kernel(int n, const SacDev* __restrict__ list, const float* __restrict__ staged,
+                                      int stride, float* __restrict__ pos)
+{
+    const int i = blockIdx.x;
+    if (i >= n) return;
+    const SacDev d = list[i];
+    const int len = d.T * d.C;
+    for (int k = threadIdx.x; k < len; k += blockDim.x) pos[d.pos_off + k] = staged[(size_t)i * stride + k];
+}
+
 double now_s()
 {
     using namespace std::chrono;
@@ -93,11 +105,12 @@ struct opmm_server {
     float* d_seed = nullptr;   // [slots][18]
     float* d_out = nullptr;    // [slots][18 + 2] opc, rmse, mae
     int32_t* d_st = nullptr;   // [slots]
+    float* d_adm_trace = nullptr;  // [max_admit][max_T * 2]: staged admitted traces
     // pinned host staging
     SacDev* h_list = nullptr;  // 4 x [slots]: restart, admitted, active and finished lists of a step
     float* h_out = nullptr;
     int32_t* h_st = nullptr;
-    float* h_trace = nullptr;  // [slots][max_T * 2]
+    float* h_adm_trace = nullptr;  // [max_admit][max_T * 2]: traces admitted in one step
     // host state
     std::vector<Slot> slot;
     std::vector<int> free_slots;
@@ -221,12 +234,11 @@ int opmm_server_create(opmm_ctx* ctx, opmm_surrogate* sg, const opmm_serve_param
     hm((void**)&sv->h_list, sizeof(SacDev) * 4 * (size_t)slots);
     hm((void**)&sv->h_out, sizeof(float) * (P + 2) * (size_t)slots);
     hm((void**)&sv->h_st, sizeof(int32_t) * slots);
-    hm((void**)&sv->h_trace, sizeof(float) * (size_t)slots * sv->max_T * 2);
     // a step admits at most max_admit requests; size the per-call scratch for that now, so no step
     // reallocates (which would synchronise the device) when a burst arrives
     sv->max_admit = std::min(slots, kMaxAdmitPerStep);
-    if (rc == OPMM_OK)
-        rc = opmm_rt::reserve_batch(ctx, sv->max_admit, (int64_t)sv->max_admit * sv->max_T);
+    hm((void**)&sv->h_adm_trace, sizeof(float) * (size_t)sv->max_admit * sv->max_T * 2);
+    dm((void**)&sv->d_adm_trace, sizeof(float) * (size_t)sv->max_admit * sv->max_T * 2);
     if (rc == OPMM_OK && sg) rc = opmm_rt::surrogate_reserve(sg, sv->max_admit);
     if (rc != OPMM_OK) {
         opmm_server_destroy(sv);
@@ -252,9 +264,10 @@ int opmm_server_destroy(opmm_server* sv)
     (void)hipSetDevice(sv->device);
     if (sv->stream) (void)hipStreamSynchronize(sv->stream);
     for (void* p : {(void*)sv->d_pos, (void*)sv->d_box, (void*)sv->d_status, (void*)sv->d_keys, (void*)sv->d_proj,
-                    (void*)sv->d_qorth, (void*)sv->d_list, (void*)sv->d_seed, (void*)sv->d_out, (void*)sv->d_st})
+                    (void*)sv->d_qorth, (void*)sv->d_list, (void*)sv->d_seed, (void*)sv->d_out, (void*)sv->d_st,
+                    (void*)sv->d_adm_trace})
         if (p) (void)hipFree(p);
-    for (void* p : {(void*)sv->h_list, (void*)sv->h_out, (void*)sv->h_st, (void*)sv->h_trace})
+    for (void* p : {(void*)sv->h_list, (void*)sv->h_out, (void*)sv->h_st, (void*)sv->h_adm_trace})
         if (p) (void)hipHostFree(p);
     if (sv->stream) (void)hipStreamDestroy(sv->stream);
     delete sv;
@@ -345,9 +358,7 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
         sl.round = 0;
         sl.rounds = phase_params(sv, PH_FIRST).n_rounds;
         sl.n_cand = phase_params(sv, PH_FIRST).n_cand;
-        std::memcpy(sv->h_trace + (size_t)k * sv->max_T * 2, r.trace.data(), sizeof(float) * r.trace.size());
-        SV_HIP(hipMemcpyAsync(sv->d_pos + (size_t)k * sv->max_T * 2, sv->h_trace + (size_t)k * sv->max_T * 2,
-                              sizeof(float) * r.trace.size(), hipMemcpyHostToDevice, st));
+        std::memcpy(sv->h_adm_trace + adm.size() * sv->max_T * 2, r.trace.data(), sizeof(float) * r.trace.size());
         adm.push_back(k);
         sv->pending.pop_front();
         sv->n_admitted++;
@@ -355,7 +366,12 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
     if (!adm.empty()) {
         const int n = (int)adm.size();
         for (int i = 0; i < n; ++i) h_adm[i] = slot_record(sv, adm[i]);
+        SV_HIP(hipMemcpyAsync(sv->d_adm_trace, sv->h_adm_trace, sizeof(float) * n * sv->max_T * 2,
+                              hipMemcpyHostToDevice, st));
         SV_HIP(hipMemcpyAsync(sv->d_list, h_adm, sizeof(SacDev) * n, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(scatter_traces_kernel, dim3(n), dim3(64), 0, st, n, (const SacDev*)sv->d_list,
+                           (const float*)sv->d_adm_trace, sv->max_T * 2, sv->d_pos);
+        SV_HIP(hipGetLastError());
         SV_HIP(opmm_rt::launch_prep(sv->d_list, n, sv->d_pos, sv->ss, st));
         const float* seeds = nullptr;
         if (sv->sg) {
