@@ -93,6 +93,8 @@ int shape_tile(int shape);
 int default_shape(const opmm_ctx* ctx);
 // default_shape, or a smaller-tile shape when a saccade has fewer candidates than its tile
 int shape_for_candidates(const opmm_ctx* ctx, int64_t n_cand);
+// `base`, or a smaller-tile shape when a launch of `tiles` tiles of `base` would leave CUs idle
+int launch_shape(const opmm_ctx* ctx, int base, int64_t tiles);
 
 // Gradient polish of n listed saccades (T <= max_T) on ctx's device: opc [n][18] in/out,
 // rmse/mae [n] out, status indexed by SacDev::slot.

@@ -384,23 +384,30 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
         SV_HIP(opmm_rt::launch_init(sv->d_list, n, box, fp.w_init_frac, seeds, sv->ss, st));
         queued = true;
     }
-    // 3. one round for every occupied slot, each at its own round
+    // 3. one round for every occupied slot, each at its own round; a step too small to fill the
+    // device takes the smaller-tile shape
     std::vector<int> act;
-    int tiles = 0;
+    int64_t base_tiles = 0;
     for (int k = 0; k < sv->slots; ++k) {
         Slot& sl = sv->slot[k];
         if (!sl.busy || sl.round >= sl.rounds) continue;
-        SacDev d = slot_record(sv, k);
-        d.tile_base = tiles;
-        tiles += d.tiles;
-        h_act[act.size()] = d;
+        h_act[act.size()] = slot_record(sv, k);
+        base_tiles += h_act[act.size()].tiles;
         act.push_back(k);
     }
     const int na = (int)act.size();
+    const int shape = opmm_rt::launch_shape(sv->ctx, sv->shape, base_tiles);
+    const int tile = opmm_rt::shape_tile(shape);
+    int tiles = 0;
+    for (int i = 0; i < na; ++i) {
+        h_act[i].tiles = (h_act[i].n_cand + tile - 1) / tile;
+        h_act[i].tile_base = tiles;
+        tiles += h_act[i].tiles;
+    }
     if (na > 0) {
         SV_HIP(hipMemcpyAsync(sv->d_list, h_act, sizeof(SacDev) * na, hipMemcpyHostToDevice, st));
         SV_HIP(opmm_rt::launch_reset_keys(sv->d_list, na, sv->ss, st));
-        SV_HIP(opmm_rt::launch_round(sv->shape, sv->d_list, na, tiles, dt, sv->ss, st));
+        SV_HIP(opmm_rt::launch_round(shape, sv->d_list, na, tiles, dt, sv->ss, st));
         SV_HIP(opmm_rt::launch_refine(sv->d_list, na, phase_params(sv, PH_FIRST).shrink, sv->ss, st));
         for (int k : act) sv->slot[k].round++;
         queued = true;
