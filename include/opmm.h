@@ -101,7 +101,10 @@ typedef struct {
     int32_t mode;        /* OPMM_FIT_ROUNDS: one launch per round;
                             OPMM_FIT_PERSISTENT: one work-queue launch for
                             every round and saccade (uneven batches)         */
-    int32_t tile;        /* kernel shape index; -1 = autotuned/default       */
+    int32_t tile;        /* kernel shape index; -1 = autotuned/default, and
+                            the 512-candidate tile for a launch with fewer
+                            tiles than the device has CUs (same results,
+                            each block finishes sooner)                      */
     int32_t model;       /* 18: the 18-parameter OPMM (Section 2.2.1);
                             9: the 9-parameter OPMM (Section 2.2.2, Table 2):
                             one K_SE and one K_LT for both muscles (the

@@ -985,11 +985,12 @@ constexpr int kSmallTileShape = 1;  // tpb256_pass2_unroll1
 
 // Shape for a launch of `tiles` tiles of shape `base`.  A launch with fewer tiles than the device
 // has CUs leaves CUs idle, and its time is one block's: the small tile (more, shorter blocks)
-// finishes sooner, e.g. one saccade x 4096 candidates in 0.074 instead of 0.125 ms per captured
-// fit.  A tuned context keeps its shape.
+// finishes sooner, e.g. one saccade x 4096 candidates in 0.075 instead of 0.125 ms per captured
+// fit.  This holds for a shape the autotuner picked too (it times full batches); only an explicit
+// opmm_fit_params.tile is kept as given.
 int launch_shape_impl(const opmm_ctx* ctx, int base, int64_t tiles)
 {
-    if (ctx->tuned_shape >= 0 || shape_tile(base) <= shape_tile(kSmallTileShape)) return base;
+    if (shape_tile(base) <= shape_tile(kSmallTileShape)) return base;
     return tiles < std::max(ctx->cu_count, 1) ? kSmallTileShape : base;
 }
 
