@@ -30,6 +30,7 @@ namespace {
 
 constexpr int P = OPMM_P;
 constexpr int kMaxAdmitPerStep = 4096;
+constexpr int kPolishBatches = 3;
 
 struct Request {
     int64_t id;
@@ -53,6 +54,17 @@ struct Slot {
     float prev_opc[P];
     float prev_rmse = 0, prev_mae = 0;
     int32_t prev_status = 0;
+};
+
+struct PolishBatch {
+    hipStream_t stream = nullptr;  // batches run concurrently, each on its own stream
+    hipEvent_t done = nullptr;
+    SacDev* d_list = nullptr;  // [slots]
+    float* d_out = nullptr;    // [slots][18 + 2]
+    int32_t* d_st = nullptr;   // [slots]
+    float* h_out = nullptr;
+    int32_t* h_st = nullptr;
+    std::vector<int> fin;      // slots of the batch
 };
 
 struct Done {
@@ -106,6 +118,12 @@ struct opmm_server {
     float* d_out = nullptr;    // [slots][18 + 2] opc, rmse, mae
     int32_t* d_st = nullptr;   // [slots]
     float* d_adm_trace = nullptr;  // [max_admit][max_T * 2]: staged admitted traces
+    // Polish of finished searches on streams of their own, so it overlaps the following steps'
+    // rounds.  Up to kPolishBatches batches are in flight, each on its own stream with its
+    // records, outputs (the d_out layout) and status, taken in order when their event completes.
+    hipEvent_t ev_fin = nullptr;
+    PolishBatch pb[kPolishBatches];
+    int pb_head = 0, pb_count = 0;  // ring of in-flight batches, oldest at pb_head
     // pinned host staging
     SacDev* h_list = nullptr;  // 4 x [slots]: restart, admitted, active and finished lists of a step
     float* h_out = nullptr;
@@ -201,7 +219,10 @@ int opmm_server_create(opmm_ctx* ctx, opmm_surrogate* sg, const opmm_serve_param
         return opmm_rt::fail(ctx, OPMM_EINVAL, "polish_iter must be in 0..100");
     // slots admitted by memory: what one resident request costs on the device
     const size_t per_slot = sizeof(float) * (3 * (size_t)prm->max_T + 4 * P + P + P + 2) + sizeof(int32_t) * 2 +
-                            sizeof(uint64_t) + sizeof(double) + sizeof(SacDev);
+                            sizeof(uint64_t) + sizeof(double) + sizeof(SacDev) +
+                            (prm->polish_iter > 0
+                                 ? kPolishBatches * (sizeof(SacDev) + sizeof(float) * (P + 2) + sizeof(int32_t))
+                                 : 0);
     const int64_t by_budget = (int64_t)(prm->hbm_budget_bytes / per_slot);
     const int slots = (int)std::min<int64_t>(prm->max_slots, by_budget);
     if (slots < 1) return opmm_rt::fail(ctx, OPMM_ENOMEM, "HBM budget below one slot");
@@ -239,6 +260,20 @@ int opmm_server_create(opmm_ctx* ctx, opmm_surrogate* sg, const opmm_serve_param
     sv->max_admit = std::min(slots, kMaxAdmitPerStep);
     hm((void**)&sv->h_adm_trace, sizeof(float) * (size_t)sv->max_admit * sv->max_T * 2);
     dm((void**)&sv->d_adm_trace, sizeof(float) * (size_t)sv->max_admit * sv->max_T * 2);
+    if (prm->polish_iter > 0) {
+        if (rc == OPMM_OK && hipEventCreateWithFlags(&sv->ev_fin, hipEventDisableTiming) != hipSuccess)
+            rc = OPMM_EDEVICE;
+        for (PolishBatch& b : sv->pb) {
+            if (rc == OPMM_OK && (hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking) != hipSuccess ||
+                                  hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess))
+                rc = OPMM_EDEVICE;
+            dm((void**)&b.d_list, sizeof(SacDev) * slots);
+            dm((void**)&b.d_out, sizeof(float) * (P + 2) * (size_t)slots);
+            dm((void**)&b.d_st, sizeof(int32_t) * slots);
+            hm((void**)&b.h_out, sizeof(float) * (P + 2) * (size_t)slots);
+            hm((void**)&b.h_st, sizeof(int32_t) * slots);
+        }
+    }
     if (rc == OPMM_OK && sg) rc = opmm_rt::surrogate_reserve(sg, sv->max_admit);
     if (rc != OPMM_OK) {
         opmm_server_destroy(sv);
@@ -263,12 +298,23 @@ int opmm_server_destroy(opmm_server* sv)
     if (!sv) return OPMM_OK;
     (void)hipSetDevice(sv->device);
     if (sv->stream) (void)hipStreamSynchronize(sv->stream);
+    for (PolishBatch& b : sv->pb)
+        if (b.stream) (void)hipStreamSynchronize(b.stream);
     for (void* p : {(void*)sv->d_pos, (void*)sv->d_box, (void*)sv->d_status, (void*)sv->d_keys, (void*)sv->d_proj,
                     (void*)sv->d_qorth, (void*)sv->d_list, (void*)sv->d_seed, (void*)sv->d_out, (void*)sv->d_st,
                     (void*)sv->d_adm_trace})
         if (p) (void)hipFree(p);
     for (void* p : {(void*)sv->h_list, (void*)sv->h_out, (void*)sv->h_st, (void*)sv->h_adm_trace})
         if (p) (void)hipHostFree(p);
+    for (PolishBatch& b : sv->pb) {
+        for (void* p : {(void*)b.d_list, (void*)b.d_out, (void*)b.d_st})
+            if (p) (void)hipFree(p);
+        for (void* p : {(void*)b.h_out, (void*)b.h_st})
+            if (p) (void)hipHostFree(p);
+        if (b.done) (void)hipEventDestroy(b.done);
+        if (b.stream) (void)hipStreamDestroy(b.stream);
+    }
+    if (sv->ev_fin) (void)hipEventDestroy(sv->ev_fin);
     if (sv->stream) (void)hipStreamDestroy(sv->stream);
     delete sv;
     return OPMM_OK;
@@ -314,6 +360,68 @@ int opmm_server_submit_many(opmm_server* sv, const float* host_pos, int64_t pos_
         if (ids_out) ids_out[i] = id;
     }
     return OPMM_OK;
+}
+
+// Results of the finished slots fin (host arrays: opc [nf][18] at hout, rmse at hout + 18 x slots,
+// mae after it, status at hst): a seeded result above the fallback threshold restarts its slot
+// with the plain search, every other one completes its request.  Returns the number completed.
+static int take_results(opmm_server* sv, const std::vector<int>& fin, const float* hout, const int32_t* hst)
+{
+    const double t = now_s();
+    int ndone = 0;
+    for (size_t i = 0; i < fin.size(); ++i) {
+        const int k = fin[i];
+        Slot& sl = sv->slot[k];
+        const float r = hout[(size_t)P * sv->slots + i];
+        const float m = hout[(size_t)P * sv->slots + sv->slots + i];
+        int32_t status = hst[i];
+        const float* o = hout + (size_t)P * i;
+        if (sv->sg && sl.phase == PH_FIRST && !(r <= sv->prm.fallback_rmse) && !(status & OPMM_ST_NONFINITE_INPUT)) {
+            // the plain search judges: restart this slot from the nominal centre
+            sl.has_prev = true;
+            std::memcpy(sl.prev_opc, o, sizeof(float) * P);
+            sl.prev_rmse = r;
+            sl.prev_mae = m;
+            sl.prev_status = status;
+            sl.phase = PH_FALLBACK;
+            sl.round = 0;
+            sl.rounds = sv->prm.plain.n_rounds;
+            sl.n_cand = sv->prm.plain.n_cand;
+            sv->reinit.push_back(k);
+            sv->n_fallback++;
+            continue;
+        }
+        Done d;
+        d.id = sl.id;
+        if (sl.has_prev && sl.prev_rmse <= r) {
+            std::memcpy(d.opc, sl.prev_opc, sizeof(float) * P);
+            d.rmse = sl.prev_rmse;
+            d.mae = sl.prev_mae;
+        } else {
+            std::memcpy(d.opc, o, sizeof(float) * P);
+            d.rmse = r;
+            d.mae = m;
+        }
+        if (sl.has_prev) status |= OPMM_ST_FALLBACK | sl.prev_status;
+        d.status = status;
+        d.t_arrival = sl.t_arrival;
+        d.t_done = t;
+        sv->done.push_back(d);
+        sl.busy = false;
+        sv->free_slots.push_back(k);
+        sv->n_completed++;
+        ndone++;
+    }
+    return ndone;
+}
+
+// The oldest polished batch, once its event has completed.
+static int take_polished(opmm_server* sv)
+{
+    PolishBatch& b = sv->pb[sv->pb_head];
+    sv->pb_head = (sv->pb_head + 1) % kPolishBatches;
+    sv->pb_count--;
+    return take_results(sv, b.fin, b.h_out, b.h_st);
 }
 
 int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
@@ -416,79 +524,67 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
     std::vector<int> fin;
     for (int k : act)
         if (sv->slot[k].round >= sv->slot[k].rounds) fin.push_back(k);
+    int ndone = 0;
     if (!fin.empty()) {
         const int nf = (int)fin.size();
         for (int i = 0; i < nf; ++i) h_fin[i] = slot_record(sv, fin[i]);
         SV_HIP(hipMemcpyAsync(sv->d_list, h_fin, sizeof(SacDev) * nf, hipMemcpyHostToDevice, st));
-        float* opc = sv->d_out;
-        float* rm = sv->d_out + (size_t)P * sv->slots;
-        float* ma = rm + sv->slots;
-        SV_HIP(opmm_rt::launch_report(sv->d_list, nf, sv->d_pos, dt, sv->ss, opc, rm, ma, sv->d_st, st));
         if (sv->prm.polish_iter > 0) {
+            // with every batch buffer in flight, the oldest batch is taken first
+            if (sv->pb_count == kPolishBatches) {
+                SV_HIP(hipEventSynchronize(sv->pb[sv->pb_head].done));
+                ndone += take_polished(sv);
+            }
+            PolishBatch& b = sv->pb[(sv->pb_head + sv->pb_count) % kPolishBatches];
+            float* opc = b.d_out;
+            float* rm = b.d_out + (size_t)P * sv->slots;
+            float* ma = rm + sv->slots;
+            SV_HIP(opmm_rt::launch_report(sv->d_list, nf, sv->d_pos, dt, sv->ss, opc, rm, ma, b.d_st, st));
+            SV_HIP(hipMemcpyAsync(b.d_list, sv->d_list, sizeof(SacDev) * nf, hipMemcpyDeviceToDevice, st));
+            SV_HIP(hipEventRecord(sv->ev_fin, st));
+            hipStream_t ps = b.stream;
+            SV_HIP(hipStreamWaitEvent(ps, sv->ev_fin, 0));
             opmm_polish_params pp;
             opmm_polish_params_default(&pp);
             pp.max_iter = sv->prm.polish_iter;
             pp.box_frac = sv->prm.plain.box_frac;
             pp.dt_ms = dt;
-            SV_HIP(opmm_rt::launch_polish(sv->ctx, sv->d_list, nf, sv->max_T, sv->d_pos, sv->ss.status,
-                                          sv->prm.plain.model, pp, opc, rm, ma, st));
+            SV_HIP(opmm_rt::launch_polish(sv->ctx, b.d_list, nf, sv->max_T, sv->d_pos, sv->ss.status,
+                                          sv->prm.plain.model, pp, opc, rm, ma, ps));
+            SV_HIP(hipMemcpyAsync(b.h_out, opc, sizeof(float) * P * nf, hipMemcpyDeviceToHost, ps));
+            SV_HIP(hipMemcpyAsync(b.h_out + (size_t)P * sv->slots, rm, sizeof(float) * nf, hipMemcpyDeviceToHost, ps));
+            SV_HIP(hipMemcpyAsync(b.h_out + (size_t)P * sv->slots + sv->slots, ma, sizeof(float) * nf,
+                                  hipMemcpyDeviceToHost, ps));
+            SV_HIP(hipMemcpyAsync(b.h_st, b.d_st, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, ps));
+            SV_HIP(hipEventRecord(b.done, ps));
+            b.fin = fin;
+            sv->pb_count++;
+            queued = true;
+        } else {
+            float* opc = sv->d_out;
+            float* rm = sv->d_out + (size_t)P * sv->slots;
+            float* ma = rm + sv->slots;
+            SV_HIP(opmm_rt::launch_report(sv->d_list, nf, sv->d_pos, dt, sv->ss, opc, rm, ma, sv->d_st, st));
+            SV_HIP(hipMemcpyAsync(sv->h_out, opc, sizeof(float) * P * nf, hipMemcpyDeviceToHost, st));
+            SV_HIP(hipMemcpyAsync(sv->h_out + (size_t)P * sv->slots, rm, sizeof(float) * nf, hipMemcpyDeviceToHost,
+                                  st));
+            SV_HIP(hipMemcpyAsync(sv->h_out + (size_t)P * sv->slots + sv->slots, ma, sizeof(float) * nf,
+                                  hipMemcpyDeviceToHost, st));
+            SV_HIP(hipMemcpyAsync(sv->h_st, sv->d_st, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, st));
+            SV_HIP(hipStreamSynchronize(st));
+            queued = false;
+            ndone += take_results(sv, fin, sv->h_out, sv->h_st);
         }
-        SV_HIP(hipMemcpyAsync(sv->h_out, opc, sizeof(float) * P * nf, hipMemcpyDeviceToHost, st));
-        SV_HIP(hipMemcpyAsync(sv->h_out + (size_t)P * sv->slots, rm, sizeof(float) * nf, hipMemcpyDeviceToHost, st));
-        SV_HIP(hipMemcpyAsync(sv->h_out + (size_t)P * sv->slots + sv->slots, ma, sizeof(float) * nf,
-                              hipMemcpyDeviceToHost, st));
-        SV_HIP(hipMemcpyAsync(sv->h_st, sv->d_st, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, st));
-        SV_HIP(hipStreamSynchronize(st));
-        const double t = now_s();
-        int ndone = 0;
-        for (int i = 0; i < nf; ++i) {
-            const int k = fin[i];
-            Slot& sl = sv->slot[k];
-            const float r = sv->h_out[(size_t)P * sv->slots + i];
-            const float m = sv->h_out[(size_t)P * sv->slots + sv->slots + i];
-            int32_t status = sv->h_st[i];
-            const float* o = sv->h_out + (size_t)P * i;
-            if (sv->sg && sl.phase == PH_FIRST && !(r <= sv->prm.fallback_rmse) &&
-                !(status & OPMM_ST_NONFINITE_INPUT)) {
-                // the plain search judges: restart this slot from the nominal centre
-                sl.has_prev = true;
-                std::memcpy(sl.prev_opc, o, sizeof(float) * P);
-                sl.prev_rmse = r;
-                sl.prev_mae = m;
-                sl.prev_status = status;
-                sl.phase = PH_FALLBACK;
-                sl.round = 0;
-                sl.rounds = sv->prm.plain.n_rounds;
-                sl.n_cand = sv->prm.plain.n_cand;
-                sv->reinit.push_back(k);
-                sv->n_fallback++;
-                continue;
-            }
-            Done d;
-            d.id = sl.id;
-            if (sl.has_prev && sl.prev_rmse <= r) {
-                std::memcpy(d.opc, sl.prev_opc, sizeof(float) * P);
-                d.rmse = sl.prev_rmse;
-                d.mae = sl.prev_mae;
-            } else {
-                std::memcpy(d.opc, o, sizeof(float) * P);
-                d.rmse = r;
-                d.mae = m;
-            }
-            if (sl.has_prev) status |= OPMM_ST_FALLBACK | sl.prev_status;
-            d.status = status;
-            d.t_arrival = sl.t_arrival;
-            d.t_done = t;
-            sv->done.push_back(d);
-            sl.busy = false;
-            sv->free_slots.push_back(k);
-            sv->n_completed++;
-            ndone++;
-        }
-        if (n_done_out) *n_done_out = ndone;
-    } else if (queued) {
-        SV_HIP(hipStreamSynchronize(st));
     }
+    if (queued) SV_HIP(hipStreamSynchronize(st));
+    // 5. polish batches that finished meanwhile, oldest first
+    while (sv->pb_count > 0) {
+        const hipError_t e = hipEventQuery(sv->pb[sv->pb_head].done);
+        if (e == hipErrorNotReady) break;
+        if (e != hipSuccess) return opmm_rt::hip_fail(sv->ctx, e, "polish batch");
+        ndone += take_polished(sv);
+    }
+    if (n_done_out) *n_done_out = ndone;
     sv->n_steps++;
     return OPMM_OK;
 }

@@ -125,6 +125,43 @@ def test_learned_server_results_equal_learned_fit_alone(ctx, opmm):
     sg.close()
 
 
+
+def test_learned_polished_server_with_fallback(ctx, opmm):
+    """Learned seed, polish and forced fallback together (the polish runs on the server's second
+    stream and its results are taken in a later step): each result equals the seeded refine and
+    the plain search, each polished alone, the lower-RMSE one kept."""
+    sg = opmm.Surrogate(ctx, init_seed=9)
+    sg.train(data_seed=5, batch=2048, n_steps=150)
+    b, traces = make_batch(8, "full", seed=synth.BASE_SEED + 43)
+    recs = records(b, opmm)
+    recs["pos_offset"] = 0
+    prm = opmm.serve_params(max_slots=4, fallback_rmse=0.0, polish_iter=3)
+    prm.plain.n_cand, prm.plain.n_rounds = 2048, 3
+    prm.seeded.n_cand, prm.seeded.n_rounds = 1024, 3
+    sv = opmm.Server(ctx, prm, sg)
+    res = stream_through(sv, b, traces, recs, waves=(3, 2))
+    assert len(res["id"]) == b["S"]
+    pp = opmm.polish_params(max_iter=3)
+    for s in range(b["S"]):
+        pos = torch.from_numpy(traces[s].reshape(-1)).cuda()
+        seed = torch.zeros(1, 18, device="cuda")
+        sg.predict(pos, recs[s:s + 1], seed, dt_ms=prm.seeded.dt_ms, box_frac=prm.seeded.box_frac)
+        o1 = torch.zeros(1, 18, device="cuda"); r1 = torch.zeros(1, device="cuda")
+        ctx.fit(pos, recs[s:s + 1], prm.seeded, o1, r1, seed_opc=seed)
+        ctx.polish(pos, recs[s:s + 1], pp, o1, r1)
+        o2 = torch.zeros(1, 18, device="cuda"); r2 = torch.zeros(1, device="cuda")
+        ctx.fit(pos, recs[s:s + 1], prm.plain, o2, r2)
+        ctx.polish(pos, recs[s:s + 1], pp, o2, r2)
+        torch.cuda.synchronize()
+        r1v, r2v = r1.cpu().numpy()[0], r2.cpu().numpy()[0]
+        want = (o1 if r1v <= r2v else o2).cpu().numpy()[0]
+        assert np.array_equal(want.view(np.uint32), res["opc"][s].view(np.uint32)), s
+        assert res["rmse"][s] == min(r1v, r2v), s
+        assert res["status"][s] & opmm.ST_FALLBACK, s
+    assert sv.stats()["fallbacks"] == b["S"]
+    sv.close()
+    sg.close()
+
 def test_admission_is_bounded_by_the_hbm_budget(ctx, opmm):
     prm = opmm.serve_params(max_slots=1000, hbm_budget_bytes=3 * 2800)
     prm.plain.n_cand, prm.plain.n_rounds = 512, 2
