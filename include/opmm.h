@@ -283,8 +283,9 @@ int opmm_surrogate_load(opmm_surrogate* sg, const char* path);
  * result is kept, status gets OPMM_ST_FALLBACK); without, they run `plain`.
  * With polish_iter > 0, every finished search is polished (opmm_polish with
  * that many iterations, the RMSE objective, the searches' box and dt) before
- * the fallback rule and the result are taken.
- * The server owns its stream; calls on one server must not overlap.
+ * the fallback rule and the result are taken; the polish runs on streams of
+ * the server's own and its results are taken by a later step.
+ * The server owns its streams; calls on one server must not overlap.
  * ------------------------------------------------------------------------ */
 typedef struct opmm_server opmm_server;
 typedef struct {
@@ -317,8 +318,8 @@ int opmm_server_submit(opmm_server* sv, const float* host_trace, const opmm_sacc
 int opmm_server_submit_many(opmm_server* sv, const float* host_pos, int64_t pos_len, const opmm_saccade* sacs,
                             int32_t n, const double* t_arrival, int64_t* ids_out);
 /* Admit, run one round over all occupied slots, harvest finished requests
- * (synchronises the server stream).  *n_done_out (nullable) = requests
- * completed by this step. */
+ * (synchronises the server stream; polish batches still running are taken by
+ * a later step).  *n_done_out (nullable) = requests completed by this step. */
 int opmm_server_step(opmm_server* sv, int32_t* n_done_out);
 /* Pop up to max completed results (host arrays, each nullable except n_out):
  * ids[n], opc[n][18], rmse[n], mae[n], status[n], t_arrival[n], t_done[n]. */
