@@ -72,16 +72,17 @@ def test_plain_server_results_equal_fit_alone(ctx, opmm):
 
 
 def test_polished_server_results_equal_fit_and_polish_alone(ctx, opmm):
-    """With polish_iter > 0 every finished search is polished in the server's harvest launch: the
-    result equals opmm_fit followed by opmm_polish on that saccade alone."""
-    b, traces = make_batch(9, "full", seed=synth.BASE_SEED + 35)
+    """With polish_iter > 0 every finished search is polished on the server's polish streams (up to
+    three batches in flight; 24 requests through 4 slots keep them full): the result equals
+    opmm_fit followed by opmm_polish on that saccade alone."""
+    b, traces = make_batch(24, "full", seed=synth.BASE_SEED + 35)
     recs = records(b, opmm)
     recs["pos_offset"] = 0
     prm = opmm.serve_params(max_slots=4, polish_iter=3)
     prm.plain.n_cand = 2048
     prm.plain.n_rounds = 3
     sv = opmm.Server(ctx, prm)
-    res = stream_through(sv, b, traces, recs, waves=(3, 2))
+    res = stream_through(sv, b, traces, recs, waves=(3, 2, 5, 4))
     assert len(res["id"]) == b["S"]
     fp = opmm.fit_params(n_cand=2048, n_rounds=3)
     pp = opmm.polish_params(max_iter=3)
