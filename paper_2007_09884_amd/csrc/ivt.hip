@@ -172,61 +172,72 @@ int opmm_ivt_extract(opmm_ctx* ctx, const float* gaze, int64_t N, float dt_ms, f
         ok(hipStreamSynchronize(st), "sync");
     }
     if (rc == OPMM_OK && n_runs > 0) {
-        int32_t *keep = nullptr, *slot = nullptr, *off = nullptr, *Ts = nullptr;
-        float *amp = nullptr, *dir = nullptr;
-        ok(hipMallocAsync((void**)&starts, sizeof(int64_t) * n_runs, st), "alloc");
-        for (void** p : {(void**)&keep, (void**)&slot, (void**)&off, (void**)&Ts, (void**)&amp, (void**)&dir})
-            ok(hipMallocAsync(p, sizeof(int32_t) * n_runs, st), "alloc");
+        // one allocation for the per-run arrays: starts (int64), then seven 4-byte arrays: keep, T,
+        // slot, offset, keep after truncation (int32), amplitude, direction (float).  keep and T are
+        // adjacent (one copy down), and so are slot, offset and the truncated keep (one copy up).
+        const size_t R = (size_t)n_runs;
+        char* runbuf = nullptr;
+        ok(hipMallocAsync((void**)&runbuf, R * (sizeof(int64_t) + 7 * sizeof(int32_t)), st), "alloc");
+        if (rc != OPMM_OK) runbuf = nullptr;
+        starts = (int64_t*)runbuf;
         if (rc == OPMM_OK) {
+            int32_t* keep = (int32_t*)(runbuf + R * sizeof(int64_t));
+            int32_t* Ts = keep + R;
+            int32_t* slot = Ts + R;
+            int32_t* off = slot + R;
+            int32_t* keep2 = off + R;  // keep after truncation
+            float* amp = (float*)(keep2 + R);
+            float* dir = amp + R;
             hipLaunchKernelGGL(ivt_scatter_kernel, dim3(nb), dim3(IVT_TPB), 0, st, gaze, N, thr2, blk, starts);
             hipLaunchKernelGGL(ivt_segments_kernel, dim3(blocks_of(n_runs, 128)), dim3(128), 0, st, gaze, N, thr2,
                                n_runs, starts, dt_ms, min_dur_ms, min_amp_deg, max_T, keep, Ts, amp, dir);
-
-        }
-        std::vector<int32_t> hk(n_runs), hT(n_runs);
-        ok(hipMemcpyAsync(hk.data(), keep, sizeof(int32_t) * n_runs, hipMemcpyDeviceToHost, st), "copy");
-        ok(hipMemcpyAsync(hT.data(), Ts, sizeof(int32_t) * n_runs, hipMemcpyDeviceToHost, st), "copy");
-        ok(hipStreamSynchronize(st), "sync");
-        if (rc == OPMM_OK) {
-            // output slot and trace offset of the kept runs, in stream order; output stops at the
-            // first kept run past max_out records or pos_cap floats of trace (a prefix of the stream)
-            std::vector<int32_t> ho(n_runs, 0), hs(n_runs, 0);
-            int64_t acc = 0;
-            int32_t emitted = 0;
-            bool full = false;
-            for (int i = 0; i < n_runs; ++i) {
-                if (!hk[i]) continue;
-                full = full || emitted >= max_out || 2 * (acc + hT[i]) > pos_cap;
-                if (full) { hk[i] = 0; continue; }
-                ho[i] = (int32_t)acc;
-                hs[i] = emitted;
-                acc += hT[i];
-                ++emitted;
-            }
-            opmm_saccade* d_recs = nullptr;
-            int64_t* d_src = nullptr;
-            ok(hipMallocAsync((void**)&d_recs, sizeof(opmm_saccade) * std::max(emitted, 1), st), "alloc");
-            ok(hipMallocAsync((void**)&d_src, sizeof(int64_t) * std::max(emitted, 1), st), "alloc");
-            ok(hipMemcpyAsync(off, ho.data(), sizeof(int32_t) * n_runs, hipMemcpyHostToDevice, st), "copy");
-            ok(hipMemcpyAsync(slot, hs.data(), sizeof(int32_t) * n_runs, hipMemcpyHostToDevice, st), "copy");
-            ok(hipMemcpyAsync(keep, hk.data(), sizeof(int32_t) * n_runs, hipMemcpyHostToDevice, st), "copy");
-            if (rc == OPMM_OK)
-                hipLaunchKernelGGL(ivt_emit_kernel, dim3(blocks_of(n_runs, 128)), dim3(128), 0, st, gaze, n_runs,
-                                   starts, keep, slot, off, Ts, amp, dir, dt_ms, seed_base, max_out, d_recs, pos_out,
-                                   d_src);
-            if (emitted > 0) {
-                ok(hipMemcpyAsync(sacs_out, d_recs, sizeof(opmm_saccade) * emitted, hipMemcpyDeviceToHost, st), "copy");
-                if (src_start_out)
-                    ok(hipMemcpyAsync(src_start_out, d_src, sizeof(int64_t) * emitted, hipMemcpyDeviceToHost, st),
-                       "copy");
-            }
+            std::vector<int32_t> hkT(2 * R);  // keep, then T
+            ok(hipMemcpyAsync(hkT.data(), keep, sizeof(int32_t) * 2 * R, hipMemcpyDeviceToHost, st), "copy");
             ok(hipStreamSynchronize(st), "sync");
-            if (d_recs) (void)hipFreeAsync(d_recs, st);
-            if (d_src) (void)hipFreeAsync(d_src, st);
-            *n_out = emitted;
+            if (rc == OPMM_OK) {
+                // output slot and trace offset of the kept runs, in stream order; output stops at the
+                // first kept run past max_out records or pos_cap floats of trace (a prefix of the stream)
+                const int32_t* hk = hkT.data();
+                const int32_t* hT = hk + R;
+                std::vector<int32_t> up(3 * R, 0);  // slot, offset, keep after truncation
+                int32_t* hs = up.data();
+                int32_t* ho = hs + R;
+                int32_t* hk2 = ho + R;
+                int64_t acc = 0;
+                int32_t emitted = 0;
+                bool full = false;
+                for (size_t i = 0; i < R; ++i) {
+                    if (!hk[i]) continue;
+                    full = full || emitted >= max_out || 2 * (acc + hT[i]) > pos_cap;
+                    if (full) continue;
+                    hk2[i] = 1;
+                    ho[i] = (int32_t)acc;
+                    hs[i] = emitted;
+                    acc += hT[i];
+                    ++emitted;
+                }
+                opmm_saccade* d_recs = nullptr;
+                int64_t* d_src = nullptr;
+                ok(hipMallocAsync((void**)&d_recs, sizeof(opmm_saccade) * std::max(emitted, 1), st), "alloc");
+                ok(hipMallocAsync((void**)&d_src, sizeof(int64_t) * std::max(emitted, 1), st), "alloc");
+                ok(hipMemcpyAsync(slot, up.data(), sizeof(int32_t) * 3 * R, hipMemcpyHostToDevice, st), "copy");
+                if (rc == OPMM_OK)
+                    hipLaunchKernelGGL(ivt_emit_kernel, dim3(blocks_of(n_runs, 128)), dim3(128), 0, st, gaze, n_runs,
+                                       starts, keep2, slot, off, Ts, amp, dir, dt_ms, seed_base, max_out, d_recs,
+                                       pos_out, d_src);
+                if (emitted > 0) {
+                    ok(hipMemcpyAsync(sacs_out, d_recs, sizeof(opmm_saccade) * emitted, hipMemcpyDeviceToHost, st),
+                       "copy");
+                    if (src_start_out)
+                        ok(hipMemcpyAsync(src_start_out, d_src, sizeof(int64_t) * emitted, hipMemcpyDeviceToHost, st),
+                           "copy");
+                }
+                ok(hipStreamSynchronize(st), "sync");
+                if (d_recs) (void)hipFreeAsync(d_recs, st);
+                if (d_src) (void)hipFreeAsync(d_src, st);
+                *n_out = emitted;
+            }
         }
-        for (void* p : {(void*)keep, (void*)slot, (void*)off, (void*)Ts, (void*)amp, (void*)dir})
-            if (p) (void)hipFreeAsync(p, st);
     }
     if (starts) (void)hipFreeAsync(starts, st);
     if (blk) (void)hipFreeAsync(blk, st);
