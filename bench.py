@@ -58,7 +58,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the batched-uneven (persistent launch) leg")
     ap.add_argument("--no-nm", action="store_true")
-    ap.add_argument("--no-ivt", action="store_true", help="skip the I-VT leg (gaze stream -> saccades -> fit)")
+    ap.add_argument("--no-ivt", action="store_true", help="skip the I-VT leg (gaze stream -> saccade records and traces)")
     ap.add_argument("--ivt-saccades", type=int, default=2000)
     ap.add_argument("--no-model9", action="store_true", help="skip the 9-parameter model leg")
     ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-configuration latency leg")
