@@ -362,18 +362,19 @@ int opmm_server_submit_many(opmm_server* sv, const float* host_pos, int64_t pos_
     return OPMM_OK;
 }
 
-// Results of the finished slots fin (host arrays: opc [nf][18] at hout, rmse at hout + 18 x slots,
-// mae after it, status at hst): a seeded result above the fallback threshold restarts its slot
-// with the plain search, every other one completes its request.  Returns the number completed.
+// Results of the nf finished slots fin (host arrays: opc [nf][18], then rmse [nf] and mae [nf] at
+// hout, status at hst): a seeded result above the fallback threshold restarts its slot with the
+// plain search, every other one completes its request.  Returns the number completed.
 static int take_results(opmm_server* sv, const std::vector<int>& fin, const float* hout, const int32_t* hst)
 {
     const double t = now_s();
+    const size_t nf = fin.size();
     int ndone = 0;
-    for (size_t i = 0; i < fin.size(); ++i) {
+    for (size_t i = 0; i < nf; ++i) {
         const int k = fin[i];
         Slot& sl = sv->slot[k];
-        const float r = hout[(size_t)P * sv->slots + i];
-        const float m = hout[(size_t)P * sv->slots + sv->slots + i];
+        const float r = hout[P * nf + i];
+        const float m = hout[(P + 1) * nf + i];
         int32_t status = hst[i];
         const float* o = hout + (size_t)P * i;
         if (sv->sg && sl.phase == PH_FIRST && !(r <= sv->prm.fallback_rmse) && !(status & OPMM_ST_NONFINITE_INPUT)) {
@@ -536,9 +537,10 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
                 ndone += take_polished(sv);
             }
             PolishBatch& b = sv->pb[(sv->pb_head + sv->pb_count) % kPolishBatches];
+            // outputs packed for nf: opc [nf][18], rmse [nf], mae [nf] (one copy down)
             float* opc = b.d_out;
-            float* rm = b.d_out + (size_t)P * sv->slots;
-            float* ma = rm + sv->slots;
+            float* rm = b.d_out + (size_t)P * nf;
+            float* ma = rm + nf;
             SV_HIP(opmm_rt::launch_report(sv->d_list, nf, sv->d_pos, dt, sv->ss, opc, rm, ma, b.d_st, st));
             SV_HIP(hipMemcpyAsync(b.d_list, sv->d_list, sizeof(SacDev) * nf, hipMemcpyDeviceToDevice, st));
             SV_HIP(hipEventRecord(sv->ev_fin, st));
@@ -551,10 +553,7 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
             pp.dt_ms = dt;
             SV_HIP(opmm_rt::launch_polish(sv->ctx, b.d_list, nf, sv->max_T, sv->d_pos, sv->ss.status,
                                           sv->prm.plain.model, pp, opc, rm, ma, ps));
-            SV_HIP(hipMemcpyAsync(b.h_out, opc, sizeof(float) * P * nf, hipMemcpyDeviceToHost, ps));
-            SV_HIP(hipMemcpyAsync(b.h_out + (size_t)P * sv->slots, rm, sizeof(float) * nf, hipMemcpyDeviceToHost, ps));
-            SV_HIP(hipMemcpyAsync(b.h_out + (size_t)P * sv->slots + sv->slots, ma, sizeof(float) * nf,
-                                  hipMemcpyDeviceToHost, ps));
+            SV_HIP(hipMemcpyAsync(b.h_out, opc, sizeof(float) * (P + 2) * nf, hipMemcpyDeviceToHost, ps));
             SV_HIP(hipMemcpyAsync(b.h_st, b.d_st, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, ps));
             SV_HIP(hipEventRecord(b.done, ps));
             b.fin = fin;
@@ -562,14 +561,10 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
             queued = true;
         } else {
             float* opc = sv->d_out;
-            float* rm = sv->d_out + (size_t)P * sv->slots;
-            float* ma = rm + sv->slots;
+            float* rm = sv->d_out + (size_t)P * nf;
+            float* ma = rm + nf;
             SV_HIP(opmm_rt::launch_report(sv->d_list, nf, sv->d_pos, dt, sv->ss, opc, rm, ma, sv->d_st, st));
-            SV_HIP(hipMemcpyAsync(sv->h_out, opc, sizeof(float) * P * nf, hipMemcpyDeviceToHost, st));
-            SV_HIP(hipMemcpyAsync(sv->h_out + (size_t)P * sv->slots, rm, sizeof(float) * nf, hipMemcpyDeviceToHost,
-                                  st));
-            SV_HIP(hipMemcpyAsync(sv->h_out + (size_t)P * sv->slots + sv->slots, ma, sizeof(float) * nf,
-                                  hipMemcpyDeviceToHost, st));
+            SV_HIP(hipMemcpyAsync(sv->h_out, opc, sizeof(float) * (P + 2) * nf, hipMemcpyDeviceToHost, st));
             SV_HIP(hipMemcpyAsync(sv->h_st, sv->d_st, sizeof(int32_t) * nf, hipMemcpyDeviceToHost, st));
             SV_HIP(hipStreamSynchronize(st));
             queued = false;
