@@ -435,3 +435,71 @@ def test_nelder_mead_steps_follow_lagarias():
         best = V[int(np.argsort(F, kind="stable")[0])]
         assert np.array_equal(r["opc"], np.float32(np.clip(best, 0.75, 1.25) * oracle.nominal(dur))), seed
     assert seen >= {0, 1, 2, 3, 4}, seen
+
+
+# --- regression anchor: numbers computed independently for the nominal plant ---------------------
+
+def _anchor_rows():
+    rows = {}
+    for line in open(os.path.join(GOLD, "anchor_nominal_10deg.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, *v = line.split()
+            rows.setdefault(k, []).append([float(x) for x in v])
+    return rows
+
+
+def anchor_trajectory_errors(simulate):
+    """Largest deviations of a simulator from the anchor: (theta error in deg, peak-velocity error in
+    deg/s).  `simulate(p, amp, T, dt_ms)` returns theta at t_k = k dt_ms."""
+    rows = _anchor_rows()
+    p = oracle.nominal(43.0)
+    th = simulate(p, 10.0, 80, 1.0)
+    err = max(abs(th[int(t)] - v) for t, v in rows["theta"])
+    fine = simulate(p, 10.0, 800, 0.1)
+    vmax = float(np.max(np.diff(fine))) / 1e-4
+    return err, abs(vmax - rows["peak_velocity"][0][0])
+
+
+def test_anchor_nominal_trajectory():
+    """Nominal OPC, A = 10 deg, D = 43 ms: theta at 10..79 ms to the anchor's three decimals and the
+    peak velocity to ~1 deg/s (independent numbers for the same model reading)."""
+    err, verr = anchor_trajectory_errors(lambda p, a, T, dt: oracle.simulate(p, a, T, dt_ms=dt))
+    assert err <= 5e-4 + 1e-12, err
+    assert verr < 1.0, verr
+
+
+def anchor_eigen_errors(rhs):
+    """Worst relative deviation of the eigenvalues of each piece's system matrix from the anchor.
+    `rhs(p, x, n_ag, n_ant, tau_ag_s, tau_ant_s)` is the plant's right-hand side (1/s units)."""
+    rows = _anchor_rows()
+
+    def eig(p, n_ag, n_ant, ta, tn):
+        b = rhs(p, np.zeros(6), n_ag, n_ant, ta, tn)
+        A = np.zeros((6, 6))
+        for j in range(6):
+            e = np.zeros(6); e[j] = 1.0
+            A[:, j] = rhs(p, e, n_ag, n_ant, ta, tn) - b
+        ev = np.linalg.eigvals(A)
+        return np.sort(ev.real), float(np.abs(ev.imag).max())
+
+    worst = 0.0
+    p = oracle.nominal(43.0)
+    lv = oracle.control_levels(p, 10.0)
+    for piece, (n_ag, n_ant, ta, tn) in (("act_pulse", (lv[2], lv[3], p[10] * 1e-3, p[11] * 1e-3)),
+                                         ("act_post", (lv[4], lv[5], p[12] * 1e-3, p[13] * 1e-3))):
+        ev, im = eig(p, n_ag, n_ant, ta, tn)
+        worst = max(worst, im)
+        for want in rows[piece][0]:      # -1/tau of each active state is an eigenvalue
+            worst = max(worst, np.min(np.abs(ev - want)) / abs(want))
+    q = p.copy(); q[7] = 0.0             # K_P = N_C_ANT = 0.5 g/deg
+    ev, im = eig(q, lv[2], lv[3], p[10] * 1e-3, p[11] * 1e-3)
+    want = np.sort(np.array(rows["mech_kp0.5"][0] + rows["act_pulse"][0]))
+    worst = max(worst, im, float(np.max(np.abs(ev - want) / np.abs(want))))
+    return worst
+
+
+def test_anchor_eigenvalues():
+    """Eigenvalues of the pulse and post system matrices (probed from the plant's right-hand side)
+    against the anchor to 0.1 %: the activation modes -1/tau in each piece, and the four mechanical
+    modes (shared by both pieces) at the anchor's passive elasticity."""
+    assert anchor_eigen_errors(oracle.rhs) < 1e-3
