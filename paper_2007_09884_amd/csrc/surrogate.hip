@@ -447,18 +447,23 @@ __global__ void mse_grad_kernel(int B, const float* __restrict__ out, const floa
     if (threadIdx.x == 0) atomicAdd(loss, red[0] / (float)n);
 }
 
+// Adam (Kingma & Ba 2015, Algorithm 1) on the FP32 master weights, with a BF16
+// copy for the GEMMs.  b1, b2 and their complements om1 = 1 - b1, om2 = 1 - b2
+// are each the FP32 value nearest the exact constant, and c1 = 1 / (1 - b1^t),
+// c2 = 1 / (1 - b2^t) are formed on the host in FP64: 1 - b2^t taken in FP32
+// loses about five digits to cancellation in the first steps.
 __global__ void adam_kernel(int64_t n, float* __restrict__ w, uint16_t* __restrict__ wb, const float* __restrict__ g,
-                            float* __restrict__ m1, float* __restrict__ m2, float lr, float b1, float b2, float eps,
-                            float c1, float c2, float wd)
+                            float* __restrict__ m1, float* __restrict__ m2, float lr, float b1, float om1, float b2,
+                            float om2, float eps, float c1, float c2)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float gi = g[i];
-    float a = b1 * m1[i] + (1.0f - b1) * gi;
-    float v = b2 * m2[i] + (1.0f - b2) * gi * gi;
+    float a = b1 * m1[i] + om1 * gi;
+    float v = b2 * m2[i] + om2 * (gi * gi);
     m1[i] = a;
     m2[i] = v;
-    float upd = (a * c1) / (sqrtf(v * c2) + eps) + wd * w[i];
+    float upd = (a * c1) / (sqrtf(v * c2) + eps);
     float nw = w[i] - lr * upd;
     w[i] = nw;
     wb[i] = f2bf(nw);
@@ -605,12 +610,12 @@ int sg_backward(opmm_surrogate* sg, int B, const uint16_t* x0, const float* tgt,
 
 int sg_adam(opmm_surrogate* sg, float lr, hipStream_t st)
 {
-    const float b1 = 0.9f, b2 = 0.999f;
+    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
     sg->step += 1;
-    const float c1 = 1.0f / (1.0f - powf(b1, (float)sg->step));
-    const float c2 = 1.0f / (1.0f - powf(b2, (float)sg->step));
+    const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)sg->step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)sg->step)));
     hipLaunchKernelGGL(adam_kernel, dim3(blocks(NPARAM, 256)), dim3(256), 0, st, NPARAM, sg->w, sg->wb, sg->g, sg->m1,
-                       sg->m2, lr, b1, b2, 1e-8f, c1, c2, 0.0f);
+                       sg->m2, lr, (float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), (float)eps, c1, c2);
     return hipGetLastError() == hipSuccess ? OPMM_OK : OPMM_EDEVICE;
 }
 

@@ -265,3 +265,71 @@ def test_training_loop_equals_step_by_step(ctx, opmm):
     assert np.array_equal(sa.params(0).view(np.uint32), sb.params(0).view(np.uint32))
     sa.close()
     sb.close()
+
+
+def test_adam_steps_match_reference(ctx, opmm):
+    """opmm_surrogate_adam_step against Adam written out in FP64 (oracle/mlp_ref.py, Kingma & Ba 2015,
+    Algorithm 1), fed the GPU's own gradients (pinned separately above): after each of 10 steps with a
+    cosine learning rate, the FP32 master weights and both moments are within the reference's running
+    bound for an FP32 evaluation (a few roundings per step, accumulated).  The biases start at zero,
+    where the update is not hidden under the rounding of w, so a bias correction or eps placement off
+    by 1e-5 relative fails.  The BF16 copy the GEMMs read is the rounding of the new master weights."""
+    B = 256
+    w, x, t = random_problem(B, 4)
+    off = 0
+    for l in range(4):
+        off += W[l] * W[l + 1]
+        w[off:off + W[l + 1]] = 0.0
+        off += W[l + 1]
+    sg = opmm.Surrogate(ctx)
+    sg.set_params(w)
+    ref = mlp_ref.Adam(w.astype(np.float64))
+    xb = torch.from_numpy(mlp_ref.bf16_bits(x).view(np.int16)).cuda()
+    tt = torch.from_numpy(t).cuda()
+    n = 10
+    for k in range(n):
+        sg.backward(xb, tt, want_loss=False)
+        g = sg.params(1).astype(np.float64)
+        assert np.count_nonzero(g) > 0.5 * g.size
+        lr = np.float32(mlp_ref.cosine_lr(k, n, 2e-3, 1e-4))
+        sg.adam_step(float(lr))
+        ref.step(g, float(lr))
+        wg, mg, vg = (sg.params(j).astype(np.float64) for j in (0, 2, 3))
+        assert np.all(np.abs(mg - ref.m) <= ref.em), (k, np.max(np.abs(mg - ref.m) / np.maximum(ref.em, 1e-300)))
+        assert np.all(np.abs(vg - ref.v) <= ref.ev), (k, np.max(np.abs(vg - ref.v) / np.maximum(ref.ev, 1e-300)))
+        assert np.all(np.abs(wg - ref.w) <= ref.ew), (k, np.max(np.abs(wg - ref.w) / np.maximum(ref.ew, 1e-300)))
+    # the BF16 copy: the network after the steps computes what a fresh one loaded with its weights does
+    sg2 = opmm.Surrogate(ctx)
+    sg2.set_params(sg.params(0))
+    o1 = torch.zeros(B, 18, device="cuda")
+    o2 = torch.zeros(B, 18, device="cuda")
+    sg.forward(xb, o1)
+    sg2.forward(xb, o2)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2)
+    sg2.close()
+    sg.close()
+
+
+@pytest.mark.parametrize("sigma_max", [0.0, 0.1])
+def test_generated_batch_matches_oracle(ctx, opmm, sigma_max):
+    """Every sample of a generated training batch (96 rows: one full wave and a ragged one) against the
+    oracle's sample (oracle/mlp_ref.py: the same SplitMix64 draws, the oracle's FP64 RK4 trajectory,
+    FP64 Box-Muller noise, the FP64 resampling): targets equal to the FP32 ulp; features within one
+    BF16 ulp, plus 1e-6 deg/16 on positions and 2e-5 on velocities (x4 scale) for the GPU trajectory's
+    1e-6 deg error and the FP32 trace roundings, doubled by the velocity's difference."""
+    sg = opmm.Surrogate(ctx)
+    B, seed, step = 96, 31, 5
+    feat = torch.zeros(B, 256, dtype=torch.int16, device="cuda")
+    tgt = torch.zeros(B, 18, device="cuda")
+    sg.generate(seed, step, feat, tgt, spread=0.3, sigma_max=sigma_max)
+    torch.cuda.synchronize()
+    zg = tgt.cpu().numpy()
+    fg = (feat.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    for i in range(B):
+        rf, z, tr, opc, amp = mlp_ref.training_sample(seed, step, i, spread=0.3, sigma_max=sigma_max)
+        assert np.all(np.abs(zg[i] - z) <= np.spacing(np.abs(z).astype(np.float32))), (i, zg[i] - z)
+        pos_ok = np.abs(fg[i, 0::2] - rf[0::2]) <= 2 ** -7 * np.abs(rf[0::2]) + 1e-6
+        vel_ok = np.abs(fg[i, 1::2] - rf[1::2]) <= 2 ** -7 * np.abs(rf[1::2]) + 2e-5
+        assert np.all(pos_ok) and np.all(vel_ok), (i, np.flatnonzero(~pos_ok), np.flatnonzero(~vel_ok))
+    sg.close()
