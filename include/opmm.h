@@ -59,7 +59,10 @@ enum {
     OPMM_ST_NONFINITE_INPUT = 1,    /* trace holds NaN/Inf: not fitted, outputs NaN */
     OPMM_ST_NO_FINITE_CANDIDATE = 2,/* some round had no candidate with finite cost */
     OPMM_ST_SEEDED = 4,             /* search started from a supplied/learned seed  */
-    OPMM_ST_FALLBACK = 8            /* seeded result rejected; plain search used    */
+    OPMM_ST_FALLBACK = 8,           /* seeded result rejected; plain search used    */
+    OPMM_ST_WAIT_TIMEOUT = 16       /* persistent launch: a tile gave up waiting for
+                                       its round (opmm_set_wait_limit); that tile
+                                       was not searched, the result is no estimate */
 };
 
 typedef struct opmm_ctx opmm_ctx;
@@ -127,6 +130,21 @@ void opmm_nominal(float dur_ms, float* out);
 int opmm_create(opmm_ctx** out, int device);
 int opmm_destroy(opmm_ctx* ctx);
 const char* opmm_last_error(const opmm_ctx* ctx);
+
+/* The persistent launch (OPMM_FIT_PERSISTENT) has blocks wait on the device
+ * for the previous round of their saccade (Algorithm 1 runs the rounds of a
+ * task in order).  The wait is bounded by `polls` polls (default 2^26, several
+ * seconds); a block that gives up leaves its tile unsearched, sets
+ * OPMM_ST_WAIT_TIMEOUT on that saccade and is counted in the context's
+ * report, and the launch still runs to its end.  0 makes every such wait give
+ * up at once (to exercise the report).  Applies to fits queued and plans
+ * created after the call. */
+int opmm_set_wait_limit(opmm_ctx* ctx, uint32_t polls);
+/* Synchronise `stream`, then read and clear the context's report: returns
+ * OPMM_EDEVICE (with the count in opmm_last_error) if any persistent launch
+ * of this context that has completed gave up a wait since the last call,
+ * else OPMM_OK. */
+int opmm_sync(opmm_ctx* ctx, void* stream);
 
 /* Candidate vectors of the search stream (for replay and for callers that
  * score their own candidate sets).  Writes out[n][18] for candidate indices

@@ -152,7 +152,7 @@ __device__ __forceinline__ void refine_one(const SacDev& sd, int s, int r, uint6
     }
     uint32_t idx = (uint32_t)(key & 0xFFFFFFFFull);
     if ((key >> 32) >= 0x7F800000ull) {
-        status[s] |= OPMM_ST_NO_FINITE_CANDIDATE;
+        atomicOr(&status[s], (int32_t)OPMM_ST_NO_FINITE_CANDIDATE);
         idx = 0;
     }
     float p[P];
@@ -418,15 +418,19 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_round_kernel(const Sa
 // saccade's round refines that saccade and publishes the next round; a block
 // that takes a tile of a later round waits for that.  Every item it can wait
 // on was handed out earlier to a running block, so the queue always drains.
+// The wait is bounded (wait_limit polls): a block that gives up does not
+// search its tile, marks the saccade OPMM_ST_WAIT_TIMEOUT and counts the
+// give-up in *errflag, and still counts the tile as done, so the queue drains
+// and every block exits.
 template <int TPB, int PASSES, int UNROLL>
 __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_persistent_kernel(
     const SacDev* __restrict__ sacs, int S, int R, int tiles_per_round, float dt, float shrink,
     const float* __restrict__ proj, float* centre, float* hw, const float* lo, const float* hi,
     int32_t* status, uint64_t* keys, uint32_t* head, uint32_t* done, uint32_t* ready, uint32_t* errflag,
-    const int* __restrict__ ord, const int* __restrict__ obase)
+    const int* __restrict__ ord, const int* __restrict__ obase, uint32_t wait_limit)
 {
     __shared__ TileSmem<TPB, PASSES> sm;
-    __shared__ int s_item, s_sac;
+    __shared__ int s_item, s_sac, s_gaveup;
     const int64_t total = (int64_t)R * tiles_per_round;
     for (;;) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(head, 1u);
@@ -437,7 +441,10 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_persistent_kernel(
         const int b = (int)(item % tiles_per_round);
         if (threadIdx.x < 64) {
             const int sw = saccade_of_tile(sacs, ord, obase, S, b);
-            if (threadIdx.x == 0) s_sac = sw;
+            if (threadIdx.x == 0) {
+                s_sac = sw;
+                s_gaveup = 0;
+            }
         }
         __syncthreads();
         const int s = s_sac;
@@ -447,20 +454,25 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_persistent_kernel(
         if (!skip) {
             if (r > 0) {
                 if (threadIdx.x == 0) {
-                    uint32_t spins = 0;
-                    while (__hip_atomic_load(&ready[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
-                           (uint32_t)r) {
-                        __builtin_amdgcn_s_sleep(2);
-                        if (++spins > (1u << 26)) {  // safety valve: never hang the queue
-                            atomicOr(errflag, 1u);
+                    bool ok = false;
+                    for (uint32_t polls = 0; polls < wait_limit; ++polls) {
+                        if (__hip_atomic_load(&ready[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= (uint32_t)r) {
+                            ok = true;
                             break;
                         }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                    if (!ok) {
+                        s_gaveup = 1;
+                        atomicAdd(errflag, 1u);
+                        atomicOr(&status[s], (int32_t)OPMM_ST_WAIT_TIMEOUT);
                     }
                 }
                 __syncthreads();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
-            uint64_t best = process_tile<TPB, PASSES, UNROLL>(sm, sd, s, t, r, dt, proj, centre, hw, lo, hi);
+            uint64_t best = ~0ull;
+            if (!s_gaveup) best = process_tile<TPB, PASSES, UNROLL>(sm, sd, s, t, r, dt, proj, centre, hw, lo, hi);
             if (threadIdx.x == 0) {
                 if (best != ~0ull)
                     atomicMin((unsigned long long*)&keys[(int64_t)r * S + s], (unsigned long long)best);
@@ -477,6 +489,16 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_persistent_kernel(
             }
         }
         __syncthreads();
+    }
+}
+
+// After a persistent launch: add its give-up count to the context's report
+// (read and cleared by opmm_sync).
+__global__ void harvest_giveups_kernel(const uint32_t* __restrict__ errflag, uint32_t* report)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const uint32_t n = *errflag;
+        if (n) atomicAdd(report, n);
     }
 }
 
@@ -619,6 +641,7 @@ struct FitLaunch {
     uint32_t *head, *done, *ready, *errflag;
     int grid_persistent;
     const int *ord, *obase;  // dispatch order (nullable: record order)
+    uint32_t wait_limit;     // polls of a persistent block waiting for its round
 };
 
 template <int TPB, int PASSES, int UNROLL>
@@ -627,7 +650,8 @@ hipError_t launch_shape(const FitLaunch& L, bool persistent, int round, hipStrea
     if (persistent) {
         hipLaunchKernelGGL((fit_persistent_kernel<TPB, PASSES, UNROLL>), dim3(L.grid_persistent), dim3(TPB), 0,
                            st, L.sacs, L.S, L.R, L.tiles_per_round, L.dt, L.shrink, L.proj, L.centre, L.hw,
-                           L.lo, L.hi, L.status, L.keys, L.head, L.done, L.ready, L.errflag, L.ord, L.obase);
+                           L.lo, L.hi, L.status, L.keys, L.head, L.done, L.ready, L.errflag, L.ord, L.obase,
+                           L.wait_limit);
     } else {
         hipLaunchKernelGGL((fit_round_kernel<TPB, PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(TPB), 0, st,
                            L.sacs, L.S, round, L.key_stride, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status,
@@ -712,6 +736,8 @@ struct FitScratch {
 struct opmm_ctx {
     int device = 0;
     int cu_count = 0;
+    uint32_t wait_limit = 1u << 26;        // polls before a persistent block gives up (several seconds)
+    uint32_t* giveup_report = nullptr;     // device word: give-ups since the last opmm_sync
     std::string err;
     FitScratch scratch;
     FitScratch aux;  // projections for the learned seed, independent of the fit's scratch
@@ -936,6 +962,7 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
     L.ord = (const int*)sc.order.p;
     L.obase = L.ord + S;
     L.key_stride = S;
+    L.wait_limit = ctx->wait_limit;
     if (tiles_per_round > 0) {
         if (prm->mode == OPMM_FIT_PERSISTENT) {
             // The queue needs no co-residency, so oversubscribe: blocks that start
@@ -945,6 +972,8 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
             int64_t total = (int64_t)R * tiles_per_round;
             L.grid_persistent = (int)std::max<int64_t>(1, std::min(want, total));
             OPMM_HIP(ctx, launch_fit_kernel(shape, L, true, 0, st));
+            hipLaunchKernelGGL(harvest_giveups_kernel, dim3(1), dim3(64), 0, st, errflag, ctx->giveup_report);
+            OPMM_HIP(ctx, hipGetLastError());
         } else {
             for (int r = 0; r < R; ++r) {
                 OPMM_HIP(ctx, launch_fit_kernel(shape, L, false, r, st));
@@ -1216,6 +1245,14 @@ int opmm_create(opmm_ctx** out, int device)
         delete c;
         return OPMM_EDEVICE;
     }
+    if (hipMalloc((void**)&c->giveup_report, sizeof(uint32_t)) != hipSuccess ||
+        hipMemset(c->giveup_report, 0, sizeof(uint32_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->giveup_report) (void)hipFree(c->giveup_report);
+        (void)hipStreamDestroy(c->cap_stream);
+        delete c;
+        return OPMM_ENOMEM;
+    }
     *out = c;
     return OPMM_OK;
 }
@@ -1227,11 +1264,34 @@ int opmm_destroy(opmm_ctx* ctx)
     (void)hipDeviceSynchronize();
     if (ctx->d_cand) (void)hipFree(ctx->d_cand);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->giveup_report) (void)hipFree(ctx->giveup_report);
     delete ctx;
     return OPMM_OK;
 }
 
 const char* opmm_last_error(const opmm_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+int opmm_set_wait_limit(opmm_ctx* ctx, uint32_t polls)
+{
+    if (!ctx) return OPMM_EINVAL;
+    ctx->wait_limit = polls;
+    return OPMM_OK;
+}
+
+int opmm_sync(opmm_ctx* ctx, void* stream)
+{
+    if (!ctx) return OPMM_EINVAL;
+    OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    OPMM_HIP(ctx, hipStreamSynchronize((hipStream_t)stream));
+    uint32_t n = 0;
+    OPMM_HIP(ctx, hipMemcpy(&n, ctx->giveup_report, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (n) OPMM_HIP(ctx, hipMemset(ctx->giveup_report, 0, sizeof(uint32_t)));
+    if (n)
+        return fail(ctx, OPMM_EDEVICE,
+                    std::to_string(n) + " tile(s) of a persistent fit gave up waiting for their round; the "
+                    "saccades concerned carry OPMM_ST_WAIT_TIMEOUT and their results are not estimates");
+    return OPMM_OK;
+}
 
 int opmm_tile_count(void) { return kNumShapes; }
 int opmm_tile_default(void) { return kDefaultShape; }

@@ -18,7 +18,7 @@ P = 18
 MAX_T = 2048
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTREADY = 0, -1, -2, -3, -4
-ST_OK, ST_NONFINITE_INPUT, ST_NO_FINITE_CANDIDATE, ST_SEEDED, ST_FALLBACK = 0, 1, 2, 4, 8
+ST_OK, ST_NONFINITE_INPUT, ST_NO_FINITE_CANDIDATE, ST_SEEDED, ST_FALLBACK, ST_WAIT_TIMEOUT = 0, 1, 2, 4, 8, 16
 FIT_ROUNDS, FIT_PERSISTENT = 0, 1
 
 SACCADE_DTYPE = np.dtype([("pos_offset", "<i8"), ("T", "<i4"), ("C", "<i4"), ("amp_deg", "<f4"),
@@ -69,6 +69,8 @@ def _load():
         "opmm_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int]),
         "opmm_destroy": (ctypes.c_int, [vp]),
         "opmm_last_error": (ctypes.c_char_p, [vp]),
+        "opmm_set_wait_limit": (ctypes.c_int, [vp, u32]),
+        "opmm_sync": (ctypes.c_int, [vp, vp]),
         "opmm_candidates": (ctypes.c_int, [vp, u64, u32, u32, i64, vp, vp, vp, vp, vp, vp]),
         "opmm_simulate": (ctypes.c_int, [vp, vp, vp, i64, i32, f, vp, vp]),
         "opmm_score": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, f, vp, vp]),
@@ -228,6 +230,13 @@ class Context:
             raise OpmmError(rc, lib.opmm_last_error(self._h).decode())
 
     # -- calls -------------------------------------------------------------------------------
+    def set_wait_limit(self, polls):
+        self._check(lib.opmm_set_wait_limit(self._h, int(polls)))
+
+    def sync(self, stream=None):
+        """Synchronise the stream; raises OpmmError(EDEVICE) if a persistent launch gave up a wait."""
+        self._check(lib.opmm_sync(self._h, _stream(stream)))
+
     def candidates(self, seed, rnd, idx0, n, c, w, lo, hi, out, stream=None):
         arr = [np.ascontiguousarray(a, np.float32) for a in (c, w, lo, hi)]
         ps = [a.ctypes.data_as(ctypes.c_void_p) for a in arr]

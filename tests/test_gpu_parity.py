@@ -240,92 +240,145 @@ def test_fit_model9_replay_rounds(ctx, opmm):
         assert abs(oracle.cost(th, traces[s], b["dir_deg"][s])[0] - res["rmse"][s]) <= 1e-6
 
 
+def sampled_round_check(ctx, opmm, b, s, trace, r, cen, w, lo, hi, idx, N, rng, where):
+    """One round of one saccade at full size, on a sample the oracle can afford: the GPU re-scores the
+    whole round (opmm_score on the regenerated candidates); the oracle scores the GPU's 64 best, 64
+    uniformly drawn others and the winner.  The cost error bound eps is taken over that whole sample, so
+    it does not rest on the GPU's own ranking alone.  An unsampled candidate j has GPU cost >= that of the
+    64th best, so oracle cost >= g[top[-1]] - eps; it cannot undercut the winner (oracle cost <= g[idx] +
+    eps) by more than GAP once the GPU margin g[top[-1]] - g[idx] >= 2 eps - GAP."""
+    rec = records(synth.subset(b, [s]), opmm)
+    rec["pos_offset"] = 0
+    allc = torch.zeros(N, 18, device="cuda")
+    ctx.candidates(int(b["seed"][s]), r, 0, N, cen, w, lo, hi, allc)
+    g = torch.zeros(N, device="cuda")
+    ctx.score(allc, dev(trace.reshape(-1)), rec, g)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    assert g[idx] == g.min() or g[idx] - g.min() <= 1e-7, where   # fused kernel and score agree
+    top = np.argsort(g, kind="stable")[:64]
+    uni = rng.choice(N, size=min(64, N), replace=False)
+    sample = np.unique(np.r_[top, uni, idx])
+    cands = oracle.candidates(int(b["seed"][s]), r, sample, cen, w, lo, hi)
+    ref, _ = oracle.score(cands, trace, b["amp"][s], b["dir_deg"][s], nthreads=NTH)
+    err = np.abs(g[sample] - ref)
+    assert np.all(err <= cost_tol(ref)), (where, err.max())
+    wi = int(np.where(sample == idx)[0][0])
+    assert ref[wi] - ref.min() <= GAP, where
+    eps = 2 * err.max() + 1e-9
+    margin = g[top[-1]] - g[idx]
+    assert margin >= 2 * eps - GAP, (where, margin, eps)
+    return err.max()
+
+
 def test_fit_full_size_sampled(ctx, opmm):
-    """65536 candidates x 10 halving rounds on two full-estimation saccades.  Rounds 0 and 9 are
-    checked on a sample the oracle can afford: the GPU re-scores the whole round (opmm_score on the
-    regenerated candidates), the oracle scores the 64 best and the winner."""
-    full, traces_all = make_batch(16, "full")
-    pick = [1, 9]
-    b = synth.subset(full, pick)
-    traces = [traces_all[i] for i in pick]
+    """The full-estimation configuration's oracle subset: 16 saccades, 65536 candidates x 10 halving
+    rounds, every round of every saccade checked on a sample (sampled_round_check), persistent and
+    per-round launches identical, and each final RMSE the oracle's for the returned OPC (the CPU_check
+    pattern of Section 3.4)."""
+    b, traces = make_batch(16, "full")
     N, R = 65536, 10
     res = run_fit(ctx, opmm, b, traces, N, R, mode=opmm.FIT_PERSISTENT)
     res2 = run_fit(ctx, opmm, b, traces, N, R, mode=opmm.FIT_ROUNDS)
     assert np.array_equal(res["keys"], res2["keys"]) and np.array_equal(res["opc"], res2["opc"])
+    assert np.all(res["status"] == 0)
+    rng = np.random.default_rng(77)
+    worst = 0.0
     for s in range(b["S"]):
         cen, w, lo, hi = centre_chain(b, s, res["keys"], R)
-        rec = records(synth.subset(b, [s]), opmm)
-        rec["pos_offset"] = 0
-        for r in (0, R - 1):
-            ww = w * np.float32(0.5 ** r)
-            allc = torch.zeros(N, 18, device="cuda")
-            ctx.candidates(int(b["seed"][s]), r, 0, N, cen[r], ww, lo, hi, allc)
-            g = torch.zeros(N, device="cuda")
-            ctx.score(allc, dev(traces[s].reshape(-1)), rec, g)
-            torch.cuda.synchronize()
-            g = g.cpu().numpy().astype(np.float64)
+        for r in range(R):
             idx = int(res["keys"][r, s] & np.uint64(0xFFFFFFFF))
-            assert g[idx] == g.min() or g[idx] - g.min() <= 1e-7   # fused kernel and score agree
-            top = np.argsort(g, kind="stable")[:64]
-            sample = np.unique(np.r_[top, idx])
-            cands = oracle.candidates(int(b["seed"][s]), r, sample, cen[r], ww, lo, hi)
-            ref, _ = oracle.score(cands, traces[s], b["amp"][s], b["dir_deg"][s], nthreads=NTH)
-            err = np.abs(g[sample] - ref)
-            assert np.all(err <= cost_tol(ref))
-            wi = int(np.where(sample == idx)[0][0])
-            assert ref[wi] - ref.min() <= GAP
-            # An unsampled candidate j has oracle cost >= g[top[-1]] - eps, so it cannot undercut the
-            # winner by more than GAP once the GPU margin exceeds 2 eps - GAP (eps: cost error bound).
-            eps = 2 * err.max() + 1e-9
-            margin = g[top[-1]] - g[idx]
-            assert margin >= 2 * eps - GAP, (margin, eps)
+            worst = max(worst, sampled_round_check(ctx, opmm, b, s, traces[s], r, cen[r], w * np.float32(0.5 ** r),
+                                                   lo, hi, idx, N, rng, (s, r)))
+        assert np.array_equal(res["opc"][s], cen[R])
+        th = oracle.simulate(res["opc"][s].astype(np.float64), b["amp"][s], int(b["T"][s]))
+        rm, ma = oracle.cost(th, traces[s], b["dir_deg"][s])
+        assert abs(rm - res["rmse"][s]) <= 1e-6 * max(1.0, rm) and abs(ma - res["mae"][s]) <= 1e-6 * max(1.0, ma)
+    print("largest sampled cost error over 16 saccades x 10 rounds: %.3g" % worst)
 
 
 def test_fit_uneven_full_size_sampled(ctx, opmm):
     """The batched-uneven configuration at its full size: 4096 saccades of 20-150 samples with
     per-saccade candidate counts from {4096, 16384, 65536}, autotuned shape, one persistent launch
-    captured in a graph (4 rounds).  Sampled saccades: identical alone (per-round launches) and in the
-    batch, and round 0's winner checked against the oracle on the GPU's 64 best plus the winner."""
+    captured in a graph, 10 rounds.  Sampled saccades: identical alone (per-round launches) and in the
+    batch, and every one of their rounds checked against the oracle (sampled_round_check)."""
     b, traces = make_batch(4096, "uneven")
     ncand = b["n_cand"]
-    S, R = b["S"], 4
+    S, R = b["S"], 10
     recs = records(b, opmm, n_cand=ncand)
     pos = dev(opmm.pack_traces(traces))
     prm = opmm.fit_params(n_cand=4096, n_rounds=R, mode=opmm.FIT_PERSISTENT)
     prm.tile = ctx.autotune(pos, recs, prm)
     opc = torch.zeros(S, 18, device="cuda")
     rmse = torch.zeros(S, device="cuda")
+    st = torch.zeros(S, dtype=torch.int32, device="cuda")
     keys = torch.zeros(R, S, dtype=torch.int64, device="cuda")
-    plan = ctx.plan(pos, recs, prm, opc, rmse, round_keys=keys)
+    plan = ctx.plan(pos, recs, prm, opc, rmse, status_out=st, round_keys=keys)
     plan.launch()
-    torch.cuda.synchronize()
+    ctx.sync()
     plan.close()
     keys = keys.cpu().numpy().view(np.uint64)
     opc = opc.cpu().numpy()
-    assert np.all(np.isfinite(rmse.cpu().numpy()))
-    picks = [int(np.argmax(b["T"])), int(np.nonzero(ncand == 65536)[0][0]), 1234]
+    assert np.all(np.isfinite(rmse.cpu().numpy())) and np.all(st.cpu().numpy() == 0)
+    rng = np.random.default_rng(78)
+    picks = [int(np.argmax(b["T"])), int(np.argmin(b["T"])), int(np.nonzero(ncand == 65536)[0][0]),
+             int(np.nonzero(ncand == 4096)[0][0]), 1234]
     for s in picks:
         one = run_fit(ctx, opmm, synth.subset(b, [s]), [traces[s]], int(ncand[s]), R)
         assert np.array_equal(one["keys"][:, 0], keys[:, s]), s
         assert np.array_equal(one["opc"][0].view(np.uint32), opc[s].view(np.uint32)), s
-        c, w, lo, hi = oracle.initial_box(b["dur_ms"][s])
-        N = int(ncand[s])
-        rec = records(synth.subset(b, [s]), opmm)
-        rec["pos_offset"] = 0
-        allc = torch.zeros(N, 18, device="cuda")
-        ctx.candidates(int(b["seed"][s]), 0, 0, N, c, w, lo, hi, allc)
-        g = torch.zeros(N, device="cuda")
-        ctx.score(allc, dev(traces[s].reshape(-1)), rec, g)
-        torch.cuda.synchronize()
-        g = g.cpu().numpy().astype(np.float64)
-        idx = int(keys[0, s] & np.uint64(0xFFFFFFFF))
-        assert g[idx] - g.min() <= 1e-7
-        sample = np.unique(np.r_[np.argsort(g, kind="stable")[:64], idx])
-        cands = oracle.candidates(int(b["seed"][s]), 0, sample, c, w, lo, hi)
-        ref, _ = oracle.score(cands, traces[s], b["amp"][s], b["dir_deg"][s], nthreads=NTH)
-        assert np.all(np.abs(g[sample] - ref) <= cost_tol(ref)), s
-        wi = int(np.where(sample == idx)[0][0])
-        assert ref[wi] - ref.min() <= GAP, s
+        cen, w, lo, hi = centre_chain(b, s, keys, R)
+        for r in range(R):
+            idx = int(keys[r, s] & np.uint64(0xFFFFFFFF))
+            sampled_round_check(ctx, opmm, b, s, traces[s], r, cen[r], w * np.float32(0.5 ** r), lo, hi, idx,
+                                int(ncand[s]), rng, (s, r))
+
+
+def test_persistent_wait_giveup_is_reported(ctx, opmm):
+    """The persistent launch's bounded wait, forced to give up at once from the host (wait limit 0):
+    every kernel still ends, the queued call returns OK, opmm_sync reports OPMM_EDEVICE, and every
+    saccade whose later rounds had to wait carries OPMM_ST_WAIT_TIMEOUT -- for opmm_fit and for a
+    captured plan.  The per-round mode never waits and is unaffected; with the default limit the same
+    persistent fit is clean and equals the per-round launches."""
+    b, traces = make_batch(5, "uneven")
+    ncand = np.array([64, 3000, 1024, 5000, 700], np.int32)
+    S, R = b["S"], 3
+    recs = records(b, opmm, n_cand=ncand)
+    pos = dev(opmm.pack_traces(traces))
+    ref = run_fit(ctx, opmm, b, traces, 64, R, mode=opmm.FIT_ROUNDS, n_cand_per=ncand)
+    ctx.sync()
+    try:
+        ctx.set_wait_limit(0)
+        for mode in (opmm.FIT_PERSISTENT, "plan"):
+            prm = opmm.fit_params(n_cand=64, n_rounds=R, mode=opmm.FIT_PERSISTENT)
+            opc = torch.zeros(S, 18, device="cuda"); rmse = torch.zeros(S, device="cuda")
+            st = torch.zeros(S, dtype=torch.int32, device="cuda")
+            if mode == "plan":
+                plan = ctx.plan(pos, recs, prm, opc, rmse, status_out=st)
+                with pytest.raises(opmm.OpmmError) as e:   # the plan's warm-up run gave up too
+                    ctx.sync()
+                assert e.value.code == opmm.EDEVICE
+                st.zero_()
+                plan.launch()
+            else:
+                ctx.fit(pos, recs, prm, opc, rmse, None, st)
+            with pytest.raises(opmm.OpmmError) as e:
+                ctx.sync()
+            assert e.value.code == opmm.EDEVICE and "gave up" in str(e.value), mode
+            if mode == "plan":
+                plan.close()
+            assert np.all(st.cpu().numpy() & opmm.ST_WAIT_TIMEOUT), (mode, st.cpu().numpy())
+            ctx.sync()   # the report was cleared by the previous call
+        rounds = run_fit(ctx, opmm, b, traces, 64, R, mode=opmm.FIT_ROUNDS, n_cand_per=ncand)
+        ctx.sync()
+        assert np.array_equal(rounds["keys"], ref["keys"]) and np.all(rounds["status"] == 0)
+    finally:
+        ctx.set_wait_limit(1 << 26)
+    res = run_fit(ctx, opmm, b, traces, 64, R, mode=opmm.FIT_PERSISTENT, n_cand_per=ncand)
+    ctx.sync()
+    assert np.all(res["status"] == 0)
+    assert np.array_equal(res["keys"], ref["keys"]) and np.array_equal(res["opc"].view(np.uint32),
+                                                                       ref["opc"].view(np.uint32))
 
 
 def test_modes_and_shapes_bit_identical(ctx, opmm):
@@ -407,6 +460,40 @@ def test_edge_cases(ctx, opmm):
             assert idx == 0
         else:
             check_argmin(ref, idx, s)
+
+
+def test_non_finite_costs(ctx, opmm):
+    """NaN -> +Inf in the cost (header of opmm_score, argmin rule of the search): an OPC with a NaN
+    component or a zero inertia J scores +Inf, a nominal one the oracle's finite RMSE; a fit in which
+    every candidate's cost is non-finite (a finite trace of 3e19 deg: its squared residual overflows
+    the FP32 cost) sets OPMM_ST_NO_FINITE_CANDIDATE in every round, keeps candidate 0 -- the centre --
+    and so returns the nominal OPC with the +Inf key's exponent bits."""
+    rng = np.random.default_rng(9)
+    p1 = oracle.nominal(43.0) * rng.uniform(0.9, 1.1, 18)
+    tr = oracle.make_target(p1, 10.0, 0.0, 80, 1, rng.standard_normal((80, 1)), 0.05)
+    rec = opmm.saccade_records([80], 1, [10.0], [0.0], [43.0], np.array([5], np.uint64))
+    nom = oracle.nominal(43.0).astype(np.float32)
+    bad_nan = nom.copy(); bad_nan[4] = np.nan
+    bad_j = nom.copy(); bad_j[9] = 0.0
+    opc = np.stack([nom, bad_nan, bad_j])
+    g = torch.zeros(3, device="cuda")
+    ctx.score(dev(opc), dev(tr.reshape(-1)), rec, g)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    ref, _ = oracle.score(nom[None], tr, 10.0, 0.0)
+    assert abs(g[0] - ref[0]) <= cost_tol(ref[0]) and np.isposinf(g[1]) and np.isposinf(g[2]), g
+    huge = np.full((80, 1), 3e19, np.float32)
+    S, R = 1, 3
+    opc_o = torch.zeros(S, 18, device="cuda"); rmse = torch.zeros(S, device="cuda")
+    st = torch.zeros(S, dtype=torch.int32, device="cuda"); keys = torch.zeros(R, S, dtype=torch.int64, device="cuda")
+    for mode in (opmm.FIT_ROUNDS, opmm.FIT_PERSISTENT):
+        ctx.fit(dev(huge.reshape(-1)), rec, opmm.fit_params(n_cand=2000, n_rounds=R, mode=mode), opc_o, rmse, None,
+                st, keys)
+        ctx.sync()
+        assert int(st.cpu()[0]) == opmm.ST_NO_FINITE_CANDIDATE, mode
+        k = keys.cpu().numpy().view(np.uint64)[:, 0]
+        assert np.all(k >> np.uint64(32) == np.uint64(0x7F800000)) and np.all(k & np.uint64(0xFFFFFFFF) == 0)
+        assert np.array_equal(opc_o.cpu().numpy()[0], oracle.initial_box(43.0)[0]), mode
 
 
 def test_maximum_trace_length(ctx, opmm):
