@@ -190,6 +190,28 @@ int opmm_fit(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccad
              float* rmse_out, float* mae_out, int32_t* status_out, uint64_t* round_keys,
              void* stream);
 
+/* Allocation-free variant of opmm_fit, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and status words as opmm_fit, bit for
+ * bit.  Its device scratch is one static array per device of
+ * OPMM_NOALLOC_SCRATCH_BYTES, held until the process ends, and its host
+ * staging a static buffer; the call makes no hipMalloc, hipFree or other
+ * allocation.  Limits: S <= OPMM_NOALLOC_MAX_S and a scratch layout within
+ * OPMM_NOALLOC_SCRATCH_BYTES (per saccade 80 B record, 8 B order, 8 B energy,
+ * 288 B box, 4 B status, 8 B counters and, without round_keys, 8 B per round;
+ * 4 B per trace sample; each part 256-byte aligned), else OPMM_EINVAL.  Every
+ * call on a device shares that device's array and keeps the last call's
+ * contents (each call rewrites every part before reading it): calls that
+ * overlap on one device (other streams, contexts or threads) race, so the
+ * caller must order them.  Like opmm_fit it uploads the records
+ * synchronously and queues the rest on `stream`. */
+#define OPMM_NOALLOC_MAX_S 4096
+#define OPMM_NOALLOC_SCRATCH_BYTES (8u << 20)
+int opmm_fit_noalloc(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs,
+                     int32_t S, const opmm_fit_params* params, const float* seed_opc, float* opc_out,
+                     float* rmse_out, float* mae_out, int32_t* status_out, uint64_t* round_keys,
+                     void* stream);
+
 /* A fit captured once into a HIP graph and replayed: the same work as
  * opmm_fit with the same arguments, bound to these buffers.  Creation runs
  * the fit once (synchronously) and then captures it; opmm_plan_launch replays

@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -733,6 +734,10 @@ struct FitScratch {
 
 }  // namespace
 
+// Device scratch of opmm_fit_noalloc: one array per device, held until the
+// process ends.  Host code uses the address opmm_create looked up, never this name.
+static __device__ __align__(256) unsigned char scratch[OPMM_NOALLOC_SCRATCH_BYTES];
+
 struct opmm_ctx {
     int device = 0;
     int cu_count = 0;
@@ -745,6 +750,7 @@ struct opmm_ctx {
     size_t d_cand_cap = 0;
     int tuned_shape = -1;
     hipStream_t cap_stream = nullptr;
+    unsigned char* noalloc_scratch = nullptr;  // device address of `scratch` on this device (set at creation)
 };
 
 struct opmm_plan {
@@ -861,18 +867,12 @@ int validate_params(opmm_ctx* ctx, const opmm_fit_params* p)
     return OPMM_OK;
 }
 
-// Host records -> device records, prefix sums of tiles; uploads synchronously
-// (the records are small) so the caller's host array can be reused at once.
-int upload_saccades(opmm_ctx* ctx, FitScratch& sc, const opmm_saccade* sacs, int S,
-                    const opmm_fit_params* prm, int tile_size, int64_t* total_T, int* tiles_per_round,
-                    hipStream_t st)
+// Host records of a batch (no allocation): h[S] device records, ob[2S] the
+// dispatch order and each ordered saccade's first tile, cnt[OPMM_MAX_T + 1]
+// counting scratch.  Returns the summed trace length and tile count.
+void build_records(const opmm_saccade* sacs, int S, const opmm_fit_params* prm, int tile_size, SacDev* h, int* ob,
+                   int* cnt, int64_t* total_T, int64_t* tiles_out)
 {
-    int rc;
-    const size_t rec_bytes = sizeof(SacDev) * (size_t)S, ord_bytes = sizeof(int) * 2 * (size_t)S;
-    if ((rc = ensure_host(ctx, sc.stage, rec_bytes + ord_bytes)) != OPMM_OK) return rc;
-    static_assert(sizeof(SacDev) % alignof(int) == 0, "the order array follows the records");
-    SacDev* h = (SacDev*)sc.stage.p;
-    int* ob = (int*)((char*)sc.stage.p + rec_bytes);
     int64_t toff = 0;
     for (int i = 0; i < S; ++i) {
         SacDev& d = h[i];
@@ -887,8 +887,7 @@ int upload_saccades(opmm_ctx* ctx, FitScratch& sc, const opmm_saccade* sacs, int
     // short blocks; ord[k] is the k-th saccade in that order and obase[k] its first tile.  The
     // order changes only which block takes a tile, never a result.  T is bounded, so a counting
     // sort on (OPMM_MAX_T - T) gives the order in O(S), ties in batch order.
-    std::vector<int>& cnt = sc.h_count;
-    cnt.assign(OPMM_MAX_T + 1, 0);
+    for (int k = 0; k <= OPMM_MAX_T; ++k) cnt[k] = 0;
     for (int i = 0; i < S; ++i) cnt[OPMM_MAX_T - sacs[i].T]++;  // T in 1..OPMM_MAX_T (validated)
     for (int k = 0, run = 0; k <= OPMM_MAX_T; ++k) {
         const int c = cnt[k];
@@ -903,6 +902,25 @@ int upload_saccades(opmm_ctx* ctx, FitScratch& sc, const opmm_saccade* sacs, int
         ob[S + k] = (int)tiles;
         tiles += d.tiles;
     }
+    *total_T = toff;
+    *tiles_out = tiles;
+}
+
+// Host records -> device records, prefix sums of tiles; uploads synchronously
+// (the records are small) so the caller's host array can be reused at once.
+int upload_saccades(opmm_ctx* ctx, FitScratch& sc, const opmm_saccade* sacs, int S,
+                    const opmm_fit_params* prm, int tile_size, int64_t* total_T, int* tiles_per_round,
+                    hipStream_t st)
+{
+    int rc;
+    const size_t rec_bytes = sizeof(SacDev) * (size_t)S, ord_bytes = sizeof(int) * 2 * (size_t)S;
+    if ((rc = ensure_host(ctx, sc.stage, rec_bytes + ord_bytes)) != OPMM_OK) return rc;
+    static_assert(sizeof(SacDev) % alignof(int) == 0, "the order array follows the records");
+    SacDev* h = (SacDev*)sc.stage.p;
+    int* ob = (int*)((char*)sc.stage.p + rec_bytes);
+    sc.h_count.resize(OPMM_MAX_T + 1);
+    int64_t toff, tiles;
+    build_records(sacs, S, prm, tile_size, h, ob, sc.h_count.data(), &toff, &tiles);
     if (tiles > 0x7FFFFFFF / 8) return fail(ctx, OPMM_EINVAL, "too many candidate tiles in one batch");
     if ((rc = ensure(ctx, sc.sacs, rec_bytes)) != OPMM_OK) return rc;
     if ((rc = ensure(ctx, sc.order, ord_bytes)) != OPMM_OK) return rc;
@@ -913,6 +931,24 @@ int upload_saccades(opmm_ctx* ctx, FitScratch& sc, const opmm_saccade* sacs, int
     *tiles_per_round = (int)tiles;
     return OPMM_OK;
 }
+
+// Device buffers of one fit (sizes for S saccades, summed length total_T, R
+// rounds): records [S], dispatch order [2S], projected traces [total_T], orthogonal
+// energies [S], box [4][S][18], status [S], counters [2S + 2], round keys [R][S].
+struct FitBufs {
+    SacDev* sacs;
+    int* order;
+    float* proj;
+    double* qorth;
+    float* box;
+    int32_t* status;
+    uint32_t* counters;
+    uint64_t* keys;
+};
+
+int enqueue_fit_bufs(opmm_ctx* ctx, const FitBufs& B, const float* pos, int S, int tiles_per_round,
+                     const opmm_fit_params* prm, int shape, const float* seed_opc, float* opc_out, float* rmse_out,
+                     float* mae_out, int32_t* status_out, hipStream_t st, bool run_prep);
 
 // Queue the whole fit on `st` (no host synchronisation inside: capturable).
 // run_prep = false: the projection of this upload is already queued (fit_stage).
@@ -932,15 +968,35 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
         if ((rc = ensure(ctx, sc.keys, sizeof(uint64_t) * (size_t)R * S)) != OPMM_OK) return rc;
         keys = (uint64_t*)sc.keys.p;
     }
-    const SacDev* d_sacs = (const SacDev*)sc.sacs.p;
-    float* proj = (float*)sc.proj.p;
-    double* qorth = (double*)sc.qorth.p;
-    float* centre = (float*)sc.box.p;
+    FitBufs B;
+    B.sacs = (SacDev*)sc.sacs.p;
+    B.order = (int*)sc.order.p;
+    B.proj = (float*)sc.proj.p;
+    B.qorth = (double*)sc.qorth.p;
+    B.box = (float*)sc.box.p;
+    B.status = (int32_t*)sc.status.p;
+    B.counters = (uint32_t*)sc.counters.p;
+    B.keys = keys;
+    return enqueue_fit_bufs(ctx, B, pos, S, tiles_per_round, prm, shape, seed_opc, opc_out, rmse_out, mae_out,
+                            status_out, st, run_prep);
+}
+
+// The fit's kernels on given buffers; allocates nothing.
+int enqueue_fit_bufs(opmm_ctx* ctx, const FitBufs& B, const float* pos, int S, int tiles_per_round,
+                     const opmm_fit_params* prm, int shape, const float* seed_opc, float* opc_out, float* rmse_out,
+                     float* mae_out, int32_t* status_out, hipStream_t st, bool run_prep)
+{
+    const int R = prm->n_rounds;
+    uint64_t* keys = B.keys;
+    const SacDev* d_sacs = B.sacs;
+    float* proj = B.proj;
+    double* qorth = B.qorth;
+    float* centre = B.box;
     float* hw = centre + P * S;
     float* lo = hw + P * S;
     float* hi = lo + P * S;
-    int32_t* status = (int32_t*)sc.status.p;
-    uint32_t* done = (uint32_t*)sc.counters.p;
+    int32_t* status = B.status;
+    uint32_t* done = B.counters;
     uint32_t* ready = done + S;
     uint32_t* head = ready + S;
     uint32_t* errflag = head + 1;
@@ -959,8 +1015,8 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
     L.shrink = prm->shrink; L.proj = proj; L.centre = centre; L.hw = hw; L.lo = lo; L.hi = hi;
     L.status = status; L.keys = keys; L.head = head; L.done = done; L.ready = ready; L.errflag = errflag;
     L.grid_persistent = 0;
-    L.ord = (const int*)sc.order.p;
-    L.obase = L.ord + S;
+    L.ord = B.order;
+    L.obase = B.order ? B.order + S : nullptr;
     L.key_stride = S;
     L.wait_limit = ctx->wait_limit;
     if (tiles_per_round > 0) {
@@ -1245,6 +1301,12 @@ int opmm_create(opmm_ctx** out, int device)
         delete c;
         return OPMM_EDEVICE;
     }
+    // The allocation-free fit's scratch: look up this device's copy of the array once, here.
+    void* sp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) == hipSuccess)
+        c->noalloc_scratch = (unsigned char*)sp;
+    else
+        (void)hipGetLastError();  // opmm_fit_noalloc then reports OPMM_EDEVICE
     if (hipMalloc((void**)&c->giveup_report, sizeof(uint32_t)) != hipSuccess ||
         hipMemset(c->giveup_report, 0, sizeof(uint32_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         (void)hipGetLastError();
@@ -1496,6 +1558,68 @@ int opmm_autotune(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_s
     ctx->tuned_shape = best;
     if (tile_out) *tile_out = best;
     return OPMM_OK;
+}
+
+// Host staging of opmm_fit_noalloc: static, shared by every call and guarded
+// by its mutex until the records are on the device.
+namespace {
+struct NoallocStage {
+    std::mutex mu;
+    SacDev recs[OPMM_NOALLOC_MAX_S];
+    int order[2 * OPMM_NOALLOC_MAX_S];
+    int cnt[OPMM_MAX_T + 1];
+};
+NoallocStage g_noalloc_stage;
+}  // namespace
+
+int opmm_fit_noalloc(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,
+                     const opmm_fit_params* params, const float* seed_opc, float* opc_out, float* rmse_out,
+                     float* mae_out, int32_t* status_out, uint64_t* round_keys, void* stream)
+{
+    int rc = check_fit_args(ctx, pos, pos_len, sacs, S, params, opc_out, rmse_out);
+    if (rc != OPMM_OK || S == 0) return rc;
+    if (S > OPMM_NOALLOC_MAX_S) return fail(ctx, OPMM_EINVAL, "S exceeds OPMM_NOALLOC_MAX_S");
+    if (!ctx->noalloc_scratch) return fail(ctx, OPMM_EDEVICE, "no device address for the allocation-free scratch");
+    OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int shape = pick_shape(ctx, params, sacs, S);
+    NoallocStage& g = g_noalloc_stage;
+    std::lock_guard<std::mutex> lock(g.mu);
+    int64_t total_T, tiles;
+    build_records(sacs, S, params, shape_tile(shape), g.recs, g.order, g.cnt, &total_T, &tiles);
+    if (tiles > 0x7FFFFFFF / 8) return fail(ctx, OPMM_EINVAL, "too many candidate tiles in one batch");
+    // carve the scratch: each part 256-byte aligned
+    size_t off = 0;
+    auto carve = [&off](size_t bytes) {
+        const size_t o = off;
+        off = (off + bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t o_sacs = carve(sizeof(SacDev) * (size_t)S), o_ord = carve(sizeof(int) * 2 * (size_t)S),
+                 o_proj = carve(sizeof(float) * (size_t)total_T), o_q = carve(sizeof(double) * (size_t)S),
+                 o_box = carve(sizeof(float) * 4 * P * (size_t)S), o_st = carve(sizeof(int32_t) * (size_t)S),
+                 o_cnt = carve(sizeof(uint32_t) * (2 * (size_t)S + 2)),
+                 o_keys = round_keys ? 0 : carve(sizeof(uint64_t) * (size_t)params->n_rounds * S);
+    if (off > (size_t)OPMM_NOALLOC_SCRATCH_BYTES)
+        return fail(ctx, OPMM_EINVAL, "the batch needs " + std::to_string(off) + " bytes of scratch; the "
+                    "allocation-free fit has " + std::to_string((size_t)OPMM_NOALLOC_SCRATCH_BYTES));
+    unsigned char* base = ctx->noalloc_scratch;
+    FitBufs B;
+    B.sacs = (SacDev*)(base + o_sacs);
+    B.order = (int*)(base + o_ord);
+    B.proj = (float*)(base + o_proj);
+    B.qorth = (double*)(base + o_q);
+    B.box = (float*)(base + o_box);
+    B.status = (int32_t*)(base + o_st);
+    B.counters = (uint32_t*)(base + o_cnt);
+    B.keys = round_keys ? round_keys : (uint64_t*)(base + o_keys);
+    OPMM_HIP(ctx, hipMemcpyAsync(B.sacs, g.recs, sizeof(SacDev) * (size_t)S, hipMemcpyHostToDevice, st));
+    OPMM_HIP(ctx, hipMemcpyAsync(B.order, g.order, sizeof(int) * 2 * (size_t)S, hipMemcpyHostToDevice, st));
+    OPMM_HIP(ctx, hipStreamSynchronize(st));
+    // every part is written before it is read: records and order above, projection, energies and
+    // status by the prep kernel, the box by init, counters and keys by fill kernels
+    return enqueue_fit_bufs(ctx, B, pos, S, (int)tiles, params, shape, seed_opc, opc_out, rmse_out, mae_out,
+                            status_out, st, true);
 }
 
 }  // extern "C"

@@ -76,6 +76,8 @@ def _load():
         "opmm_score": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, f, vp, vp]),
         "opmm_fit": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(FitParams), vp, vp, vp, vp, vp,
                                     vp, vp]),
+        "opmm_fit_noalloc": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(FitParams), vp, vp, vp, vp, vp,
+                                            vp, vp]),
         "opmm_fit_plan_create": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(FitParams), vp, vp,
                                                 vp, vp, vp, vp, vp, ctypes.POINTER(vp)]),
         "opmm_plan_launch": (ctypes.c_int, [vp, vp]),
@@ -261,6 +263,14 @@ class Context:
                                  recs.shape[0], ctypes.byref(params), _ptr(seed_opc), _ptr(opc_out),
                                  _ptr(rmse_out), _ptr(mae_out), _ptr(status_out), _ptr(round_keys),
                                  _stream(stream)))
+
+    def fit_noalloc(self, pos, recs, params: FitParams, opc_out, rmse_out, mae_out=None, status_out=None,
+                    round_keys=None, seed_opc=None, stream=None):
+        recs = np.ascontiguousarray(recs, SACCADE_DTYPE)
+        self._check(lib.opmm_fit_noalloc(self._h, _ptr(pos), pos.numel(), recs.ctypes.data_as(ctypes.c_void_p),
+                                         recs.shape[0], ctypes.byref(params), _ptr(seed_opc), _ptr(opc_out),
+                                         _ptr(rmse_out), _ptr(mae_out), _ptr(status_out), _ptr(round_keys),
+                                         _stream(stream)))
 
     def fit_nm(self, pos, recs, params: NmParams, opc_out, rmse_out, iters_out=None, decisions_out=None,
                status_out=None, seed_opc=None, stream=None):
