@@ -167,8 +167,9 @@ def surrogate_leg(a, ctx, opmm, torch, synth, keep=False):
     t0 = time.perf_counter()
     loss = sg.train(data_seed=1, batch=B, n_steps=steps, lr0=2e-3, lr_min=2e-5)
     train_s = time.perf_counter() - t0
-    # the training GEMMs' share of the BF16 MFMA peak: forward + backward of one generated batch (4 forward,
-    # 4 weight-gradient and 3 input-gradient GEMMs plus their small reductions), timed with HIP events
+    # the training kernels' share of the BF16 MFMA peak: forward + backward of one generated batch (one fused
+    # kernel for the forward pass, the loss and the input gradients, one for the four layers' weight
+    # gradients, plus the loss reset), timed with HIP events
     feat = torch.empty(B, 256, dtype=torch.int16, device="cuda")
     target = torch.empty(B, 18, dtype=torch.float32, device="cuda")
     sg.generate(1, 0, feat, target)
@@ -234,7 +235,7 @@ def surrogate_leg(a, ctx, opmm, torch, synth, keep=False):
         sg = None
     return sg, {"train": {"saccades": steps * B, "steps": steps, "batch": B, "seconds": train_s,
                       "loss_first": float(loss[:10].mean()), "loss_last": float(loss[-10:].mean()),
-                      "forward_backward": fb},
+                      "step_ms": 1e3 * train_s / steps, "forward_backward": fb},
             "heldout_saccades": S,
             "plain": {"n_cand": a.n_cand, "rounds": a.rounds, "saccades_fitted_per_s": S / plain_s,
                       "mean_rmse_deg": float(rp.mean()), "median_rmse_deg": float(np.median(rp))},

@@ -29,230 +29,464 @@ namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
+typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4_t;
 
+// FP32 -> BF16, round to nearest even; a NaN stays a (quiet) NaN.  Branch-free: it runs on every
+// element the network writes.
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-    return (uint16_t)(u >> 16);
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t r = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+    return (uint16_t)((u & 0x7FFFFFFFu) > 0x7F800000u ? ((u >> 16) | 0x40u) : r);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ---------------------------------------------------------------------------
-// BF16 MFMA GEMM: C[M][N] = sum_k A(m,k) B(k,n), FP32 accumulate.
-//   TA = false: A stored [M][K] (row stride lda); true: stored [K][M].
-//   TB = false: B stored [K][N] (row stride ldb); true: stored [N][K].
-// Tile 64 x 64 x GBK per 256-thread block; each wave owns a 32 x 32 sub-tile
-// and issues GBK / 16 v_mfma_f32_32x32x16_bf16 per K step.  Operands are staged
-// through LDS with k contiguous, so every MFMA fragment is one 16-byte LDS
-// read; two LDS buffers let the global loads of step i+1 (16 bytes per
-// thread and load, into registers) overlap the MFMAs of step i, with one
-// barrier per step.  A k-contiguous operand goes to LDS as 16-byte rows; an
-// operand contiguous along m or n is transposed on the way (eight 2-byte
-// LDS writes per load).
+// Network shape and the BF16 weight layouts the MFMA kernels read
 // ---------------------------------------------------------------------------
 
-#ifndef OPMM_GEMM_BK
-#define OPMM_GEMM_BK 64
-#endif
-enum Epi { EPI_F32 = 0, EPI_BIAS_RELU_BF16 = 1, EPI_BIAS_F32 = 2, EPI_RELU_MASK_BF16 = 3 };
+constexpr int NL = 4;
+constexpr int WIDTH[NL + 1] = {256, 512, 512, 256, 18};
+constexpr int NPAD[NL] = {512, 512, 256, 32};  // layer outputs padded to whole 32-column MFMA tiles
 
-constexpr int GBM = 64, GBN = 64, GBK = OPMM_GEMM_BK, GPAD = 8;
-constexpr int GROW = GBK + GPAD;  // LDS row length (elements), a multiple of 8 (16 bytes)
-constexpr int GCH = GBK / 32;     // 16-byte chunks per thread of one 64 x GBK operand tile
-
-typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
-
-// GCH 16-byte chunks per thread of a 64 (outer) x GBK (k) operand tile.  KC:
-// the operand is k-contiguous (rows = outer index); else rows are k.  Chunks
-// that leave the matrix, or all chunks when the rows are not 16-byte aligned
-// (vec false), are read element by element with zero fill.
-template <bool KC>
-__device__ __forceinline__ void tile_load(const uint16_t* __restrict__ X, int ld, int o0, int O, int k0, int kend,
-                                          bool vec, u32x4 v[GCH])
+// Each layer's weights exist twice in BF16, padded to NPAD columns with zeros, each in the order
+// the MFMA B fragments are read: for output tile t (32 columns) and contraction step s (16
+// indices) the 64 lanes' fragments (8 contraction indices of one column each) are 1 KB in a row,
+// so a wave's fragment load is one contiguous read.
+//   forward  WF_l: output = layer output n, contraction = layer input k;
+//   backward WB_l: output = layer input k, contraction = layer output n (the dX pass).
+__host__ __device__ constexpr int64_t wpack_off(int l)
 {
-    const int tid = threadIdx.x;
+    int64_t n = 0;
+    for (int i = 0; i < l; ++i) n += (int64_t)NPAD[i] * WIDTH[i];
+    return n;
+}
+constexpr int64_t NPACK = wpack_off(NL);
+
+// Position of W_l[k][n] in a fragment-ordered layout with `out` the output index (tile out / 32,
+// lane column out % 32) and `in` the contraction index (step in / 16, lane half (in % 16) / 8,
+// element in % 8); nsteps = contraction length / 16.
+__host__ __device__ __forceinline__ int64_t frag_index(int out, int in, int nsteps)
+{
+    return ((int64_t)((out >> 5) * nsteps + (in >> 4)) * 64 + (out & 31) + 32 * ((in & 15) >> 3)) * 8 + (in & 7);
+}
+__host__ __device__ __forceinline__ int64_t wf_index(int l, int k, int n)
+{
+    return wpack_off(l) + frag_index(n, k, WIDTH[l] / 16);
+}
+__host__ __device__ __forceinline__ int64_t wb_index(int l, int k, int n)
+{
+    return wpack_off(l) + frag_index(k, n, NPAD[l] / 16);
+}
+
+// ---------------------------------------------------------------------------
+// MFMA building blocks: v_mfma_f32_32x32x16_bf16, 64-wide waves.  Fragment
+// layout (checked against a CPU matmul): lane l supplies A row (l % 32) and B
+// column (l % 32), contraction indices 8 (l / 32) + 0..7; accumulator j of
+// lane l is row 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int acc_row(int j, int lane) { return 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3); }
+
+// NT 32-column tiles of a 32-row product  X[32][KC] . Bop, X in LDS (row stride xs elements), Bop a
+// fragment-ordered weight layout at Bg (global, L2-resident).  acc[t] is the tile whose first column is
+// n0[t].  The B fragments run PF contraction steps ahead in registers: the global latency hides behind
+// the MFMAs of the steps between.
+template <int KC, int NT>
+__device__ __forceinline__ void mma_rows32(const uint16_t* X, int xs, const uint16_t* __restrict__ Bg,
+                                           const int (&n0)[NT], floatx16 (&acc)[NT])
+{
+    constexpr int NS = KC / 16;
+    constexpr int PF = NS < 8 ? NS : 8;
+    const int lane = threadIdx.x & 63;
+    const uint16_t* xa = X + (lane & 31) * xs + 8 * (lane >> 5);
+    const uint16_t* bp[NT];
 #pragma unroll
-    for (int j = 0; j < GCH; ++j) {
-        const int c = tid + 256 * j;
-        // KC: GBK / 8 chunks per outer row; else 8 chunks per k row
-        const int r = KC ? c / (GBK / 8) : c >> 3, q = (KC ? c % (GBK / 8) : c & 7) * 8;
-        // KC: element i is (outer o0 + r, k k0 + q + i); else (k k0 + r, outer o0 + q + i)
-        const int ro = KC ? o0 + r : k0 + r;             // storage row
-        const int co = KC ? k0 + q : o0 + q;             // storage column of element 0
-        const int rlim = KC ? O : kend, clim = KC ? kend : O;
-        if (vec && ro < rlim && co + 8 <= clim) {
-            v[j] = *reinterpret_cast<const u32x4*>(X + (int64_t)ro * ld + co);
-        } else {
-            uint16_t e[8];
+    for (int t = 0; t < NT; ++t) {
+        bp[t] = Bg + ((int64_t)(n0[t] >> 5) * NS * 64 + lane) * 8;
+        acc[t] = floatx16{};
+    }
+    bf16x8 bq[PF][NT];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) e[i] = (ro < rlim && co + i < clim) ? X[(int64_t)ro * ld + co + i] : (uint16_t)0;
+    for (int i = 0; i < PF; ++i)
 #pragma unroll
-            for (int w = 0; w < 4; ++w) v[j][w] = (uint32_t)e[2 * w] | ((uint32_t)e[2 * w + 1] << 16);
+        for (int t = 0; t < NT; ++t) bq[i][t] = *reinterpret_cast<const bf16x8*>(bp[t] + 512 * i);
+    // the scheduling barriers keep each refill where it is written: left alone, the scheduler sinks the
+    // loads next to their MFMAs and only one or two stay in flight
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int ks = 0; ks < NS; ++ks) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(xa + 16 * ks);
+        bf16x8 b[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            b[t] = bq[ks % PF][t];
+            if (ks + PF < NS) bq[ks % PF][t] = *reinterpret_cast<const bf16x8*>(bp[t] + 512 * (ks + PF));
         }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b[t], acc[t], 0, 0, 0);
     }
 }
 
-// Writes the chunks of tile_load into S[outer][k].
-template <bool KC>
-__device__ __forceinline__ void tile_store(uint16_t (*S)[GROW], const u32x4 v[GCH])
+
+// ---------------------------------------------------------------------------
+// Fused network pass: one block of 8 waves per 32 batch rows, every layer's
+// activations in LDS.  Forward: H1..H3 = ReLU(H_l W_l + b_l) in BF16, output
+// H3 W3 + b3 in FP32.  TRAIN also takes the loss and back-propagates the
+// output gradient through the hidden layers (each gradient overwrites, in
+// place, the activation that gives its ReLU mask), and writes to global
+// memory what the weight-gradient kernel contracts over the batch: the
+// activations H1..H3 and the gradients G0..G3 of each layer's output
+// (G3 = dLoss/dOut padded to 32 columns, in BF16).
+// ---------------------------------------------------------------------------
+
+constexpr int FR = 32;       // batch rows per block
+constexpr int FTHREADS = 512;
+constexpr int XPAD = 8;      // LDS row padding (elements): rows shift by 16 bytes across banks
+
+struct MlpSmem {
+    uint16_t h0[FR][256 + XPAD];
+    uint16_t h1[FR][512 + XPAD];
+    uint16_t h2[FR][512 + XPAD];
+    uint16_t h3[FR][256 + XPAD];
+    uint16_t d3[FR][32 + XPAD];
+    float red[FTHREADS / 64];
+};
+
+struct MlpArgs {
+    int B;
+    int Bp;                 // (TRAIN) row stride of the transposed operands: B rounded up to DW_BK
+    const uint16_t* x0;     // [B][256]
+    const uint16_t* wf;     // forward layouts
+    const uint16_t* wbk;    // backward layouts
+    const float* w;         // FP32 parameters (biases read from here)
+    float* out;             // [B][18] (forward only), nullable in TRAIN
+    const float* target;    // [B][18] (TRAIN)
+    float* loss;            // (TRAIN) mean squared error added here
+    uint16_t* ht[NL];       // (TRAIN) layer inputs H_0 = x0 .. H_3, transposed: [WIDTH[l]][Bp], zero past B
+    uint16_t* gt[NL];       // (TRAIN) output gradients G_0 .. G_3, transposed: [NPAD[l]][Bp], zero past B
+};
+
+// Lane's four consecutive rows 8q + 4 (lane / 32) + 0..3 of accumulator group q (j = 4q .. 4q + 3) as
+// one 8-byte store into a transposed operand T[col][row0 + row] (rows past B written as zeros).
+__device__ __forceinline__ void store_t4(uint16_t* __restrict__ T, int64_t ld, int col, int row0, int B, int q,
+                                         int lane, const uint16_t (&h)[16])
 {
-    const int tid = threadIdx.x;
+    const int r = row0 + 8 * q + 4 * (lane >> 5);
+    uint32_t lo = 0, hi = 0;
+    if (r + 0 < B) lo |= (uint32_t)h[4 * q + 0];
+    if (r + 1 < B) lo |= (uint32_t)h[4 * q + 1] << 16;
+    if (r + 2 < B) hi |= (uint32_t)h[4 * q + 2];
+    if (r + 3 < B) hi |= (uint32_t)h[4 * q + 3] << 16;
+    *reinterpret_cast<uint2*>(T + (int64_t)col * ld + r) = make_uint2(lo, hi);
+}
+
+__host__ __device__ constexpr int64_t w_off_c(int l)
+{
+    int64_t n = 0;
+    for (int i = 0; i < l; ++i) n += (int64_t)WIDTH[i] * WIDTH[i + 1] + WIDTH[i + 1];
+    return n;
+}
+__host__ __device__ constexpr int64_t b_off_c(int l) { return w_off_c(l) + (int64_t)WIDTH[l] * WIDTH[l + 1]; }
+
+// One hidden layer forward: Y = ReLU(X W_l + b_l) for the block's 32 rows; HT (nullable): also the
+// transposed copy for the weight gradients.
+template <int K, int N>
+__device__ __forceinline__ void fwd_hidden(const uint16_t* X, int xs, uint16_t* Y, int ys, const uint16_t* wf,
+                                           const float* bias, uint16_t* HT, int ld, int row0, int B)
+{
+    constexpr int NT = N / 32 / (FTHREADS / 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int n0[NT];
 #pragma unroll
-    for (int j = 0; j < GCH; ++j) {
-        const int c = tid + 256 * j;
-        const int r = KC ? c / (GBK / 8) : c >> 3, q = (KC ? c % (GBK / 8) : c & 7) * 8;
-        if (KC) {
-            *reinterpret_cast<u32x4*>(&S[r][q]) = v[j];
-        } else {
+    for (int t = 0; t < NT; ++t) n0[t] = 32 * (wave + t * (FTHREADS / 64));
+    floatx16 acc[NT];
+    mma_rows32<K, NT>(X, xs, wf, n0, acc);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) S[q + i][r] = (uint16_t)(v[j][i >> 1] >> (16 * (i & 1)));
+    for (int t = 0; t < NT; ++t) {
+        const int col = n0[t] + (lane & 31);
+        const float bv = bias[col];
+        uint16_t h[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            h[j] = f2bf(fmaxf(acc[t][j] + bv, 0.0f));
+            Y[acc_row(j, lane) * ys + col] = h[j];
         }
+        if (HT)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) store_t4(HT, ld, col, row0, B, q, lane, h);
     }
 }
 
-template <bool TA, bool TB, int EPI>
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(int M, int N, int K, const uint16_t* __restrict__ A, int lda,
-                                                        const uint16_t* __restrict__ B, int ldb, void* C, int ldc,
-                                                        const float* __restrict__ bias,
-                                                        const uint16_t* __restrict__ mask, int ldm, int kchunk,
-                                                        float* __restrict__ colsum)
+// One backward step through hidden layer l: G_{l-1} = (G_l W_l^T) masked by H_l > 0, written over
+// H_l (which holds the mask) -- each element is read and written by the same lane -- and transposed
+// into GT.
+template <int KC, int N>
+__device__ __forceinline__ void bwd_hidden(const uint16_t* G, int gs, uint16_t* HM, int hs, const uint16_t* wbk,
+                                           uint16_t* GT, int ld, int row0, int B)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][GBM][GROW];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][GBN][GROW];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    floatx16 acc = {};
-    // split K: block z covers [z kchunk, (z+1) kchunk); with EPI_F32 it writes slice z of C
-    const int kbeg = blockIdx.z * kchunk;
-    const int kend = min(K, kbeg + kchunk);
-    if (EPI == EPI_F32) C = (float*)C + (int64_t)blockIdx.z * M * ldc;
-    const bool va = (lda % 8 == 0) && (((uintptr_t)A & 15) == 0);
-    const bool vb = (ldb % 8 == 0) && (((uintptr_t)B & 15) == 0);
-    u32x4 ra[GCH], rb[GCH];
-    // colsum (non-null): the first row of blocks also sums its B tiles over k, i.e. the column sums of
-    // B over this block's K range (the bias gradient when B is the output gradient)
-    const bool csum = colsum != nullptr && blockIdx.y == 0 && tid < 64;
-    float cs = 0.0f;
-    if (kbeg < kend) {
-        tile_load<!TA>(A, lda, m0, M, kbeg, kend, va, ra);
-        tile_load<TB>(B, ldb, n0, N, kbeg, kend, vb, rb);
-        tile_store<!TA>(As[0], ra);
-        tile_store<TB>(Bs[0], rb);
+    constexpr int NT = N / 32 / (FTHREADS / 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int n0[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) n0[t] = 32 * (wave + t * (FTHREADS / 64));
+    floatx16 acc[NT];
+    mma_rows32<KC, NT>(G, gs, wbk, n0, acc);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int col = n0[t] + (lane & 31);
+        uint16_t gv[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            uint16_t& h = HM[acc_row(j, lane) * hs + col];
+            gv[j] = h != 0 ? f2bf(acc[t][j]) : (uint16_t)0;
+            h = gv[j];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) store_t4(GT, ld, col, row0, B, q, lane, gv);
+    }
+}
+
+template <bool TRAIN>
+__global__ __launch_bounds__(FTHREADS) void mlp_pass_kernel(MlpArgs A)
+{
+    __shared__ __attribute__((aligned(16))) MlpSmem sm;
+    const int r0 = blockIdx.x * FR;
+    const int nrows = max(0, min(FR, A.B - r0));
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ld = A.Bp;
+    // stage the input rows (zeros past the batch)
+    for (int c = tid; c < FR * 32; c += FTHREADS) {
+        const int r = c >> 5, q = (c & 31) * 8;
+        u32x4_t v = {0u, 0u, 0u, 0u};
+        if (r < nrows) v = *reinterpret_cast<const u32x4_t*>(A.x0 + (int64_t)(r0 + r) * 256 + q);
+        *reinterpret_cast<u32x4_t*>(&sm.h0[r][q]) = v;
     }
     __syncthreads();
-    int cur = 0;
-    for (int k0 = kbeg; k0 < kend; k0 += GBK) {
-        const bool more = k0 + GBK < kend;
-        if (more) {
-            tile_load<!TA>(A, lda, m0, M, k0 + GBK, kend, va, ra);
-            tile_load<TB>(B, ldb, n0, N, k0 + GBK, kend, vb, rb);
-        }
+    if (TRAIN) {  // H_0 transposed: thread c takes feature c % 256, rows 8 (c / 256) .. + 7
+        for (int c = tid; c < 256 * 4; c += FTHREADS) {
+            const int f = c & 255, rq = (c >> 8) * 8;
+            uint32_t v[4];
 #pragma unroll
-        for (int ks = 0; ks < GBK; ks += 16) {
-            // lane l: A row (l % 32), k = 8 (l / 32) + 0..7; B col (l % 32), same k
+            for (int i = 0; i < 4; ++i) v[i] = (uint32_t)sm.h0[rq + 2 * i][f] | ((uint32_t)sm.h0[rq + 2 * i + 1][f] << 16);
+            *reinterpret_cast<u32x4_t*>(A.ht[0] + (int64_t)f * ld + r0 + rq) = u32x4_t{v[0], v[1], v[2], v[3]};
+        }
+    }
+    fwd_hidden<256, 512>(&sm.h0[0][0], 256 + XPAD, &sm.h1[0][0], 512 + XPAD, A.wf + wpack_off(0), A.w + b_off_c(0),
+                         TRAIN ? A.ht[1] : nullptr, ld, r0, A.B);
+    __syncthreads();
+    fwd_hidden<512, 512>(&sm.h1[0][0], 512 + XPAD, &sm.h2[0][0], 512 + XPAD, A.wf + wpack_off(1), A.w + b_off_c(1),
+                         TRAIN ? A.ht[2] : nullptr, ld, r0, A.B);
+    __syncthreads();
+    fwd_hidden<512, 256>(&sm.h2[0][0], 512 + XPAD, &sm.h3[0][0], 256 + XPAD, A.wf + wpack_off(2), A.w + b_off_c(2),
+                         TRAIN ? A.ht[3] : nullptr, ld, r0, A.B);
+    __syncthreads();
+    // output layer (one 32-column tile, 18 used): wave 0
+    if (wave == 0) {
+        int n0[1] = {0};
+        floatx16 acc[1];
+        mma_rows32<256, 1>(&sm.h3[0][0], 256 + XPAD, A.wf + wpack_off(3), n0, acc);
+        const int col = lane & 31;
+        const float bv = col < 18 ? A.w[b_off_c(3) + col] : 0.0f;
+        const float nf = (float)(A.B * 18);
+        float sq = 0.0f;
+        uint16_t gv[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int r = acc_row(j, lane);
+            const bool ok = r < nrows && col < 18;
+            const float o = acc[0][j] + bv;
+            if (!TRAIN) {
+                if (ok) A.out[(int64_t)(r0 + r) * 18 + col] = o;
+            } else {
+                float e = 0.0f;
+                if (ok) e = o - A.target[(int64_t)(r0 + r) * 18 + col];
+                sq += e * e;
+                gv[j] = ok ? f2bf(2.0f * e / nf) : (uint16_t)0;
+                sm.d3[r][col] = gv[j];
+            }
+        }
+        if (TRAIN) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) store_t4(A.gt[3], ld, col, r0, A.B, q, lane, gv);
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) sq += __shfl_xor(sq, o);
+            if (lane == 0) atomicAdd(A.loss, sq / nf);
+        }
+    }
+    if (!TRAIN) return;
+    __syncthreads();
+    // G2 = (G3 W3^T) . [H3 > 0]   (contraction over the 32 padded outputs)
+    bwd_hidden<32, 256>(&sm.d3[0][0], 32 + XPAD, &sm.h3[0][0], 256 + XPAD, A.wbk + wpack_off(3), A.gt[2], ld, r0, A.B);
+    __syncthreads();
+    // G1 = (G2 W2^T) . [H2 > 0]
+    bwd_hidden<256, 512>(&sm.h3[0][0], 256 + XPAD, &sm.h2[0][0], 512 + XPAD, A.wbk + wpack_off(2), A.gt[1], ld, r0,
+                         A.B);
+    __syncthreads();
+    // G0 = (G1 W1^T) . [H1 > 0]
+    bwd_hidden<512, 512>(&sm.h2[0][0], 512 + XPAD, &sm.h1[0][0], 512 + XPAD, A.wbk + wpack_off(1), A.gt[0], ld, r0,
+                         A.B);
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradients of all four layers in one launch: dW_l = H_l^T G_l, a
+// contraction over the batch, from the transposed operands the pass kernel
+// wrote (batch contiguous, zero past B up to Bp).  One 64 x 64 output tile per
+// block over the whole batch, so every gradient element is one fixed-order sum
+// (deterministic, no split); the first row of tiles also sums its G tiles:
+// the bias gradient.  DW_BK batch rows per step through two LDS buffers; the
+// loads of the next step are issued before this step's MFMAs.
+// ADAM: the block also takes the Adam step (adam_update) on its tile.
+// ---------------------------------------------------------------------------
+
+constexpr int DBM = 64, DBN = 64, DW_BK = 128, DROW = DW_BK + 8;
+constexpr int DW_CH = DBM * DW_BK / 8 / 256;  // 16-byte chunks per thread and operand tile
+constexpr int DW_TILES[NL] = {(256 / 64) * (512 / 64), (512 / 64) * (512 / 64), (512 / 64) * (256 / 64),
+                              (256 / 64) * 1};
+constexpr int DW_BLOCKS = DW_TILES[0] + DW_TILES[1] + DW_TILES[2] + DW_TILES[3];
+
+struct AdamArgs {
+    float lr, b1, om1, b2, om2, eps, c1, c2;
+};
+
+// Adam (Kingma & Ba 2015, Algorithm 1) on parameter i with gradient gi; weights (wl >= 0: weight of
+// layer wl at input row k, output column n) also refresh their two BF16 copies.
+__device__ __forceinline__ void adam_update(int64_t i, float gi, float* __restrict__ w, float* __restrict__ m1,
+                                            float* __restrict__ m2, const AdamArgs& a, uint16_t* __restrict__ wf,
+                                            uint16_t* __restrict__ wbk, int wl, int k, int n)
+{
+    float mm = a.b1 * m1[i] + a.om1 * gi;
+    float vv = a.b2 * m2[i] + a.om2 * (gi * gi);
+    m1[i] = mm;
+    m2[i] = vv;
+    float upd = (mm * a.c1) / (sqrtf(vv * a.c2) + a.eps);
+    float nw = w[i] - a.lr * upd;
+    w[i] = nw;
+    if (wl >= 0) {
+        const uint16_t h = f2bf(nw);
+        wf[wf_index(wl, k, n)] = h;
+        wbk[wb_index(wl, k, n)] = h;
+    }
+}
+
+// Rows o0 .. o0 + 63 (rows >= O read as zeros) and batch columns b0 .. b0 + DW_BK - 1 of a transposed
+// operand X [O][ld]: DW_CH 16-byte chunks per thread.
+__device__ __forceinline__ void dw_load(const uint16_t* __restrict__ X, int64_t ld, int O, int o0, int b0,
+                                        u32x4_t v[DW_CH])
+{
+#pragma unroll
+    for (int j = 0; j < DW_CH; ++j) {
+        const int c = threadIdx.x + 256 * j;
+        const int r = c / (DW_BK / 8), q = (c % (DW_BK / 8)) * 8;
+        v[j] = o0 + r < O ? *reinterpret_cast<const u32x4_t*>(X + (int64_t)(o0 + r) * ld + b0 + q)
+                          : u32x4_t{0u, 0u, 0u, 0u};
+    }
+}
+__device__ __forceinline__ void dw_store(uint16_t (*S)[DROW], const u32x4_t v[DW_CH])
+{
+#pragma unroll
+    for (int j = 0; j < DW_CH; ++j) {
+        const int c = threadIdx.x + 256 * j;
+        const int r = c / (DW_BK / 8), q = (c % (DW_BK / 8)) * 8;
+        *reinterpret_cast<u32x4_t*>(&S[r][q]) = v[j];
+    }
+}
+
+struct DwOperands {
+    const uint16_t* ht[NL];  // H_l^T [WIDTH[l]][Bp]
+    const uint16_t* gt[NL];  // G_l^T [NPAD[l]][Bp]
+};
+
+template <bool ADAM>
+__global__ __launch_bounds__(256) void mlp_dw_kernel(int Bp, DwOperands ops, float* __restrict__ g,
+                                                     float* __restrict__ w, float* __restrict__ m1,
+                                                     float* __restrict__ m2, uint16_t* __restrict__ wf,
+                                                     uint16_t* __restrict__ wbk, AdamArgs adam,
+                                                     uint64_t* __restrict__ step_counter)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][DBM][DROW];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][DBN][DROW];
+    // block -> (layer, tile); the largest layer first
+    int bid = blockIdx.x, l;
+    if (bid < DW_TILES[1]) l = 1;
+    else if ((bid -= DW_TILES[1]) < DW_TILES[0]) l = 0;
+    else if ((bid -= DW_TILES[0]) < DW_TILES[2]) l = 2;
+    else { bid -= DW_TILES[2]; l = 3; }
+    const int K = WIDTH[l], N = WIDTH[l + 1], NPd = NPAD[l];
+    const int ntn = (NPd + DBN - 1) / DBN;
+    const int m0 = (bid / ntn) * DBM, n0 = (bid % ntn) * DBN;
+    const uint16_t* H = ops.ht[l];
+    const uint16_t* G = ops.gt[l];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    floatx16 acc = {};
+    const bool csum = m0 == 0 && tid < 64;
+    float cs = 0.0f;
+    u32x4_t ra[DW_CH], rb[DW_CH];
+    dw_load(H, Bp, K, m0, 0, ra);
+    dw_load(G, Bp, NPd, n0, 0, rb);
+    dw_store(As[0], ra);
+    dw_store(Bs[0], rb);
+    __syncthreads();
+    int cur = 0;
+    for (int b0 = 0; b0 < Bp; b0 += DW_BK) {
+        const bool more = b0 + DW_BK < Bp;
+        if (more) {
+            dw_load(H, Bp, K, m0, b0 + DW_BK, ra);
+            dw_load(G, Bp, NPd, n0, b0 + DW_BK, rb);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
+#pragma unroll
+        for (int ks = 0; ks < DW_BK; ks += 16) {
             const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[cur][wm + (lane & 31)][ks + 8 * (lane >> 5)]);
             const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[cur][wn + (lane & 31)][ks + 8 * (lane >> 5)]);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
         }
         if (csum) {
 #pragma unroll
-            for (int kq = 0; kq < GBK; kq += 8) {
-                const u32x4 w = *reinterpret_cast<const u32x4*>(&Bs[cur][tid][kq]);
+            for (int kq = 0; kq < DW_BK; kq += 8) {
+                const u32x4_t v = *reinterpret_cast<const u32x4_t*>(&Bs[cur][tid][kq]);
 #pragma unroll
-                for (int i = 0; i < 8; ++i) cs += bf2f((uint16_t)(w[i >> 1] >> (16 * (i & 1))));
+                for (int i = 0; i < 8; ++i) cs += bf2f((uint16_t)(v[i >> 1] >> (16 * (i & 1))));
             }
         }
         if (more) {
-            tile_store<!TA>(As[cur ^ 1], ra);
-            tile_store<TB>(Bs[cur ^ 1], rb);
+            dw_store(As[cur ^ 1], ra);
+            dw_store(Bs[cur ^ 1], rb);
         }
         __syncthreads();
         cur ^= 1;
     }
-    if (csum && n0 + tid < N) colsum[(int64_t)blockIdx.z * N + n0 + tid] = cs;
-    // accumulator j of lane l holds row 8 (j / 4) + 4 (l / 32) + j % 4, column l % 32
+    // weights: element (m, n) of dW_l is parameter w_off(l) + m N + n
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const int m = m0 + wm + 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3);
+        const int m = m0 + wm + acc_row(j, lane);
         const int n = n0 + wn + (lane & 31);
-        if (m >= M || n >= N) continue;
-        float v = acc[j];
-        if (EPI == EPI_F32) {
-            ((float*)C)[(int64_t)m * ldc + n] = v;
-        } else if (EPI == EPI_BIAS_RELU_BF16) {
-            v = fmaxf(v + bias[n], 0.0f);
-            ((uint16_t*)C)[(int64_t)m * ldc + n] = f2bf(v);
-        } else if (EPI == EPI_BIAS_F32) {
-            ((float*)C)[(int64_t)m * ldc + n] = v + bias[n];
-        } else {  // backward through ReLU: the layer input was a post-ReLU activation
-            const bool on = mask[(int64_t)m * ldm + n] != 0;
-            ((uint16_t*)C)[(int64_t)m * ldc + n] = on ? f2bf(v) : (uint16_t)0;
-        }
+        if (m >= K || n >= N) continue;
+        const int64_t i = w_off_c(l) + (int64_t)m * N + n;
+        g[i] = acc[j];
+        if (ADAM) adam_update(i, acc[j], w, m1, m2, adam, wf, wbk, l, m, n);
     }
+    // biases: sums of G_l over the batch
+    if (csum && n0 + tid < N) {
+        const int64_t i = b_off_c(l) + n0 + tid;
+        g[i] = cs;
+        if (ADAM) adam_update(i, cs, w, m1, m2, adam, wf, wbk, -1, 0, 0);
+    }
+    if (ADAM && step_counter && blockIdx.x == 0 && tid == 0) *step_counter += 1;
 }
-
-// nsplit > 1 (EPI_F32 only): C holds nsplit slices [M][ldc] of partial sums over K.  colsum (nullable,
-// B stored [K][N]): [nsplit][N] column sums of B over each slice's K range.
-template <bool TA, bool TB, int EPI>
-hipError_t gemm(int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb, void* C, int ldc,
-                const float* bias, const uint16_t* mask, int ldm, hipStream_t st, int nsplit = 1,
-                float* colsum = nullptr)
-{
-    const int kchunk = (((K + nsplit - 1) / nsplit) + GBK - 1) / GBK * GBK;
-    dim3 grid((N + GBN - 1) / GBN, (M + GBM - 1) / GBM, nsplit);
-    hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc, bias,
-                       mask, ldm, kchunk, colsum);
-    return hipGetLastError();
-}
-
-// Deterministic split-K reduction of a layer's gradients, slices summed in z order:
-// out[i] = sum_z wparts[z][i] for i < nw (weights), out[nw + j] = sum_z bparts[z][j] for
-// j < nb (the bias, stored right after the weights).
-__global__ void splitk_sum_kernel(int64_t nw, int nb, int nsplit, const float* __restrict__ wparts,
-                                  const float* __restrict__ bparts, float* __restrict__ out)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nw + nb) return;
-    const bool w = i < nw;
-    const float* src = w ? wparts + i : bparts + (i - nw);
-    const int64_t stride = w ? nw : nb;
-    float a = 0.0f;
-    for (int z = 0; z < nsplit; ++z) a += src[(int64_t)z * stride];
-    out[i] = a;
-}
-
-constexpr int SPLITK_ROWS = 512;  // batch rows per split of the weight-gradient GEMM
-constexpr int SPLITK_MAX = 16;
 
 // ---------------------------------------------------------------------------
 // Network state
 // ---------------------------------------------------------------------------
 
-constexpr int NL = 4;
-constexpr int WIDTH[NL + 1] = {256, 512, 512, 256, 18};
 constexpr int NPTS = 128;        // resampled points
 constexpr float FEAT_POS = 1.0f / 16.0f;  // feature scale of position (deg)
 constexpr float FEAT_VEL = 4.0f;          // feature scale of velocity (deg/ms)
 constexpr float ZSCALE = 0.3f;            // z = (p/p_nom - 1) / ZSCALE
 
-constexpr int64_t param_count()
-{
-    int64_t n = 0;
-    for (int l = 0; l < NL; ++l) n += (int64_t)WIDTH[l] * WIDTH[l + 1] + WIDTH[l + 1];
-    return n;
-}
-constexpr int64_t NPARAM = param_count();
-
-int64_t w_off(int l)
-{
-    int64_t n = 0;
-    for (int i = 0; i < l; ++i) n += (int64_t)WIDTH[i] * WIDTH[i + 1] + WIDTH[i + 1];
-    return n;
-}
-int64_t b_off(int l) { return w_off(l) + (int64_t)WIDTH[l] * WIDTH[l + 1]; }
+constexpr int64_t NPARAM = w_off_c(NL);
 
 }  // namespace
 
@@ -263,22 +497,19 @@ struct opmm_surrogate {
     int64_t step = 0;  // Adam steps taken
     // parameters: [W0 (256x512), b0, W1, b1, W2, b2, W3, b3], W_l stored [in][out]
     float* w = nullptr;       // FP32 master
-    uint16_t* wb = nullptr;   // BF16 copy used by the GEMMs
     float* g = nullptr;       // gradients
     float* m1 = nullptr;      // Adam first moment
     float* m2 = nullptr;      // Adam second moment
-    // activations for cap_batch rows
-    uint16_t* act[NL] = {};   // act[0] = input features, act[l] = output of hidden layer l (post-ReLU)
-    float* out = nullptr;     // [B][18]
-    uint16_t* dact[NL] = {};  // gradient w.r.t. act[l] (l >= 1) and w.r.t. the output (index 0 reused)
-    float* target = nullptr;  // [B][18]
+    uint16_t* wf = nullptr;   // BF16 weights, forward layout (NPACK)
+    uint16_t* wbk = nullptr;  // BF16 weights, backward layout (NPACK)
+    // per batch row (cap_batch rows; the transposed operands padded to whole DW_BK rows)
+    uint16_t* ht[NL] = {};    // layer inputs H_0..H_3, transposed [WIDTH[l]][rows]
+    uint16_t* gt[NL] = {};    // gradients of the layer outputs G_0..G_3, transposed [NPAD[l]][rows]
+    uint16_t* x0 = nullptr;   // features of a predicted batch [256]
+    float* out = nullptr;     // network outputs [18]
     float* loss = nullptr;    // [1]
     float* trace = nullptr;   // [B][MAX_T_GEN] generated traces
-    int32_t* tlen = nullptr;  // [B]
-    float* dur = nullptr;     // [B]
     uint64_t* counter = nullptr;  // device step counter for data generation (graph-replay safe)
-    float* gpart = nullptr;       // split-K partial weight gradients [SPLITK_MAX][512 x 512]
-    float* cpart = nullptr;       // split-K partial bias gradients [SPLITK_MAX][512]
     // training data ring: GEN_BATCHES consecutive batches generated in one launch
     uint16_t* ring_feat = nullptr;  // [GEN_BATCHES][ring_cap][256]
     float* ring_tgt = nullptr;      // [GEN_BATCHES][ring_cap][18]
@@ -297,12 +528,20 @@ __global__ void fill_f32_kernel(float* p, int64_t n, float v)
     if (i < n) p[i] = v;
 }
 
-__global__ void to_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst, int64_t n)
+// FP32 master weights -> both BF16 layouts (zero padding included), one packed element per thread.
+__global__ void pack_weights_kernel(const float* __restrict__ w, uint16_t* __restrict__ wf, uint16_t* __restrict__ wbk)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = f2bf(src[i]);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPACK) return;
+    int l = 0;
+    while (l < NL - 1 && i >= wpack_off(l + 1)) ++l;
+    const int64_t off = i - wpack_off(l);
+    const int K = WIDTH[l], N = WIDTH[l + 1];
+    const int n = (int)(off / K), k = (int)(off % K);
+    const uint16_t h = n < N ? f2bf(w[w_off_c(l) + (int64_t)k * N + n]) : (uint16_t)0;
+    wf[wf_index(l, k, n)] = h;
+    wbk[wb_index(l, k, n)] = h;
 }
-
 // He-uniform initialisation from the SplitMix64 stream; biases zero.
 __global__ void init_params_kernel(float* w, uint64_t seed)
 {
@@ -426,52 +665,22 @@ __global__ __launch_bounds__(64) void gen_batch_kernel(int B, uint64_t seed, con
     trace_features(tr, T, 1.0f, feat + (int64_t)ii * (2 * NPTS));
 }
 
-// Output gradient of the MSE loss; loss accumulated (mean over B x 18).
-__global__ void mse_grad_kernel(int B, const float* __restrict__ out, const float* __restrict__ target,
-                                uint16_t* __restrict__ dout, float* __restrict__ loss)
+// Adam step over every parameter on the stored gradients (the same update the fused weight-gradient
+// kernel applies); b1, b2 and their complements om1 = 1 - b1, om2 = 1 - b2 are each the FP32 value
+// nearest the exact constant, and c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t) are formed on the host in
+// FP64: 1 - b2^t taken in FP32 loses about five digits to cancellation in the first steps.
+__global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m1,
+                            float* __restrict__ m2, uint16_t* __restrict__ wf, uint16_t* __restrict__ wbk,
+                            AdamArgs a)
 {
-    __shared__ float red[256];
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int n = B * P;
-    float e = 0.0f;
-    if (i < n) {
-        e = out[i] - target[i];
-        dout[i] = f2bf(2.0f * e / (float)n);
-    }
-    red[threadIdx.x] = e * e;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicAdd(loss, red[0] / (float)n);
-}
-
-// Adam (Kingma & Ba 2015, Algorithm 1) on the FP32 master weights, with a BF16
-// copy for the GEMMs.  b1, b2 and their complements om1 = 1 - b1, om2 = 1 - b2
-// are each the FP32 value nearest the exact constant, and c1 = 1 / (1 - b1^t),
-// c2 = 1 / (1 - b2^t) are formed on the host in FP64: 1 - b2^t taken in FP32
-// loses about five digits to cancellation in the first steps.
-__global__ void adam_kernel(int64_t n, float* __restrict__ w, uint16_t* __restrict__ wb, const float* __restrict__ g,
-                            float* __restrict__ m1, float* __restrict__ m2, float lr, float b1, float om1, float b2,
-                            float om2, float eps, float c1, float c2)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float gi = g[i];
-    float a = b1 * m1[i] + om1 * gi;
-    float v = b2 * m2[i] + om2 * (gi * gi);
-    m1[i] = a;
-    m2[i] = v;
-    float upd = (a * c1) / (sqrtf(v * c2) + eps);
-    float nw = w[i] - lr * upd;
-    w[i] = nw;
-    wb[i] = f2bf(nw);
-}
-
-__global__ void bump_kernel(uint64_t* c)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) *c += 1;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPARAM) return;
+    int l = 0;
+    while (l < NL - 1 && i >= w_off_c(l + 1)) ++l;
+    const int64_t off = i - w_off_c(l);
+    const int N = WIDTH[l + 1];
+    const bool is_w = i < b_off_c(l);
+    adam_update(i, g[i], w, m1, m2, a, wf, wbk, is_w ? l : -1, is_w ? (int)(off / N) : 0, is_w ? (int)(off % N) : 0);
 }
 
 // z (network output) -> OPC seed, clamped into the search box of the saccade
@@ -528,23 +737,22 @@ int sg_alloc(opmm_surrogate* sg, int batch)
     if (batch <= sg->cap_batch) return OPMM_OK;
     SG_HIP(hipDeviceSynchronize());
     for (int l = 0; l < NL; ++l) {
-        if (sg->act[l]) (void)hipFree(sg->act[l]);
-        if (sg->dact[l]) (void)hipFree(sg->dact[l]);
-        sg->act[l] = sg->dact[l] = nullptr;
+        if (sg->ht[l]) (void)hipFree(sg->ht[l]);
+        if (sg->gt[l]) (void)hipFree(sg->gt[l]);
+        sg->ht[l] = sg->gt[l] = nullptr;
     }
-    for (void* p : {(void*)sg->out, (void*)sg->target, (void*)sg->trace, (void*)sg->tlen, (void*)sg->dur})
+    for (void* p : {(void*)sg->x0, (void*)sg->out, (void*)sg->trace})
         if (p) (void)hipFree(p);
+    sg->x0 = nullptr;
+    sg->out = sg->trace = nullptr;
+    const size_t rows = (size_t)(batch + DW_BK - 1) / DW_BK * DW_BK;
     for (int l = 0; l < NL; ++l) {
-        SG_HIP(hipMalloc(&sg->act[l], sizeof(uint16_t) * (size_t)batch * WIDTH[l]));
-        SG_HIP(hipMalloc(&sg->dact[l], sizeof(uint16_t) * (size_t)batch * (l == 0 ? WIDTH[NL] : WIDTH[l])));
+        SG_HIP(hipMalloc(&sg->ht[l], sizeof(uint16_t) * rows * WIDTH[l]));
+        SG_HIP(hipMalloc(&sg->gt[l], sizeof(uint16_t) * rows * NPAD[l]));
     }
+    SG_HIP(hipMalloc(&sg->x0, sizeof(uint16_t) * (size_t)batch * WIDTH[0]));
     SG_HIP(hipMalloc(&sg->out, sizeof(float) * (size_t)batch * WIDTH[NL]));
-    SG_HIP(hipMalloc(&sg->target, sizeof(float) * (size_t)batch * WIDTH[NL]));
     SG_HIP(hipMalloc(&sg->trace, sizeof(float) * (size_t)batch * MAX_T_GEN));
-    SG_HIP(hipMalloc(&sg->tlen, sizeof(int32_t) * (size_t)batch));
-    SG_HIP(hipMalloc(&sg->dur, sizeof(float) * (size_t)batch));
-    if (!sg->gpart) SG_HIP(hipMalloc(&sg->gpart, sizeof(float) * (size_t)SPLITK_MAX * 512 * 512));
-    if (!sg->cpart) SG_HIP(hipMalloc(&sg->cpart, sizeof(float) * (size_t)SPLITK_MAX * 512));
     sg->cap_batch = batch;
     return OPMM_OK;
 }
@@ -557,65 +765,86 @@ int surrogate_reserve(opmm_surrogate* sg, int batch) { return sg_alloc(sg, batch
 
 namespace {
 
-// forward pass over the B rows of x0 (features); output in sg->out
-int sg_forward(opmm_surrogate* sg, int B, const uint16_t* x0, hipStream_t st)
+MlpArgs mlp_args(opmm_surrogate* sg, int B, const uint16_t* x0)
 {
+    MlpArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.B = B;
+    A.x0 = x0;
+    A.wf = sg->wf;
+    A.wbk = sg->wbk;
+    A.w = sg->w;
+    A.Bp = (B + DW_BK - 1) / DW_BK * DW_BK;
     for (int l = 0; l < NL; ++l) {
-        const uint16_t* W = sg->wb + w_off(l);
-        const float* bias = sg->w + b_off(l);
-        const int K = WIDTH[l], N = WIDTH[l + 1];
-        hipError_t e;
-        if (l < NL - 1)
-            e = gemm<false, false, EPI_BIAS_RELU_BF16>(B, N, K, l == 0 ? x0 : sg->act[l], K, W, N, sg->act[l + 1], N,
-                                                       bias, nullptr, 0, st);
-        else
-            e = gemm<false, false, EPI_BIAS_F32>(B, N, K, l == 0 ? x0 : sg->act[l], K, W, N, sg->out, N, bias, nullptr,
-                                                 0, st);
-        if (e != hipSuccess) return opmm_rt::hip_fail(sg->ctx, e, "gemm forward");
+        A.ht[l] = sg->ht[l];
+        A.gt[l] = sg->gt[l];
     }
+    return A;
+}
+
+// network outputs of the B rows of x0 into out [B][18]: one launch
+int sg_forward(opmm_surrogate* sg, int B, const uint16_t* x0, float* out, hipStream_t st)
+{
+    MlpArgs A = mlp_args(sg, B, x0);
+    A.out = out;
+    hipLaunchKernelGGL(mlp_pass_kernel<false>, dim3((B + FR - 1) / FR), dim3(FTHREADS), 0, st, A);
+    SG_HIP(hipGetLastError());
     return OPMM_OK;
 }
 
-// backward pass after sg_forward on x0, against tgt [B][18]; gradients into sg->g
-// loss: device scalar the MSE is accumulated into (zeroed by the caller)
-int sg_backward(opmm_surrogate* sg, int B, const uint16_t* x0, const float* tgt, float* loss, hipStream_t st)
+AdamArgs adam_args(opmm_surrogate* sg, float lr)
 {
-    const int NO = WIDTH[NL];
-    hipLaunchKernelGGL(mse_grad_kernel, dim3(blocks((int64_t)B * NO, 256)), dim3(256), 0, st, B, sg->out, tgt,
-                       sg->dact[0], loss);
-    for (int l = NL - 1; l >= 0; --l) {
-        const int K = WIDTH[l], N = WIDTH[l + 1];
-        const uint16_t* dy = (l == NL - 1) ? sg->dact[0] : sg->dact[l + 1];
-        // dW_l = act[l]^T . dY   ([K][B] x [B][N]): the batch is the long contraction, split it so
-        // that a 512 x 512 gradient fills the chip, then sum the slices in a fixed order
-        const int nsplit = std::min(SPLITK_MAX, std::max(1, (B + SPLITK_ROWS - 1) / SPLITK_ROWS));
-        // the bias gradient (column sums of dY) comes out of the same GEMM
-        hipError_t e = gemm<true, false, EPI_F32>(K, N, B, l == 0 ? x0 : sg->act[l], K, dy, N,
-                                                  nsplit > 1 ? sg->gpart : sg->g + w_off(l),
-                                                  N, nullptr, nullptr, 0, st, nsplit,
-                                                  nsplit > 1 ? sg->cpart : sg->g + b_off(l));
-        if (e != hipSuccess) return opmm_rt::hip_fail(sg->ctx, e, "gemm dW");
-        if (nsplit > 1)
-            hipLaunchKernelGGL(splitk_sum_kernel, dim3(blocks((int64_t)K * N + N, 256)), dim3(256), 0, st,
-                               (int64_t)K * N, N, nsplit, sg->gpart, sg->cpart, sg->g + w_off(l));
-        if (l > 0) {
-            // dX_l = (dY . W_l^T) masked by act[l] > 0   ([B][N] x [N][K])
-            e = gemm<false, true, EPI_RELU_MASK_BF16>(B, K, N, dy, N, sg->wb + w_off(l), N, sg->dact[l], K, nullptr,
-                                                      sg->act[l], K, st);
-            if (e != hipSuccess) return opmm_rt::hip_fail(sg->ctx, e, "gemm dX");
-        }
+    const double b1 = 0.9, b2 = 0.999;
+    sg->step += 1;
+    AdamArgs a;
+    a.lr = lr;
+    a.b1 = (float)b1;
+    a.om1 = (float)(1.0 - b1);
+    a.b2 = (float)b2;
+    a.om2 = (float)(1.0 - b2);
+    a.eps = 1e-8f;
+    a.c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)sg->step)));
+    a.c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)sg->step)));
+    return a;
+}
+
+// Forward, MSE against tgt [B][18] (added to *loss, zeroed by the caller) and backward over the B
+// rows of x0: gradients into sg->g.  ADAM: also the Adam step with learning rate lr, and one bump of
+// the data-generation counter.  Two launches.
+template <bool ADAM>
+int sg_step(opmm_surrogate* sg, int B, const uint16_t* x0, const float* tgt, float* loss, float lr, hipStream_t st)
+{
+    MlpArgs A = mlp_args(sg, B, x0);
+    A.target = tgt;
+    A.loss = loss;
+    // blocks up to Bp: those past the batch write the zero rows of the transposed operands
+    hipLaunchKernelGGL(mlp_pass_kernel<true>, dim3(A.Bp / FR), dim3(FTHREADS), 0, st, A);
+    SG_HIP(hipGetLastError());
+    DwOperands ops;
+    for (int l = 0; l < NL; ++l) {
+        ops.ht[l] = sg->ht[l];
+        ops.gt[l] = sg->gt[l];
     }
+    AdamArgs a;
+    std::memset(&a, 0, sizeof a);
+    if (ADAM) a = adam_args(sg, lr);
+    hipLaunchKernelGGL(mlp_dw_kernel<ADAM>, dim3(DW_BLOCKS), dim3(256), 0, st, A.Bp, ops, sg->g, sg->w, sg->m1, sg->m2,
+                       sg->wf, sg->wbk, a, ADAM ? sg->counter : nullptr);
+    SG_HIP(hipGetLastError());
     return OPMM_OK;
 }
 
 int sg_adam(opmm_surrogate* sg, float lr, hipStream_t st)
 {
-    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
-    sg->step += 1;
-    const float c1 = (float)(1.0 / (1.0 - std::pow(b1, (double)sg->step)));
-    const float c2 = (float)(1.0 / (1.0 - std::pow(b2, (double)sg->step)));
-    hipLaunchKernelGGL(adam_kernel, dim3(blocks(NPARAM, 256)), dim3(256), 0, st, NPARAM, sg->w, sg->wb, sg->g, sg->m1,
-                       sg->m2, lr, (float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), (float)eps, c1, c2);
+    const AdamArgs a = adam_args(sg, lr);
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks(NPARAM, 256)), dim3(256), 0, st, sg->w, sg->g, sg->m1, sg->m2, sg->wf,
+                       sg->wbk, a);
+    return hipGetLastError() == hipSuccess ? OPMM_OK : OPMM_EDEVICE;
+}
+
+int sg_pack(opmm_surrogate* sg, hipStream_t st)
+{
+    hipLaunchKernelGGL(pack_weights_kernel, dim3(blocks(NPACK, 256)), dim3(256), 0, st, sg->w, sg->wf, sg->wbk);
     return hipGetLastError() == hipSuccess ? OPMM_OK : OPMM_EDEVICE;
 }
 
@@ -635,16 +864,17 @@ int opmm_surrogate_create(opmm_ctx* ctx, uint64_t init_seed, opmm_surrogate** ou
     int rc = OPMM_OK;
     if (hipMalloc(&sg->w, sizeof(float) * NPARAM) != hipSuccess || hipMalloc(&sg->g, sizeof(float) * NPARAM) != hipSuccess ||
         hipMalloc(&sg->m1, sizeof(float) * NPARAM) != hipSuccess || hipMalloc(&sg->m2, sizeof(float) * NPARAM) != hipSuccess ||
-        hipMalloc(&sg->wb, sizeof(uint16_t) * NPARAM) != hipSuccess || hipMalloc(&sg->loss, sizeof(float)) != hipSuccess ||
+        hipMalloc(&sg->wf, sizeof(uint16_t) * NPACK) != hipSuccess ||
+        hipMalloc(&sg->wbk, sizeof(uint16_t) * NPACK) != hipSuccess || hipMalloc(&sg->loss, sizeof(float)) != hipSuccess ||
         hipMalloc(&sg->counter, sizeof(uint64_t)) != hipSuccess)
         rc = OPMM_ENOMEM;
     if (rc == OPMM_OK) {
         hipLaunchKernelGGL(init_params_kernel, dim3(blocks(NPARAM, 256)), dim3(256), 0, 0, sg->w, init_seed);
-        hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(NPARAM, 256)), dim3(256), 0, 0, sg->w, sg->wb, NPARAM);
         hipLaunchKernelGGL(fill_f32_kernel, dim3(blocks(NPARAM, 256)), dim3(256), 0, 0, sg->m1, NPARAM, 0.0f);
         hipLaunchKernelGGL(fill_f32_kernel, dim3(blocks(NPARAM, 256)), dim3(256), 0, 0, sg->m2, NPARAM, 0.0f);
         hipLaunchKernelGGL(fill_f32_kernel, dim3(blocks(NPARAM, 256)), dim3(256), 0, 0, sg->g, NPARAM, 0.0f);
-        if (hipMemset(sg->counter, 0, sizeof(uint64_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        if (sg_pack(sg, 0) != OPMM_OK || hipMemset(sg->counter, 0, sizeof(uint64_t)) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess)
             rc = OPMM_EDEVICE;
     }
     if (rc != OPMM_OK) {
@@ -661,13 +891,12 @@ int opmm_surrogate_destroy(opmm_surrogate* sg)
     (void)hipSetDevice(sg->device);
     (void)hipDeviceSynchronize();
     for (int l = 0; l < NL; ++l) {
-        if (sg->act[l]) (void)hipFree(sg->act[l]);
-        if (sg->dact[l]) (void)hipFree(sg->dact[l]);
+        if (sg->ht[l]) (void)hipFree(sg->ht[l]);
+        if (sg->gt[l]) (void)hipFree(sg->gt[l]);
     }
-    for (void* p : {(void*)sg->w, (void*)sg->wb, (void*)sg->g, (void*)sg->m1, (void*)sg->m2, (void*)sg->out,
-                    (void*)sg->target, (void*)sg->loss, (void*)sg->trace, (void*)sg->tlen, (void*)sg->dur,
-                    (void*)sg->counter, (void*)sg->gpart, (void*)sg->cpart, (void*)sg->ring_feat,
-                    (void*)sg->ring_tgt, (void*)sg->ring_trace})
+    for (void* p : {(void*)sg->w, (void*)sg->g, (void*)sg->m1, (void*)sg->m2, (void*)sg->wf, (void*)sg->wbk,
+                    (void*)sg->x0, (void*)sg->out, (void*)sg->loss, (void*)sg->trace, (void*)sg->counter,
+                    (void*)sg->ring_feat, (void*)sg->ring_tgt, (void*)sg->ring_trace})
         if (p) (void)hipFree(p);
     delete sg;
     return OPMM_OK;
@@ -692,7 +921,7 @@ int opmm_surrogate_set_params(opmm_surrogate* sg, const float* host_w)
     SG_HIP(hipSetDevice(sg->device));
     SG_HIP(hipDeviceSynchronize());
     SG_HIP(hipMemcpy(sg->w, host_w, sizeof(float) * NPARAM, hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(NPARAM, 256)), dim3(256), 0, 0, sg->w, sg->wb, NPARAM);
+    if (sg_pack(sg, 0) != OPMM_OK) return opmm_rt::fail(sg->ctx, OPMM_EDEVICE, "weight packing failed");
     SG_HIP(hipDeviceSynchronize());
     return OPMM_OK;
 }
@@ -702,13 +931,7 @@ int opmm_surrogate_forward(opmm_surrogate* sg, const uint16_t* feat, int32_t B, 
     if (!sg || B < 0 || (B > 0 && (!feat || !out))) return OPMM_EINVAL;
     if (B == 0) return OPMM_OK;
     SG_HIP(hipSetDevice(sg->device));
-    hipStream_t st = (hipStream_t)stream;
-    int rc;
-    if ((rc = sg_alloc(sg, B)) != OPMM_OK) return rc;
-    SG_HIP(hipMemcpyAsync(sg->act[0], feat, sizeof(uint16_t) * (size_t)B * WIDTH[0], hipMemcpyDeviceToDevice, st));
-    if ((rc = sg_forward(sg, B, sg->act[0], st)) != OPMM_OK) return rc;
-    SG_HIP(hipMemcpyAsync(out, sg->out, sizeof(float) * (size_t)B * WIDTH[NL], hipMemcpyDeviceToDevice, st));
-    return OPMM_OK;
+    return sg_forward(sg, B, feat, out, (hipStream_t)stream);
 }
 
 int opmm_surrogate_backward(opmm_surrogate* sg, const uint16_t* feat, const float* target, int32_t B, float* loss_out,
@@ -719,11 +942,8 @@ int opmm_surrogate_backward(opmm_surrogate* sg, const uint16_t* feat, const floa
     hipStream_t st = (hipStream_t)stream;
     int rc;
     if ((rc = sg_alloc(sg, B)) != OPMM_OK) return rc;
-    SG_HIP(hipMemcpyAsync(sg->act[0], feat, sizeof(uint16_t) * (size_t)B * WIDTH[0], hipMemcpyDeviceToDevice, st));
-    SG_HIP(hipMemcpyAsync(sg->target, target, sizeof(float) * (size_t)B * WIDTH[NL], hipMemcpyDeviceToDevice, st));
     hipLaunchKernelGGL(fill_f32_kernel, dim3(1), dim3(64), 0, st, sg->loss, 1, 0.0f);
-    if ((rc = sg_forward(sg, B, sg->act[0], st)) != OPMM_OK) return rc;
-    if ((rc = sg_backward(sg, B, sg->act[0], sg->target, sg->loss, st)) != OPMM_OK) return rc;
+    if ((rc = sg_step<false>(sg, B, feat, target, sg->loss, 0.0f, st)) != OPMM_OK) return rc;
     if (loss_out) {
         SG_HIP(hipMemcpyAsync(loss_out, sg->loss, sizeof(float), hipMemcpyDeviceToHost, st));
         SG_HIP(hipStreamSynchronize(st));
@@ -783,13 +1003,11 @@ int opmm_surrogate_train(opmm_surrogate* sg, uint64_t data_seed, int32_t B, int3
                                sg->ring_tgt);
         const uint16_t* x0 = sg->ring_feat + (size_t)j * B * WIDTH[0];
         const float* tgt = sg->ring_tgt + (size_t)j * B * WIDTH[NL];
-        if ((rc = sg_forward(sg, B, x0, st)) != OPMM_OK) break;
-        if ((rc = sg_backward(sg, B, x0, tgt, hist + t, st)) != OPMM_OK) break;
         // cosine decay from lr0 to lr_min over this call's steps
         const double ph = n_steps > 1 ? (double)t / (double)(n_steps - 1) : 1.0;
         const float lr = (float)(lr_min + 0.5 * (lr0 - lr_min) * (1.0 + std::cos(M_PI * ph)));
-        if ((rc = sg_adam(sg, lr, st)) != OPMM_OK) break;
-        hipLaunchKernelGGL(bump_kernel, dim3(1), dim3(64), 0, st, sg->counter);
+        // forward + loss + backward + Adam (and the counter bump): two launches
+        rc = sg_step<true>(sg, B, x0, tgt, hist + t, lr, st);
     }
     if (rc == OPMM_OK && loss_out && n_steps > 0)
         rc = hipMemcpyAsync(loss_out, hist, sizeof(float) * (size_t)n_steps, hipMemcpyDeviceToHost, st) == hipSuccess
@@ -816,8 +1034,8 @@ static int sg_predict(opmm_surrogate* sg, int32_t S, const opmm_rt::SacDev* sd, 
 {
     int rc;
     if ((rc = sg_alloc(sg, S)) != OPMM_OK) return rc;
-    hipLaunchKernelGGL(features_kernel, dim3(S), dim3(64), 0, st, S, sd, proj, dt_ms, sg->act[0]);
-    if ((rc = sg_forward(sg, S, sg->act[0], st)) != OPMM_OK) return rc;
+    hipLaunchKernelGGL(features_kernel, dim3(S), dim3(64), 0, st, S, sd, proj, dt_ms, sg->x0);
+    if ((rc = sg_forward(sg, S, sg->x0, sg->out, st)) != OPMM_OK) return rc;
     hipLaunchKernelGGL(denorm_kernel, dim3(blocks((int64_t)S * P, 256)), dim3(256), 0, st, S, sg->out, sd, box_frac,
                        opc_out);
     SG_HIP(hipGetLastError());
@@ -974,7 +1192,7 @@ int opmm_surrogate_load(opmm_surrogate* sg, const char* path)
     SG_HIP(hipMemcpy(sg->w, buf.data(), sizeof(float) * NPARAM, hipMemcpyHostToDevice));
     SG_HIP(hipMemcpy(sg->m1, buf.data() + NPARAM, sizeof(float) * NPARAM, hipMemcpyHostToDevice));
     SG_HIP(hipMemcpy(sg->m2, buf.data() + 2 * NPARAM, sizeof(float) * NPARAM, hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks(NPARAM, 256)), dim3(256), 0, 0, sg->w, sg->wb, NPARAM);
+    if (sg_pack(sg, 0) != OPMM_OK) return opmm_rt::fail(sg->ctx, OPMM_EDEVICE, "weight packing failed");
     SG_HIP(hipDeviceSynchronize());
     sg->step = hdr[1];
     return OPMM_OK;
