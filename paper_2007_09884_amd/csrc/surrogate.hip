@@ -89,39 +89,57 @@ __host__ __device__ __forceinline__ int64_t wb_index(int l, int k, int n)
 __device__ __forceinline__ int acc_row(int j, int lane) { return 8 * (j >> 2) + 4 * (lane >> 5) + (j & 3); }
 
 // NT 32-column tiles of a 32-row product  X[32][KC] . Bop, X in LDS (row stride xs elements), Bop a
-// fragment-ordered weight layout at Bg (global, L2-resident).  acc[t] is the tile whose first column is
-// n0[t].  The B fragments run PF contraction steps ahead in registers: the global latency hides behind
-// the MFMAs of the steps between.
+// fragment-ordered weight layout in global memory (L2-resident).  The B fragments run PF contraction
+// steps ahead in registers (a Ring): the global latency hides behind the MFMAs of the steps between.
+// A ring is started, i.e. its first PF fragments requested, before the product that uses it, so a
+// layer's first loads overlap the previous layer's epilogue and barrier.
+#ifndef OPMM_MLP_PF
+#define OPMM_MLP_PF 8  // contraction steps of B fragments in flight per product
+#endif
+
 template <int KC, int NT>
-__device__ __forceinline__ void mma_rows32(const uint16_t* X, int xs, const uint16_t* __restrict__ Bg,
-                                           const int (&n0)[NT], floatx16 (&acc)[NT])
+struct Ring {
+    static constexpr int NS = KC / 16;
+    static constexpr int PF = NS < OPMM_MLP_PF ? NS : OPMM_MLP_PF;
+    const uint16_t* bp[NT];
+    bf16x8 q[PF][NT];
+    __device__ __forceinline__ void start(const uint16_t* __restrict__ Bg, const int (&n0)[NT])
+    {
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bp[t] = Bg + ((int64_t)(n0[t] >> 5) * NS * 64 + lane) * 8;
+#pragma unroll
+        for (int i = 0; i < PF; ++i)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) q[i][t] = *reinterpret_cast<const bf16x8*>(bp[t] + 512 * i);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+};
+
+template <int KC, int NT>
+__device__ __forceinline__ void mma_rows32(const uint16_t* X, int xs, Ring<KC, NT>& r, floatx16 (&acc)[NT])
 {
-    constexpr int NS = KC / 16;
-    constexpr int PF = NS < 8 ? NS : 8;
+    constexpr int NS = Ring<KC, NT>::NS, PF = Ring<KC, NT>::PF;
+    constexpr int PA = NS < 4 ? NS : 4;  // A fragments (LDS) in flight
     const int lane = threadIdx.x & 63;
     const uint16_t* xa = X + (lane & 31) * xs + 8 * (lane >> 5);
-    const uint16_t* bp[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        bp[t] = Bg + ((int64_t)(n0[t] >> 5) * NS * 64 + lane) * 8;
-        acc[t] = floatx16{};
-    }
-    bf16x8 bq[PF][NT];
+    for (int t = 0; t < NT; ++t) acc[t] = floatx16{};
+    bf16x8 aq[PA];
 #pragma unroll
-    for (int i = 0; i < PF; ++i)
-#pragma unroll
-        for (int t = 0; t < NT; ++t) bq[i][t] = *reinterpret_cast<const bf16x8*>(bp[t] + 512 * i);
+    for (int i = 0; i < PA; ++i) aq[i] = *reinterpret_cast<const bf16x8*>(xa + 16 * i);
     // the scheduling barriers keep each refill where it is written: left alone, the scheduler sinks the
     // loads next to their MFMAs and only one or two stay in flight
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ks = 0; ks < NS; ++ks) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8*>(xa + 16 * ks);
+        const bf16x8 a = aq[ks % PA];
+        if (ks + PA < NS) aq[ks % PA] = *reinterpret_cast<const bf16x8*>(xa + 16 * (ks + PA));
         bf16x8 b[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            b[t] = bq[ks % PF][t];
-            if (ks + PF < NS) bq[ks % PF][t] = *reinterpret_cast<const bf16x8*>(bp[t] + 512 * (ks + PF));
+            b[t] = r.q[ks % PF][t];
+            if (ks + PF < NS) r.q[ks % PF][t] = *reinterpret_cast<const bf16x8*>(r.bp[t] + 512 * (ks + PF));
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -189,20 +207,15 @@ __host__ __device__ constexpr int64_t w_off_c(int l)
     return n;
 }
 __host__ __device__ constexpr int64_t b_off_c(int l) { return w_off_c(l) + (int64_t)WIDTH[l] * WIDTH[l + 1]; }
+constexpr int64_t NPARAM_C = w_off_c(NL);
 
-// One hidden layer forward: Y = ReLU(X W_l + b_l) for the block's 32 rows; HT (nullable): also the
-// transposed copy for the weight gradients.
-template <int K, int N>
-__device__ __forceinline__ void fwd_hidden(const uint16_t* X, int xs, uint16_t* Y, int ys, const uint16_t* wf,
-                                           const float* bias, uint16_t* HT, int ld, int row0, int B)
+// Epilogue of a hidden layer's forward product: Y = ReLU(acc + b) in BF16 for the block's 32 rows;
+// HT (nullable): also the transposed copy for the weight gradients.
+template <int NT>
+__device__ __forceinline__ void fwd_epilogue(const floatx16 (&acc)[NT], const int (&n0)[NT], uint16_t* Y, int ys,
+                                             const float* bias, uint16_t* HT, int ld, int row0, int B)
 {
-    constexpr int NT = N / 32 / (FTHREADS / 64);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int n0[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) n0[t] = 32 * (wave + t * (FTHREADS / 64));
-    floatx16 acc[NT];
-    mma_rows32<K, NT>(X, xs, wf, n0, acc);
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int col = n0[t] + (lane & 31);
@@ -219,20 +232,14 @@ __device__ __forceinline__ void fwd_hidden(const uint16_t* X, int xs, uint16_t* 
     }
 }
 
-// One backward step through hidden layer l: G_{l-1} = (G_l W_l^T) masked by H_l > 0, written over
+// Epilogue of a backward product through hidden layer l: G_{l-1} = acc masked by H_l > 0, written over
 // H_l (which holds the mask) -- each element is read and written by the same lane -- and transposed
 // into GT.
-template <int KC, int N>
-__device__ __forceinline__ void bwd_hidden(const uint16_t* G, int gs, uint16_t* HM, int hs, const uint16_t* wbk,
-                                           uint16_t* GT, int ld, int row0, int B)
+template <int NT>
+__device__ __forceinline__ void bwd_epilogue(const floatx16 (&acc)[NT], const int (&n0)[NT], uint16_t* HM, int hs,
+                                             uint16_t* GT, int ld, int row0, int B)
 {
-    constexpr int NT = N / 32 / (FTHREADS / 64);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int n0[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) n0[t] = 32 * (wave + t * (FTHREADS / 64));
-    floatx16 acc[NT];
-    mma_rows32<KC, NT>(G, gs, wbk, n0, acc);
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         const int col = n0[t] + (lane & 31);
@@ -248,6 +255,8 @@ __device__ __forceinline__ void bwd_hidden(const uint16_t* G, int gs, uint16_t* 
     }
 }
 
+// Wave w owns output tiles {w, w + 8} of a 512-wide product and tile w of a 256-wide one; wave 0 also
+// computes the 32-wide output layer.  Each product's ring is started before the previous epilogue.
 template <bool TRAIN>
 __global__ __launch_bounds__(FTHREADS) void mlp_pass_kernel(MlpArgs A)
 {
@@ -256,6 +265,11 @@ __global__ __launch_bounds__(FTHREADS) void mlp_pass_kernel(MlpArgs A)
     const int nrows = max(0, min(FR, A.B - r0));
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int ld = A.Bp;
+    const int n512[2] = {32 * wave, 32 * (wave + 8)};
+    const int n256[1] = {32 * wave};
+    const int n32[1] = {0};
+    Ring<256, 2> rf0;
+    rf0.start(A.wf + wpack_off(0), n512);
     // stage the input rows (zeros past the batch)
     for (int c = tid; c < FR * 32; c += FTHREADS) {
         const int r = c >> 5, q = (c & 31) * 8;
@@ -273,20 +287,31 @@ __global__ __launch_bounds__(FTHREADS) void mlp_pass_kernel(MlpArgs A)
             *reinterpret_cast<u32x4_t*>(A.ht[0] + (int64_t)f * ld + r0 + rq) = u32x4_t{v[0], v[1], v[2], v[3]};
         }
     }
-    fwd_hidden<256, 512>(&sm.h0[0][0], 256 + XPAD, &sm.h1[0][0], 512 + XPAD, A.wf + wpack_off(0), A.w + b_off_c(0),
-                         TRAIN ? A.ht[1] : nullptr, ld, r0, A.B);
+    floatx16 acc2[2], acc1[1];
+    // H1 = ReLU(H0 W0 + b0)
+    mma_rows32<256, 2>(&sm.h0[0][0], 256 + XPAD, rf0, acc2);
+    Ring<512, 2> rf1;
+    rf1.start(A.wf + wpack_off(1), n512);
+    fwd_epilogue<2>(acc2, n512, &sm.h1[0][0], 512 + XPAD, A.w + b_off_c(0), TRAIN ? A.ht[1] : nullptr, ld, r0, A.B);
     __syncthreads();
-    fwd_hidden<512, 512>(&sm.h1[0][0], 512 + XPAD, &sm.h2[0][0], 512 + XPAD, A.wf + wpack_off(1), A.w + b_off_c(1),
-                         TRAIN ? A.ht[2] : nullptr, ld, r0, A.B);
+    // H2 = ReLU(H1 W1 + b1)
+    mma_rows32<512, 2>(&sm.h1[0][0], 512 + XPAD, rf1, acc2);
+    Ring<512, 1> rf2;
+    rf2.start(A.wf + wpack_off(2), n256);
+    fwd_epilogue<2>(acc2, n512, &sm.h2[0][0], 512 + XPAD, A.w + b_off_c(1), TRAIN ? A.ht[2] : nullptr, ld, r0, A.B);
     __syncthreads();
-    fwd_hidden<512, 256>(&sm.h2[0][0], 512 + XPAD, &sm.h3[0][0], 256 + XPAD, A.wf + wpack_off(2), A.w + b_off_c(2),
-                         TRAIN ? A.ht[3] : nullptr, ld, r0, A.B);
+    // H3 = ReLU(H2 W2 + b2)
+    mma_rows32<512, 1>(&sm.h2[0][0], 512 + XPAD, rf2, acc1);
+    Ring<256, 1> rf3;
+    Ring<32, 1> rb3;
+    if (wave == 0) rf3.start(A.wf + wpack_off(3), n32);
+    else if (TRAIN) rb3.start(A.wbk + wpack_off(3), n256);
+    fwd_epilogue<1>(acc1, n256, &sm.h3[0][0], 256 + XPAD, A.w + b_off_c(2), TRAIN ? A.ht[3] : nullptr, ld, r0, A.B);
     __syncthreads();
     // output layer (one 32-column tile, 18 used): wave 0
     if (wave == 0) {
-        int n0[1] = {0};
-        floatx16 acc[1];
-        mma_rows32<256, 1>(&sm.h3[0][0], 256 + XPAD, A.wf + wpack_off(3), n0, acc);
+        mma_rows32<256, 1>(&sm.h3[0][0], 256 + XPAD, rf3, acc1);
+        if (TRAIN) rb3.start(A.wbk + wpack_off(3), n256);
         const int col = lane & 31;
         const float bv = col < 18 ? A.w[b_off_c(3) + col] : 0.0f;
         const float nf = (float)(A.B * 18);
@@ -296,7 +321,7 @@ __global__ __launch_bounds__(FTHREADS) void mlp_pass_kernel(MlpArgs A)
         for (int j = 0; j < 16; ++j) {
             const int r = acc_row(j, lane);
             const bool ok = r < nrows && col < 18;
-            const float o = acc[0][j] + bv;
+            const float o = acc1[0][j] + bv;
             if (!TRAIN) {
                 if (ok) A.out[(int64_t)(r0 + r) * 18 + col] = o;
             } else {
@@ -318,30 +343,38 @@ __global__ __launch_bounds__(FTHREADS) void mlp_pass_kernel(MlpArgs A)
     if (!TRAIN) return;
     __syncthreads();
     // G2 = (G3 W3^T) . [H3 > 0]   (contraction over the 32 padded outputs)
-    bwd_hidden<32, 256>(&sm.d3[0][0], 32 + XPAD, &sm.h3[0][0], 256 + XPAD, A.wbk + wpack_off(3), A.gt[2], ld, r0, A.B);
+    mma_rows32<32, 1>(&sm.d3[0][0], 32 + XPAD, rb3, acc1);
+    Ring<256, 2> rb2;
+    rb2.start(A.wbk + wpack_off(2), n512);
+    bwd_epilogue<1>(acc1, n256, &sm.h3[0][0], 256 + XPAD, A.gt[2], ld, r0, A.B);
     __syncthreads();
     // G1 = (G2 W2^T) . [H2 > 0]
-    bwd_hidden<256, 512>(&sm.h3[0][0], 256 + XPAD, &sm.h2[0][0], 512 + XPAD, A.wbk + wpack_off(2), A.gt[1], ld, r0,
-                         A.B);
+    mma_rows32<256, 2>(&sm.h3[0][0], 256 + XPAD, rb2, acc2);
+    Ring<512, 2> rb1;
+    rb1.start(A.wbk + wpack_off(1), n512);
+    bwd_epilogue<2>(acc2, n512, &sm.h2[0][0], 512 + XPAD, A.gt[1], ld, r0, A.B);
     __syncthreads();
     // G0 = (G1 W1^T) . [H1 > 0]
-    bwd_hidden<512, 512>(&sm.h2[0][0], 512 + XPAD, &sm.h1[0][0], 512 + XPAD, A.wbk + wpack_off(1), A.gt[0], ld, r0,
-                         A.B);
+    mma_rows32<512, 2>(&sm.h2[0][0], 512 + XPAD, rb1, acc2);
+    bwd_epilogue<2>(acc2, n512, &sm.h1[0][0], 512 + XPAD, A.gt[0], ld, r0, A.B);
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradients of all four layers in one launch: dW_l = H_l^T G_l, a
-// contraction over the batch, from the transposed operands the pass kernel
-// wrote (batch contiguous, zero past B up to Bp).  One 64 x 64 output tile per
-// block over the whole batch, so every gradient element is one fixed-order sum
-// (deterministic, no split); the first row of tiles also sums its G tiles:
-// the bias gradient.  DW_BK batch rows per step through two LDS buffers; the
-// loads of the next step are issued before this step's MFMAs.
-// ADAM: the block also takes the Adam step (adam_update) on its tile.
+// Weight gradients of all four layers: dW_l = H_l^T G_l, a contraction over the
+// batch, from the transposed operands the pass kernel wrote (batch contiguous,
+// zero past B up to Bp).  Blocks are dispatched to the eight XCDs in turn, so
+// pass-kernel block b (batch rows 32 b ..) ran on XCD b % 8 and its operand
+// rows sit in that XCD's L2.  The gradient launch therefore runs every 64 x 64
+// output tile eight times, block 8 t + x contracting tile t over the rows of
+// XCD x only, into partial slice x; grad_reduce_kernel sums the eight slices in
+// a fixed order (deterministic) and, when training, takes the Adam step.  The
+// dispatch order is what makes the reads L2 hits; the results never depend on
+// it.  The first row of tiles also sums its G tiles: the bias gradient.
 // ---------------------------------------------------------------------------
 
 constexpr int DBM = 64, DBN = 64, DW_BK = 128, DROW = DW_BK + 8;
 constexpr int DW_CH = DBM * DW_BK / 8 / 256;  // 16-byte chunks per thread and operand tile
+constexpr int DW_SLICES = 8;                  // XCDs: partial gradient slices
 constexpr int DW_TILES[NL] = {(256 / 64) * (512 / 64), (512 / 64) * (512 / 64), (512 / 64) * (256 / 64),
                               (256 / 64) * 1};
 constexpr int DW_BLOCKS = DW_TILES[0] + DW_TILES[1] + DW_TILES[2] + DW_TILES[3];
@@ -370,17 +403,21 @@ __device__ __forceinline__ void adam_update(int64_t i, float gi, float* __restri
     }
 }
 
-// Rows o0 .. o0 + 63 (rows >= O read as zeros) and batch columns b0 .. b0 + DW_BK - 1 of a transposed
-// operand X [O][ld]: DW_CH 16-byte chunks per thread.
-__device__ __forceinline__ void dw_load(const uint16_t* __restrict__ X, int64_t ld, int O, int o0, int b0,
-                                        u32x4_t v[DW_CH])
+// One step of DW_BK batch columns of a transposed operand X [O][ld] for rows o0 .. o0 + 63 (rows >= O
+// read as zeros): the four 32-row segments 4 step .. 4 step + 3 of XCD x, i.e. batch rows
+// 32 (8 j + x) .. + 31 for those j (segments past the batch read as zeros).  DW_CH 16-byte chunks
+// per thread.
+__device__ __forceinline__ void dw_load(const uint16_t* __restrict__ X, int64_t ld, int O, int o0, int nseg_all,
+                                        int x, int step, u32x4_t v[DW_CH])
 {
 #pragma unroll
     for (int j = 0; j < DW_CH; ++j) {
         const int c = threadIdx.x + 256 * j;
         const int r = c / (DW_BK / 8), q = (c % (DW_BK / 8)) * 8;
-        v[j] = o0 + r < O ? *reinterpret_cast<const u32x4_t*>(X + (int64_t)(o0 + r) * ld + b0 + q)
-                          : u32x4_t{0u, 0u, 0u, 0u};
+        const int seg = 8 * (4 * step + q / 32) + x;
+        v[j] = (o0 + r < O && seg < nseg_all)
+                   ? *reinterpret_cast<const u32x4_t*>(X + (int64_t)(o0 + r) * ld + 32 * seg + (q & 31))
+                   : u32x4_t{0u, 0u, 0u, 0u};
     }
 }
 __device__ __forceinline__ void dw_store(uint16_t (*S)[DROW], const u32x4_t v[DW_CH])
@@ -398,17 +435,14 @@ struct DwOperands {
     const uint16_t* gt[NL];  // G_l^T [NPAD[l]][Bp]
 };
 
-template <bool ADAM>
-__global__ __launch_bounds__(256) void mlp_dw_kernel(int Bp, DwOperands ops, float* __restrict__ g,
-                                                     float* __restrict__ w, float* __restrict__ m1,
-                                                     float* __restrict__ m2, uint16_t* __restrict__ wf,
-                                                     uint16_t* __restrict__ wbk, AdamArgs adam,
-                                                     uint64_t* __restrict__ step_counter)
+// gpart: DW_SLICES slices of NPARAM partial gradients, slice x over the batch rows of XCD x.
+__global__ __launch_bounds__(256) void mlp_dw_kernel(int Bp, DwOperands ops, float* __restrict__ gpart)
 {
     __shared__ __attribute__((aligned(16))) uint16_t As[2][DBM][DROW];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[2][DBN][DROW];
-    // block -> (layer, tile); the largest layer first
-    int bid = blockIdx.x, l;
+    const int x = blockIdx.x % DW_SLICES;
+    // tile -> layer; the largest layer first
+    int bid = blockIdx.x / DW_SLICES, l;
     if (bid < DW_TILES[1]) l = 1;
     else if ((bid -= DW_TILES[1]) < DW_TILES[0]) l = 0;
     else if ((bid -= DW_TILES[0]) < DW_TILES[2]) l = 2;
@@ -420,21 +454,26 @@ __global__ __launch_bounds__(256) void mlp_dw_kernel(int Bp, DwOperands ops, flo
     const uint16_t* G = ops.gt[l];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int nseg_all = Bp / 32;                                  // 32-row segments of the batch
+    const int nseg_x = nseg_all > x ? (nseg_all - x + 7) / 8 : 0;  // those of XCD x
+    const int nsteps = (nseg_x + 3) / 4;
     floatx16 acc = {};
     const bool csum = m0 == 0 && tid < 64;
     float cs = 0.0f;
     u32x4_t ra[DW_CH], rb[DW_CH];
-    dw_load(H, Bp, K, m0, 0, ra);
-    dw_load(G, Bp, NPd, n0, 0, rb);
-    dw_store(As[0], ra);
-    dw_store(Bs[0], rb);
+    if (nsteps > 0) {
+        dw_load(H, Bp, K, m0, nseg_all, x, 0, ra);
+        dw_load(G, Bp, NPd, n0, nseg_all, x, 0, rb);
+        dw_store(As[0], ra);
+        dw_store(Bs[0], rb);
+    }
     __syncthreads();
     int cur = 0;
-    for (int b0 = 0; b0 < Bp; b0 += DW_BK) {
-        const bool more = b0 + DW_BK < Bp;
+    for (int st = 0; st < nsteps; ++st) {
+        const bool more = st + 1 < nsteps;
         if (more) {
-            dw_load(H, Bp, K, m0, b0 + DW_BK, ra);
-            dw_load(G, Bp, NPd, n0, b0 + DW_BK, rb);
+            dw_load(H, Bp, K, m0, nseg_all, x, st + 1, ra);
+            dw_load(G, Bp, NPd, n0, nseg_all, x, st + 1, rb);
         }
         __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
 #pragma unroll
@@ -458,23 +497,40 @@ __global__ __launch_bounds__(256) void mlp_dw_kernel(int Bp, DwOperands ops, flo
         __syncthreads();
         cur ^= 1;
     }
+    float* gp = gpart + (int64_t)x * NPARAM_C;
     // weights: element (m, n) of dW_l is parameter w_off(l) + m N + n
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int m = m0 + wm + acc_row(j, lane);
         const int n = n0 + wn + (lane & 31);
-        if (m >= K || n >= N) continue;
-        const int64_t i = w_off_c(l) + (int64_t)m * N + n;
-        g[i] = acc[j];
-        if (ADAM) adam_update(i, acc[j], w, m1, m2, adam, wf, wbk, l, m, n);
+        if (m < K && n < N) gp[w_off_c(l) + (int64_t)m * N + n] = acc[j];
     }
-    // biases: sums of G_l over the batch
-    if (csum && n0 + tid < N) {
-        const int64_t i = b_off_c(l) + n0 + tid;
-        g[i] = cs;
-        if (ADAM) adam_update(i, cs, w, m1, m2, adam, wf, wbk, -1, 0, 0);
+    // biases: sums of G_l over the batch rows
+    if (csum && n0 + tid < N) gp[b_off_c(l) + n0 + tid] = cs;
+}
+
+// g = the sum of the DW_SLICES partial slices, in slice order; ADAM: the Adam step on every parameter and
+// one bump of the data-generation counter.
+template <bool ADAM>
+__global__ void grad_reduce_kernel(const float* __restrict__ gpart, float* __restrict__ g, float* __restrict__ w,
+                                   float* __restrict__ m1, float* __restrict__ m2, uint16_t* __restrict__ wf,
+                                   uint16_t* __restrict__ wbk, AdamArgs a, uint64_t* __restrict__ step_counter)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (ADAM && step_counter && i == 0) *step_counter += 1;
+    if (i >= NPARAM_C) return;
+    float gi = gpart[i];
+#pragma unroll
+    for (int x = 1; x < DW_SLICES; ++x) gi += gpart[(int64_t)x * NPARAM_C + i];
+    g[i] = gi;
+    if (ADAM) {
+        int l = 0;
+        while (l < NL - 1 && i >= w_off_c(l + 1)) ++l;
+        const int64_t off = i - w_off_c(l);
+        const int N = WIDTH[l + 1];
+        const bool is_w = i < b_off_c(l);
+        adam_update(i, gi, w, m1, m2, a, wf, wbk, is_w ? l : -1, is_w ? (int)(off / N) : 0, is_w ? (int)(off % N) : 0);
     }
-    if (ADAM && step_counter && blockIdx.x == 0 && tid == 0) *step_counter += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -486,7 +542,7 @@ constexpr float FEAT_POS = 1.0f / 16.0f;  // feature scale of position (deg)
 constexpr float FEAT_VEL = 4.0f;          // feature scale of velocity (deg/ms)
 constexpr float ZSCALE = 0.3f;            // z = (p/p_nom - 1) / ZSCALE
 
-constexpr int64_t NPARAM = w_off_c(NL);
+constexpr int64_t NPARAM = NPARAM_C;
 
 }  // namespace
 
@@ -508,6 +564,7 @@ struct opmm_surrogate {
     uint16_t* x0 = nullptr;   // features of a predicted batch [256]
     float* out = nullptr;     // network outputs [18]
     float* loss = nullptr;    // [1]
+    float* gpart = nullptr;   // [DW_SLICES][NPARAM] partial weight gradients
     float* trace = nullptr;   // [B][MAX_T_GEN] generated traces
     uint64_t* counter = nullptr;  // device step counter for data generation (graph-replay safe)
     // training data ring: GEN_BATCHES consecutive batches generated in one launch
@@ -810,7 +867,7 @@ AdamArgs adam_args(opmm_surrogate* sg, float lr)
 
 // Forward, MSE against tgt [B][18] (added to *loss, zeroed by the caller) and backward over the B
 // rows of x0: gradients into sg->g.  ADAM: also the Adam step with learning rate lr, and one bump of
-// the data-generation counter.  Two launches.
+// the data-generation counter.  Three launches.
 template <bool ADAM>
 int sg_step(opmm_surrogate* sg, int B, const uint16_t* x0, const float* tgt, float* loss, float lr, hipStream_t st)
 {
@@ -825,11 +882,13 @@ int sg_step(opmm_surrogate* sg, int B, const uint16_t* x0, const float* tgt, flo
         ops.ht[l] = sg->ht[l];
         ops.gt[l] = sg->gt[l];
     }
+    hipLaunchKernelGGL(mlp_dw_kernel, dim3(DW_SLICES * DW_BLOCKS), dim3(256), 0, st, A.Bp, ops, sg->gpart);
+    SG_HIP(hipGetLastError());
     AdamArgs a;
     std::memset(&a, 0, sizeof a);
     if (ADAM) a = adam_args(sg, lr);
-    hipLaunchKernelGGL(mlp_dw_kernel<ADAM>, dim3(DW_BLOCKS), dim3(256), 0, st, A.Bp, ops, sg->g, sg->w, sg->m1, sg->m2,
-                       sg->wf, sg->wbk, a, ADAM ? sg->counter : nullptr);
+    hipLaunchKernelGGL(grad_reduce_kernel<ADAM>, dim3(blocks(NPARAM, 256)), dim3(256), 0, st, sg->gpart, sg->g, sg->w,
+                       sg->m1, sg->m2, sg->wf, sg->wbk, a, ADAM ? sg->counter : nullptr);
     SG_HIP(hipGetLastError());
     return OPMM_OK;
 }
@@ -866,6 +925,7 @@ int opmm_surrogate_create(opmm_ctx* ctx, uint64_t init_seed, opmm_surrogate** ou
         hipMalloc(&sg->m1, sizeof(float) * NPARAM) != hipSuccess || hipMalloc(&sg->m2, sizeof(float) * NPARAM) != hipSuccess ||
         hipMalloc(&sg->wf, sizeof(uint16_t) * NPACK) != hipSuccess ||
         hipMalloc(&sg->wbk, sizeof(uint16_t) * NPACK) != hipSuccess || hipMalloc(&sg->loss, sizeof(float)) != hipSuccess ||
+        hipMalloc(&sg->gpart, sizeof(float) * DW_SLICES * NPARAM) != hipSuccess ||
         hipMalloc(&sg->counter, sizeof(uint64_t)) != hipSuccess)
         rc = OPMM_ENOMEM;
     if (rc == OPMM_OK) {
@@ -895,7 +955,8 @@ int opmm_surrogate_destroy(opmm_surrogate* sg)
         if (sg->gt[l]) (void)hipFree(sg->gt[l]);
     }
     for (void* p : {(void*)sg->w, (void*)sg->g, (void*)sg->m1, (void*)sg->m2, (void*)sg->wf, (void*)sg->wbk,
-                    (void*)sg->x0, (void*)sg->out, (void*)sg->loss, (void*)sg->trace, (void*)sg->counter,
+                    (void*)sg->x0, (void*)sg->out, (void*)sg->loss, (void*)sg->gpart, (void*)sg->trace,
+                    (void*)sg->counter,
                     (void*)sg->ring_feat, (void*)sg->ring_tgt, (void*)sg->ring_trace})
         if (p) (void)hipFree(p);
     delete sg;
@@ -1006,7 +1067,7 @@ int opmm_surrogate_train(opmm_surrogate* sg, uint64_t data_seed, int32_t B, int3
         // cosine decay from lr0 to lr_min over this call's steps
         const double ph = n_steps > 1 ? (double)t / (double)(n_steps - 1) : 1.0;
         const float lr = (float)(lr_min + 0.5 * (lr0 - lr_min) * (1.0 + std::cos(M_PI * ph)));
-        // forward + loss + backward + Adam (and the counter bump): two launches
+        // forward + loss + backward + Adam (and the counter bump): three launches
         rc = sg_step<true>(sg, B, x0, tgt, hist + t, lr, st);
     }
     if (rc == OPMM_OK && loss_out && n_steps > 0)
