@@ -68,7 +68,7 @@ def lib():
         L.oracle_jacobian.restype = i
         L.oracle_damped_solve.argtypes = [i, P, P, d, P, P]
         L.oracle_damped_solve.restype = i
-        L.oracle_polish.argtypes = [P, i, i, d, d, d, d, P, i, i, i, d, d, d, i, P, P, P, P, P, P]
+        L.oracle_polish.argtypes = [P, i, i, d, d, d, d, P, i, i, i, d, d, d, i, d, P, P, P, P, P, P]
         L.oracle_polish.restype = i
         _lib = L
     return _lib
@@ -251,10 +251,10 @@ def damped_solve(H, g, lam, held=None):
 
 
 def polish(pos, amp, dir_deg, dur_ms, x0, *, model=18, objective=0, max_iter=20, tol_f=1e-10, lam0=1e-3,
-           box_frac=0.25, dt_ms=1.0, nsub=NSUB, forced=None):
-    """Levenberg-Marquardt polish (objective 0: sum of squares, 1: sum of absolute differences).
-    Returns dict(opc, f, iters, own, margin, fhist); with forced, exactly len(forced) iterations
-    following those decisions."""
+           box_frac=0.25, dt_ms=1.0, nsub=NSUB, forced=None, h_rel=3e-5):
+    """Levenberg-Marquardt polish (objective 0: sum of squares, 1: sum of absolute differences), the
+    Jacobian by central differences with step h_rel |p_j|.  Returns dict(opc, f, iters, own, margin,
+    fhist); with forced, exactly len(forced) iterations following those decisions."""
     pos = _f32(pos); T, C = pos.shape
     x0 = _f32(x0)
     n = max_iter if forced is None else len(forced)
@@ -263,7 +263,7 @@ def polish(pos, amp, dir_deg, dur_ms, x0, *, model=18, objective=0, max_iter=20,
     opc = np.zeros(NP_, np.float32); f = ctypes.c_double()
     it = lib().oracle_polish(_p(pos), T, C, float(amp), float(dir_deg), float(dur_ms), float(dt_ms), _p(x0),
                              int(model), int(objective), int(n), float(tol_f), float(lam0), float(box_frac),
-                             int(nsub), None if fc is None else _p(fc), _p(own), _p(mar), _p(fh), _p(opc),
+                             int(nsub), float(h_rel), None if fc is None else _p(fc), _p(own), _p(mar), _p(fh), _p(opc),
                              ctypes.byref(f))
     return dict(opc=opc, f=f.value, iters=it, own=own[:it], margin=mar[:it], fhist=fh[:it])
 

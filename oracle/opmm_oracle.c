@@ -711,8 +711,8 @@ static double lm_cost(const lm_problem* pb, const double x[NP], double* sq_out, 
  * objective. */
 int oracle_polish(const float* pos, int T, int C, double amp, double dir_deg, double dur_ms, double dt_ms,
                   const float* x0_opc, int model, int objective, int max_iter, double tol_f, double lam0,
-                  double box_frac, int nsub, const signed char* forced, signed char* own, double* margin,
-                  double* fhist, float opc_out[NP], double* f_out)
+                  double box_frac, int nsub, double h_rel, const signed char* forced, signed char* own,
+                  double* margin, double* fhist, float opc_out[NP], double* f_out)
 {
     static const double fac[8] = {1e-4, 1e-3, 1e-2, 1e-1, 1.0, 1e1, 1e2, 1e3};
     lm_problem pb;
@@ -754,7 +754,7 @@ int oracle_polish(const float* pos, int T, int C, double amp, double dir_deg, do
         /* 1-2: normal equations at x */
         double p[NP];
         for (int j = 0; j < NP; ++j) p[j] = (double)(float)(x[j] * pb.nom[j]);
-        oracle_jacobian(p, amp, T, dt_ms, nsub, 3e-5, th, ja);
+        oracle_jacobian(p, amp, T, dt_ms, nsub, h_rel, th, ja);
         for (int k = 0; k < T; ++k)
             for (int f = 0; f < nf; ++f) {
                 double v = pb.nom[fr[f]] * ja[(int64_t)k * NP + fr[f]];

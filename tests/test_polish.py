@@ -72,6 +72,46 @@ def test_jacobian_matches_expm_frechet_in_the_pulse():
         assert np.abs(J[:, j] - ref).max() <= 1e-6 * np.abs(ref).max() + 1e-12, j
 
 
+def test_jacobian_difference_error():
+    """The oracle's central differences (step 3e-5 |p_j|) against Richardson extrapolation of the steps
+    1.5e-5 and 3e-5, which removes the h^2 term: every column within 1e-7 of its scale (measured
+    <= 4e-8, median 1e-9)."""
+    rng = np.random.default_rng(1)
+    for _ in range(4):
+        p = oracle.nominal(45.0) * rng.uniform(0.8, 1.2, 18)
+        amp = float(rng.uniform(5, 25))
+        _, J = oracle.jacobian(p, amp, 70, h_rel=3e-5)
+        _, J2 = oracle.jacobian(p, amp, 70, h_rel=1.5e-5)
+        JR = (4 * J2 - J) / 3
+        scale = np.abs(JR).max(0) + 1e-30
+        assert (np.abs(J - JR).max(0) / scale).max() <= 1e-7
+
+
+def test_polish_end_point_follows_the_jacobian():
+    """How far Levenberg-Marquardt end points part when only the Jacobian differs: the oracle's polish
+    with difference steps 3e-5 and 6e-5 (columns differing by ~4e-8 of their scale), the second run
+    forced onto the first one's decisions, six iterations, both objectives.  The end points stay within
+    1e-5 (objective) and 1e-4 (OPC) of each other -- the spread that bounds the GPU-vs-oracle replay,
+    whose Jacobians differ by up to 1e-7."""
+    from paper_2007_09884_amd import synth
+    from workload import make_batch
+    worst_f = worst_p = 0.0
+    for kind in ("tiny", "full"):
+        b, traces = make_batch(2, kind, seed=synth.BASE_SEED + 321)
+        for s in range(2):
+            start = oracle.fit(traces[s], b["amp"][s], b["dir_deg"][s], b["dur_ms"][s], int(b["seed"][s]), 2048, 2,
+                               nthreads=4)["opc"]
+            for obj in (0, 1):
+                r1 = oracle.polish(traces[s], b["amp"][s], b["dir_deg"][s], b["dur_ms"][s], start, objective=obj,
+                                   max_iter=6, tol_f=0.0)
+                r2 = oracle.polish(traces[s], b["amp"][s], b["dir_deg"][s], b["dur_ms"][s], start, objective=obj,
+                                   forced=r1["own"], h_rel=6e-5)
+                worst_f = max(worst_f, abs(r1["f"] - r2["f"]) / r1["f"])
+                worst_p = max(worst_p, np.abs(r1["opc"].astype(np.float64) / r2["opc"] - 1).max())
+    assert worst_f <= 1e-5 and worst_p <= 1e-4, (worst_f, worst_p)
+    assert worst_p > 0.0   # the perturbation does reach the end point
+
+
 def test_damped_solve_matches_numpy():
     rng = np.random.default_rng(5)
     n = 18
@@ -253,7 +293,10 @@ def test_sensitivity_matches_oracle(ctx, opmm, kind):
         assert np.abs(th[off:off + T] - t_ref).max() <= 1e-8, i
         scale = np.abs(J_ref).max(0) + 1e-30
         err = np.abs(jac[off:off + T] - J_ref).max(0) / scale
-        assert err.max() <= 1e-6, (i, err)
+        print("sensitivity %s %d: largest column error %.2e of the column scale" % (kind, i, err.max()))
+        # measured 1.3e-8 .. 9.8e-8: the oracle's central differences are good to 4e-8 (Richardson,
+        # test_jacobian_difference_error), the GPU's discretisation to ~1e-8 deg on trajectories
+        assert err.max() <= 3e-7, (i, err)
         off += T
 
 
@@ -340,11 +383,18 @@ def test_polish_replays_against_oracle(ctx, opmm, kind, objective):
         th = oracle.simulate(opc[s].astype(np.float64), b["amp"][s], T)
         r_rm, r_ma = oracle.cost(th, traces[s], b["dir_deg"][s])
         assert abs(r_rm - rm[s]) <= 1e-6 * r_rm and abs(r_ma - ma[s]) <= 1e-6 * r_ma, s
-        # ... and the oracle, following the same decisions, walks the same path: its Jacobian is a
-        # finite-difference one, so the points agree to the conditioning of the damped systems
+        # ... and the oracle, following the same decisions, walks the same path.  Its Jacobian (central
+        # differences) and the GPU's (exact, on the search discretisation) differ by up to 1e-7 of a
+        # column's scale, and the damped systems are near-singular along the force-scale gauge, so the
+        # end points part by more than the Jacobians do: measured up to 3.1e-6 in the objective and
+        # 1.2e-5 in the OPC (the L1 objective's reweighting is the most sensitive); on the CPU, two
+        # oracle runs whose Jacobians differ by 4e-8 part by 3e-7 and 2e-6
+        # (test_polish_end_point_follows_the_jacobian).  Bounds: ten times the largest measured.
         got = rm[s] ** 2 * T * C if objective == 0 else ma[s] * T * C
-        assert abs(r["f"] - got) <= 1e-4 * got, (s, r["f"], got)
-        assert np.abs(r["opc"].astype(np.float64) / opc[s] - 1).max() <= 1e-3, s
+        print("replay %s obj %d saccade %d: end objective rel gap %.2e, OPC rel gap %.2e" % (
+            kind, objective, s, abs(r["f"] - got) / got, np.abs(r["opc"].astype(np.float64) / opc[s] - 1).max()))
+        assert abs(r["f"] - got) <= 3e-5 * got, (s, r["f"], got)
+        assert np.abs(r["opc"].astype(np.float64) / opc[s] - 1).max() <= 1e-4, s
 
 
 @pytest.mark.gpu
@@ -353,6 +403,7 @@ def test_polish_improves_the_box_search(ctx, opmm):
     start, rm0 = _fit(ctx, opmm, b, traces, 4096, 4)
     _, rm_big = _fit(ctx, opmm, b, traces, 65536, 10)
     opc, rm, ma, it, dec = _polish(ctx, opmm, b, traces, opmm.polish_params(), start)
+    print("mean RMSE: 4096x4 %.6f, polished %.6f, 65536x10 %.6f" % (rm0.mean(), rm.mean(), rm_big.mean()))
     assert np.all(rm <= rm0 * (1 + 1e-7)) and rm.mean() < rm0.mean()
     assert np.all((it >= 1) & (it <= 20))
     # the polish is local: from the long search's result it still lowers the RMSE of every saccade
