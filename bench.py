@@ -361,10 +361,31 @@ def nm_leg(a, ctx, opmm, torch, pos, recs, rm_box, box_s):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     r, its = rm.cpu().numpy(), it.cpu().numpy()
-    return {"max_iter": a.nm_iter, "tol_x": 1e-4, "tol_f": 1e-6, "saccades_fitted_per_s": S / dt,
-            "mean_rmse_deg": float(r.mean()), "mean_iters": float(its.mean()),
-            "converged": int(np.count_nonzero(its < a.nm_iter)),
-            "box_search_saccades_fitted_per_s": S / box_s, "box_search_mean_rmse_deg": float(rm_box.mean())}
+    out = {"max_iter": a.nm_iter, "tol_x": 1e-4, "tol_f": 1e-6, "saccades_fitted_per_s": S / dt,
+           "mean_rmse_deg": float(r.mean()), "mean_iters": float(its.mean()),
+           "converged": int(np.count_nonzero(its < a.nm_iter)),
+           "box_search_saccades_fitted_per_s": S / box_s, "box_search_mean_rmse_deg": float(rm_box.mean())}
+    # a batch that oversubscribes the device's waves: 4096 saccades of the same distributions, one or
+    # two tasks per wave (auto picks two here)
+    from paper_2007_09884_amd import synth
+    b = synth.draw_saccades(4096, "full", seed=synth.BASE_SEED + 4)
+    pos4 = gpu_targets(ctx, opmm, torch, b)
+    recs4 = opmm.saccade_records(b["T"], 2, b["amp"], b["dir_deg"], b["dur_ms"], b["seed"])
+    S4 = 4096
+    opc4 = torch.zeros(S4, 18, device="cuda")
+    rm4 = torch.zeros(S4, device="cuda")
+    big = {}
+    for name, g in (("one_per_wave", 1), ("two_per_wave", 2)):
+        prm4 = opmm.nm_params(max_iter=a.nm_iter, tol_x=1e-4, tol_f=1e-6, tasks_per_wave=g)
+        ctx.fit_nm(pos4, recs4, prm4, opc4, rm4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.fit_nm(pos4, recs4, prm4, opc4, rm4)
+        torch.cuda.synchronize()
+        big[name] = S4 / (time.perf_counter() - t0)
+    big["mean_rmse_deg"] = float(rm4.cpu().numpy().mean())
+    out["saccades_4096"] = big
+    return out
 
 
 def serve_leg(a, ctx, opmm, torch, synth, sg, rates=None, polish_iter=0):

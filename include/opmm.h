@@ -60,9 +60,11 @@ enum {
     OPMM_ST_NO_FINITE_CANDIDATE = 2,/* some round had no candidate with finite cost */
     OPMM_ST_SEEDED = 4,             /* search started from a supplied/learned seed  */
     OPMM_ST_FALLBACK = 8,           /* seeded result rejected; plain search used    */
-    OPMM_ST_WAIT_TIMEOUT = 16       /* persistent launch: a tile gave up waiting for
+    OPMM_ST_WAIT_TIMEOUT = 16,      /* persistent launch: a tile gave up waiting for
                                        its round (opmm_set_wait_limit); that tile
                                        was not searched, the result is no estimate */
+    OPMM_ST_DEADLINE = 32           /* Nelder-Mead: the time bound ended the task
+                                       before its tolerances held (best vertex so far) */
 };
 
 typedef struct opmm_ctx opmm_ctx;
@@ -386,6 +388,12 @@ typedef struct {
     float tol_f;        /* value tolerance (deg RMSE)       [1e-6] */
     float box_frac;     /* evaluation clamp                 [0.25] */
     float dt_ms;        /* sample period                    [1.0]  */
+    float max_ms;       /* time bound per task, ms of device wall clock
+                           from the launch's start; 0 = none [0].  A task
+                           still iterating then stops with its best vertex
+                           and OPMM_ST_DEADLINE (Section 3.3 names a time
+                           limit among the exit criteria)              */
+    int32_t tasks_per_wave; /* 0 auto, 1 or 2 tasks per 64-lane wave   [0] */
 } opmm_nm_params;
 void opmm_nm_params_default(opmm_nm_params* p);
 /* seed_opc: NULL (start at nominal) or device [S][18].  Outputs (device):

@@ -18,7 +18,8 @@ P = 18
 MAX_T = 2048
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTREADY = 0, -1, -2, -3, -4
-ST_OK, ST_NONFINITE_INPUT, ST_NO_FINITE_CANDIDATE, ST_SEEDED, ST_FALLBACK, ST_WAIT_TIMEOUT = 0, 1, 2, 4, 8, 16
+ST_OK, ST_NONFINITE_INPUT, ST_NO_FINITE_CANDIDATE, ST_SEEDED, ST_FALLBACK, ST_WAIT_TIMEOUT, ST_DEADLINE = \
+    0, 1, 2, 4, 8, 16, 32
 FIT_ROUNDS, FIT_PERSISTENT = 0, 1
 
 SACCADE_DTYPE = np.dtype([("pos_offset", "<i8"), ("T", "<i4"), ("C", "<i4"), ("amp_deg", "<f4"),
@@ -40,7 +41,8 @@ class ServeParams(ctypes.Structure):
 
 class NmParams(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("tol_x", ctypes.c_float), ("tol_f", ctypes.c_float),
-                ("box_frac", ctypes.c_float), ("dt_ms", ctypes.c_float)]
+                ("box_frac", ctypes.c_float), ("dt_ms", ctypes.c_float), ("max_ms", ctypes.c_float),
+                ("tasks_per_wave", ctypes.c_int32)]
 
 
 class PolishParams(ctypes.Structure):
