@@ -36,7 +36,10 @@ def test_struct_layouts_match_header():
     from paper_2007_09884_amd import opmm
     assert opmm.SACCADE_DTYPE.itemsize == 40
     assert ctypes.sizeof(opmm.FitParams) == 36
-    assert ctypes.sizeof(opmm.ServeParams) == 96 and ctypes.sizeof(opmm.NmParams) == 20
+    assert ctypes.sizeof(opmm.ServeParams) == 96 and ctypes.sizeof(opmm.NmParams) == 28
+    n = opmm.nm_params()
+    assert (n.max_iter, n.tol_x, n.tol_f, n.box_frac, n.dt_ms, n.max_ms, n.tasks_per_wave) == \
+        (500, np.float32(1e-4), np.float32(1e-6), 0.25, 1.0, 0.0, 0)
     assert ctypes.sizeof(opmm.PolishParams) == 24
     q = opmm.polish_params()
     assert (q.max_iter, q.objective, q.lambda0, q.box_frac, q.dt_ms) == (20, 0, np.float32(1e-3), 0.25, 1.0)
