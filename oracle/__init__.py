@@ -17,18 +17,27 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "opmm_oracle.c")
 _SO = os.path.join(_HERE, "libopmm_oracle.so")
+_SAN_SO = os.path.join(_HERE, "libopmm_oracle_san.so")
+# OPMM_ORACLE_SANITIZE=1 loads the build instrumented with AddressSanitizer and UndefinedBehaviorSanitizer
+# (the process must then start with the ASan runtime preloaded; tests/test_oracle_sanitized.py does this)
+_SANITIZE = os.environ.get("OPMM_ORACLE_SANITIZE") == "1"
 NP_ = 18
 
+_FLAGS = ["-std=c11", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra", "-shared", "-fPIC"]
 
-def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc: FP64, no fast-math, no FMA contraction."""
-    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-                               "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC,
-                               "-lm", "-lpthread"])
-        os.replace(tmp, _SO)
-    return _SO
+
+def build(force: bool = False, sanitize: bool = None) -> str:
+    """Compile the C oracle with gcc: FP64, no fast-math, no FMA contraction.  sanitize (default: the
+    OPMM_ORACLE_SANITIZE setting): the ASan + UBSan build, every finding fatal."""
+    sanitize = _SANITIZE if sanitize is None else sanitize
+    so = _SAN_SO if sanitize else _SO
+    if force or not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(_SRC):
+        tmp = so + ".tmp%d" % os.getpid()
+        opt = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+               "-fno-omit-frame-pointer"] if sanitize else ["-O2"]
+        subprocess.check_call(["gcc"] + opt + _FLAGS + ["-o", tmp, _SRC, "-lm", "-lpthread"])
+        os.replace(tmp, so)
+    return so
 
 
 _lib = None
@@ -37,8 +46,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_SO)
+        L = ctypes.CDLL(build())
         d, i, f = ctypes.c_double, ctypes.c_int, ctypes.c_float
         P = ctypes.c_void_p
         u64, i64, u32 = ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32

@@ -97,3 +97,29 @@ def test_result_file_matches_the_papers_format(tmp_path):
     # a result without the serial re-check leaves that column empty
     report.write_csv(str(out), opc[:1], err[:1])
     assert out.read_text().splitlines()[1].split(",")[2] == ""
+
+
+def test_null_handles_are_rejected():
+    """Every call that takes a context, surrogate, plan or server handle rejects a null one with
+    OPMM_EINVAL before touching anything (no GPU needed); destroy calls accept null."""
+    from paper_2007_09884_amd import opmm
+    seen = 0
+    for n in _declared():
+        fn = getattr(opmm.lib, n)
+        a = fn.argtypes
+        if not a or a[0] is not ctypes.c_void_p:
+            continue
+        vals = [0.0 if t in (ctypes.c_float, ctypes.c_double) else
+                0 if t in (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64) else None
+                for t in a]
+        r = fn(*vals)
+        if n.endswith("_destroy"):
+            assert r == 0, n
+        elif n == "opmm_last_error":
+            assert r
+        elif n == "opmm_server_slots":
+            assert r == 0
+        else:
+            assert r == -1, (n, r)
+        seen += 1
+    assert seen >= 35
