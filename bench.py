@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--serve-polish", type=int, default=4,
                     help="polish iterations per served request in the extra polished-serving line (0: skip it)")
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="arrival window per rate")
+    ap.add_argument("--serve-long-rate", type=float, default=50000.0,
+                    help="rate of the one long serving window (the serving configuration's 60 s)")
+    ap.add_argument("--serve-long-seconds", type=float, default=60.0, help="0 skips the long window")
     return ap.parse_args()
 
 
@@ -388,18 +391,29 @@ def nm_leg(a, ctx, opmm, torch, pos, recs, rm_box, box_s):
     return out
 
 
-def serve_leg(a, ctx, opmm, torch, synth, sg, rates=None, polish_iter=0):
+def note(msg):
+    """Progress of the legs on stderr (the JSON line on stdout stays the only output there)."""
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def serve_leg(a, ctx, opmm, torch, synth, sg, rates=None, polish_iter=0, seconds=None, pool=50000):
     """Continuous batching: saccades of the full-estimation distributions arrive as a Poisson stream;
     the server admits them into device slots, seeds them from the learned network, advances every
     resident request by one round per step (and, with polish_iter, polishes each finished search).
-    Latency = arrival to result on the host."""
+    Latency = arrival to result on the host.  Requests beyond `pool` distinct synthetic saccades reuse
+    their traces with seeds of their own (so each still runs its own candidate stream)."""
     rates = rates or [float(r) for r in a.serve_rates.split(",") if r]
+    seconds = a.serve_seconds if seconds is None else seconds
     out = []
     for lam in rates:
-        n = max(16, int(lam * a.serve_seconds))
-        b = synth.draw_saccades(n, "full", seed=synth.BASE_SEED + 100 + int(lam))
+        n = max(16, int(lam * seconds))
+        m = min(n, pool)
+        b = synth.draw_saccades(m, "full", seed=synth.BASE_SEED + 100 + int(lam))
         pos = gpu_targets(ctx, opmm, torch, b).cpu().numpy()
-        recs = opmm.saccade_records(b["T"], 2, b["amp"], b["dir_deg"], b["dur_ms"], b["seed"])
+        base = opmm.saccade_records(b["T"], 2, b["amp"], b["dir_deg"], b["dur_ms"], b["seed"])
+        recs = base[np.arange(n) % m]
+        if n > m:
+            recs["seed"] = (np.uint64(synth.BASE_SEED) * np.uint64(1000003) + np.arange(n, dtype=np.uint64))
         rng = np.random.default_rng(int(lam))
         arrive = np.cumsum(rng.exponential(1.0 / lam, n))
         prm = opmm.serve_params(max_slots=65536, hbm_budget_bytes=1 << 30, fallback_rmse=1.5 * synth.SIGMA,
@@ -428,8 +442,10 @@ def serve_leg(a, ctx, opmm, torch, synth, sg, rates=None, polish_iter=0):
         st = sv.stats()
         sv.close()
         lat = np.concatenate(lat) * 1e3
-        out.append({"rate_per_s": lam, "requests": n, "p50_ms": float(np.percentile(lat, 50)),
-                    "p99_ms": float(np.percentile(lat, 99)), "sustained_per_s": n / span,
+        out.append({"rate_per_s": lam, "window_s": seconds, "requests": n, "distinct_traces": m,
+                    "p50_ms": float(np.percentile(lat, 50)),
+                    "p99_ms": float(np.percentile(lat, 99)), "p999_ms": float(np.percentile(lat, 99.9)),
+                    "sustained_per_s": n / span,
                     "mean_rmse_deg": float(np.concatenate(rm).mean()), "fallbacks": fb, "steps": st["steps"],
                     "slots": st["slots"], "polish_iter": polish_iter})
     return out
@@ -604,6 +620,7 @@ def main():
     if tuned:
         out["autotune"] = tuned
     if not a.no_uneven:
+        note("batched uneven")
         out["batched_uneven"] = uneven_leg(a, ctx, opmm, torch, synth)
     if not a.no_model9:
         # the 9-parameter model (Table 2) on the same batch and launch
@@ -612,15 +629,24 @@ def main():
         out["model9"] = {"ms_per_step": ms9, "candidate_sims_per_s": sims / (ms9 * 1e-3),
                          "mean_final_rmse_deg": float(rmse.mean().item())}
     if not a.no_ivt:
+        note("I-VT")
         out["ivt"] = ivt_leg(a, ctx, opmm, torch, synth)
     if not a.no_tiny:
+        note("tiny configuration")
         out["tiny"] = tiny_leg(a, ctx, opmm, torch, synth)
     if not a.no_nm:
+        note("Nelder-Mead")
         out["nelder_mead"] = nm_leg(a, ctx, opmm, torch, pos, recs, rm, ms_per_step * 1e-3)
     if not a.no_surrogate:
+        note("learned seed")
         sg, out["surrogate_vs_plain"] = surrogate_leg(a, ctx, opmm, torch, synth, keep=not a.no_serve)
         if not a.no_serve:
+            note("serving")
             out["serving"] = serve_leg(a, ctx, opmm, torch, synth, sg)
+            if a.serve_long_seconds > 0:
+                note("serving, %.0f s window at %.0f/s" % (a.serve_long_seconds, a.serve_long_rate))
+                out["serving_long"] = serve_leg(a, ctx, opmm, torch, synth, sg, rates=[a.serve_long_rate],
+                                                seconds=a.serve_long_seconds)[0]
             if a.serve_polish > 0:
                 out["serving_polished"] = serve_leg(a, ctx, opmm, torch, synth, sg, rates=[20000.0],
                                                     polish_iter=a.serve_polish)
@@ -632,6 +658,7 @@ def main():
         for s in range(1):
             T = int(b["T"][s])
             pos_host.append(ph[off:off + 2 * T].reshape(T, 2))
+        note("oracle on the host")
         out["cpu_baseline"] = cpu_baseline(b, pos_host, a.cpu_seconds)
     out["paper_figures"] = PAPER_FIGURES
     print(json.dumps(out), flush=True)
