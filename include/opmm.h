@@ -31,6 +31,15 @@
  *      17 PW                                             (ms)
  *   - A context is bound to one device and is not thread-safe; calls on one
  *     context must not overlap.
+ *   - Streams: a context, a surrogate and a plan each reuse device scratch
+ *     from call to call.  Calls on one object may use different streams: the
+ *     library orders them itself, so each call's device work starts after the
+ *     previous call's (the first call on a second stream waits on the host
+ *     for the device to drain; later calls wait on an event, on the device).
+ *     Calls that all use one stream add nothing to it.  A call queued under
+ *     stream capture is left out of this ordering; inside a graph the caller
+ *     orders the work.  opmm_fit_noalloc's scratch is one per device, shared
+ *     by every context (see there).
  */
 #ifndef OPMM_H
 #define OPMM_H
@@ -203,9 +212,10 @@ int opmm_fit(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccad
  * 288 B box, 4 B status, 8 B counters and, without round_keys, 8 B per round;
  * 4 B per trace sample; each part 256-byte aligned), else OPMM_EINVAL.  Every
  * call on a device shares that device's array and keeps the last call's
- * contents (each call rewrites every part before reading it): calls that
- * overlap on one device (other streams, contexts or threads) race, so the
- * caller must order them.  Like opmm_fit it uploads the records
+ * contents (each call rewrites every part before reading it).  Calls through
+ * one context are ordered across streams as every call on a context is;
+ * calls through different contexts or threads that overlap on one device
+ * race, so the caller must order them.  Like opmm_fit it uploads the records
  * synchronously and queues the rest on `stream`. */
 #define OPMM_NOALLOC_MAX_S 4096
 #define OPMM_NOALLOC_SCRATCH_BYTES (8u << 20)

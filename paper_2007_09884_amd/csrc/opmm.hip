@@ -751,11 +751,13 @@ struct opmm_ctx {
     int tuned_shape = -1;
     hipStream_t cap_stream = nullptr;
     unsigned char* noalloc_scratch = nullptr;  // device address of `scratch` on this device (set at creation)
+    opmm_rt::StreamOrder order;  // orders calls on different streams (scratch, aux, d_cand, give-up word)
 };
 
 struct opmm_plan {
     opmm_ctx* ctx = nullptr;
     FitScratch scratch;
+    opmm_rt::StreamOrder order;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -773,7 +775,54 @@ int hip_fail(opmm_ctx* ctx, hipError_t e, const char* what)
     return fail(ctx, OPMM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+hipError_t order_init(StreamOrder& o) { return hipEventCreateWithFlags(&o.ev, hipEventDisableTiming); }
+
+void order_release(StreamOrder& o)
+{
+    if (o.ev) (void)hipEventDestroy(o.ev);
+    o.ev = nullptr;
+    o.recorded = false;
+}
+
+hipError_t order_host_wait(const StreamOrder& o, hipStream_t st)
+{
+    if (o.ev && o.recorded) return hipEventSynchronize(o.ev);
+    if (o.seen && o.last != st) return hipDeviceSynchronize();  // one stream so far, not this one
+    return hipSuccess;
+}
+
+Ordered::Ordered(StreamOrder& o, hipStream_t st) : o_(o), st_(st)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    err_ = hipStreamIsCapturing(st, &cs);
+    skip_ = !o.ev || err_ != hipSuccess || cs != hipStreamCaptureStatusNone;
+    if (skip_) return;
+    if (o.seen && st != o.last) {
+        if (!o.multi) {
+            // no event marks the earlier calls: wait for all of them once, then record from now on
+            err_ = hipDeviceSynchronize();
+            o.multi = true;
+        } else if (o.recorded) {
+            err_ = hipStreamWaitEvent(st, o.ev, 0);
+        }
+    }
+    o.seen = true;
+    if (err_ != hipSuccess) skip_ = true;
+}
+
+Ordered::~Ordered()
+{
+    if (skip_) return;
+    o_.last = st_;
+    if (!o_.multi) return;
+    if (hipEventRecord(o_.ev, st_) == hipSuccess)
+        o_.recorded = true;
+    else
+        (void)hipGetLastError();
+}
+
 int ctx_device(const opmm_ctx* ctx) { return ctx ? ctx->device : 0; }
+StreamOrder& ctx_order(opmm_ctx* ctx) { return ctx->order; }
 int ctx_cu_count(const opmm_ctx* ctx) { return ctx && ctx->cu_count > 0 ? ctx->cu_count : 256; }
 
 }  // namespace opmm_rt
@@ -1308,9 +1357,11 @@ int opmm_create(opmm_ctx** out, int device)
     else
         (void)hipGetLastError();  // opmm_fit_noalloc then reports OPMM_EDEVICE
     if (hipMalloc((void**)&c->giveup_report, sizeof(uint32_t)) != hipSuccess ||
-        hipMemset(c->giveup_report, 0, sizeof(uint32_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        hipMemset(c->giveup_report, 0, sizeof(uint32_t)) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+        opmm_rt::order_init(c->order) != hipSuccess) {
         (void)hipGetLastError();
         if (c->giveup_report) (void)hipFree(c->giveup_report);
+        opmm_rt::order_release(c->order);
         (void)hipStreamDestroy(c->cap_stream);
         delete c;
         return OPMM_ENOMEM;
@@ -1327,6 +1378,7 @@ int opmm_destroy(opmm_ctx* ctx)
     if (ctx->d_cand) (void)hipFree(ctx->d_cand);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->giveup_report) (void)hipFree(ctx->giveup_report);
+    opmm_rt::order_release(ctx->order);
     delete ctx;
     return OPMM_OK;
 }
@@ -1344,6 +1396,7 @@ int opmm_sync(opmm_ctx* ctx, void* stream)
 {
     if (!ctx) return OPMM_EINVAL;
     OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    OPMM_HIP(ctx, opmm_rt::order_host_wait(ctx->order, (hipStream_t)stream));  // the last call, whatever its stream
     OPMM_HIP(ctx, hipStreamSynchronize((hipStream_t)stream));
     uint32_t n = 0;
     OPMM_HIP(ctx, hipMemcpy(&n, ctx->giveup_report, sizeof(uint32_t), hipMemcpyDeviceToHost));
@@ -1409,6 +1462,8 @@ int opmm_score(opmm_ctx* ctx, const float* opc, int64_t n, const float* pos, int
     if (n == 0) return OPMM_OK;
     OPMM_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
+    opmm_rt::Ordered ord(ctx->order, st);
+    OPMM_HIP(ctx, ord.error());
     FitScratch& sc = ctx->scratch;
     int64_t total_T;
     int tiles;
@@ -1428,7 +1483,11 @@ int opmm_fit(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccad
              const opmm_fit_params* params, const float* seed_opc, float* opc_out, float* rmse_out, float* mae_out,
              int32_t* status_out, uint64_t* round_keys, void* stream)
 {
+    if (!ctx) return OPMM_EINVAL;
     hipStream_t st = (hipStream_t)stream;
+    OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    opmm_rt::Ordered ord(ctx->order, st);
+    OPMM_HIP(ctx, ord.error());
     opmm_rt::FitStage fs;
     const SacDev* sd;
     const float* proj;
@@ -1451,6 +1510,11 @@ int opmm_fit_plan_create(opmm_ctx* ctx, const float* pos, int64_t pos_len, const
     opmm_plan* pl = new (std::nothrow) opmm_plan();
     if (!pl) return fail(ctx, OPMM_ENOMEM, "plan allocation failed");
     pl->ctx = ctx;
+    if (opmm_rt::order_init(pl->order) != hipSuccess) {
+        (void)hipGetLastError();
+        delete pl;
+        return fail(ctx, OPMM_EDEVICE, "plan event creation failed");
+    }
     const int shape = pick_shape(ctx, params, sacs, S);
     int64_t total_T;
     int tiles;
@@ -1490,6 +1554,8 @@ int opmm_plan_launch(opmm_plan* plan, void* stream)
     if (!plan || !plan->exec) return OPMM_EINVAL;
     opmm_ctx* ctx = plan->ctx;
     OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    opmm_rt::Ordered ord(plan->order, (hipStream_t)stream);  // launches of one plan share its scratch
+    OPMM_HIP(ctx, ord.error());
     OPMM_HIP(ctx, hipGraphLaunch(plan->exec, (hipStream_t)stream));
     return OPMM_OK;
 }
@@ -1501,6 +1567,7 @@ int opmm_plan_destroy(opmm_plan* plan)
     (void)hipDeviceSynchronize();
     if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    opmm_rt::order_release(plan->order);
     delete plan;
     return OPMM_OK;
 }
@@ -1513,6 +1580,8 @@ int opmm_autotune(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_s
     if (S == 0) return fail(ctx, OPMM_EINVAL, "autotune needs S >= 1");
     OPMM_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
+    opmm_rt::Ordered ord(ctx->order, st);
+    OPMM_HIP(ctx, ord.error());
     // sample: every k-th saccade, at most 256
     const int stride = std::max(1, S / 256);
     std::vector<opmm_saccade> sub;
@@ -1582,6 +1651,8 @@ int opmm_fit_noalloc(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opm
     if (!ctx->noalloc_scratch) return fail(ctx, OPMM_EDEVICE, "no device address for the allocation-free scratch");
     OPMM_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;
+    opmm_rt::Ordered ord(ctx->order, st);
+    OPMM_HIP(ctx, ord.error());
     const int shape = pick_shape(ctx, params, sacs, S);
     NoallocStage& g = g_noalloc_stage;
     std::lock_guard<std::mutex> lock(g.mu);

@@ -780,6 +780,8 @@ int opmm_polish(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_sac
         return opmm_rt::fail(ctx, OPMM_EINVAL, "bad arguments");
     if (S == 0) return OPMM_OK;
     hipStream_t st = (hipStream_t)stream;
+    opmm_rt::Ordered ord(opmm_rt::ctx_order(ctx), st);
+    if (ord.error() != hipSuccess) return opmm_rt::hip_fail(ctx, ord.error(), "stream ordering");
     const SacDev* d_sacs;
     const float* proj;
     const double* qorth;

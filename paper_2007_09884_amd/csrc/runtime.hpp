@@ -23,6 +23,43 @@ struct SacDev {
     int32_t model;     // 18 or 9 (tied K_SE/K_LT, neural parameters fixed)
 };
 
+// Calls on one object (context, surrogate, plan) share that object's device scratch, so a call on
+// one stream must not start on the scratch while an earlier call on another stream still uses it.
+// While every call comes on one stream, stream order does it and nothing is added.  At the first
+// call on a second stream the host waits once for the device to drain; from then on every call
+// records `ev` on its stream when it has queued its work, and a call on a stream other than the
+// last call's first makes its stream wait for that event (on the device).  A call queued under
+// stream capture takes no part: inside a graph the caller orders its work.
+struct StreamOrder {
+    hipEvent_t ev = nullptr;      // created with the object, timing disabled
+    hipStream_t last = nullptr;   // stream of the last call
+    bool seen = false;            // a call has been made
+    bool multi = false;           // calls have come on more than one stream
+    bool recorded = false;        // ev holds the end of the last call
+};
+hipError_t order_init(StreamOrder& o);
+void order_release(StreamOrder& o);
+// Host-side wait for the last call, for a synchronous call about to use stream `st`.
+hipError_t order_host_wait(const StreamOrder& o, hipStream_t st);
+
+// Scope of one call's use of an object's scratch on `st`: orders it after the previous call in the
+// constructor, records its end in the destructor.
+class Ordered {
+  public:
+    Ordered(StreamOrder& o, hipStream_t st);
+    ~Ordered();
+    Ordered(const Ordered&) = delete;
+    Ordered& operator=(const Ordered&) = delete;
+    hipError_t error() const { return err_; }
+
+  private:
+    StreamOrder& o_;
+    hipStream_t st_;
+    bool skip_ = false;
+    hipError_t err_ = hipSuccess;
+};
+StreamOrder& ctx_order(opmm_ctx* ctx);
+
 int fail(opmm_ctx* ctx, int code, const std::string& msg);
 int hip_fail(opmm_ctx* ctx, hipError_t e, const char* what);
 int ctx_device(const opmm_ctx* ctx);

@@ -572,6 +572,7 @@ struct opmm_surrogate {
     float* ring_tgt = nullptr;      // [GEN_BATCHES][ring_cap][18]
     float* ring_trace = nullptr;    // [GEN_BATCHES][ring_cap][MAX_T_GEN]
     int ring_cap = 0;
+    opmm_rt::StreamOrder order;  // orders calls on different streams (activations, gradients, Adam state)
 };
 
 namespace {
@@ -926,7 +927,7 @@ int opmm_surrogate_create(opmm_ctx* ctx, uint64_t init_seed, opmm_surrogate** ou
         hipMalloc(&sg->wf, sizeof(uint16_t) * NPACK) != hipSuccess ||
         hipMalloc(&sg->wbk, sizeof(uint16_t) * NPACK) != hipSuccess || hipMalloc(&sg->loss, sizeof(float)) != hipSuccess ||
         hipMalloc(&sg->gpart, sizeof(float) * DW_SLICES * NPARAM) != hipSuccess ||
-        hipMalloc(&sg->counter, sizeof(uint64_t)) != hipSuccess)
+        hipMalloc(&sg->counter, sizeof(uint64_t)) != hipSuccess || opmm_rt::order_init(sg->order) != hipSuccess)
         rc = OPMM_ENOMEM;
     if (rc == OPMM_OK) {
         hipLaunchKernelGGL(init_params_kernel, dim3(blocks(NPARAM, 256)), dim3(256), 0, 0, sg->w, init_seed);
@@ -959,6 +960,7 @@ int opmm_surrogate_destroy(opmm_surrogate* sg)
                     (void*)sg->counter,
                     (void*)sg->ring_feat, (void*)sg->ring_tgt, (void*)sg->ring_trace})
         if (p) (void)hipFree(p);
+    opmm_rt::order_release(sg->order);
     delete sg;
     return OPMM_OK;
 }
@@ -992,6 +994,8 @@ int opmm_surrogate_forward(opmm_surrogate* sg, const uint16_t* feat, int32_t B, 
     if (!sg || B < 0 || (B > 0 && (!feat || !out))) return OPMM_EINVAL;
     if (B == 0) return OPMM_OK;
     SG_HIP(hipSetDevice(sg->device));
+    opmm_rt::Ordered ord(sg->order, (hipStream_t)stream);
+    SG_HIP(ord.error());
     return sg_forward(sg, B, feat, out, (hipStream_t)stream);
 }
 
@@ -1001,6 +1005,8 @@ int opmm_surrogate_backward(opmm_surrogate* sg, const uint16_t* feat, const floa
     if (!sg || B <= 0 || !feat || !target) return OPMM_EINVAL;
     SG_HIP(hipSetDevice(sg->device));
     hipStream_t st = (hipStream_t)stream;
+    opmm_rt::Ordered ord(sg->order, st);
+    SG_HIP(ord.error());
     int rc;
     if ((rc = sg_alloc(sg, B)) != OPMM_OK) return rc;
     hipLaunchKernelGGL(fill_f32_kernel, dim3(1), dim3(64), 0, st, sg->loss, 1, 0.0f);
@@ -1018,6 +1024,8 @@ int opmm_surrogate_generate(opmm_surrogate* sg, uint64_t data_seed, uint64_t ste
     if (!sg || B <= 0 || !feat_out || !target_out) return OPMM_EINVAL;
     SG_HIP(hipSetDevice(sg->device));
     hipStream_t st = (hipStream_t)stream;
+    opmm_rt::Ordered ord(sg->order, st);
+    SG_HIP(ord.error());
     int rc;
     if ((rc = sg_alloc(sg, B)) != OPMM_OK) return rc;
     SG_HIP(hipMemcpyAsync(sg->counter, &step, sizeof(uint64_t), hipMemcpyHostToDevice, st));
@@ -1034,6 +1042,8 @@ int opmm_surrogate_train(opmm_surrogate* sg, uint64_t data_seed, int32_t B, int3
     if (!sg || B <= 0 || n_steps < 0) return OPMM_EINVAL;
     SG_HIP(hipSetDevice(sg->device));
     hipStream_t st = (hipStream_t)stream;
+    opmm_rt::Ordered ord(sg->order, st);
+    SG_HIP(ord.error());
     int rc;
     if ((rc = sg_alloc(sg, B)) != OPMM_OK) return rc;
     if (sg->ring_cap < B) {
@@ -1085,6 +1095,8 @@ int opmm_surrogate_adam_step(opmm_surrogate* sg, float lr, void* stream)
 {
     if (!sg) return OPMM_EINVAL;
     SG_HIP(hipSetDevice(sg->device));
+    opmm_rt::Ordered ord(sg->order, (hipStream_t)stream);
+    SG_HIP(ord.error());
     return sg_adam(sg, lr, (hipStream_t)stream);
 }
 
@@ -1110,6 +1122,8 @@ int surrogate_predict_projected(opmm_surrogate* sg, int n, const SacDev* sacs, c
                                 float box_frac, float* opc_out, hipStream_t st)
 {
     if (n <= 0) return OPMM_OK;
+    opmm_rt::Ordered ord(sg->order, st);
+    SG_HIP(ord.error());
     return sg_predict(sg, n, sacs, proj, dt_ms, box_frac, opc_out, st);
 }
 }  // namespace opmm_rt
@@ -1126,6 +1140,10 @@ int opmm_surrogate_predict(opmm_surrogate* sg, const float* pos, int64_t pos_len
     if (S == 0) return OPMM_OK;
     SG_HIP(hipSetDevice(sg->device));
     hipStream_t st = (hipStream_t)stream;
+    opmm_rt::Ordered ord_ctx(opmm_rt::ctx_order(ctx), st);
+    SG_HIP(ord_ctx.error());
+    opmm_rt::Ordered ord(sg->order, st);
+    SG_HIP(ord.error());
     int rc;
     const opmm_rt::SacDev* sd;
     const float* proj;
@@ -1141,6 +1159,10 @@ int opmm_surrogate_features(opmm_surrogate* sg, const float* pos, int64_t pos_le
     if (S <= 0 || !pos || !sacs || !feat_out) return opmm_rt::fail(ctx, OPMM_EINVAL, "bad arguments");
     SG_HIP(hipSetDevice(sg->device));
     hipStream_t st = (hipStream_t)stream;
+    opmm_rt::Ordered ord_ctx(opmm_rt::ctx_order(ctx), st);
+    SG_HIP(ord_ctx.error());
+    opmm_rt::Ordered ord(sg->order, st);
+    SG_HIP(ord.error());
     const opmm_rt::SacDev* sd;
     const float* proj;
     int rc;
@@ -1165,6 +1187,10 @@ int opmm_fit_learned(opmm_surrogate* sg, const float* pos, int64_t pos_len, cons
     if (S == 0) return OPMM_OK;
     SG_HIP(hipSetDevice(sg->device));
     hipStream_t st = (hipStream_t)stream;
+    opmm_rt::Ordered ord_ctx(opmm_rt::ctx_order(ctx), st);
+    SG_HIP(ord_ctx.error());
+    opmm_rt::Ordered ord(sg->order, st);
+    SG_HIP(ord.error());
     // 1. one upload and projection of the batch serves the learned seeds and the seeded refine
     opmm_rt::FitStage fs;
     const opmm_rt::SacDev* sd;
