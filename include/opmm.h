@@ -245,6 +245,25 @@ int opmm_plan_destroy(opmm_plan* plan);
  * Writes the chosen shape index to *tile_out (host, nullable). */
 int opmm_autotune(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs,
                   int32_t S, const opmm_fit_params* params, int32_t* tile_out, void* stream);
+/* Autotuner cache.  Each opmm_autotune also files its pick under the batch's
+ * key: launch mode, model, the longest trace and the batch size each rounded
+ * up to a power of two, and the largest candidate count.  A later fit, plan
+ * or learned fit with tile = -1 whose batch has a filed key runs that shape;
+ * other batches keep the context's last pick, or the library default.
+ *   opmm_tune_cache_lookup: the filed shape of a batch in *tile_out (host), or
+ *     -1 if none.  Host only.
+ *   opmm_tune_cache_save: writes the context's entries to a text file, one
+ *     line each: device architecture name, the key, shape name, measured ms.
+ *   opmm_tune_cache_load: adds the entries of such a file that were written
+ *     for this device's architecture (other lines, and shapes this build
+ *     does not have, are skipped; a filed key is replaced).  Nothing is added
+ *     if any line is malformed.
+ * Errors: OPMM_EINVAL for a NULL argument, a file that cannot be opened or
+ * written, or a malformed line (opmm_last_error names it). */
+int opmm_tune_cache_lookup(opmm_ctx* ctx, const opmm_saccade* sacs, int32_t S,
+                           const opmm_fit_params* params, int32_t* tile_out);
+int opmm_tune_cache_save(opmm_ctx* ctx, const char* path);
+int opmm_tune_cache_load(opmm_ctx* ctx, const char* path);
 /* Number of kernel shapes, a description of shape i (host string), and the
  * shape used for tile = -1 on a context that has not been autotuned (the
  * fastest per-round shape of a sweep on the full-estimation workload). */

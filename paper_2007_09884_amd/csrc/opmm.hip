@@ -738,8 +738,27 @@ struct FitScratch {
 // process ends.  Host code uses the address opmm_create looked up, never this name.
 static __device__ __align__(256) unsigned char scratch[OPMM_NOALLOC_SCRATCH_BYTES];
 
+// Autotuner cache key: what decides which kernel shape is fastest for a batch.
+struct TuneKey {
+    int mode, model;
+    int t_bucket, s_bucket;  // longest trace and batch size, each rounded up to a power of two
+    int64_t n_cand;          // largest candidate count in the batch
+    bool operator==(const TuneKey& o) const
+    {
+        return mode == o.mode && model == o.model && t_bucket == o.t_bucket && s_bucket == o.s_bucket &&
+               n_cand == o.n_cand;
+    }
+};
+struct TuneEntry {
+    TuneKey key;
+    int shape;
+    float ms;
+};
+
 struct opmm_ctx {
     int device = 0;
+    std::string arch;                 // device architecture name (autotuner cache files are per architecture)
+    std::vector<TuneEntry> tune;      // autotuner picks by batch key
     int cu_count = 0;
     uint32_t wait_limit = 1u << 26;        // polls before a persistent block gives up (several seconds)
     uint32_t* giveup_report = nullptr;     // device word: give-ups since the last opmm_sync
@@ -1128,9 +1147,47 @@ int launch_shape_impl(const opmm_ctx* ctx, int base, int64_t tiles)
     return tiles < std::max(ctx->cu_count, 1) ? kSmallTileShape : base;
 }
 
+int pow2_at_least(int64_t v)
+{
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return (int)p;
+}
+
+TuneKey tune_key(const opmm_fit_params* prm, const opmm_saccade* sacs, int S)
+{
+    int max_t = 1;
+    int64_t most = 0;
+    for (int i = 0; i < S; ++i) {
+        max_t = std::max(max_t, (int)sacs[i].T);
+        most = std::max<int64_t>(most, sacs[i].n_cand > 0 ? sacs[i].n_cand : prm->n_cand);
+    }
+    return TuneKey{prm->mode, prm->model, pow2_at_least(max_t), pow2_at_least(std::max(S, 1)), most};
+}
+
+int tune_find(const opmm_ctx* ctx, const TuneKey& k)
+{
+    for (const TuneEntry& e : ctx->tune)
+        if (e.key == k) return e.shape;
+    return -1;
+}
+
+void tune_file(opmm_ctx* ctx, const TuneKey& k, int shape, float ms)
+{
+    for (TuneEntry& e : ctx->tune)
+        if (e.key == k) {
+            e.shape = shape;
+            e.ms = ms;
+            return;
+        }
+    ctx->tune.push_back(TuneEntry{k, shape, ms});
+}
+
 int pick_shape(opmm_ctx* ctx, const opmm_fit_params* prm, const opmm_saccade* sacs, int S)
 {
     if (prm->tile >= 0) return prm->tile;
+    const int filed = tune_find(ctx, tune_key(prm, sacs, S));
+    if (filed >= 0) return filed;
     int64_t most = 0;
     for (int i = 0; i < S; ++i) most = std::max<int64_t>(most, sacs[i].n_cand > 0 ? sacs[i].n_cand : prm->n_cand);
     const int base = shape_for(ctx, most);
@@ -1345,7 +1402,10 @@ int opmm_create(opmm_ctx** out, int device)
     if (!c) return OPMM_ENOMEM;
     c->device = device;
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->cu_count = prop.multiProcessorCount;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        c->cu_count = prop.multiProcessorCount;
+        c->arch = prop.gcnArchName;
+    }
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return OPMM_EDEVICE;
@@ -1412,6 +1472,66 @@ int opmm_tile_count(void) { return kNumShapes; }
 int opmm_tile_default(void) { return kDefaultShape; }
 
 const char* opmm_tile_name(int i) { return (i >= 0 && i < kNumShapes) ? kShapes[i].name : ""; }
+
+int opmm_tune_cache_lookup(opmm_ctx* ctx, const opmm_saccade* sacs, int32_t S, const opmm_fit_params* params,
+                           int32_t* tile_out)
+{
+    if (!ctx) return OPMM_EINVAL;
+    if (!params || !tile_out || S < 0 || (S > 0 && !sacs)) return fail(ctx, OPMM_EINVAL, "bad arguments");
+    *tile_out = tune_find(ctx, tune_key(params, sacs, S));
+    return OPMM_OK;
+}
+
+int opmm_tune_cache_save(opmm_ctx* ctx, const char* path)
+{
+    if (!ctx) return OPMM_EINVAL;
+    if (!path) return fail(ctx, OPMM_EINVAL, "path is NULL");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(ctx, OPMM_EINVAL, std::string("cannot write ") + path);
+    bool ok = std::fprintf(f, "# opmm autotuner cache: arch mode model t_bucket s_bucket n_cand shape ms\n") > 0;
+    for (const TuneEntry& e : ctx->tune)
+        ok = ok && std::fprintf(f, "%s %d %d %d %d %lld %s %.4f\n", ctx->arch.c_str(), e.key.mode, e.key.model,
+                                e.key.t_bucket, e.key.s_bucket, (long long)e.key.n_cand, kShapes[e.shape].name,
+                                (double)e.ms) > 0;
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? OPMM_OK : fail(ctx, OPMM_EINVAL, std::string("write failed: ") + path);
+}
+
+int opmm_tune_cache_load(opmm_ctx* ctx, const char* path)
+{
+    if (!ctx) return OPMM_EINVAL;
+    if (!path) return fail(ctx, OPMM_EINVAL, "path is NULL");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(ctx, OPMM_EINVAL, std::string("cannot read ") + path);
+    std::vector<TuneEntry> add;
+    char line[512];
+    int lineno = 0, rc = OPMM_OK;
+    while (rc == OPMM_OK && std::fgets(line, sizeof line, f)) {
+        ++lineno;
+        if (line[0] == '#' || line[0] == '\n' || line[0] == '\0') continue;
+        char arch[256], name[128];
+        int mode, model, tb, sb;
+        long long nc;
+        float ms;
+        if (std::sscanf(line, "%255s %d %d %d %d %lld %127s %f", arch, &mode, &model, &tb, &sb, &nc, name, &ms) != 8 ||
+            (mode != OPMM_FIT_ROUNDS && mode != OPMM_FIT_PERSISTENT) || (model != 18 && model != 9) || tb < 1 ||
+            sb < 1 || nc < 1) {
+            rc = fail(ctx, OPMM_EINVAL, std::string("malformed autotuner cache line ") + std::to_string(lineno) +
+                                            " in " + path);
+            break;
+        }
+        if (ctx->arch != arch) continue;  // written for another device
+        int shape = -1;
+        for (int i = 0; i < kNumShapes; ++i)
+            if (std::strcmp(kShapes[i].name, name) == 0) shape = i;
+        if (shape < 0) continue;  // a shape this build does not have
+        add.push_back(TuneEntry{TuneKey{mode, model, tb, sb, (int64_t)nc}, shape, ms});
+    }
+    std::fclose(f);
+    if (rc != OPMM_OK) return rc;
+    for (const TuneEntry& e : add) tune_file(ctx, e.key, e.shape, e.ms);
+    return OPMM_OK;
+}
 
 int opmm_candidates(opmm_ctx* ctx, uint64_t seed, uint32_t round, uint32_t idx0, int64_t n, const float* c,
                     const float* w, const float* lo, const float* hi, float* out, void* stream)
@@ -1625,6 +1745,7 @@ int opmm_autotune(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_s
     (void)hipFree(out.p);
     if (rc != OPMM_OK) return rc;
     ctx->tuned_shape = best;
+    tune_file(ctx, tune_key(params, sacs, S), best, best_ms);
     if (tile_out) *tile_out = best;
     return OPMM_OK;
 }

@@ -86,6 +86,9 @@ def _load():
         "opmm_plan_destroy": (ctypes.c_int, [vp]),
         "opmm_autotune": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(FitParams),
                                          ctypes.POINTER(i32), vp]),
+        "opmm_tune_cache_lookup": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(FitParams), ctypes.POINTER(i32)]),
+        "opmm_tune_cache_save": (ctypes.c_int, [vp, ctypes.c_char_p]),
+        "opmm_tune_cache_load": (ctypes.c_int, [vp, ctypes.c_char_p]),
         "opmm_tile_count": (ctypes.c_int, []),
         "opmm_tile_default": (ctypes.c_int, []),
         "opmm_tile_name": (ctypes.c_char_p, [ctypes.c_int]),
@@ -316,6 +319,20 @@ class Context:
         self._check(lib.opmm_autotune(self._h, _ptr(pos), pos.numel(), recs.ctypes.data_as(ctypes.c_void_p),
                                       recs.shape[0], ctypes.byref(params), ctypes.byref(t), _stream(stream)))
         return t.value
+
+    def tune_cache_lookup(self, recs, params: FitParams) -> int:
+        """The shape the autotuner cache holds for this batch, or -1."""
+        recs = np.ascontiguousarray(recs, SACCADE_DTYPE)
+        t = ctypes.c_int32(-1)
+        self._check(lib.opmm_tune_cache_lookup(self._h, recs.ctypes.data_as(ctypes.c_void_p), recs.shape[0],
+                                               ctypes.byref(params), ctypes.byref(t)))
+        return t.value
+
+    def tune_cache_save(self, path):
+        self._check(lib.opmm_tune_cache_save(self._h, os.fsencode(path)))
+
+    def tune_cache_load(self, path):
+        self._check(lib.opmm_tune_cache_load(self._h, os.fsencode(path)))
 
     def plan(self, pos, recs, params: FitParams, opc_out, rmse_out, mae_out=None, status_out=None,
              round_keys=None, seed_opc=None, stream=None) -> "Plan":
