@@ -297,6 +297,48 @@ def test_fit_full_size_sampled(ctx, opmm):
     print("largest sampled cost error over 16 saccades x 10 rounds: %.3g" % worst)
 
 
+def test_bench_configuration_sampled(ctx, opmm):
+    """The full-estimation workload exactly as the benchmark times it: 256 saccades x 65536 candidates x
+    10 rounds, the default kernel shape, per-round launches captured in one graph.  Every saccade's
+    reported RMSE and OptErr are the oracle's for the returned OPC (Section 3.4's CPU_check); the graph
+    replay equals an eager fit bit for bit; four saccades (longest, shortest, two more) have every
+    round checked on a sample (sampled_round_check)."""
+    b, traces = make_batch(256, "full")
+    S, N, R = b["S"], 65536, 10
+    recs = records(b, opmm)
+    pos = dev(opmm.pack_traces(traces))
+    prm = opmm.fit_params(n_cand=N, n_rounds=R, mode=opmm.FIT_ROUNDS, tile=opmm.lib.opmm_tile_default())
+    opc = torch.zeros(S, 18, device="cuda")
+    rmse = torch.zeros(S, device="cuda")
+    mae = torch.zeros(S, device="cuda")
+    st = torch.zeros(S, dtype=torch.int32, device="cuda")
+    keys = torch.zeros(R, S, dtype=torch.int64, device="cuda")
+    plan = ctx.plan(pos, recs, prm, opc, rmse, mae, st, keys)
+    for t in (opc, rmse, mae, st, keys):
+        t.zero_()
+    plan.launch()
+    ctx.sync()
+    plan.close()
+    keys = keys.cpu().numpy().view(np.uint64)
+    opc, rmse, mae = opc.cpu().numpy(), rmse.cpu().numpy(), mae.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    eager = run_fit(ctx, opmm, b, traces, N, R, mode=opmm.FIT_ROUNDS, tile=opmm.lib.opmm_tile_default())
+    assert np.array_equal(eager["keys"], keys) and np.array_equal(eager["opc"].view(np.uint32), opc.view(np.uint32))
+    for s in range(S):
+        th = oracle.simulate(opc[s].astype(np.float64), b["amp"][s], int(b["T"][s]))
+        rm, ma = oracle.cost(th, traces[s], b["dir_deg"][s])
+        assert abs(rm - rmse[s]) <= 1e-6 * max(1.0, rm) and abs(ma - mae[s]) <= 1e-6 * max(1.0, ma), s
+    rng = np.random.default_rng(79)
+    picks = [int(np.argmax(b["T"])), int(np.argmin(b["T"])), 100, 201]
+    for s in picks:
+        cen, w, lo, hi = centre_chain(b, s, keys, R)
+        assert np.array_equal(opc[s], cen[R])
+        for r in range(R):
+            idx = int(keys[r, s] & np.uint64(0xFFFFFFFF))
+            sampled_round_check(ctx, opmm, b, s, traces[s], r, cen[r], w * np.float32(0.5 ** r), lo, hi, idx, N,
+                                rng, (s, r))
+
+
 def test_fit_uneven_full_size_sampled(ctx, opmm):
     """The batched-uneven configuration at its full size: 4096 saccades of 20-150 samples with
     per-saccade candidate counts from {4096, 16384, 65536}, autotuned shape, one persistent launch
