@@ -188,7 +188,8 @@ int opmm_score(opmm_ctx* ctx, const float* opc, int64_t n, const float* pos, int
  *   pos, pos_len   packed traces (device), see opmm_saccade
  *   sacs           host [S]
  *   seed_opc       NULL, or device [S][18] round-0 centres (clamped into the
- *                  box; status gets OPMM_ST_SEEDED)
+ *                  box; a NaN component keeps the nominal centre; status
+ *                  gets OPMM_ST_SEEDED)
  *   opc_out        device [S][18]  fitted OPC (the final argmin)
  *   rmse_out       device [S]      its RMSE over both channels (deg)
  *   mae_out        NULL or device [S]: its mean absolute difference (OptErr)

@@ -390,7 +390,8 @@ int oracle_score(const float* opc, int64_t n, const float* pos, int T, int C, do
  * half-width w^r (candidate 0 = c^r), scores them all, takes the argmin (lowest
  * RMSE, ties to the lowest index, NaN ranks last), and sets c^{r+1} to the
  * winner and w^{r+1} = shrink * w^r.  c_init (nullable) replaces the nominal
- * round-0 centre (it is clamped into the box); w_init_frac scales the round-0
+ * round-0 centre (it is clamped into the box; a NaN component keeps the
+ * nominal value); w_init_frac scales the round-0
  * half-width relative to the box half-width.  Outputs: the final OPC, its
  * RMSE and mean-abs, and per round the winner index, its RMSE and the centre
  * the round was drawn around (centres: [n_rounds][18], nullable). */
@@ -408,6 +409,7 @@ int oracle_fit(const float* pos, int T, int C, double amp, double dir_deg, doubl
     if (c_init)
         for (int j = 0; j < NP; ++j) {
             float v = c_init[(model == 9 && (j == 1 || j == 3)) ? j - 1 : j];
+            if (v != v) continue;  /* an unusable (NaN) seed component keeps the nominal centre */
             c[j] = v < lo[j] ? lo[j] : (v > hi[j] ? hi[j] : v);
         }
     float* cand = (float*)malloc(sizeof(float) * NP * n_cand);

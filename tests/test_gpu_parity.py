@@ -297,6 +297,49 @@ def test_fit_full_size_sampled(ctx, opmm):
     print("largest sampled cost error over 16 saccades x 10 rounds: %.3g" % worst)
 
 
+def test_seeded_refine_replays_against_oracle(ctx, opmm):
+    """The learned path's refine configuration -- 1024 candidates x 3 rounds around a given round-0
+    centre with a quarter-width box -- replayed round by round: every candidate of every round scored
+    by the oracle around the GPU's chain of winners, the winner checked by the argmin rule.  Seeds
+    include a component outside the box (clamped) and a NaN component (the nominal centre is kept);
+    the oracle's own seeded fit starts from the same round-0 centre."""
+    b, traces = make_batch(6, "full", seed=synth.BASE_SEED + 31)
+    S, N, R = b["S"], 1024, 3
+    rng = np.random.default_rng(5)
+    seeds = np.stack([oracle.true_opc(b["mult"][s], b["dur_ms"][s]) * rng.uniform(0.9, 1.1, 18)
+                      for s in range(S)]).astype(np.float32)
+    seeds[1, 4] *= np.float32(3.0)
+    seeds[2, 7] = np.nan
+    recs = records(b, opmm)
+    pos = dev(opmm.pack_traces(traces))
+    prm = opmm.fit_params(n_cand=N, n_rounds=R, w_init_frac=0.25)
+    opc = torch.zeros(S, 18, device="cuda")
+    rmse = torch.zeros(S, device="cuda")
+    st = torch.zeros(S, dtype=torch.int32, device="cuda")
+    keys = torch.zeros(R, S, dtype=torch.int64, device="cuda")
+    ctx.fit(pos, recs, prm, opc, rmse, None, st, keys, seed_opc=dev(seeds))
+    ctx.sync()
+    keys = keys.cpu().numpy().view(np.uint64)
+    opc, rmse = opc.cpu().numpy(), rmse.cpu().numpy()
+    assert np.all(st.cpu().numpy() == opmm.ST_SEEDED)
+    for s in range(S):
+        c0, w0, lo, hi = oracle.initial_box(b["dur_ms"][s])
+        ref = oracle.fit(traces[s], b["amp"][s], b["dir_deg"][s], b["dur_ms"][s], int(b["seed"][s]), N, R,
+                         w_init_frac=0.25, c_init=seeds[s], nthreads=NTH)
+        start = np.where(np.isnan(seeds[s]), c0, np.clip(seeds[s], lo, hi)).astype(np.float32)
+        assert np.array_equal(ref["centres"][0], start), s
+        cen, w = start, w0 * np.float32(0.25)
+        for r in range(R):
+            cands = oracle.candidates(int(b["seed"][s]), r, range(N), cen, w * np.float32(0.5 ** r), lo, hi)
+            costs, _ = oracle.score(cands, traces[s], b["amp"][s], b["dir_deg"][s], nthreads=NTH)
+            idx = int(keys[r, s] & np.uint64(0xFFFFFFFF))
+            check_argmin(costs, idx, (s, r))
+            cen = cands[idx]
+        assert np.array_equal(opc[s], cen), s
+        th = oracle.simulate(opc[s].astype(np.float64), b["amp"][s], int(b["T"][s]))
+        assert abs(oracle.cost(th, traces[s], b["dir_deg"][s])[0] - rmse[s]) <= 1e-6 * max(1.0, rmse[s])
+
+
 def test_bench_configuration_sampled(ctx, opmm):
     """The full-estimation workload exactly as the benchmark times it: 256 saccades x 65536 candidates x
     10 rounds, the default kernel shape, per-round launches captured in one graph.  Every saccade's

@@ -503,3 +503,18 @@ def test_anchor_eigenvalues():
     against the anchor to 0.1 %: the activation modes -1/tau in each piece, and the four mechanical
     modes (shared by both pieces) at the anchor's passive elasticity."""
     assert anchor_eigen_errors(oracle.rhs) < 1e-3
+
+
+def test_seeded_round0_centre():
+    """A seeded fit starts at the seed clamped into the box; a NaN component keeps the nominal centre
+    (the library's documented rule for an unusable seed); with one candidate per round (the centre)
+    nothing moves, so the reported OPC is that start."""
+    c0, w0, lo, hi = oracle.initial_box(43.0)
+    seed = (c0 * np.float32(1.1)).astype(np.float32)
+    seed[4] = hi[4] * np.float32(2.0)
+    seed[7] = np.nan
+    pos = np.zeros((80, 1), np.float32)
+    res = oracle.fit(pos, 10.0, 0.0, 43.0, 5, 1, 2, w_init_frac=0.25, c_init=seed)
+    want = np.where(np.isnan(seed), c0, np.minimum(np.maximum(seed, lo), hi)).astype(np.float32)
+    assert want[4] == hi[4] and want[7] == c0[7]
+    assert np.array_equal(res["centres"][0], want) and np.array_equal(res["opc"], want)
