@@ -333,3 +333,43 @@ def test_generated_batch_matches_oracle(ctx, opmm, sigma_max):
         vel_ok = np.abs(fg[i, 1::2] - rf[1::2]) <= 2 ** -7 * np.abs(rf[1::2]) + 2e-5
         assert np.all(pos_ok) and np.all(vel_ok), (i, np.flatnonzero(~pos_ok), np.flatnonzero(~vel_ok))
     sg.close()
+
+
+def test_predict_and_learned_fit_compose_the_pinned_parts(ctx, opmm):
+    """The learned seed is composed of separately pinned parts, and nothing else: opmm_surrogate_predict
+    equals the network's forward pass on opmm_surrogate_features, de-normalised as
+    nominal x clip(1 + 0.3 z, 1 - box_frac, 1 + box_frac) in FP32 (bit for bit); opmm_fit_learned with
+    no fallback equals opmm_fit seeded with those predictions (bit for bit)."""
+    sg = opmm.Surrogate(ctx, init_seed=9)
+    sg.train(data_seed=3, batch=1024, n_steps=40)
+    b, traces = make_batch(40, "full", seed=synth.BASE_SEED + 901)
+    S = b["S"]
+    recs = records(b, opmm)
+    pos = torch.from_numpy(opmm.pack_traces(traces)).cuda()
+    feat = torch.zeros(S, 256, dtype=torch.int16, device="cuda")
+    sg.features(pos, recs, feat)
+    z = torch.zeros(S, 18, device="cuda")
+    sg.forward(feat, z)
+    pred = torch.zeros(S, 18, device="cuda")
+    box = 0.25
+    sg.predict(pos, recs, pred, box_frac=box)
+    torch.cuda.synchronize()
+    z, pred = z.cpu().numpy(), pred.cpu().numpy()
+    f32 = np.float32
+    for s in range(S):
+        nom = opmm.nominal(float(b["dur_ms"][s]))
+        mlt = np.minimum(np.maximum(f32(1.0) + f32(0.3) * z[s], f32(1.0 - box)), f32(1.0 + box))
+        assert np.array_equal((nom * mlt).astype(np.float32).view(np.uint32), pred[s].view(np.uint32)), s
+    seeded = opmm.fit_params(n_cand=1024, n_rounds=3, w_init_frac=0.25, box_frac=box)
+    opc1 = torch.zeros(S, 18, device="cuda"); rm1 = torch.zeros(S, device="cuda")
+    st1 = torch.zeros(S, dtype=torch.int32, device="cuda")
+    nf = sg.fit(pos, recs, seeded, opmm.fit_params(n_cand=1024, n_rounds=3), 1e9, opc1, rm1, st1)
+    opc2 = torch.zeros(S, 18, device="cuda"); rm2 = torch.zeros(S, device="cuda")
+    st2 = torch.zeros(S, dtype=torch.int32, device="cuda")
+    ctx.fit(pos, recs, seeded, opc2, rm2, None, st2, seed_opc=torch.from_numpy(pred).cuda())
+    torch.cuda.synchronize()
+    assert nf == 0
+    assert np.array_equal(opc1.cpu().numpy().view(np.uint32), opc2.cpu().numpy().view(np.uint32))
+    assert np.array_equal(rm1.cpu().numpy(), rm2.cpu().numpy())
+    assert np.array_equal(st1.cpu().numpy(), st2.cpu().numpy())
+    sg.close()
