@@ -347,7 +347,11 @@ int opmm_surrogate_load(opmm_surrogate* sg, const char* path);
  * Each admitted request owns a device slot (trace, projection, search box,
  * status, round key stay resident in HBM); opmm_server_step advances every
  * occupied slot by one search round in one launch, whatever round each is
- * at, and admits waiting requests as slots free up.  The slot count is the
+ * at, and admits waiting requests as slots free up.  While such a launch
+ * would leave compute units idle (fewer candidate tiles than CUs), the step
+ * runs further rounds for the slots still searching, up to rounds_per_step
+ * launches: a light load then finishes a search in one step instead of one
+ * step per round.  The slot count is the
  * HBM budget divided by one slot's footprint (capped by max_slots).  A
  * result depends only on its own request: the same alone and in the mix.
  * With a surrogate, requests start from the learned seed (`seeded`) and fall
@@ -368,10 +372,11 @@ typedef struct {
     opmm_fit_params seeded;   /* search from the learned seed                */
     float fallback_rmse;      /* deg; e.g. 1.5 x the noise floor             */
     int32_t polish_iter;      /* polish iterations per finished search, 0-100 */
+    int32_t rounds_per_step;  /* most round launches in one step, 1-64     */
 } opmm_serve_params;
 
 /* Defaults: 4096 slots, max_T 160, 1 GiB; plain 4096 x 10, seeded 1024 x 3
- * with w_init_frac 0.25; fallback 0.075 deg; no polish.  plain and seeded
+ * with w_init_frac 0.25; fallback 0.075 deg; no polish; 16 rounds per step.  plain and seeded
  * must share dt_ms, box_frac and shrink. */
 void opmm_serve_params_default(opmm_serve_params* p);
 /* sg nullable (no learned seed).  The server keeps ctx and sg. */
@@ -389,9 +394,9 @@ int opmm_server_submit(opmm_server* sv, const float* host_trace, const opmm_sacc
  * records are validated before any is queued. */
 int opmm_server_submit_many(opmm_server* sv, const float* host_pos, int64_t pos_len, const opmm_saccade* sacs,
                             int32_t n, const double* t_arrival, int64_t* ids_out);
-/* Admit, run one round over all occupied slots, harvest finished requests
- * (synchronises the server stream; polish batches still running are taken by
- * a later step).  *n_done_out (nullable) = requests completed by this step. */
+/* Admit, run one round over all occupied slots (more while the device would
+ * sit idle, see above), harvest finished requests (synchronises the server
+ * stream; polish batches still running are taken by a later step).  *n_done_out (nullable) = requests completed by this step. */
 int opmm_server_step(opmm_server* sv, int32_t* n_done_out);
 /* Pop up to max completed results (host arrays, each nullable except n_out):
  * ids[n], opc[n][18], rmse[n], mae[n], status[n], t_arrival[n], t_done[n]. */

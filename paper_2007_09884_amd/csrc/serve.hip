@@ -30,6 +30,7 @@ namespace {
 
 constexpr int P = OPMM_P;
 constexpr int kMaxAdmitPerStep = 4096;
+constexpr int kMaxRoundsPerStep = 64;
 constexpr int kPolishBatches = 3;
 
 struct Request {
@@ -126,6 +127,8 @@ struct opmm_server {
     int pb_head = 0, pb_count = 0;  // ring of in-flight batches, oldest at pb_head
     // pinned host staging
     SacDev* h_list = nullptr;  // 4 x [slots]: restart, admitted, active and finished lists of a step
+    SacDev* h_more = nullptr;  // [rounds_per_step - 1][cus]: active lists of a step's further rounds
+    int cus = 1;               // compute units of the device
     float* h_out = nullptr;
     int32_t* h_st = nullptr;
     float* h_adm_trace = nullptr;  // [max_admit][max_T * 2]: traces admitted in one step
@@ -195,6 +198,7 @@ void opmm_serve_params_default(opmm_serve_params* p)
     p->seeded.n_rounds = 3;
     p->seeded.w_init_frac = 0.25f;
     p->fallback_rmse = 0.075f;
+    p->rounds_per_step = 16;
 }
 
 double opmm_server_now(void) { return now_s(); }
@@ -217,6 +221,8 @@ int opmm_server_create(opmm_ctx* ctx, opmm_surrogate* sg, const opmm_serve_param
         return opmm_rt::fail(ctx, OPMM_EINVAL, "plain and seeded searches must share dt_ms, box_frac, shrink and model");
     if (prm->polish_iter < 0 || prm->polish_iter > 100)
         return opmm_rt::fail(ctx, OPMM_EINVAL, "polish_iter must be in 0..100");
+    if (prm->rounds_per_step < 1 || prm->rounds_per_step > kMaxRoundsPerStep)
+        return opmm_rt::fail(ctx, OPMM_EINVAL, "rounds_per_step must be in 1..64");
     // slots admitted by memory: what one resident request costs on the device
     const size_t per_slot = sizeof(float) * (3 * (size_t)prm->max_T + 4 * P + P + P + 2) + sizeof(int32_t) * 2 +
                             sizeof(uint64_t) + sizeof(double) + sizeof(SacDev) +
@@ -253,6 +259,9 @@ int opmm_server_create(opmm_ctx* ctx, opmm_surrogate* sg, const opmm_serve_param
     dm((void**)&sv->d_out, sizeof(float) * (P + 2) * (size_t)slots);
     dm((void**)&sv->d_st, sizeof(int32_t) * slots);
     hm((void**)&sv->h_list, sizeof(SacDev) * 4 * (size_t)slots);
+    sv->cus = opmm_rt::ctx_cu_count(ctx);
+    if (prm->rounds_per_step > 1)
+        hm((void**)&sv->h_more, sizeof(SacDev) * (size_t)(prm->rounds_per_step - 1) * sv->cus);
     hm((void**)&sv->h_out, sizeof(float) * (P + 2) * (size_t)slots);
     hm((void**)&sv->h_st, sizeof(int32_t) * slots);
     // a step admits at most max_admit requests; size the per-call scratch for that now, so no step
@@ -304,7 +313,7 @@ int opmm_server_destroy(opmm_server* sv)
                     (void*)sv->d_qorth, (void*)sv->d_list, (void*)sv->d_seed, (void*)sv->d_out, (void*)sv->d_st,
                     (void*)sv->d_adm_trace})
         if (p) (void)hipFree(p);
-    for (void* p : {(void*)sv->h_list, (void*)sv->h_out, (void*)sv->h_st, (void*)sv->h_adm_trace})
+    for (void* p : {(void*)sv->h_list, (void*)sv->h_more, (void*)sv->h_out, (void*)sv->h_st, (void*)sv->h_adm_trace})
         if (p) (void)hipHostFree(p);
     for (PolishBatch& b : sv->pb) {
         for (void* p : {(void*)b.d_list, (void*)b.d_out, (void*)b.d_st})
@@ -494,36 +503,47 @@ int opmm_server_step(opmm_server* sv, int32_t* n_done_out)
         queued = true;
     }
     // 3. one round for every occupied slot, each at its own round; a step too small to fill the
-    // device takes the smaller-tile shape
+    // device takes the smaller-tile shape.  While a round's launch has fewer tiles than the device
+    // has CUs, further rounds follow for the slots still searching (each runs its own sequence of
+    // rounds, so results do not depend on how rounds fall into steps), up to rounds_per_step.  A
+    // further round's list is a subset of the previous one (fewer than `cus` records), staged in its
+    // own part of h_more.
     std::vector<int> act;
-    int64_t base_tiles = 0;
     for (int k = 0; k < sv->slots; ++k) {
-        Slot& sl = sv->slot[k];
-        if (!sl.busy || sl.round >= sl.rounds) continue;
-        h_act[act.size()] = slot_record(sv, k);
-        base_tiles += h_act[act.size()].tiles;
-        act.push_back(k);
+        const Slot& sl = sv->slot[k];
+        if (sl.busy && sl.round < sl.rounds) act.push_back(k);
     }
-    const int na = (int)act.size();
-    const int shape = opmm_rt::launch_shape(sv->ctx, sv->shape, base_tiles);
-    const int tile = opmm_rt::shape_tile(shape);
-    int tiles = 0;
-    for (int i = 0; i < na; ++i) {
-        h_act[i].tiles = (h_act[i].n_cand + tile - 1) / tile;
-        h_act[i].tile_base = tiles;
-        tiles += h_act[i].tiles;
-    }
-    if (na > 0) {
-        SV_HIP(hipMemcpyAsync(sv->d_list, h_act, sizeof(SacDev) * na, hipMemcpyHostToDevice, st));
+    const std::vector<int> act0 = act;
+    for (int it = 0; it < sv->prm.rounds_per_step && !act.empty(); ++it) {
+        SacDev* h_it = it == 0 ? h_act : sv->h_more + (size_t)(it - 1) * sv->cus;
+        const int na = (int)act.size();
+        int64_t base_tiles = 0;
+        for (int i = 0; i < na; ++i) {
+            h_it[i] = slot_record(sv, act[i]);
+            base_tiles += h_it[i].tiles;
+        }
+        const int shape = opmm_rt::launch_shape(sv->ctx, sv->shape, base_tiles);
+        const int tile = opmm_rt::shape_tile(shape);
+        int tiles = 0;
+        for (int i = 0; i < na; ++i) {
+            h_it[i].tiles = (h_it[i].n_cand + tile - 1) / tile;
+            h_it[i].tile_base = tiles;
+            tiles += h_it[i].tiles;
+        }
+        SV_HIP(hipMemcpyAsync(sv->d_list, h_it, sizeof(SacDev) * na, hipMemcpyHostToDevice, st));
         SV_HIP(opmm_rt::launch_reset_keys(sv->d_list, na, sv->ss, st));
         SV_HIP(opmm_rt::launch_round(shape, sv->d_list, na, tiles, dt, sv->ss, st));
         SV_HIP(opmm_rt::launch_refine(sv->d_list, na, phase_params(sv, PH_FIRST).shrink, sv->ss, st));
-        for (int k : act) sv->slot[k].round++;
         queued = true;
+        std::vector<int> next;
+        for (int k : act)
+            if (++sv->slot[k].round < sv->slot[k].rounds) next.push_back(k);
+        if (base_tiles >= sv->cus) break;  // this round filled the device: one round per step
+        act.swap(next);
     }
     // 4. harvest slots whose search is complete
     std::vector<int> fin;
-    for (int k : act)
+    for (int k : act0)
         if (sv->slot[k].round >= sv->slot[k].rounds) fin.push_back(k);
     int ndone = 0;
     if (!fin.empty()) {

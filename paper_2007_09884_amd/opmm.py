@@ -36,7 +36,7 @@ class FitParams(ctypes.Structure):
 class ServeParams(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int32), ("max_T", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
                 ("plain", FitParams), ("seeded", FitParams), ("fallback_rmse", ctypes.c_float),
-                ("polish_iter", ctypes.c_int32)]
+                ("polish_iter", ctypes.c_int32), ("rounds_per_step", ctypes.c_int32)]
 
 
 class NmParams(ctypes.Structure):

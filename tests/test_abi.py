@@ -36,7 +36,9 @@ def test_struct_layouts_match_header():
     from paper_2007_09884_amd import opmm
     assert opmm.SACCADE_DTYPE.itemsize == 40
     assert ctypes.sizeof(opmm.FitParams) == 36
-    assert ctypes.sizeof(opmm.ServeParams) == 96 and ctypes.sizeof(opmm.NmParams) == 28
+    assert ctypes.sizeof(opmm.ServeParams) == 104 and ctypes.sizeof(opmm.NmParams) == 28
+    sv = opmm.serve_params()
+    assert (sv.max_slots, sv.max_T, sv.polish_iter, sv.rounds_per_step) == (4096, 160, 0, 16)
     n = opmm.nm_params()
     assert (n.max_iter, n.tol_x, n.tol_f, n.box_frac, n.dt_ms, n.max_ms, n.tasks_per_wave) == \
         (500, np.float32(1e-4), np.float32(1e-6), 0.25, 1.0, 0.0, 0)

@@ -48,15 +48,20 @@ def stream_through(server, b, traces, recs, waves=(4, 3, 5)):
     return {k: v[order] for k, v in res.items()}
 
 
-def test_plain_server_results_equal_fit_alone(ctx, opmm):
+@pytest.mark.parametrize("rounds_per_step", [1, 16])
+def test_plain_server_results_equal_fit_alone(ctx, opmm, rounds_per_step):
+    """Results equal opmm_fit on each saccade alone, whether a step runs one round (rounds_per_step
+    1) or, while the device would idle, several (the default 16: a light load like this one then
+    finishes each search in the step that admitted it)."""
     b, traces = make_batch(14, "full", seed=synth.BASE_SEED + 31)
     recs = records(b, opmm)
     recs["pos_offset"] = 0
-    prm = opmm.serve_params(max_slots=6)
+    prm = opmm.serve_params(max_slots=6, rounds_per_step=rounds_per_step)
     prm.plain.n_cand = 3000
     prm.plain.n_rounds = 4
     sv = opmm.Server(ctx, prm)
     res = stream_through(sv, b, traces, recs)
+    steps = sv.stats()["steps"]
     assert len(res["id"]) == b["S"] and np.all(res["status"] == 0)
     assert np.all(res["t_done"] >= res["t_arrival"])
     fp = opmm.fit_params(n_cand=3000, n_rounds=4)
@@ -68,7 +73,13 @@ def test_plain_server_results_equal_fit_alone(ctx, opmm):
         assert rm.cpu().numpy()[0] == res["rmse"][s]
     st = sv.stats()
     assert st["completed"] == b["S"] and st["busy"] == 0 and st["pending"] == 0
+    # 14 requests x 4 rounds through at most 6 slots take at least 10 steps at one round per step;
+    # with several, each search ends in the step that admitted it (four submission waves)
+    assert steps >= 10 if rounds_per_step == 1 else steps <= 6, steps
     sv.close()
+    for bad in (0, 65):
+        with pytest.raises(opmm.OpmmError):
+            opmm.Server(ctx, opmm.serve_params(rounds_per_step=bad))
 
 
 def test_polished_server_results_equal_fit_and_polish_alone(ctx, opmm):
@@ -177,7 +188,9 @@ def test_admission_is_bounded_by_the_hbm_budget(ctx, opmm):
     assert list(ids) == list(range(9))
     sv.step()
     st = sv.stats()
-    assert st["busy"] == 3 and st["pending"] == 6   # requests wait for memory, nothing fails
+    # three slots: three requests admitted (a light step may already finish them), the rest wait for
+    # memory, nothing fails
+    assert st["busy"] + st["completed"] == 3 and st["pending"] == 6
     for _ in range(50):
         if sv.stats()["completed"] == 9:
             break
