@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--mode", choices=["auto", "persistent", "rounds"], default="rounds",
                     help="auto: autotune the tile for both launch modes and keep the faster")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--screen-rounds", type=int, default=8,
+                    help="rounds screened in FP32 with the FP64 argmin of the candidates within --screen-tol "
+                         "(per-round mode; results equal the FP64-only fit, which a side leg times); 0: FP64 only")
+    ap.add_argument("--screen-tol", type=float, default=5e-5, help="screening tolerance, deg of RMSE")
     ap.add_argument("--tile", type=int, default=-1, help="kernel shape index; -1 library default, -2 autotune")
     ap.add_argument("--no-autotune-leg", action="store_true",
                     help="skip the side leg that autotunes both launch modes and times their picks")
@@ -114,24 +118,25 @@ def executed_fig(flop_per_launch, launch_ms):
         return None
     t = flop_per_launch / (launch_ms * 1e-3) / 1e12
     return {"flop_per_launch": flop_per_launch, "tflops": t, "frac": t / ALU_PEAK_TFLOPS,
-            "source": "SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes x active-lane share (rocprofv3 summary in profiles/)"}
+            "source": "the VALU's own FLOP count: SQ_INSTS_VALU_FLOPS_FP64 (+ _FP32 with screened rounds) x 64 "
+                      "lanes x active-lane share (rocprofv3 summary in profiles/)"}
 
 
-def profiled_traffic(mode, tile_name):
+def profiled_traffic(mode, tile_name, screen=0):
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading)."""
-    return profiled_value("traffic_per_launch_bytes", mode, tile_name)
+    return profiled_value("traffic_per_launch_bytes", mode, tile_name, screen)
 
 
-def profiled_value(key, mode, tile_name):
-    """A per-launch figure of the dominant kernel from the committed rocprofv3 counter summary
-    (a `key=value mode=.. tile=.. sources_sha256=..` line), if that summary was taken on the same
-    launch mode and tile shape from the current kernel sources; else None."""
+def profiled_value(key, mode, tile_name, screen=0):
+    """A per-launch figure from the committed rocprofv3 counter summaries (a `key=value mode=.. tile=..
+    [screen=..] sources_sha256=..` line), if one was taken on the same launch mode, tile shape and
+    screened-round count (absent: 0) from the current kernel sources; else None."""
     import glob
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
         for line in open(path):
             if line.startswith(key + "="):
                 kv = dict(t.split("=", 1) for t in line.split()[1:])
-                if (kv.get("mode") == mode and kv.get("tile") == tile_name
+                if (kv.get("mode") == mode and kv.get("tile") == tile_name and int(kv.get("screen", 0)) == screen
                         and kv.get("sources_sha256") == sources_digest()):
                     return int(line.split()[0].split("=")[1])
     return None
@@ -539,6 +544,8 @@ def main():
         prm.tile = autotuned(a.mode).tile if a.tile == -2 else a.tile
     if prm.tile < 0:
         prm.tile = opmm.lib.opmm_tile_default()
+    if a.screen_rounds > 0:
+        prm.screen_rounds, prm.screen_tol = min(a.screen_rounds, R), a.screen_tol
     for v in tuned.values():
         del v["params"]
     torch.cuda.synchronize()
@@ -572,8 +579,20 @@ def main():
     sum_T = int(np.sum(b["T"]))
     flop = FLOP_PER_CAND_SAMPLE * N * R * sum_T
     # one kernel per round (rounds mode) or one for the whole step (persistent); the HIP events bracket
-    # the captured step, so the per-launch time includes the small kernels' ~1 %
+    # the captured step, so the per-launch time includes the small kernels' ~1 %.  With screened rounds a
+    # "launch" is a whole round: the FP32 pass and the FP64 verification, or the FP64 round kernel
     n_launch = R if a.mode == "rounds" else 1
+    scr = int(prm.screen_rounds)
+    if scr > 0:
+        kernel_text = ("whole round, %d per step: rounds 0-%d fit_screen_kernel (FP32, every candidate) + "
+                       "fit_verify_kernel (FP64, the candidates within %.0e deg RMSE of the FP32 best)%s; "
+                       "launch_ms is the captured step / %d" % (
+                           R, scr - 1, prm.screen_tol,
+                           ", rounds %d-%d fit_round_kernel (FP64)" % (scr, R - 1) if scr < R else "", R))
+    else:
+        kernel_text = (("fit_persistent_kernel (one launch per step" if a.mode == "persistent" else
+                        "fit_round_kernel (%d launches per step" % R) +
+                       "; launch_ms is the whole captured step: prep/init/refine/report kernels add ~1%)")
     achieved = flop / (launch_ms * 1e-3) / 1e12
     st = status.cpu().numpy()
     rm = rmse.cpu().numpy()
@@ -589,25 +608,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32 screen + f64 verify" if scr > 0 else "f64",
         "data": "synthetic",
         "config": {"workload": "full estimation: %d 2-D saccades (A~U[2,30] deg, D=2.2A+21 ms, 1 kHz), "
                                "%d candidates x %d halving rounds, plain box search" % (S, N, R),
                    "saccades": S, "n_cand": N, "rounds": R, "mean_T": float(np.mean(b["T"])),
-                   "mode": a.mode, "graph": not a.no_graph, "tile": opmm.tile_names()[prm.tile]},
+                   "mode": a.mode, "graph": not a.no_graph, "tile": opmm.tile_names()[prm.tile],
+                   "screen_rounds": int(prm.screen_rounds), "screen_tol_deg": float(prm.screen_tol)},
         "saccades_fitted_per_s": S * a.steps / wall,
         "mean_final_rmse_deg": float(np.mean(rm)),
         "status_nonzero": int(np.count_nonzero(st)),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / ALU_PEAK_TFLOPS,
-                     "traffic": profiled_traffic(a.mode, opmm.tile_names()[prm.tile]),
-                     "kernel": ("fit_persistent_kernel (one launch per step" if a.mode == "persistent" else
-                                "fit_round_kernel (%d launches per step" % R) +
-                               "; launch_ms is the whole captured step: prep/init/refine/report kernels add ~1%)",
+                     "traffic": profiled_traffic(a.mode, opmm.tile_names()[prm.tile], scr),
+                     "kernel": kernel_text,
                      "launch_ms": launch_ms / n_launch, "launches_per_step": n_launch,
                      "algorithmic_flop_per_launch": flop // n_launch,
                      "executed": executed_fig(profiled_value("executed_flop_per_launch", a.mode,
-                                                             opmm.tile_names()[prm.tile]), launch_ms / n_launch),
+                                                             opmm.tile_names()[prm.tile], scr), launch_ms / n_launch),
                      "frac_of_published_fp32_157": achieved / PUBLISHED_FP32_PEAK},
     }
     if a.report_csv:
@@ -617,6 +635,14 @@ def main():
         mae = torch.zeros(S, device="cuda")
         ctx.fit(pos, recs, prm, opc, rmse, mae, status)
         report.write_csv(a.report_csv, opc.cpu().numpy(), mae.cpu().numpy())
+    if scr > 0:
+        # the same workload with every round in FP64 only: its time, and that it returns the same fit
+        p64 = opmm.fit_params(n_cand=N, n_rounds=R, mode=modes[a.mode], tile=prm.tile)
+        opc_s = opc.clone()
+        ms64 = time_plan(p64, reps=5)
+        out["fp64_only"] = {"ms_per_step": ms64, "candidate_sims_per_s": sims / (ms64 * 1e-3),
+                            "roofline_frac": flop / R / (ms64 / R * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+                            "same_opc_as_screened": bool(torch.equal(opc, opc_s))}
     if tuned:
         out["autotune"] = tuned
     if not a.no_uneven:

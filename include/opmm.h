@@ -125,10 +125,20 @@ typedef struct {
                             stream's K_SE_ANT := K_SE_AG, K_LT_ANT := K_LT_AG)
                             and the neural parameters (tau_AC/DE, N_SAC, PW)
                             held at nominal (half-width 0)                   */
+    int32_t screen_rounds; /* rounds 0..screen_rounds-1 are screened: every
+                            candidate is simulated with an FP32 recurrence,
+                            and only those whose FP32 RMSE lies within
+                            screen_tol of the round's FP32 best are simulated
+                            again in FP64, which decides the argmin.  The
+                            winner is the FP64 argmin whenever the FP32 RMSE
+                            errors stay below screen_tol / 2 (measured: below
+                            4.4e-6 deg).  0 = every round in FP64 only.
+                            Per-round mode only; 0..n_rounds           [0]   */
+    float screen_tol;    /* deg of RMSE, > 0                         [5e-5]  */
 } opmm_fit_params;
 
 /* Defaults: n_cand 4096, n_rounds 1, box 0.25, w_init 1, shrink 0.5, dt 1 ms,
- * model 18. */
+ * model 18, no screening (tolerance 5e-5 deg when enabled). */
 void opmm_fit_params_default(opmm_fit_params* p);
 
 /* Nominal OPC for a saccade of duration dur_ms (Table 1; PW = D - 6 ms).

@@ -183,15 +183,17 @@ __global__ void refine_kernel(int S, const SacDev* __restrict__ sacs, int round,
 // Sinks for run_trajectory
 // ---------------------------------------------------------------------------
 
-struct SseSink {  // squared residual against the projected trace in LDS, FP64 sum
-    const R* r;
+template <class RT>
+struct SseSinkT {  // squared residual against the projected trace in LDS, FP64 sum
+    const RT* r;
     double sse;
-    __device__ __forceinline__ void operator()(int k, R dth, R theq)
+    __device__ __forceinline__ void operator()(int k, RT dth, RT theq)
     {
-        R e = (r[k] - theq) - dth;
+        RT e = (r[k] - theq) - dth;
         sse = fma((double)e, (double)e, sse);
     }
 };
+using SseSink = SseSinkT<R>;
 
 struct TrajSink {  // theta_k to global memory
     float* out;
@@ -237,26 +239,29 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
 // Fused tile: draw, sort by pulse-end sample, simulate + score, argmin
 // ---------------------------------------------------------------------------
 
-template <int TPB, int PASSES>
+template <int TPB, int PASSES, class RT = R>
 struct TileSmem {
-    R r[OPMM_MAX_T];
+    RT r[OPMM_MAX_T];
     Box box;
     int hist[NBIN];
     uint16_t perm[TPB * PASSES];
     uint64_t red[TPB / 64];
 };
 
-// Returns the block's best key (valid in thread 0).
-template <int TPB, int PASSES, int UNROLL>
-__device__ __forceinline__ uint64_t process_tile(TileSmem<TPB, PASSES>& sm, const SacDev& sd, int s, int t,
+// Returns the block's best key (valid in thread 0).  RT: the recurrence's precision (the screening
+// pass runs it in FP32).  costs (nullable): for every slot q of the tile in pulse-end order, at
+// [(tile_base + t) * TILE + q], the candidate's squared-residual sum rounded to FP32 (high word) and
+// its index in the tile (low word), or all ones for a slot past the saccade's candidates.
+template <int TPB, int PASSES, int UNROLL, class RT = R>
+__device__ __forceinline__ uint64_t process_tile(TileSmem<TPB, PASSES, RT>& sm, const SacDev& sd, int s, int t,
                                                  int round, float dt, const float* __restrict__ proj,
                                                  const float* centre, const float* hw, const float* lo,
-                                                 const float* hi)
+                                                 const float* hi, uint64_t* __restrict__ costs = nullptr)
 {
     constexpr int TILE = TPB * PASSES;
     const int tid = threadIdx.x;
     const int T = sd.T;
-    for (int k = tid; k < T; k += TPB) sm.r[k] = (R)proj[sd.proj_off + k];
+    for (int k = tid; k < T; k += TPB) sm.r[k] = (RT)proj[sd.proj_off + k];
     load_box(sm.box, sd.slot, centre, hw, lo, hi);
     for (int i = tid; i < NBIN; i += TPB) sm.hist[i] = 0;
     __syncthreads();
@@ -311,23 +316,28 @@ __device__ __forceinline__ uint64_t process_tile(TileSmem<TPB, PASSES>& sm, cons
         const uint32_t j = sm.perm[ps * TPB + tid];
         const uint32_t idx = base + j;
         const bool valid = (int64_t)idx < sd.n_cand;
-        if (!__any(valid)) continue;
+        uint64_t* cslot = costs ? costs + (int64_t)(sd.tile_base + t) * TILE + ps * TPB + tid : nullptr;
+        if (!__any(valid)) {
+            if (cslot) *cslot = ~0ull;
+            continue;
+        }
         float p[P];
         draw_candidate(sd.seed, (uint32_t)round, idx, sm.box, p, sd.model);
-        Plant pl;
+        PlantT<RT> pl;
         plant_setup(p, sd.amp, dt, pl);
-        R frac;
+        RT frac;
         int k0 = pulse_end_sample(pl.pwd, T, frac);
         int kmin = wave_min(valid ? k0 : 0x7FFFFFFF);
         int kmax = wave_max(valid ? k0 : -0x7FFFFFFF);
         kmin = __builtin_amdgcn_readfirstlane(kmin);
         kmax = __builtin_amdgcn_readfirstlane(kmax);
-        SseSink sink{sm.r, 0.0};
+        SseSinkT<RT> sink{sm.r, 0.0};
         if (valid) {
-            run_trajectory<UNROLL>(pl, T, (R)dt, k0, frac, kmin, kmax, sink);
+            run_trajectory<UNROLL>(pl, T, (RT)dt, k0, frac, kmin, kmax, sink);
             uint64_t key = cost_key(sink.sse, idx);
             best = key < best ? key : best;
         }
+        if (cslot) *cslot = valid ? ((uint64_t)__float_as_uint((float)sink.sse) << 32) | j : ~0ull;
     }
     best = wave_min_u64(best);
     if ((tid & 63) == 0) sm.red[tid >> 6] = best;
@@ -412,6 +422,155 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_round_kernel(const Sa
     if (threadIdx.x == 0 && best != ~0ull)
         atomicMin((unsigned long long*)&keys[(int64_t)(round >= 0 ? r : 0) * key_stride + sd.slot],
                   (unsigned long long)best);
+}
+
+// Screened round, first pass: the round's tiles with the recurrence in FP32.  Every candidate's
+// squared-residual sum goes to costs; each saccade's FP32 best key to smin[slot].
+// The FP32 pass needs ~172 registers as compiled for 2 waves per SIMD; held to 168 it runs 3 (one
+// spilled register) and took 14.3-14.4 instead of 15.4 ms per full-estimation step (4 waves: 14.5).
+#ifndef OPMM_SCREEN_MIN_WAVES
+#define OPMM_SCREEN_MIN_WAVES 3
+#endif
+template <int TPB, int PASSES, int UNROLL>
+__global__ __launch_bounds__(TPB, OPMM_SCREEN_MIN_WAVES) void fit_screen_kernel(const SacDev* __restrict__ sacs, int S,
+                                                         int round, float dt, const float* __restrict__ proj,
+                                                         const float* centre, const float* hw, const float* lo,
+                                                         const float* hi, const int32_t* __restrict__ status,
+                                                         const int* __restrict__ ord, const int* __restrict__ obase,
+                                                         uint64_t* __restrict__ costs, uint64_t* smin)
+{
+    __shared__ TileSmem<TPB, PASSES, float> sm;
+    __shared__ int s_s;
+    if (threadIdx.x < 64) {
+        const int sw = saccade_of_tile(sacs, ord, obase, S, blockIdx.x);
+        if (threadIdx.x == 0) s_s = sw;
+    }
+    __syncthreads();
+    const SacDev sd = sacs[s_s];
+    if (status[sd.slot] & OPMM_ST_NONFINITE_INPUT) return;
+    const int t = blockIdx.x - sd.tile_base;
+    const uint64_t best =
+        process_tile<TPB, PASSES, UNROLL, float>(sm, sd, s_s, t, round, dt, proj, centre, hw, lo, hi, costs);
+    if (threadIdx.x == 0 && best != ~0ull) atomicMin((unsigned long long*)&smin[sd.slot], (unsigned long long)best);
+}
+
+// Screened round, second pass.  The block of tile t with t % VG == 0 takes tiles t .. t + VG - 1 of
+// its saccade (the other blocks return at once, so fewer blocks pay the latency of an FP64
+// simulation): their candidates whose FP32 RMSE lies within tau of the saccade's FP32 best (or is
+// NaN) are simulated again exactly as the FP64 round kernel simulates them, in the first pass's
+// pulse-end order, and their FP64 keys go to keys[round][slot].  The FP32 best key fixes the
+// threshold: with n = T C samples and Q the orthogonal energy, RMSE = sqrt((SSE + Q) / n), so a
+// candidate passes when its FP32 SSE <= (RMSE_best + tau)^2 n - Q.
+#ifndef OPMM_VERIFY_TILES
+#define OPMM_VERIFY_TILES 1
+#endif
+constexpr int VG = OPMM_VERIFY_TILES;  // tiles per verifying block
+
+template <int TPB, int PASSES>
+struct VerifySmem {
+    R r[OPMM_MAX_T];
+    Box box;
+    uint32_t list[VG * TPB * PASSES];  // candidate indices to verify
+    int wcnt[TPB / 64];
+    uint64_t red[TPB / 64];
+};
+
+template <int TPB, int PASSES, int UNROLL>
+__global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_verify_kernel(const SacDev* __restrict__ sacs, int S,
+                                                         int round, int key_stride, float dt,
+                                                         const float* __restrict__ proj, const float* centre,
+                                                         const float* hw, const float* lo, const float* hi,
+                                                         const int32_t* __restrict__ status, uint64_t* keys,
+                                                         const int* __restrict__ ord, const int* __restrict__ obase,
+                                                         const uint64_t* __restrict__ costs,
+                                                         const uint64_t* __restrict__ smin,
+                                                         const double* __restrict__ qorth, float tau)
+{
+    constexpr int TILE = TPB * PASSES, NW = TPB / 64;
+    __shared__ VerifySmem<TPB, PASSES> sm;
+    __shared__ int s_s;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 64) {
+        const int sw = saccade_of_tile(sacs, ord, obase, S, blockIdx.x);
+        if (tid == 0) s_s = sw;
+    }
+    __syncthreads();
+    const SacDev sd = sacs[s_s];
+    if (status[sd.slot] & OPMM_ST_NONFINITE_INPUT) return;
+    const int t0 = blockIdx.x - sd.tile_base;
+    if (t0 % VG != 0) return;
+    const int ng = min(VG, sd.tiles - t0);
+    const int T = sd.T;
+    const float fbest = __uint_as_float((uint32_t)(smin[sd.slot] >> 32));
+    double thr = __builtin_inf();  // no finite FP32 cost: every candidate is verified
+    if (fbest <= 3.402823466e38f) {
+        const double n = (double)T * sd.C, q = qorth[sd.slot];
+        const double rm = sqrt(((double)fbest + q) / n) + (double)tau;
+        thr = rm * rm * n - q;
+    }
+    // compaction in slot order, tile by tile, TPB slots at a time; every load is issued first
+    uint64_t vals[VG * PASSES];
+#pragma unroll
+    for (int c = 0; c < VG * PASSES; ++c)
+        vals[c] = c < ng * PASSES ? costs[(int64_t)(sd.tile_base + t0 + c / PASSES) * TILE + (c % PASSES) * TPB + tid]
+                                  : ~0ull;
+    int nv = 0;
+#pragma unroll
+    for (int c = 0; c < VG * PASSES; ++c) {
+        const int g = c / PASSES;
+        const uint64_t v = vals[c];
+        const uint32_t j = (uint32_t)v;
+        const float f = __uint_as_float((uint32_t)(v >> 32));
+        const bool pass = j != 0xFFFFFFFFu && ((double)f <= thr || f != f);
+        const uint64_t m = __ballot(pass);
+        if (lane == 0) sm.wcnt[wave] = __popcll(m);
+        __syncthreads();
+        int off = nv, tot = nv;
+        for (int w = 0; w < NW; ++w) {
+            if (w < wave) off += sm.wcnt[w];
+            tot += sm.wcnt[w];
+        }
+        if (pass) sm.list[off + __popcll(m & ((1ull << lane) - 1))] = (uint32_t)(t0 + g) * TILE + j;
+        nv = tot;
+        __syncthreads();
+    }
+    if (nv == 0) return;
+    for (int k = tid; k < T; k += TPB) sm.r[k] = (R)proj[sd.proj_off + k];
+    load_box(sm.box, sd.slot, centre, hw, lo, hi);
+    __syncthreads();
+    uint64_t best = ~0ull;
+#pragma unroll 1
+    for (int i0 = 0; i0 < nv; i0 += TPB) {
+        asm volatile("" ::: "memory");
+        const int i = i0 + tid;
+        const bool valid = i < nv;
+        if (!__any(valid)) continue;
+        const uint32_t idx = valid ? sm.list[i] : 0u;
+        float p[P];
+        draw_candidate(sd.seed, (uint32_t)round, idx, sm.box, p, sd.model);
+        Plant pl;
+        plant_setup(p, sd.amp, dt, pl);
+        R frac;
+        int k0 = pulse_end_sample(pl.pwd, T, frac);
+        int kmin = wave_min(valid ? k0 : 0x7FFFFFFF);
+        int kmax = wave_max(valid ? k0 : -0x7FFFFFFF);
+        kmin = __builtin_amdgcn_readfirstlane(kmin);
+        kmax = __builtin_amdgcn_readfirstlane(kmax);
+        SseSink sink{sm.r, 0.0};
+        if (valid) {
+            run_trajectory<UNROLL>(pl, T, (R)dt, k0, frac, kmin, kmax, sink);
+            const uint64_t key = cost_key(sink.sse, idx);
+            best = key < best ? key : best;
+        }
+    }
+    best = wave_min_u64(best);
+    if (lane == 0) sm.red[wave] = best;
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < NW; ++w) best = sm.red[w] < best ? sm.red[w] : best;
+        if (best != ~0ull)
+            atomicMin((unsigned long long*)&keys[(int64_t)round * key_stride + sd.slot], (unsigned long long)best);
+    }
 }
 
 // Every round of every saccade in one launch: a work queue of (round, tile)
@@ -643,6 +802,11 @@ struct FitLaunch {
     int grid_persistent;
     const int *ord, *obase;  // dispatch order (nullable: record order)
     uint32_t wait_limit;     // polls of a persistent block waiting for its round
+    // screened rounds: FP32 costs of every candidate, FP32 best per saccade, orthogonal energies
+    uint64_t* costs;  // [tiles_per_round * tile]: FP32 cost and index of every slot (process_tile)
+    uint64_t* smin;   // [S]: FP32 best key per saccade
+    const double* qorth;
+    float tau;
 };
 
 template <int TPB, int PASSES, int UNROLL>
@@ -659,6 +823,38 @@ hipError_t launch_shape(const FitLaunch& L, bool persistent, int round, hipStrea
                            L.keys, L.ord, L.obase);
     }
     return hipGetLastError();
+}
+
+template <int TPB, int PASSES, int UNROLL>
+hipError_t launch_screened(const FitLaunch& L, int round, hipStream_t st)
+{
+    hipLaunchKernelGGL((fit_screen_kernel<TPB, PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(TPB), 0, st, L.sacs,
+                       L.S, round, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status, L.ord, L.obase, L.costs,
+                       L.smin);
+    hipLaunchKernelGGL((fit_verify_kernel<TPB, PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(TPB), 0, st, L.sacs,
+                       L.S, round, L.key_stride, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status, L.keys, L.ord,
+                       L.obase, L.costs, L.smin, L.qorth, L.tau);
+    return hipGetLastError();
+}
+
+// One screened round (FP32 pass + FP64 verification) of shape `shape`.
+hipError_t launch_screened_round(int shape, const FitLaunch& L, int round, hipStream_t st)
+{
+    switch (shape) {
+    case 0: return launch_screened<256, 4, 1>(L, round, st);
+    case 1: return launch_screened<256, 2, 1>(L, round, st);
+    case 2: return launch_screened<256, 8, 1>(L, round, st);
+    case 3: return launch_screened<128, 8, 1>(L, round, st);
+    case 4: return launch_screened<256, 4, 2>(L, round, st);
+    case 5: return launch_screened<256, 4, 4>(L, round, st);
+    case 6: return launch_screened<64, 16, 1>(L, round, st);
+    case 7: return launch_screened<256, 16, 1>(L, round, st);
+    case 8: return launch_screened<128, 32, 1>(L, round, st);
+    case 9: return launch_screened<256, 8, 4>(L, round, st);
+    case 10: return launch_screened<256, 4, 8>(L, round, st);
+    case 11: return launch_screened<64, 16, 4>(L, round, st);
+    default: return launch_screened<128, 8, 4>(L, round, st);
+    }
 }
 
 hipError_t launch_fit_kernel(int shape, const FitLaunch& L, bool persistent, int round, hipStream_t st)
@@ -720,13 +916,14 @@ struct DevBuf {
 
 struct FitScratch {
     DevBuf sacs, proj, qorth, box, keys, status, counters, order;
+    DevBuf costs, smin;  // screened rounds (see FitBufs)
     // Pinned host staging of the record upload (records, then dispatch order and tile bases), kept
     // between calls: the upload is a direct DMA and no batch pays for fresh pages.
     DevBuf stage;
     std::vector<int> h_count;
     ~FitScratch()
     {
-        for (DevBuf* b : {&sacs, &proj, &qorth, &box, &keys, &status, &counters, &order})
+        for (DevBuf* b : {&sacs, &proj, &qorth, &box, &keys, &status, &counters, &order, &costs, &smin})
             if (b->p) (void)hipFree(b->p);
         if (stage.p) (void)hipHostFree(stage.p);
     }
@@ -932,6 +1129,12 @@ int validate_params(opmm_ctx* ctx, const opmm_fit_params* p)
     if (p->mode != OPMM_FIT_ROUNDS && p->mode != OPMM_FIT_PERSISTENT) return fail(ctx, OPMM_EINVAL, "bad mode");
     if (p->tile < -1 || p->tile >= kNumShapes) return fail(ctx, OPMM_EINVAL, "bad tile index");
     if (p->model != 18 && p->model != 9) return fail(ctx, OPMM_EINVAL, "model must be 18 or 9");
+    if (p->screen_rounds < 0 || p->screen_rounds > p->n_rounds)
+        return fail(ctx, OPMM_EINVAL, "screen_rounds must be in 0..n_rounds");
+    if (p->screen_rounds > 0 && p->mode != OPMM_FIT_ROUNDS)
+        return fail(ctx, OPMM_EINVAL, "screened rounds need the per-round mode");
+    if (p->screen_rounds > 0 && !(p->screen_tol > 0.0f && p->screen_tol <= 3.402823466e38f))
+        return fail(ctx, OPMM_EINVAL, "screen_tol must be positive and finite");
     return OPMM_OK;
 }
 
@@ -1012,6 +1215,10 @@ struct FitBufs {
     int32_t* status;
     uint32_t* counters;
     uint64_t* keys;
+    // screened rounds only: FP32 cost and index of every candidate slot [tiles_per_round * tile],
+    // FP32 best key per saccade [S]
+    uint64_t* costs = nullptr;
+    uint64_t* smin = nullptr;
 };
 
 int enqueue_fit_bufs(opmm_ctx* ctx, const FitBufs& B, const float* pos, int S, int tiles_per_round,
@@ -1045,6 +1252,13 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
     B.status = (int32_t*)sc.status.p;
     B.counters = (uint32_t*)sc.counters.p;
     B.keys = keys;
+    if (prm->screen_rounds > 0 && tiles_per_round > 0) {
+        const size_t slots = (size_t)tiles_per_round * kShapes[shape].tpb * kShapes[shape].passes;
+        if ((rc = ensure(ctx, sc.costs, sizeof(uint64_t) * slots)) != OPMM_OK) return rc;
+        if ((rc = ensure(ctx, sc.smin, sizeof(uint64_t) * (size_t)S)) != OPMM_OK) return rc;
+        B.costs = (uint64_t*)sc.costs.p;
+        B.smin = (uint64_t*)sc.smin.p;
+    }
     return enqueue_fit_bufs(ctx, B, pos, S, tiles_per_round, prm, shape, seed_opc, opc_out, rmse_out, mae_out,
                             status_out, st, run_prep);
 }
@@ -1087,6 +1301,10 @@ int enqueue_fit_bufs(opmm_ctx* ctx, const FitBufs& B, const float* pos, int S, i
     L.obase = B.order ? B.order + S : nullptr;
     L.key_stride = S;
     L.wait_limit = ctx->wait_limit;
+    L.costs = B.costs;
+    L.smin = B.smin;
+    L.qorth = qorth;
+    L.tau = prm->screen_tol;
     if (tiles_per_round > 0) {
         if (prm->mode == OPMM_FIT_PERSISTENT) {
             // The queue needs no co-residency, so oversubscribe: blocks that start
@@ -1100,7 +1318,14 @@ int enqueue_fit_bufs(opmm_ctx* ctx, const FitBufs& B, const float* pos, int S, i
             OPMM_HIP(ctx, hipGetLastError());
         } else {
             for (int r = 0; r < R; ++r) {
-                OPMM_HIP(ctx, launch_fit_kernel(shape, L, false, r, st));
+                if (r < prm->screen_rounds) {
+                    if (!B.costs || !B.smin) return fail(ctx, OPMM_EINVAL, "screened rounds need their buffers");
+                    hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for(S, 256)), dim3(256), 0, st, B.smin, (int64_t)S,
+                                       ~0ull);
+                    OPMM_HIP(ctx, launch_screened_round(shape, L, r, st));
+                } else {
+                    OPMM_HIP(ctx, launch_fit_kernel(shape, L, false, r, st));
+                }
                 hipLaunchKernelGGL(refine_kernel, dim3(blocks_for(S, 128)), dim3(128), 0, st, S, d_sacs, r, S, keys,
                                    prm->shrink, centre, hw, lo, hi, status);
                 OPMM_HIP(ctx, hipGetLastError());
@@ -1383,6 +1608,8 @@ void opmm_fit_params_default(opmm_fit_params* p)
     p->mode = OPMM_FIT_ROUNDS;
     p->tile = -1;
     p->model = 18;
+    p->screen_rounds = 0;
+    p->screen_tol = 5e-5f;
 }
 
 void opmm_nominal(float dur_ms, float* out)
@@ -1769,6 +1996,8 @@ int opmm_fit_noalloc(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opm
     int rc = check_fit_args(ctx, pos, pos_len, sacs, S, params, opc_out, rmse_out);
     if (rc != OPMM_OK || S == 0) return rc;
     if (S > OPMM_NOALLOC_MAX_S) return fail(ctx, OPMM_EINVAL, "S exceeds OPMM_NOALLOC_MAX_S");
+    if (params->screen_rounds > 0)
+        return fail(ctx, OPMM_EINVAL, "the allocation-free fit runs every round in FP64 (screen_rounds = 0)");
     if (!ctx->noalloc_scratch) return fail(ctx, OPMM_EDEVICE, "no device address for the allocation-free scratch");
     OPMM_HIP(ctx, hipSetDevice(ctx->device));
     hipStream_t st = (hipStream_t)stream;

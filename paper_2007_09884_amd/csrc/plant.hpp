@@ -36,18 +36,12 @@ __device__ __forceinline__ double fmr(double a, double b, double c) { return __f
 // the exponential-vector product of the split sample, per precision: each
 // set puts the truncation error below that precision's rounding floor over
 // +/-25% boxes (FP64: ~5e-9 deg, FP32: ~6e-6 deg on 150-sample traces).
-#ifndef OPMM_TAYLOR_M
-#define OPMM_TAYLOR_M (sizeof(R) == 8 ? 6 : 8)
-#endif
-#ifndef OPMM_TAYLOR_SQ
-#define OPMM_TAYLOR_SQ (sizeof(R) == 8 ? 2 : 0)
-#endif
-#ifndef OPMM_EXPMV_M
-#define OPMM_EXPMV_M (sizeof(R) == 8 ? 11 : 8)
-#endif
-constexpr int TAYLOR_M = OPMM_TAYLOR_M;
-constexpr int TAYLOR_SQ = OPMM_TAYLOR_SQ;
-constexpr int EXPMV_M = OPMM_EXPMV_M;
+template <class RT>
+struct Prec {
+    static constexpr int taylor_m = sizeof(RT) == 8 ? 6 : 8;
+    static constexpr int taylor_sq = sizeof(RT) == 8 ? 2 : 0;
+    static constexpr int expmv_m = sizeof(RT) == 8 ? 11 : 8;
+};
 
 // Table 1 nominal values, in the table's order and units.  The pulse width
 // (index 17) is the saccade duration minus 6 ms.
@@ -171,24 +165,26 @@ __device__ __forceinline__ float draw_pw(uint64_t seed, uint32_t round, uint32_t
 // Plant coefficients of one candidate
 // ---------------------------------------------------------------------------
 
-struct Plant {
+template <class RT>
+struct PlantT {
     // continuous-time system matrix entries (per ms); theta' = omega is implicit
-    R a10, a11, a12, a13;      // omega row: theta, omega, x_ag, x_ant
-    R a20, a22, g2;            // x_ag row: theta, x_ag, F_ag
-    R a30, a33, g3;            // x_ant row: theta, x_ant, F_ant
-    R q1a, q1n, q2a, q2n;      // F rows: -1/tau, pulse (activation) and post (deactivation)
+    RT a10, a11, a12, a13;      // omega row: theta, omega, x_ag, x_ant
+    RT a20, a22, g2;            // x_ag row: theta, x_ag, F_ag
+    RT a30, a33, g3;            // x_ant row: theta, x_ant, F_ant
+    RT q1a, q1n, q2a, q2n;      // F rows: -1/tau, pulse (activation) and post (deactivation)
     // one-sample transition in D-form (Phi - I)
-    R m[4][4];                 // mechanical block
-    R x1[4][2], x2[4][2];      // coupling to (F_ag, F_ant), pulse and post pieces
-    R e1[2], e2[2];            // F decay factor minus one, pulse and post pieces
+    RT m[4][4];                 // mechanical block
+    RT x1[4][2], x2[4][2];      // coupling to (F_ag, F_ant), pulse and post pieces
+    RT e1[2], e2[2];            // F decay factor minus one, pulse and post pieces
     // equilibria and switching
-    R th1;                     // theta at the pulse equilibrium
-    R amp;                     // theta at the post equilibrium (= amplitude)
-    R sh[6];                   // pulse equilibrium minus post equilibrium
-    R d0[6];                   // resting state minus pulse equilibrium
+    RT th1;                     // theta at the pulse equilibrium
+    RT amp;                     // theta at the post equilibrium (= amplitude)
+    RT sh[6];                   // pulse equilibrium minus post equilibrium
+    RT d0[6];                   // resting state minus pulse equilibrium
     float pw;                  // PW (ms)
     double pwd;                // PW in sample periods
 };
+using Plant = PlantT<R>;
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -216,52 +212,53 @@ __device__ __forceinline__ double rcp64(double x)
 // matrix [[Mech, G1, G2], [0, Q1, 0], [0, 0, Q2]] whose off-diagonal blocks
 // give the pulse-piece and post-piece coupling columns at once, on the step
 // h/2^SQ, then SQ squarings in D-form: D_2h = D_h^2 + 2 D_h.
-__device__ __forceinline__ void transition_dform(Plant& pl, R hfull)
+template <class RT>
+__device__ __forceinline__ void transition_dform(PlantT<RT>& pl, RT hfull)
 {
-    constexpr int M = TAYLOR_M;
-    const R h = hfull * (R(1) / R(1 << TAYLOR_SQ));
-    R pm[4][4], px[4][4], pd[4];
-    const R qv[4] = {pl.q1a, pl.q1n, pl.q2a, pl.q2n};
+    constexpr int M = Prec<RT>::taylor_m, SQ = Prec<RT>::taylor_sq;
+    const RT h = hfull * (RT(1) / RT(1 << SQ));
+    RT pm[4][4], px[4][4], pd[4];
+    const RT qv[4] = {pl.q1a, pl.q1n, pl.q2a, pl.q2n};
     {   // P_M = I + hA/M
-        const R s = h * (R(1) / R(M));
-        const R s10 = pl.a10 * s, s11 = pl.a11 * s, s12 = pl.a12 * s, s13 = pl.a13 * s;
-        const R s20 = pl.a20 * s, s22 = pl.a22 * s, s30 = pl.a30 * s, s33 = pl.a33 * s;
-        pm[0][0] = R(1); pm[0][1] = s;    pm[0][2] = R(0); pm[0][3] = R(0);
-        pm[1][0] = s10;  pm[1][1] = R(1) + s11; pm[1][2] = s12; pm[1][3] = s13;
-        pm[2][0] = s20;  pm[2][1] = R(0); pm[2][2] = R(1) + s22; pm[2][3] = R(0);
-        pm[3][0] = s30;  pm[3][1] = R(0); pm[3][2] = R(0); pm[3][3] = R(1) + s33;
+        const RT s = h * (RT(1) / RT(M));
+        const RT s10 = pl.a10 * s, s11 = pl.a11 * s, s12 = pl.a12 * s, s13 = pl.a13 * s;
+        const RT s20 = pl.a20 * s, s22 = pl.a22 * s, s30 = pl.a30 * s, s33 = pl.a33 * s;
+        pm[0][0] = RT(1); pm[0][1] = s;    pm[0][2] = RT(0); pm[0][3] = RT(0);
+        pm[1][0] = s10;  pm[1][1] = RT(1) + s11; pm[1][2] = s12; pm[1][3] = s13;
+        pm[2][0] = s20;  pm[2][1] = RT(0); pm[2][2] = RT(1) + s22; pm[2][3] = RT(0);
+        pm[3][0] = s30;  pm[3][1] = RT(0); pm[3][2] = RT(0); pm[3][3] = RT(1) + s33;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            px[0][c] = R(0); px[1][c] = R(0);
-            px[2][c] = (c & 1) ? R(0) : pl.g2 * s;
-            px[3][c] = (c & 1) ? pl.g3 * s : R(0);
-            pd[c] = fmr(qv[c], s, R(1));
+            px[0][c] = RT(0); px[1][c] = RT(0);
+            px[2][c] = (c & 1) ? RT(0) : pl.g2 * s;
+            px[3][c] = (c & 1) ? pl.g3 * s : RT(0);
+            pd[c] = fmr(qv[c], s, RT(1));
         }
     }
 #pragma unroll
     for (int k = M - 1; k >= 1; --k) {
         // k >= 2: P <- I + (h/k) A P ;  k == 1: D <- h A P
-        R s = (k == 1) ? h : h * (R(1) / R(k));
+        RT s = (k == 1) ? h : h * (RT(1) / RT(k));
         // opaque per step: stops the compiler from forming every step's scaled
         // coefficients up front, which would pin ~10 registers per step
         asm volatile("" : "+v"(s));
-        const R one = (k == 1) ? R(0) : R(1);
-        const R s10 = pl.a10 * s, s11 = pl.a11 * s, s12 = pl.a12 * s, s13 = pl.a13 * s;
-        const R s20 = pl.a20 * s, s22 = pl.a22 * s, s30 = pl.a30 * s, s33 = pl.a33 * s;
-        const R sg2 = pl.g2 * s, sg3 = pl.g3 * s;
-        R nm[4][4], nx[4][4], nd[4];
+        const RT one = (k == 1) ? RT(0) : RT(1);
+        const RT s10 = pl.a10 * s, s11 = pl.a11 * s, s12 = pl.a12 * s, s13 = pl.a13 * s;
+        const RT s20 = pl.a20 * s, s22 = pl.a22 * s, s30 = pl.a30 * s, s33 = pl.a33 * s;
+        const RT sg2 = pl.g2 * s, sg3 = pl.g3 * s;
+        RT nm[4][4], nx[4][4], nd[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             OPMM_MV(s10, s11, s12, s13, s20, s22, s30, s33, s, pm[0][c], pm[1][c], pm[2][c], pm[3][c],
                     nm[0][c], nm[1][c], nm[2][c], nm[3][c],
-                    c == 0 ? one : R(0), c == 1 ? one : R(0), c == 2 ? one : R(0), c == 3 ? one : R(0));
+                    c == 0 ? one : RT(0), c == 1 ? one : RT(0), c == 2 ? one : RT(0), c == 3 ? one : RT(0));
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const R ga = (c & 1) ? R(0) : sg2 * pd[c];
-            const R gn = (c & 1) ? sg3 * pd[c] : R(0);
+            const RT ga = (c & 1) ? RT(0) : sg2 * pd[c];
+            const RT gn = (c & 1) ? sg3 * pd[c] : RT(0);
             OPMM_MV(s10, s11, s12, s13, s20, s22, s30, s33, s, px[0][c], px[1][c], px[2][c], px[3][c],
-                    nx[0][c], nx[1][c], nx[2][c], nx[3][c], R(0), R(0), ga, gn);
+                    nx[0][c], nx[1][c], nx[2][c], nx[3][c], RT(0), RT(0), ga, gn);
             nd[c] = fmr(qv[c] * s, pd[c], one);
         }
 #pragma unroll
@@ -272,17 +269,17 @@ __device__ __forceinline__ void transition_dform(Plant& pl, R hfull)
         }
     }
 #pragma unroll
-    for (int q = 0; q < TAYLOR_SQ; ++q) {
-        R nm[4][4], nx[4][4];
+    for (int q = 0; q < SQ; ++q) {
+        RT nm[4][4], nx[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                R a = pm[i][c] + pm[i][c];
+                RT a = pm[i][c] + pm[i][c];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) a = fmr(pm[i][k], pm[k][c], a);
                 nm[i][c] = a;
-                R b = px[i][c] * (pd[c] + R(2));
+                RT b = px[i][c] * (pd[c] + RT(2));
 #pragma unroll
                 for (int k = 0; k < 4; ++k) b = fmr(pm[i][k], px[k][c], b);
                 nx[i][c] = b;
@@ -292,7 +289,7 @@ __device__ __forceinline__ void transition_dform(Plant& pl, R hfull)
         for (int i = 0; i < 4; ++i) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) { pm[i][c] = nm[i][c]; px[i][c] = nx[i][c]; }
-            pd[i] = pd[i] * (pd[i] + R(2));
+            pd[i] = pd[i] * (pd[i] + RT(2));
         }
     }
 #pragma unroll
@@ -371,32 +368,34 @@ __device__ __forceinline__ void plant_scalars(const S p[P], S amp, PlantScalars<
 
 // Coefficients, transition and equilibria of candidate p for a saccade of
 // amplitude amp (deg), sample period dt (ms).  The scalar part is formed in
-// FP64 and rounded once to R: FP32 chains of reciprocals here would shift the
+// FP64 and rounded once to RT: FP32 chains of reciprocals here would shift the
 // equilibria by a few ulps of ~10 deg, i.e. ~1e-6 deg on every sample.
-__device__ __forceinline__ void plant_setup(const float p[P], float amp, float dt, Plant& pl)
+template <class RT>
+__device__ __forceinline__ void plant_setup(const float p[P], float amp, float dt, PlantT<RT>& pl)
 {
     double pd[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) pd[j] = p[j];
     PlantScalars<double> c;
     plant_scalars(pd, (double)amp, c);
-    pl.a10 = (R)c.a10; pl.a11 = (R)c.a11; pl.a12 = (R)c.a12; pl.a13 = (R)c.a13;
-    pl.a20 = (R)c.a20; pl.a22 = (R)c.a22; pl.g2 = (R)c.g2;
-    pl.a30 = (R)c.a30; pl.a33 = (R)c.a33; pl.g3 = (R)c.g3;
-    pl.q1a = (R)c.q1a; pl.q1n = (R)c.q1n; pl.q2a = (R)c.q2a; pl.q2n = (R)c.q2n;
-    transition_dform(pl, (R)dt);
-    pl.th1 = (R)c.th1;
+    pl.a10 = (RT)c.a10; pl.a11 = (RT)c.a11; pl.a12 = (RT)c.a12; pl.a13 = (RT)c.a13;
+    pl.a20 = (RT)c.a20; pl.a22 = (RT)c.a22; pl.g2 = (RT)c.g2;
+    pl.a30 = (RT)c.a30; pl.a33 = (RT)c.a33; pl.g3 = (RT)c.g3;
+    pl.q1a = (RT)c.q1a; pl.q1n = (RT)c.q1n; pl.q2a = (RT)c.q2a; pl.q2n = (RT)c.q2n;
+    transition_dform(pl, (RT)dt);
+    pl.th1 = (RT)c.th1;
     pl.amp = amp;
 #pragma unroll
-    for (int i = 0; i < 6; ++i) { pl.d0[i] = (R)c.d0[i]; pl.sh[i] = (R)c.sh[i]; }
+    for (int i = 0; i < 6; ++i) { pl.d0[i] = (RT)c.d0[i]; pl.sh[i] = (RT)c.sh[i]; }
     pl.pw = p[17];
     pl.pwd = (double)p[17] * rcp64((double)dt);
 }
 
 // d <- Phi d for one sample (D-form: d + D d)
-__device__ __forceinline__ void step(const Plant& pl, const R (&x)[4][2], const R (&e)[2], R d[6])
+template <class RT>
+__device__ __forceinline__ void step(const PlantT<RT>& pl, const RT (&x)[4][2], const RT (&e)[2], RT d[6])
 {
-    R n[4];
+    RT n[4];
     // the row's own state is the addend of the first fma
     n[0] = fmr(pl.m[0][0], d[0], d[0]);
     n[1] = fmr(pl.m[1][1], d[1], d[1]);
@@ -416,17 +415,18 @@ __device__ __forceinline__ void step(const Plant& pl, const R (&x)[4][2], const 
     for (int i = 0; i < 4; ++i) d[i] = n[i];
 }
 
-// v <- exp(A t) v by a degree-EXPMV_M Taylor polynomial in Horner form (t <= dt).
-__device__ __forceinline__ void expmv(const Plant& pl, R qa, R qn, R t, R v[6])
+// v <- exp(A t) v by a Taylor polynomial (degree Prec::expmv_m) in Horner form (t <= dt).
+template <class RT>
+__device__ __forceinline__ void expmv(const PlantT<RT>& pl, RT qa, RT qn, RT t, RT v[6])
 {
-    R w[6];
+    RT w[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) w[i] = v[i];
 #pragma unroll
-    for (int k = EXPMV_M; k >= 1; --k) {
-        R s = t * (R(1) / R(k));
+    for (int k = Prec<RT>::expmv_m; k >= 1; --k) {
+        RT s = t * (RT(1) / RT(k));
         asm volatile("" : "+v"(s));
-        R aw[6];
+        RT aw[6];
         aw[0] = w[1];
         aw[1] = fmr(pl.a13, w[3], fmr(pl.a12, w[2], fmr(pl.a11, w[1], pl.a10 * w[0])));
         aw[2] = fmr(pl.g2, w[4], fmr(pl.a22, w[2], pl.a20 * w[0]));
@@ -442,12 +442,13 @@ __device__ __forceinline__ void expmv(const Plant& pl, R qa, R qn, R t, R v[6])
 
 // The sample that contains the pulse end: pulse dynamics for frac*dt, switch
 // to the post piece's coordinates, post dynamics for the rest of the sample.
-__device__ __forceinline__ void split_step(const Plant& pl, R frac, R dt, R d[6])
+template <class RT>
+__device__ __forceinline__ void split_step(const PlantT<RT>& pl, RT frac, RT dt, RT d[6])
 {
     expmv(pl, pl.q1a, pl.q1n, frac * dt, d);
 #pragma unroll
     for (int i = 0; i < 6; ++i) d[i] += pl.sh[i];
-    expmv(pl, pl.q2a, pl.q2n, (R(1) - frac) * dt, d);
+    expmv(pl, pl.q2a, pl.q2n, (RT(1) - frac) * dt, d);
 }
 
 // wave-wide min / max of an int (64 lanes)
@@ -466,13 +467,14 @@ __device__ __forceinline__ int wave_max(int v)
 
 // Integer sample index that holds the pulse end (-1: no pulse), clamped to
 // [-1, T], and the fraction of that sample spent in the pulse.
-__device__ __forceinline__ int pulse_end_sample(double pw, int T, R& frac)
+template <class RT>
+__device__ __forceinline__ int pulse_end_sample(double pw, int T, RT& frac)
 {
     double fl = floor(pw);
     int k0;
-    if (!(pw > 0.0)) { k0 = -1; frac = R(0); }
-    else if (fl >= (double)T) { k0 = T; frac = R(0); }
-    else { k0 = (int)fl; frac = (R)(pw - fl); }
+    if (!(pw > 0.0)) { k0 = -1; frac = RT(0); }
+    else if (fl >= (double)T) { k0 = T; frac = RT(0); }
+    else { k0 = (int)fl; frac = (RT)(pw - fl); }
     return k0;
 }
 
@@ -480,14 +482,14 @@ __device__ __forceinline__ int pulse_end_sample(double pw, int T, R& frac)
 // with theta_k = dtheta + theta_eq.  kmin/kmax: wave-uniform bounds of the
 // lanes' pulse-end samples; samples below kmin are pulse for every lane and
 // samples above kmax post for every lane, so only [kmin, kmax] branches.
-template <int UNROLL, class Sink>
-__device__ __forceinline__ void run_trajectory(const Plant& pl, int T, R dt, int k0, R frac,
+template <int UNROLL, class RT, class Sink>
+__device__ __forceinline__ void run_trajectory(const PlantT<RT>& pl, int T, RT dt, int k0, RT frac,
                                                int kmin, int kmax, Sink& sink)
 {
-    R d[6];
+    RT d[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) d[i] = pl.d0[i];
-    R theq = pl.th1;
+    RT theq = pl.th1;
     if (k0 < 0) {  // PW <= 0: no pulse, the step acts from t = 0
 #pragma unroll
         for (int i = 0; i < 6; ++i) d[i] += pl.sh[i];

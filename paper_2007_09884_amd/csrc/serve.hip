@@ -221,6 +221,8 @@ int opmm_server_create(opmm_ctx* ctx, opmm_surrogate* sg, const opmm_serve_param
         return opmm_rt::fail(ctx, OPMM_EINVAL, "plain and seeded searches must share dt_ms, box_frac, shrink and model");
     if (prm->polish_iter < 0 || prm->polish_iter > 100)
         return opmm_rt::fail(ctx, OPMM_EINVAL, "polish_iter must be in 0..100");
+    if (prm->plain.screen_rounds != 0 || prm->seeded.screen_rounds != 0)
+        return opmm_rt::fail(ctx, OPMM_EINVAL, "the server runs every round in FP64 (screen_rounds = 0)");
     if (prm->rounds_per_step < 1 || prm->rounds_per_step > kMaxRoundsPerStep)
         return opmm_rt::fail(ctx, OPMM_EINVAL, "rounds_per_step must be in 1..64");
     // slots admitted by memory: what one resident request costs on the device

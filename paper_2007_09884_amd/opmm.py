@@ -30,7 +30,8 @@ assert SACCADE_DTYPE.itemsize == 40
 class FitParams(ctypes.Structure):
     _fields_ = [("n_cand", ctypes.c_int32), ("n_rounds", ctypes.c_int32), ("box_frac", ctypes.c_float),
                 ("w_init_frac", ctypes.c_float), ("shrink", ctypes.c_float), ("dt_ms", ctypes.c_float),
-                ("mode", ctypes.c_int32), ("tile", ctypes.c_int32), ("model", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("tile", ctypes.c_int32), ("model", ctypes.c_int32),
+                ("screen_rounds", ctypes.c_int32), ("screen_tol", ctypes.c_float)]
 
 
 class ServeParams(ctypes.Structure):

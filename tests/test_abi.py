@@ -35,8 +35,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     from paper_2007_09884_amd import opmm
     assert opmm.SACCADE_DTYPE.itemsize == 40
-    assert ctypes.sizeof(opmm.FitParams) == 36
-    assert ctypes.sizeof(opmm.ServeParams) == 104 and ctypes.sizeof(opmm.NmParams) == 28
+    assert ctypes.sizeof(opmm.FitParams) == 44
+    assert ctypes.sizeof(opmm.ServeParams) == 120 and ctypes.sizeof(opmm.NmParams) == 28
     sv = opmm.serve_params()
     assert (sv.max_slots, sv.max_T, sv.polish_iter, sv.rounds_per_step) == (4096, 160, 0, 16)
     n = opmm.nm_params()
@@ -46,8 +46,8 @@ def test_struct_layouts_match_header():
     q = opmm.polish_params()
     assert (q.max_iter, q.objective, q.lambda0, q.box_frac, q.dt_ms) == (20, 0, np.float32(1e-3), 0.25, 1.0)
     p = opmm.fit_params()
-    assert (p.n_cand, p.n_rounds, p.box_frac, p.w_init_frac, p.shrink, p.dt_ms, p.mode, p.tile, p.model) == \
-        (4096, 1, 0.25, 1.0, 0.5, 1.0, 0, -1, 18)
+    assert (p.n_cand, p.n_rounds, p.box_frac, p.w_init_frac, p.shrink, p.dt_ms, p.mode, p.tile, p.model,
+            p.screen_rounds, p.screen_tol) == (4096, 1, 0.25, 1.0, 0.5, 1.0, 0, -1, 18, 0, np.float32(5e-5))
 
 
 def test_nominal_is_table1():

@@ -1,0 +1,121 @@
+"""Screened rounds (opmm_fit_params.screen_rounds): every candidate is simulated with an FP32
+recurrence, and those whose FP32 RMSE lies within screen_tol of the round's FP32 best are simulated
+again in FP64, exactly as the FP64 round kernel does; the FP64 keys decide the argmin.  The results
+must equal the FP64-only fit bit for bit (round keys, OPC, RMSE, OptErr, status): on the
+full-estimation oracle subset, an uneven batch, the 9-parameter model, a seeded refine, a captured
+plan, and with a tolerance so large that every candidate is verified.  Parity of the FP64-only fit
+against the oracle is tested elsewhere, so these equalities carry it over."""
+import numpy as np
+import pytest
+
+from paper_2007_09884_amd import synth
+from workload import make_batch, records
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def opmm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2007_09884_amd import opmm as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(opmm):
+    c = opmm.Context(0)
+    yield c
+    c.close()
+
+
+def fit(ctx, opmm, b, traces, prm, n_cand_per=None, seed_opc=None, plan=False):
+    S, R = b["S"], prm.n_rounds
+    recs = records(b, opmm, n_cand=n_cand_per)
+    pos = torch.from_numpy(opmm.pack_traces(traces)).cuda()
+    out = dict(opc=torch.zeros(S, 18, device="cuda"), rmse=torch.zeros(S, device="cuda"),
+               mae=torch.zeros(S, device="cuda"), status=torch.zeros(S, dtype=torch.int32, device="cuda"),
+               keys=torch.zeros(R, S, dtype=torch.int64, device="cuda"))
+    seed = None if seed_opc is None else torch.from_numpy(seed_opc).cuda()
+    if plan:
+        pl = ctx.plan(pos, recs, prm, out["opc"], out["rmse"], out["mae"], out["status"], out["keys"], seed_opc=seed)
+        for v in out.values():
+            v.zero_()
+        pl.launch()
+        ctx.sync()
+        pl.close()
+    else:
+        ctx.fit(pos, recs, prm, out["opc"], out["rmse"], out["mae"], out["status"], out["keys"], seed_opc=seed)
+        ctx.sync()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def same(a, b, where):
+    for k in a:
+        assert np.array_equal(a[k].view(np.uint32) if a[k].dtype == np.float32 else a[k],
+                              b[k].view(np.uint32) if b[k].dtype == np.float32 else b[k]), (where, k)
+
+
+def test_screened_full_estimation_equals_fp64(ctx, opmm):
+    b, traces = make_batch(16, "full")
+    ref = fit(ctx, opmm, b, traces, opmm.fit_params(n_cand=65536, n_rounds=10))
+    for sr in (7, 10):
+        got = fit(ctx, opmm, b, traces, opmm.fit_params(n_cand=65536, n_rounds=10, screen_rounds=sr))
+        same(got, ref, ("full", sr))
+
+
+def test_screened_bench_configuration_equals_fp64(ctx, opmm):
+    """The full-estimation workload as the benchmark runs it (256 saccades x 65536 x 10 rounds, eight
+    screened rounds, captured plan) against the FP64-only fit: 256 x 8 screened argmins over 65536
+    candidates each, every one the FP64 argmin."""
+    b, traces = make_batch(256, "full")
+    tile = opmm.lib.opmm_tile_default()
+    ref = fit(ctx, opmm, b, traces, opmm.fit_params(n_cand=65536, n_rounds=10, tile=tile), plan=True)
+    got = fit(ctx, opmm, b, traces, opmm.fit_params(n_cand=65536, n_rounds=10, tile=tile, screen_rounds=8),
+              plan=True)
+    same(got, ref, "bench configuration")
+
+
+def test_screened_uneven_model9_seeded_and_plan(ctx, opmm):
+    b, traces = make_batch(12, "uneven", seed=synth.BASE_SEED + 61)
+    ncand = np.array([64, 3000, 4096, 16384, 1, 700, 5000, 2049, 4096, 300, 8192, 65536], np.int32)
+    ref = fit(ctx, opmm, b, traces, opmm.fit_params(n_cand=64, n_rounds=6), n_cand_per=ncand)
+    got = fit(ctx, opmm, b, traces, opmm.fit_params(n_cand=64, n_rounds=6, screen_rounds=6), n_cand_per=ncand)
+    same(got, ref, "uneven")
+    got = fit(ctx, opmm, b, traces, opmm.fit_params(n_cand=64, n_rounds=6, screen_rounds=6), n_cand_per=ncand,
+              plan=True)
+    same(got, ref, "uneven, captured plan")
+    b9, tr9 = make_batch(8, "full", seed=synth.BASE_SEED + 62)
+    ref = fit(ctx, opmm, b9, tr9, opmm.fit_params(n_cand=8192, n_rounds=5, model=9))
+    got = fit(ctx, opmm, b9, tr9, opmm.fit_params(n_cand=8192, n_rounds=5, model=9, screen_rounds=4))
+    same(got, ref, "model 9")
+    rng = np.random.default_rng(8)
+    seeds = np.stack([opmm.nominal(float(d)) * rng.uniform(0.9, 1.1, 18) for d in b9["dur_ms"]]).astype(np.float32)
+    prm = opmm.fit_params(n_cand=1024, n_rounds=3, w_init_frac=0.25)
+    ref = fit(ctx, opmm, b9, tr9, prm, seed_opc=seeds)
+    prm.screen_rounds = 3
+    same(fit(ctx, opmm, b9, tr9, prm, seed_opc=seeds), ref, "seeded")
+    # a tolerance this large verifies every candidate in FP64
+    prm.screen_tol = 1e3
+    same(fit(ctx, opmm, b9, tr9, prm, seed_opc=seeds), ref, "every candidate verified")
+
+
+def test_screening_argument_errors(ctx, opmm):
+    b, traces = make_batch(2, "full", seed=synth.BASE_SEED + 63)
+    for kw in (dict(screen_rounds=3, n_rounds=2), dict(screen_rounds=-1), dict(screen_rounds=1, screen_tol=0.0),
+               dict(screen_rounds=1, mode=opmm.FIT_PERSISTENT)):
+        prm = opmm.fit_params(n_cand=256, **{"n_rounds": 2, **kw})
+        with pytest.raises(opmm.OpmmError) as e:
+            fit(ctx, opmm, b, traces, prm)
+        assert e.value.code == opmm.EINVAL, kw
+    recs = records(b, opmm)
+    pos = torch.from_numpy(opmm.pack_traces(traces)).cuda()
+    opc = torch.zeros(2, 18, device="cuda"); rmse = torch.zeros(2, device="cuda")
+    with pytest.raises(opmm.OpmmError):
+        ctx.fit_noalloc(pos, recs, opmm.fit_params(n_cand=256, n_rounds=2, screen_rounds=1), opc, rmse)
+    prm = opmm.serve_params()
+    prm.plain.screen_rounds = 1
+    with pytest.raises(opmm.OpmmError):
+        opmm.Server(ctx, prm)
