@@ -47,6 +47,8 @@ def parse():
                     help="rounds screened in FP32 with the FP64 argmin of the candidates within --screen-tol "
                          "(per-round mode; results equal the FP64-only fit, which a side leg times); 0: FP64 only")
     ap.add_argument("--screen-tol", type=float, default=5e-5, help="screening tolerance, deg of RMSE")
+    ap.add_argument("--no-fp64-leg", action="store_true",
+                    help="skip the side leg that times the same fit with every round in FP64")
     ap.add_argument("--tile", type=int, default=-1, help="kernel shape index; -1 library default, -2 autotune")
     ap.add_argument("--no-autotune-leg", action="store_true",
                     help="skip the side leg that autotunes both launch modes and times their picks")
@@ -112,31 +114,26 @@ def sources_digest():
     return h.hexdigest()
 
 
-def executed_fig(flop_per_launch, launch_ms):
-    """Executed FP64 FLOP/s (the VALU's own count from the profile, over this run's launch time)."""
+def executed_fig(flop_per_launch, launch_ms, peak):
+    """Executed FLOP/s of a kernel (the VALU's own count from the profile, over this run's launch time)."""
     if flop_per_launch is None:
         return None
     t = flop_per_launch / (launch_ms * 1e-3) / 1e12
-    return {"flop_per_launch": flop_per_launch, "tflops": t, "frac": t / ALU_PEAK_TFLOPS,
-            "source": "the VALU's own FLOP count: SQ_INSTS_VALU_FLOPS_FP64 (+ _FP32 with screened rounds) x 64 "
-                      "lanes x active-lane share (rocprofv3 summary in profiles/)"}
+    return {"flop_per_launch": flop_per_launch, "tflops": t, "frac": t / peak,
+            "source": "the VALU's own FLOP count: (SQ_INSTS_VALU_FLOPS_FP32 + _FP64) x 64 lanes x active-lane "
+                      "share (rocprofv3 summary in profiles/)"}
 
 
-def profiled_traffic(mode, tile_name, screen=0):
-    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading)."""
-    return profiled_value("traffic_per_launch_bytes", mode, tile_name, screen)
-
-
-def profiled_value(key, mode, tile_name, screen=0):
-    """A per-launch figure from the committed rocprofv3 counter summaries (a `key=value mode=.. tile=..
-    [screen=..] sources_sha256=..` line), if one was taken on the same launch mode, tile shape and
-    screened-round count (absent: 0) from the current kernel sources; else None."""
+def profiled_value(key, kernel, tile_name):
+    """A per-launch figure of `kernel` from the committed rocprofv3 counter summaries (a `key=value
+    kernel=.. tile=.. sources_sha256=..` line), if one was taken on the same kernel and tile shape from
+    the current kernel sources; else None."""
     import glob
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.txt"))):
         for line in open(path):
             if line.startswith(key + "="):
                 kv = dict(t.split("=", 1) for t in line.split()[1:])
-                if (kv.get("mode") == mode and kv.get("tile") == tile_name and int(kv.get("screen", 0)) == screen
+                if (kv.get("kernel") == kernel and kv.get("tile") == tile_name
                         and kv.get("sources_sha256") == sources_digest()):
                     return int(line.split()[0].split("=")[1])
     return None
@@ -544,7 +541,7 @@ def main():
         prm.tile = autotuned(a.mode).tile if a.tile == -2 else a.tile
     if prm.tile < 0:
         prm.tile = opmm.lib.opmm_tile_default()
-    if a.screen_rounds > 0:
+    if a.screen_rounds > 0 and prm.mode == opmm.FIT_ROUNDS:
         prm.screen_rounds, prm.screen_tol = min(a.screen_rounds, R), a.screen_tol
     for v in tuned.values():
         del v["params"]
@@ -571,29 +568,47 @@ def main():
         e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    launch_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    step_ms_gpu = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))  # captured step, launch stream
 
     sims = S * N * R
     ms_per_step = wall / a.steps * 1e3
     value = sims * a.steps / wall
     sum_T = int(np.sum(b["T"]))
     flop = FLOP_PER_CAND_SAMPLE * N * R * sum_T
-    # one kernel per round (rounds mode) or one for the whole step (persistent); the HIP events bracket
-    # the captured step, so the per-launch time includes the small kernels' ~1 %.  With screened rounds a
-    # "launch" is a whole round: the FP32 pass and the FP64 verification, or the FP64 round kernel
-    n_launch = R if a.mode == "rounds" else 1
     scr = int(prm.screen_rounds)
+    tile_name = opmm.tile_names()[prm.tile]
+    # Each search kernel's own launches, timed by the library's event pairs on the launch stream over
+    # `steps` more fits of the same batch queued directly (a captured plan cannot be split by kernel).
+    ctx.kernel_timing(True)
+    for _ in range(a.steps):
+        ctx.fit(pos, recs, prm, opc, rmse, None, status)
+    kt = {}
+    for kid, kname in ((opmm.KERNEL_ROUND, "fit_round_kernel"), (opmm.KERNEL_SCREEN, "fit_screen_kernel"),
+                       (opmm.KERNEL_VERIFY, "fit_verify_kernel"), (opmm.KERNEL_PERSISTENT, "fit_persistent_kernel")):
+        tot, n = ctx.kernel_times(kid)
+        if n:
+            kt[kname] = {"avg_ms": tot / n, "launches_per_step": n / a.steps, "ms_per_step": tot / a.steps}
+    ctx.kernel_timing(False)
+    dom = max(kt, key=lambda k: kt[k]["ms_per_step"])
+    # the algorithmic unit: one recurrence step of one candidate (54 FLOP); a round kernel or a screen
+    # kernel covers one round of the batch, the persistent kernel the whole step
+    flop_launch = flop if dom == "fit_persistent_kernel" else flop // R
+    fp32 = dom == "fit_screen_kernel"
+    peak = PUBLISHED_FP32_PEAK if fp32 else ALU_PEAK_TFLOPS
+    dom_ms = kt[dom]["avg_ms"]
+    achieved = flop_launch / (dom_ms * 1e-3) / 1e12
+    # the whole step against the peak of the precision each round runs in
+    step_peak = R / (scr / PUBLISHED_FP32_PEAK + (R - scr) / ALU_PEAK_TFLOPS)
+    step_tflops = flop / (step_ms_gpu * 1e-3) / 1e12
     if scr > 0:
-        kernel_text = ("whole round, %d per step: rounds 0-%d fit_screen_kernel (FP32, every candidate) + "
-                       "fit_verify_kernel (FP64, the candidates within %.0e deg RMSE of the FP32 best)%s; "
-                       "launch_ms is the captured step / %d" % (
-                           R, scr - 1, prm.screen_tol,
-                           ", rounds %d-%d fit_round_kernel (FP64)" % (scr, R - 1) if scr < R else "", R))
+        kernel_text = ("fit_screen_kernel: the FP32 pass over every candidate of one screened round "
+                       "(%d of %d rounds are screened; their survivors within %.0e deg RMSE of the FP32 best go "
+                       "to fit_verify_kernel in FP64; the other rounds run fit_round_kernel in FP64)" % (
+                           scr, R, prm.screen_tol))
+    elif dom == "fit_persistent_kernel":
+        kernel_text = "fit_persistent_kernel: one work-queue launch for the whole step, FP64 recurrence"
     else:
-        kernel_text = (("fit_persistent_kernel (one launch per step" if a.mode == "persistent" else
-                        "fit_round_kernel (%d launches per step" % R) +
-                       "; launch_ms is the whole captured step: prep/init/refine/report kernels add ~1%)")
-    achieved = flop / (launch_ms * 1e-3) / 1e12
+        kernel_text = "fit_round_kernel: every candidate of one round, FP64 recurrence (%d launches per step)" % R
     st = status.cpu().numpy()
     rm = rmse.cpu().numpy()
 
@@ -618,15 +633,22 @@ def main():
         "saccades_fitted_per_s": S * a.steps / wall,
         "mean_final_rmse_deg": float(np.mean(rm)),
         "status_nonzero": int(np.count_nonzero(st)),
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / ALU_PEAK_TFLOPS,
-                     "traffic": profiled_traffic(a.mode, opmm.tile_names()[prm.tile], scr),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak,
+                     "traffic": profiled_value("traffic_per_launch_bytes", dom, tile_name),
                      "kernel": kernel_text,
-                     "launch_ms": launch_ms / n_launch, "launches_per_step": n_launch,
-                     "algorithmic_flop_per_launch": flop // n_launch,
-                     "executed": executed_fig(profiled_value("executed_flop_per_launch", a.mode,
-                                                             opmm.tile_names()[prm.tile], scr), launch_ms / n_launch),
-                     "frac_of_published_fp32_157": achieved / PUBLISHED_FP32_PEAK},
+                     "peak_source": ("published FP32 vector peak (non-packed FMA issues at up to twice the FP64 "
+                                     "rate on this chip)" if fp32 else
+                                     "FP64 vector peak: 256 CU x 4 SIMD x 16 lanes x FMA x 2.4 GHz"),
+                     "launch_ms": dom_ms, "launch_timing": "library event pairs around each launch, launch stream",
+                     "algorithmic_flop_per_launch": flop_launch,
+                     "executed": executed_fig(profiled_value("executed_flop_per_launch", dom, tile_name), dom_ms,
+                                              peak),
+                     "kernels": kt,
+                     "step": {"achieved": step_tflops, "peak": step_peak, "frac": step_tflops / step_peak,
+                              "note": "whole captured step (all kernels) against the peak of each round's "
+                                      "precision: %d FP32 rounds at %.1f, %d FP64 rounds at %.1f TFLOP/s" % (
+                                          scr, PUBLISHED_FP32_PEAK, R - scr, ALU_PEAK_TFLOPS)}},
     }
     if a.report_csv:
         # one more fit (untimed) for the mean absolute difference, the paper's OptErr; the serial
@@ -635,13 +657,13 @@ def main():
         mae = torch.zeros(S, device="cuda")
         ctx.fit(pos, recs, prm, opc, rmse, mae, status)
         report.write_csv(a.report_csv, opc.cpu().numpy(), mae.cpu().numpy())
-    if scr > 0:
+    if scr > 0 and not a.no_fp64_leg:
         # the same workload with every round in FP64 only: its time, and that it returns the same fit
         p64 = opmm.fit_params(n_cand=N, n_rounds=R, mode=modes[a.mode], tile=prm.tile)
         opc_s = opc.clone()
         ms64 = time_plan(p64, reps=5)
         out["fp64_only"] = {"ms_per_step": ms64, "candidate_sims_per_s": sims / (ms64 * 1e-3),
-                            "roofline_frac": flop / R / (ms64 / R * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
+                            "step_frac_of_fp64_peak": flop / (ms64 * 1e-3) / 1e12 / ALU_PEAK_TFLOPS,
                             "same_opc_as_screened": bool(torch.equal(opc, opc_s))}
     if tuned:
         out["autotune"] = tuned

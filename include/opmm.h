@@ -76,6 +76,15 @@ enum {
                                        before its tolerances held (best vertex so far) */
 };
 
+/* Search kernels that opmm_kernel_timing_read reports on. */
+enum {
+    OPMM_KERNEL_ROUND = 0,       /* one FP64 round of every tile (per-round mode)       */
+    OPMM_KERNEL_SCREEN = 1,      /* FP32 pass of a screened round                       */
+    OPMM_KERNEL_VERIFY = 2,      /* FP64 re-simulation of a screened round's survivors  */
+    OPMM_KERNEL_PERSISTENT = 3,  /* the work-queue launch of a persistent fit           */
+    OPMM_KERNEL_KINDS = 4
+};
+
 typedef struct opmm_ctx opmm_ctx;
 
 /* One recorded saccade (Section 3.1: extracted saccades are the input).
@@ -161,6 +170,24 @@ const char* opmm_last_error(const opmm_ctx* ctx);
  * up at once (to exercise the report).  Applies to fits queued and plans
  * created after the call. */
 int opmm_set_wait_limit(opmm_ctx* ctx, uint32_t polls);
+/* Kernel timing, a measurement aid with no counterpart in the paper.  With
+ * timing on, each fit queued directly on a stream (opmm_fit, opmm_fit_learned,
+ * opmm_fit_noalloc, and the one uncaptured run opmm_fit_plan_create makes
+ * before it captures; not a plan's graph launches, nothing under stream
+ * capture) records a HIP event pair on its stream around every launch of a
+ * search kernel (OPMM_KERNEL_*); the
+ * events come from a pool of 1024 pairs made when timing is switched on
+ * (host-side event objects, no device memory), and launches beyond that many
+ * between two reads are not timed.  Event timing adds a few microseconds per
+ * launch to the stream.  Off by default; `on` = 0 switches it off and keeps
+ * the pool until the context is destroyed. */
+int opmm_kernel_timing_enable(opmm_ctx* ctx, int32_t on);
+/* Wait for the recorded launches of `kernel` (OPMM_KERNEL_*), then return
+ * their summed duration in ms and their count since the last read of that
+ * kernel, and clear both.  OPMM_EINVAL for a null handle or output or an
+ * unknown kernel. */
+int opmm_kernel_timing_read(opmm_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
+
 /* Synchronise `stream`, then read and clear the context's report: returns
  * OPMM_EDEVICE (with the count in opmm_last_error) if any persistent launch
  * of this context that has completed gave up a wait since the last call,

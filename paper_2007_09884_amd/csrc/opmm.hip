@@ -30,6 +30,7 @@
 #include "runtime.hpp"
 
 using namespace opmm;
+using opmm_rt::KernelTimer;
 using opmm_rt::SacDev;
 
 namespace {
@@ -807,11 +808,28 @@ struct FitLaunch {
     uint64_t* smin;   // [S]: FP32 best key per saccade
     const double* qorth;
     float tau;
+    KernelTimer* timer;  // non-null: record an event pair around each search-kernel launch
+};
+
+// Event pair around one launch when the call is timed (see KernelTimer).
+struct TimedLaunch {
+    KernelTimer* t;
+    int kernel, slot;
+    hipStream_t st;
+    TimedLaunch(KernelTimer* timer, int k, hipStream_t s) : t(timer), kernel(k), slot(-1), st(s)
+    {
+        if (t) slot = t->begin(st);
+    }
+    ~TimedLaunch()
+    {
+        if (t) t->end(kernel, slot, st);
+    }
 };
 
 template <int TPB, int PASSES, int UNROLL>
 hipError_t launch_shape(const FitLaunch& L, bool persistent, int round, hipStream_t st)
 {
+    TimedLaunch tl(L.timer, persistent ? OPMM_KERNEL_PERSISTENT : OPMM_KERNEL_ROUND, st);
     if (persistent) {
         hipLaunchKernelGGL((fit_persistent_kernel<TPB, PASSES, UNROLL>), dim3(L.grid_persistent), dim3(TPB), 0,
                            st, L.sacs, L.S, L.R, L.tiles_per_round, L.dt, L.shrink, L.proj, L.centre, L.hw,
@@ -828,12 +846,18 @@ hipError_t launch_shape(const FitLaunch& L, bool persistent, int round, hipStrea
 template <int TPB, int PASSES, int UNROLL>
 hipError_t launch_screened(const FitLaunch& L, int round, hipStream_t st)
 {
-    hipLaunchKernelGGL((fit_screen_kernel<TPB, PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(TPB), 0, st, L.sacs,
-                       L.S, round, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status, L.ord, L.obase, L.costs,
-                       L.smin);
-    hipLaunchKernelGGL((fit_verify_kernel<TPB, PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(TPB), 0, st, L.sacs,
-                       L.S, round, L.key_stride, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status, L.keys, L.ord,
-                       L.obase, L.costs, L.smin, L.qorth, L.tau);
+    {
+        TimedLaunch tl(L.timer, OPMM_KERNEL_SCREEN, st);
+        hipLaunchKernelGGL((fit_screen_kernel<TPB, PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(TPB), 0, st,
+                           L.sacs, L.S, round, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status, L.ord, L.obase,
+                           L.costs, L.smin);
+    }
+    {
+        TimedLaunch tl(L.timer, OPMM_KERNEL_VERIFY, st);
+        hipLaunchKernelGGL((fit_verify_kernel<TPB, PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(TPB), 0, st,
+                           L.sacs, L.S, round, L.key_stride, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status,
+                           L.keys, L.ord, L.obase, L.costs, L.smin, L.qorth, L.tau);
+    }
     return hipGetLastError();
 }
 
@@ -968,6 +992,7 @@ struct opmm_ctx {
     hipStream_t cap_stream = nullptr;
     unsigned char* noalloc_scratch = nullptr;  // device address of `scratch` on this device (set at creation)
     opmm_rt::StreamOrder order;  // orders calls on different streams (scratch, aux, d_cand, give-up word)
+    KernelTimer timer;           // per-kernel timing of uncaptured fits (off unless switched on)
 };
 
 struct opmm_plan {
@@ -1305,6 +1330,11 @@ int enqueue_fit_bufs(opmm_ctx* ctx, const FitBufs& B, const float* pos, int S, i
     L.smin = B.smin;
     L.qorth = qorth;
     L.tau = prm->screen_tol;
+    L.timer = nullptr;
+    if (ctx->timer.on) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) L.timer = &ctx->timer;
+    }
     if (tiles_per_round > 0) {
         if (prm->mode == OPMM_FIT_PERSISTENT) {
             // The queue needs no co-residency, so oversubscribe: blocks that start
@@ -1666,6 +1696,7 @@ int opmm_destroy(opmm_ctx* ctx)
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->giveup_report) (void)hipFree(ctx->giveup_report);
     opmm_rt::order_release(ctx->order);
+    ctx->timer.release();
     delete ctx;
     return OPMM_OK;
 }
@@ -1676,6 +1707,32 @@ int opmm_set_wait_limit(opmm_ctx* ctx, uint32_t polls)
 {
     if (!ctx) return OPMM_EINVAL;
     ctx->wait_limit = polls;
+    return OPMM_OK;
+}
+
+int opmm_kernel_timing_enable(opmm_ctx* ctx, int32_t on)
+{
+    if (!ctx) return OPMM_EINVAL;
+    OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    if (!on) {
+        ctx->timer.on = false;
+        return OPMM_OK;
+    }
+    OPMM_HIP(ctx, ctx->timer.reserve());
+    ctx->timer.on = true;
+    return OPMM_OK;
+}
+
+int opmm_kernel_timing_read(opmm_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches)
+{
+    if (!ctx || !total_ms || !launches || kernel < 0 || kernel >= OPMM_KERNEL_KINDS)
+        return fail(ctx, OPMM_EINVAL, "opmm_kernel_timing_read: null handle or output, or unknown kernel");
+    OPMM_HIP(ctx, hipSetDevice(ctx->device));
+    OPMM_HIP(ctx, ctx->timer.collect());
+    *total_ms = ctx->timer.ms[kernel];
+    *launches = ctx->timer.n[kernel];
+    ctx->timer.ms[kernel] = 0.0;
+    ctx->timer.n[kernel] = 0;
     return OPMM_OK;
 }
 

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/opmm.h"
 
@@ -41,6 +42,73 @@ hipError_t order_init(StreamOrder& o);
 void order_release(StreamOrder& o);
 // Host-side wait for the last call, for a synchronous call about to use stream `st`.
 hipError_t order_host_wait(const StreamOrder& o, hipStream_t st);
+
+// Per-kernel timing of uncaptured fit launches (opmm_kernel_timing_*).  Event pairs come from a pool
+// made when timing is switched on, so a timed call creates nothing; a launch that finds the pool
+// empty (more than kPairs launches between two reads) is not timed.
+struct KernelTimer {
+    static constexpr int kPairs = 1024;
+    bool on = false;
+    std::vector<hipEvent_t> ev;            // 2 * kPairs, made by reserve()
+    std::vector<int> free_pairs;           // pairs not waiting to be read
+    std::vector<std::pair<int, int>> pending;  // (kernel, pair) recorded, not yet read
+    double ms[OPMM_KERNEL_KINDS] = {};
+    int64_t n[OPMM_KERNEL_KINDS] = {};
+
+    hipError_t reserve()
+    {
+        if (!ev.empty()) return hipSuccess;
+        ev.assign(2 * kPairs, nullptr);
+        for (auto& e : ev) {
+            hipError_t err = hipEventCreate(&e);
+            if (err != hipSuccess) {
+                release();
+                return err;
+            }
+        }
+        for (int i = kPairs - 1; i >= 0; --i) free_pairs.push_back(i);
+        return hipSuccess;
+    }
+    int begin(hipStream_t st)
+    {
+        if (free_pairs.empty()) return -1;
+        int i = free_pairs.back();
+        if (hipEventRecord(ev[2 * i], st) != hipSuccess) return -1;
+        free_pairs.pop_back();
+        return i;
+    }
+    void end(int kernel, int i, hipStream_t st)
+    {
+        if (i < 0) return;
+        if (hipEventRecord(ev[2 * i + 1], st) == hipSuccess) pending.emplace_back(kernel, i);
+        else free_pairs.push_back(i);
+    }
+    // Wait for every recorded pair and add its time to its kernel's total.
+    hipError_t collect()
+    {
+        for (auto& kp : pending) {
+            int i = kp.second;
+            float t = 0.f;
+            hipError_t err = hipEventSynchronize(ev[2 * i + 1]);
+            if (err == hipSuccess) err = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+            if (err != hipSuccess) return err;
+            ms[kp.first] += t;
+            n[kp.first] += 1;
+            free_pairs.push_back(i);
+        }
+        pending.clear();
+        return hipSuccess;
+    }
+    void release()
+    {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+        ev.clear();
+        free_pairs.clear();
+        pending.clear();
+        on = false;
+    }
+};
 
 // Scope of one call's use of an object's scratch on `st`: orders it after the previous call in the
 // constructor, records its end in the destructor.

@@ -21,6 +21,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOTREADY = 0, -1, -2, -3, -4
 ST_OK, ST_NONFINITE_INPUT, ST_NO_FINITE_CANDIDATE, ST_SEEDED, ST_FALLBACK, ST_WAIT_TIMEOUT, ST_DEADLINE = \
     0, 1, 2, 4, 8, 16, 32
 FIT_ROUNDS, FIT_PERSISTENT = 0, 1
+KERNEL_ROUND, KERNEL_SCREEN, KERNEL_VERIFY, KERNEL_PERSISTENT = 0, 1, 2, 3
 
 SACCADE_DTYPE = np.dtype([("pos_offset", "<i8"), ("T", "<i4"), ("C", "<i4"), ("amp_deg", "<f4"),
                           ("dir_deg", "<f4"), ("dur_ms", "<f4"), ("n_cand", "<i4"), ("seed", "<u8")])
@@ -74,6 +75,9 @@ def _load():
         "opmm_last_error": (ctypes.c_char_p, [vp]),
         "opmm_set_wait_limit": (ctypes.c_int, [vp, u32]),
         "opmm_sync": (ctypes.c_int, [vp, vp]),
+        "opmm_kernel_timing_enable": (ctypes.c_int, [vp, i32]),
+        "opmm_kernel_timing_read": (ctypes.c_int, [vp, i32, ctypes.POINTER(ctypes.c_double),
+                                                   ctypes.POINTER(ctypes.c_int64)]),
         "opmm_candidates": (ctypes.c_int, [vp, u64, u32, u32, i64, vp, vp, vp, vp, vp, vp]),
         "opmm_simulate": (ctypes.c_int, [vp, vp, vp, i64, i32, f, vp, vp]),
         "opmm_score": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, f, vp, vp]),
@@ -240,6 +244,16 @@ class Context:
     # -- calls -------------------------------------------------------------------------------
     def set_wait_limit(self, polls):
         self._check(lib.opmm_set_wait_limit(self._h, int(polls)))
+
+    def kernel_timing(self, on):
+        """Switch per-kernel event timing of directly queued fits on or off."""
+        self._check(lib.opmm_kernel_timing_enable(self._h, 1 if on else 0))
+
+    def kernel_times(self, kernel):
+        """(total ms, launches) of `kernel` (KERNEL_*) since its last read; waits for them."""
+        ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
+        self._check(lib.opmm_kernel_timing_read(self._h, int(kernel), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def sync(self, stream=None):
         """Synchronise the stream; raises OpmmError(EDEVICE) if a persistent launch gave up a wait."""
