@@ -185,13 +185,14 @@ __global__ void refine_kernel(int S, const SacDev* __restrict__ sacs, int round,
 // ---------------------------------------------------------------------------
 
 template <class RT>
-struct SseSinkT {  // squared residual against the projected trace in LDS, FP64 sum
+struct SseSinkT {  // squared residual against the projected trace in LDS, summed in Prec<RT>::acc
+    using A = typename Prec<RT>::acc;
     const RT* r;
-    double sse;
+    A sse;
     __device__ __forceinline__ void operator()(int k, RT dth, RT theq)
     {
         RT e = (r[k] - theq) - dth;
-        sse = fma((double)e, (double)e, sse);
+        sse = fmr((A)e, (A)e, sse);
     }
 };
 using SseSink = SseSinkT<R>;

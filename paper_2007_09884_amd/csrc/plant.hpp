@@ -36,11 +36,17 @@ __device__ __forceinline__ double fmr(double a, double b, double c) { return __f
 // the exponential-vector product of the split sample, per precision: each
 // set puts the truncation error below that precision's rounding floor over
 // +/-25% boxes (FP64: ~5e-9 deg, FP32: ~6e-6 deg on 150-sample traces).
+// The scalar setup (matrix entries, equilibria) and the squared-residual sum
+// run in FP64 for the FP64 recurrence; the FP32 recurrence screens candidates
+// only, so its setup and sum stay in FP32 (the FP32 rate is twice the FP64
+// rate on this chip) and their rounding joins the screening error budget.
 template <class RT>
 struct Prec {
     static constexpr int taylor_m = sizeof(RT) == 8 ? 6 : 8;
     static constexpr int taylor_sq = sizeof(RT) == 8 ? 2 : 0;
     static constexpr int expmv_m = sizeof(RT) == 8 ? 11 : 8;
+    using scalar = RT;  // type of plant_scalars
+    using acc = RT;     // type of the squared-residual sum
 };
 
 // Table 1 nominal values, in the table's order and units.  The pulse width
@@ -198,6 +204,17 @@ __device__ __forceinline__ double rcp64(double x)
     e = __fma_rn(-x, y, 1.0);
     return __fma_rn(y, e, y);
 }
+// The FP32 counterpart for plant_scalars<float>: one Newton step on the hardware reciprocal.
+__device__ __forceinline__ float rcp64(float x)
+{
+    float y = rcp(x);
+    return __fmaf_rn(y, __fmaf_rn(-x, y, 1.0f), y);
+}
+
+// Type of the decimal constants in plant_scalars: the scalar itself for plain
+// types, FP64 for the dual numbers of the sensitivity pass.
+template <class S> struct LitT { using type = double; };
+template <> struct LitT<float> { using type = float; };
 
 // mechanical rows of (s*A) V, plus `acc` on the diagonal of column `diag` (-1: none)
 #define OPMM_MV(s10, s11, s12, s13, s20, s22, s30, s33, sv, V0, V1, V2, V3, o0, o1, o2, o3, i0, i1, i2, i3) \
@@ -321,11 +338,12 @@ struct PlantScalars {
 template <class S>
 __device__ __forceinline__ void plant_scalars(const S p[P], S amp, PlantScalars<S>& o)
 {
+    using L = typename LitT<S>::type;
     const S kse_a = p[0], kse_n = p[1], klt_a = p[2], klt_n = p[3];
-    const S b_a = p[4] * 1e3, b_n = p[5] * 1e3, b_p = p[6] * 1e3;
+    const S b_a = p[4] * L(1e3), b_n = p[5] * L(1e3), b_p = p[6] * L(1e3);
     const S nc_a = p[7], nc_n = p[8];
     const S kp = nc_a + nc_n;            // passive elasticity = sum of tension slopes
-    const S jm = p[9] * 1e6;
+    const S jm = p[9] * L(1e6);
     const S ij = rcp64(jm), iba = rcp64(b_a), ibn = rcp64(b_n);
     o.a10 = -(kse_a + kse_n + kp) * ij;
     o.a11 = -b_p * ij;
@@ -344,7 +362,7 @@ __device__ __forceinline__ void plant_scalars(const S p[P], S amp, PlantScalars<
 
     // statics: c_m = K_SE/(K_SE + K_LT) is the share of the active state the series element carries
     const S iksa = rcp64(kse_a), iksn = rcp64(kse_n);
-    const S ica = 1.0 + klt_a * iksa, icn = 1.0 + klt_n * iksn;  // 1/c_m
+    const S ica = L(1.0) + klt_a * iksa, icn = L(1.0) + klt_n * iksn;  // 1/c_m
     const S ca = kse_a * rcp64(kse_a + klt_a), cn = kse_n * rcp64(kse_n + klt_n);
     const S kt = kp + ca * klt_a + cn * klt_n;
     const S nfix = p[14], ns_a = p[15], ns_n = p[16], a = amp;
@@ -367,17 +385,18 @@ __device__ __forceinline__ void plant_scalars(const S p[P], S amp, PlantScalars<
 }
 
 // Coefficients, transition and equilibria of candidate p for a saccade of
-// amplitude amp (deg), sample period dt (ms).  The scalar part is formed in
-// FP64 and rounded once to RT: FP32 chains of reciprocals here would shift the
-// equilibria by a few ulps of ~10 deg, i.e. ~1e-6 deg on every sample.
-template <class RT>
+// amplitude amp (deg), sample period dt (ms).  The scalar part is formed in ST
+// and rounded once to RT.  FP32 chains of reciprocals shift the equilibria by
+// a few ulps of ~10 deg, i.e. ~1e-6 deg on every sample: below the FP32
+// recurrence's own error, and a bias the FP64 recurrence does not take.
+template <class RT, class ST = typename Prec<RT>::scalar>
 __device__ __forceinline__ void plant_setup(const float p[P], float amp, float dt, PlantT<RT>& pl)
 {
-    double pd[P];
+    ST pd[P];
 #pragma unroll
     for (int j = 0; j < P; ++j) pd[j] = p[j];
-    PlantScalars<double> c;
-    plant_scalars(pd, (double)amp, c);
+    PlantScalars<ST> c;
+    plant_scalars(pd, (ST)amp, c);
     pl.a10 = (RT)c.a10; pl.a11 = (RT)c.a11; pl.a12 = (RT)c.a12; pl.a13 = (RT)c.a13;
     pl.a20 = (RT)c.a20; pl.a22 = (RT)c.a22; pl.g2 = (RT)c.g2;
     pl.a30 = (RT)c.a30; pl.a33 = (RT)c.a33; pl.g3 = (RT)c.g3;
