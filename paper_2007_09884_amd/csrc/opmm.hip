@@ -248,17 +248,21 @@ struct TileSmem {
     int hist[NBIN];
     uint16_t perm[TPB * PASSES];
     uint64_t red[TPB / 64];
+    int redv[TPB / 64];
 };
 
 // Returns the block's best key (valid in thread 0).  RT: the recurrence's precision (the screening
 // pass runs it in FP32).  costs (nullable): for every slot q of the tile in pulse-end order, at
 // [(tile_base + t) * TILE + q], the candidate's squared-residual sum rounded to FP32 (high word) and
-// its index in the tile (low word), or all ones for a slot past the saccade's candidates.
+// its index in the tile (low word), or all ones for a slot past the saccade's candidates.  tmin
+// (with costs): at [tile_base + t], the bits of the tile's least FP32 sum, 0 if one is NaN, +inf
+// if the tile holds no candidate.
 template <int TPB, int PASSES, int UNROLL, class RT = R>
 __device__ __forceinline__ uint64_t process_tile(TileSmem<TPB, PASSES, RT>& sm, const SacDev& sd, int s, int t,
                                                  int round, float dt, const float* __restrict__ proj,
                                                  const float* centre, const float* hw, const float* lo,
-                                                 const float* hi, uint64_t* __restrict__ costs = nullptr)
+                                                 const float* hi, uint64_t* __restrict__ costs = nullptr,
+                                                 uint32_t* __restrict__ tmin = nullptr)
 {
     constexpr int TILE = TPB * PASSES;
     const int tid = threadIdx.x;
@@ -311,6 +315,7 @@ __device__ __forceinline__ uint64_t process_tile(TileSmem<TPB, PASSES, RT>& sm, 
 
     // Phase B: simulate and score in sorted order.
     uint64_t best = ~0ull;
+    int vmin = 0x7F800000;  // bits of the lane's least FP32 sum (non-negative floats order as integers)
 #pragma unroll 1
     for (int ps = 0; ps < PASSES; ++ps) {
         // keep the box in LDS: re-read it per candidate instead of pinning 72 registers
@@ -339,13 +344,25 @@ __device__ __forceinline__ uint64_t process_tile(TileSmem<TPB, PASSES, RT>& sm, 
             uint64_t key = cost_key(sink.sse, idx);
             best = key < best ? key : best;
         }
-        if (cslot) *cslot = valid ? ((uint64_t)__float_as_uint((float)sink.sse) << 32) | j : ~0ull;
+        if (cslot) {
+            const float c = (float)sink.sse;
+            *cslot = valid ? ((uint64_t)__float_as_uint(c) << 32) | j : ~0ull;
+            if (valid) vmin = min(vmin, c != c ? 0 : (int)__float_as_uint(c));
+        }
     }
     best = wave_min_u64(best);
-    if ((tid & 63) == 0) sm.red[tid >> 6] = best;
+    if (tmin) vmin = wave_min(vmin);
+    if ((tid & 63) == 0) {
+        sm.red[tid >> 6] = best;
+        if (tmin) sm.redv[tid >> 6] = vmin;
+    }
     __syncthreads();
     if (tid == 0) {
         for (int w = 1; w < TPB / 64; ++w) best = sm.red[w] < best ? sm.red[w] : best;
+        if (tmin) {
+            for (int w = 1; w < TPB / 64; ++w) vmin = min(vmin, sm.redv[w]);
+            tmin[sd.tile_base + t] = (uint32_t)vmin;
+        }
     }
     return best;
 }
@@ -439,7 +456,8 @@ __global__ __launch_bounds__(TPB, OPMM_SCREEN_MIN_WAVES) void fit_screen_kernel(
                                                          const float* centre, const float* hw, const float* lo,
                                                          const float* hi, const int32_t* __restrict__ status,
                                                          const int* __restrict__ ord, const int* __restrict__ obase,
-                                                         uint64_t* __restrict__ costs, uint64_t* smin)
+                                                         uint64_t* __restrict__ costs, uint32_t* __restrict__ tmin,
+                                                         uint64_t* smin)
 {
     __shared__ TileSmem<TPB, PASSES, float> sm;
     __shared__ int s_s;
@@ -452,7 +470,7 @@ __global__ __launch_bounds__(TPB, OPMM_SCREEN_MIN_WAVES) void fit_screen_kernel(
     if (status[sd.slot] & OPMM_ST_NONFINITE_INPUT) return;
     const int t = blockIdx.x - sd.tile_base;
     const uint64_t best =
-        process_tile<TPB, PASSES, UNROLL, float>(sm, sd, s_s, t, round, dt, proj, centre, hw, lo, hi, costs);
+        process_tile<TPB, PASSES, UNROLL, float>(sm, sd, s_s, t, round, dt, proj, centre, hw, lo, hi, costs, tmin);
     if (threadIdx.x == 0 && best != ~0ull) atomicMin((unsigned long long*)&smin[sd.slot], (unsigned long long)best);
 }
 
@@ -462,7 +480,8 @@ __global__ __launch_bounds__(TPB, OPMM_SCREEN_MIN_WAVES) void fit_screen_kernel(
 // NaN) are simulated again exactly as the FP64 round kernel simulates them, in the first pass's
 // pulse-end order, and their FP64 keys go to keys[round][slot].  The FP32 best key fixes the
 // threshold: with n = T C samples and Q the orthogonal energy, RMSE = sqrt((SSE + Q) / n), so a
-// candidate passes when its FP32 SSE <= (RMSE_best + tau)^2 n - Q.
+// candidate passes when its FP32 SSE <= (RMSE_best + tau)^2 n - Q.  A tile whose least FP32 SSE
+// (tmin, 0 when one is NaN) misses that is left without reading its costs.
 #ifndef OPMM_VERIFY_TILES
 #define OPMM_VERIFY_TILES 1
 #endif
@@ -485,6 +504,7 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_verify_kernel(const S
                                                          const int32_t* __restrict__ status, uint64_t* keys,
                                                          const int* __restrict__ ord, const int* __restrict__ obase,
                                                          const uint64_t* __restrict__ costs,
+                                                         const uint32_t* __restrict__ tmin,
                                                          const uint64_t* __restrict__ smin,
                                                          const double* __restrict__ qorth, float tau)
 {
@@ -510,6 +530,10 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_verify_kernel(const S
         const double rm = sqrt(((double)fbest + q) / n) + (double)tau;
         thr = rm * rm * n - q;
     }
+    // a tile whose least FP32 sum misses the threshold has nothing to verify: skip its costs
+    float tm = __builtin_inff();
+    for (int g = 0; g < ng; ++g) tm = fminf(tm, __uint_as_float(tmin[sd.tile_base + t0 + g]));
+    if (!((double)tm <= thr)) return;
     // compaction in slot order, tile by tile, TPB slots at a time; every load is issued first
     uint64_t vals[VG * PASSES];
 #pragma unroll
@@ -806,6 +830,7 @@ struct FitLaunch {
     uint32_t wait_limit;     // polls of a persistent block waiting for its round
     // screened rounds: FP32 costs of every candidate, FP32 best per saccade, orthogonal energies
     uint64_t* costs;  // [tiles_per_round * tile]: FP32 cost and index of every slot (process_tile)
+    uint32_t* tmin;   // [tiles_per_round]: least FP32 cost of each tile (process_tile)
     uint64_t* smin;   // [S]: FP32 best key per saccade
     const double* qorth;
     float tau;
@@ -851,13 +876,13 @@ hipError_t launch_screened(const FitLaunch& L, int round, hipStream_t st)
         TimedLaunch tl(L.timer, OPMM_KERNEL_SCREEN, st);
         hipLaunchKernelGGL((fit_screen_kernel<TPB, PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(TPB), 0, st,
                            L.sacs, L.S, round, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status, L.ord, L.obase,
-                           L.costs, L.smin);
+                           L.costs, L.tmin, L.smin);
     }
     {
         TimedLaunch tl(L.timer, OPMM_KERNEL_VERIFY, st);
         hipLaunchKernelGGL((fit_verify_kernel<TPB, PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(TPB), 0, st,
                            L.sacs, L.S, round, L.key_stride, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status,
-                           L.keys, L.ord, L.obase, L.costs, L.smin, L.qorth, L.tau);
+                           L.keys, L.ord, L.obase, L.costs, L.tmin, L.smin, L.qorth, L.tau);
     }
     return hipGetLastError();
 }
@@ -941,14 +966,14 @@ struct DevBuf {
 
 struct FitScratch {
     DevBuf sacs, proj, qorth, box, keys, status, counters, order;
-    DevBuf costs, smin;  // screened rounds (see FitBufs)
+    DevBuf costs, tmin, smin;  // screened rounds (see FitBufs)
     // Pinned host staging of the record upload (records, then dispatch order and tile bases), kept
     // between calls: the upload is a direct DMA and no batch pays for fresh pages.
     DevBuf stage;
     std::vector<int> h_count;
     ~FitScratch()
     {
-        for (DevBuf* b : {&sacs, &proj, &qorth, &box, &keys, &status, &counters, &order, &costs, &smin})
+        for (DevBuf* b : {&sacs, &proj, &qorth, &box, &keys, &status, &counters, &order, &costs, &tmin, &smin})
             if (b->p) (void)hipFree(b->p);
         if (stage.p) (void)hipHostFree(stage.p);
     }
@@ -1242,8 +1267,9 @@ struct FitBufs {
     uint32_t* counters;
     uint64_t* keys;
     // screened rounds only: FP32 cost and index of every candidate slot [tiles_per_round * tile],
-    // FP32 best key per saccade [S]
+    // least FP32 cost per tile [tiles_per_round], FP32 best key per saccade [S]
     uint64_t* costs = nullptr;
+    uint32_t* tmin = nullptr;
     uint64_t* smin = nullptr;
 };
 
@@ -1281,8 +1307,10 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
     if (prm->screen_rounds > 0 && tiles_per_round > 0) {
         const size_t slots = (size_t)tiles_per_round * kShapes[shape].tpb * kShapes[shape].passes;
         if ((rc = ensure(ctx, sc.costs, sizeof(uint64_t) * slots)) != OPMM_OK) return rc;
+        if ((rc = ensure(ctx, sc.tmin, sizeof(uint32_t) * (size_t)tiles_per_round)) != OPMM_OK) return rc;
         if ((rc = ensure(ctx, sc.smin, sizeof(uint64_t) * (size_t)S)) != OPMM_OK) return rc;
         B.costs = (uint64_t*)sc.costs.p;
+        B.tmin = (uint32_t*)sc.tmin.p;
         B.smin = (uint64_t*)sc.smin.p;
     }
     return enqueue_fit_bufs(ctx, B, pos, S, tiles_per_round, prm, shape, seed_opc, opc_out, rmse_out, mae_out,
@@ -1328,6 +1356,7 @@ int enqueue_fit_bufs(opmm_ctx* ctx, const FitBufs& B, const float* pos, int S, i
     L.key_stride = S;
     L.wait_limit = ctx->wait_limit;
     L.costs = B.costs;
+    L.tmin = B.tmin;
     L.smin = B.smin;
     L.qorth = qorth;
     L.tau = prm->screen_tol;
@@ -1350,7 +1379,8 @@ int enqueue_fit_bufs(opmm_ctx* ctx, const FitBufs& B, const float* pos, int S, i
         } else {
             for (int r = 0; r < R; ++r) {
                 if (r < prm->screen_rounds) {
-                    if (!B.costs || !B.smin) return fail(ctx, OPMM_EINVAL, "screened rounds need their buffers");
+                    if (!B.costs || !B.tmin || !B.smin)
+                        return fail(ctx, OPMM_EINVAL, "screened rounds need their buffers");
                     hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for(S, 256)), dim3(256), 0, st, B.smin, (int64_t)S,
                                        ~0ull);
                     OPMM_HIP(ctx, launch_screened_round(shape, L, r, st));

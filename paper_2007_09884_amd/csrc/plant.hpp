@@ -35,16 +35,24 @@ __device__ __forceinline__ double fmr(double a, double b, double c) { return __f
 // Taylor degree and squarings of the one-sample transition, and the degree of
 // the exponential-vector product of the split sample, per precision: each
 // set puts the truncation error below that precision's rounding floor over
-// +/-25% boxes (FP64: ~5e-9 deg, FP32: ~6e-6 deg on 150-sample traces).
+// +/-25% boxes (FP64: ~5e-9 deg on 150-sample traces; FP32: the RMSE of a
+// candidate stays within ~8e-6 deg of its FP64 value with degrees 7 and 6,
+// as with 8 and 8, while a degree-6 transition doubles that).
 // The scalar setup (matrix entries, equilibria) and the squared-residual sum
 // run in FP64 for the FP64 recurrence; the FP32 recurrence screens candidates
 // only, so its setup and sum stay in FP32 (the FP32 rate is twice the FP64
 // rate on this chip) and their rounding joins the screening error budget.
+#ifndef OPMM_F32_TAYLOR_M
+#define OPMM_F32_TAYLOR_M 7
+#endif
+#ifndef OPMM_F32_EXPMV_M
+#define OPMM_F32_EXPMV_M 6
+#endif
 template <class RT>
 struct Prec {
-    static constexpr int taylor_m = sizeof(RT) == 8 ? 6 : 8;
+    static constexpr int taylor_m = sizeof(RT) == 8 ? 6 : OPMM_F32_TAYLOR_M;
     static constexpr int taylor_sq = sizeof(RT) == 8 ? 2 : 0;
-    static constexpr int expmv_m = sizeof(RT) == 8 ? 11 : 8;
+    static constexpr int expmv_m = sizeof(RT) == 8 ? 11 : OPMM_F32_EXPMV_M;
     using scalar = RT;  // type of plant_scalars
     using acc = RT;     // type of the squared-residual sum
 };
