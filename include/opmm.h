@@ -219,6 +219,15 @@ int opmm_simulate(opmm_ctx* ctx, const float* opc, const float* amp, int64_t n, 
  * trace.  The optimisation error of Section 3.4, recomputed per candidate. */
 int opmm_score(opmm_ctx* ctx, const float* opc, int64_t n, const float* pos, int64_t pos_len,
                const opmm_saccade* sac, float dt_ms, float* rmse_out, void* stream);
+/* opmm_score with the FP32 recurrence of screened rounds (opmm_fit_params.
+ * screen_rounds): for each candidate the very operations of the FP32 pass,
+ * so max |opmm_score_screen - opmm_score| over a caller's candidates is the
+ * screening error eps on that data, which must stay below screen_tol / 2 for
+ * a screened fit to return the FP64 fit (the argmin argument is the FP64
+ * argmin's FP32 RMSE <= FP32 best + 2 eps).  A measurement aid; arguments,
+ * layout and errors as opmm_score. */
+int opmm_score_screen(opmm_ctx* ctx, const float* opc, int64_t n, const float* pos, int64_t pos_len,
+                      const opmm_saccade* sac, float dt_ms, float* rmse_out, void* stream);
 
 /* Estimate the OPC vector of each of S saccades (Algorithm 1: one task per
  * saccade, all on the device; Section 3.3: the data stay on the GPU).

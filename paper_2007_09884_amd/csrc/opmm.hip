@@ -745,28 +745,31 @@ __global__ __launch_bounds__(256, OPMM_MIN_WAVES) void simulate_kernel(int64_t n
     run_trajectory<2>(pl, T, (R)dt, k0, frac, kmin, kmax, sink);
 }
 
+// RMSE of n candidates against one saccade, with the recurrence of precision RT (FP64: the search's
+// decisions; FP32: the screening pass's arithmetic, sample by sample the same operations).
+template <class RT>
 __global__ __launch_bounds__(256, OPMM_MIN_WAVES) void score_kernel(int64_t n, const float* __restrict__ opc,
                                                     const float* __restrict__ proj, int T, int C,
                                                     const double* __restrict__ qorth, float amp, float dt,
                                                     float* __restrict__ rmse)
 {
-    __shared__ R r[OPMM_MAX_T];
-    for (int k = threadIdx.x; k < T; k += blockDim.x) r[k] = (R)proj[k];
+    __shared__ RT r[OPMM_MAX_T];
+    for (int k = threadIdx.x; k < T; k += blockDim.x) r[k] = (RT)proj[k];
     __syncthreads();
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool valid = i < n;
     int64_t ii = valid ? i : 0;
     float p[P];
     for (int j = 0; j < P; ++j) p[j] = opc[ii * P + j];
-    Plant pl;
+    PlantT<RT> pl;
     plant_setup(p, amp, dt, pl);
-    R frac;
+    RT frac;
     int k0 = pulse_end_sample(pl.pwd, T, frac);
     int kmin = wave_min(valid ? k0 : 0x7FFFFFFF), kmax = wave_max(valid ? k0 : -0x7FFFFFFF);
     if (!valid) return;
-    SseSink sink{r, 0.0};
-    run_trajectory<2>(pl, T, (R)dt, k0, frac, kmin, kmax, sink);
-    double tot = (sink.sse + qorth[0]) / ((double)T * C);
+    SseSinkT<RT> sink{r, 0.0};
+    run_trajectory<2>(pl, T, (RT)dt, k0, frac, kmin, kmax, sink);
+    double tot = ((double)sink.sse + qorth[0]) / ((double)T * C);
     float v = (float)sqrt(tot);
     rmse[i] = (v >= 0.0f && v <= 3.402823466e38f) ? v : __int_as_float(0x7F800000);
 }
@@ -1884,8 +1887,10 @@ int opmm_simulate(opmm_ctx* ctx, const float* opc, const float* amp, int64_t n, 
     return OPMM_OK;
 }
 
-int opmm_score(opmm_ctx* ctx, const float* opc, int64_t n, const float* pos, int64_t pos_len,
-               const opmm_saccade* sac, float dt_ms, float* rmse_out, void* stream)
+namespace {
+
+int score_impl(opmm_ctx* ctx, const float* opc, int64_t n, const float* pos, int64_t pos_len, const opmm_saccade* sac,
+               float dt_ms, float* rmse_out, void* stream, bool fp32)
 {
     if (!ctx) return OPMM_EINVAL;
     if (!sac) return fail(ctx, OPMM_EINVAL, "sac is NULL");
@@ -1908,10 +1913,30 @@ int opmm_score(opmm_ctx* ctx, const float* opc, int64_t n, const float* pos, int
     if ((rc = ensure(ctx, sc.status, sizeof(int32_t))) != OPMM_OK) return rc;
     hipLaunchKernelGGL(prep_kernel, dim3(1), dim3(64), 0, st, 1, (const SacDev*)sc.sacs.p, pos, (float*)sc.proj.p,
                        (double*)sc.qorth.p, (int32_t*)sc.status.p);
-    hipLaunchKernelGGL(score_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, opc, (const float*)sc.proj.p,
-                       sac->T, sac->C, (const double*)sc.qorth.p, sac->amp_deg, dt_ms, rmse_out);
+    if (fp32)
+        hipLaunchKernelGGL(score_kernel<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, opc,
+                           (const float*)sc.proj.p, sac->T, sac->C, (const double*)sc.qorth.p, sac->amp_deg, dt_ms,
+                           rmse_out);
+    else
+        hipLaunchKernelGGL(score_kernel<R>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, opc,
+                           (const float*)sc.proj.p, sac->T, sac->C, (const double*)sc.qorth.p, sac->amp_deg, dt_ms,
+                           rmse_out);
     OPMM_HIP(ctx, hipGetLastError());
     return OPMM_OK;
+}
+
+}  // namespace
+
+int opmm_score(opmm_ctx* ctx, const float* opc, int64_t n, const float* pos, int64_t pos_len,
+               const opmm_saccade* sac, float dt_ms, float* rmse_out, void* stream)
+{
+    return score_impl(ctx, opc, n, pos, pos_len, sac, dt_ms, rmse_out, stream, false);
+}
+
+int opmm_score_screen(opmm_ctx* ctx, const float* opc, int64_t n, const float* pos, int64_t pos_len,
+                      const opmm_saccade* sac, float dt_ms, float* rmse_out, void* stream)
+{
+    return score_impl(ctx, opc, n, pos, pos_len, sac, dt_ms, rmse_out, stream, true);
 }
 
 int opmm_fit(opmm_ctx* ctx, const float* pos, int64_t pos_len, const opmm_saccade* sacs, int32_t S,

@@ -81,6 +81,7 @@ def _load():
         "opmm_candidates": (ctypes.c_int, [vp, u64, u32, u32, i64, vp, vp, vp, vp, vp, vp]),
         "opmm_simulate": (ctypes.c_int, [vp, vp, vp, i64, i32, f, vp, vp]),
         "opmm_score": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, f, vp, vp]),
+        "opmm_score_screen": (ctypes.c_int, [vp, vp, i64, vp, i64, vp, f, vp, vp]),
         "opmm_fit": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(FitParams), vp, vp, vp, vp, vp,
                                     vp, vp]),
         "opmm_fit_noalloc": (ctypes.c_int, [vp, vp, i64, vp, i32, ctypes.POINTER(FitParams), vp, vp, vp, vp, vp,
@@ -270,11 +271,12 @@ class Context:
         self._check(lib.opmm_simulate(self._h, _ptr(opc), _ptr(amp), n, int(T), ctypes.c_float(dt_ms),
                                       _ptr(traj_out), _stream(stream)))
 
-    def score(self, opc, pos, sac_rec, rmse_out, dt_ms=1.0, stream=None):
+    def score(self, opc, pos, sac_rec, rmse_out, dt_ms=1.0, stream=None, screen=False):
+        """RMSE of candidates against one saccade; screen=True: with the screening pass's FP32 recurrence."""
         rec = np.ascontiguousarray(sac_rec, SACCADE_DTYPE).reshape(1)
-        self._check(lib.opmm_score(self._h, _ptr(opc), opc.shape[0], _ptr(pos), pos.numel(),
-                                   rec.ctypes.data_as(ctypes.c_void_p), ctypes.c_float(dt_ms), _ptr(rmse_out),
-                                   _stream(stream)))
+        fn = lib.opmm_score_screen if screen else lib.opmm_score
+        self._check(fn(self._h, _ptr(opc), opc.shape[0], _ptr(pos), pos.numel(),
+                       rec.ctypes.data_as(ctypes.c_void_p), ctypes.c_float(dt_ms), _ptr(rmse_out), _stream(stream)))
 
     def fit(self, pos, recs, params: FitParams, opc_out, rmse_out, mae_out=None, status_out=None,
             round_keys=None, seed_opc=None, stream=None):
