@@ -55,6 +55,10 @@ struct Prec {
     static constexpr int expmv_m = sizeof(RT) == 8 ? 11 : OPMM_F32_EXPMV_M;
     using scalar = RT;  // type of plant_scalars
     using acc = RT;     // type of the squared-residual sum
+#ifndef OPMM_F32_SCALED_HORNER
+#define OPMM_F32_SCALED_HORNER 1
+#endif
+    static constexpr bool scaled_horner = sizeof(RT) == 4 && OPMM_F32_SCALED_HORNER;  // transition_dform_scaled
 };
 
 // Table 1 nominal values, in the table's order and units.  The pulse width
@@ -237,6 +241,90 @@ template <> struct LitT<float> { using type = float; };
 // matrix [[Mech, G1, G2], [0, Q1, 0], [0, 0, Q2]] whose off-diagonal blocks
 // give the pulse-piece and post-piece coupling columns at once, on the step
 // h/2^SQ, then SQ squarings in D-form: D_2h = D_h^2 + 2 D_h.
+// FP32 form of the same polynomial without squarings: with B = hA, the Horner iterates scaled as
+// Q_k = c_k P_k, c_M = M, c_k = k c_{k+1}, obey Q_M = M I + B, Q_k = c_k I + B Q_{k+1} (the scaled
+// coefficients are formed once instead of once per step), and D = B Q_2 / M!.
+template <class RT>
+__device__ __forceinline__ void transition_dform_scaled(PlantT<RT>& pl, RT h)
+{
+    constexpr int M = Prec<RT>::taylor_m;
+    static_assert(Prec<RT>::taylor_sq == 0, "the scaled form takes no squarings");
+    const RT qv[4] = {pl.q1a, pl.q1n, pl.q2a, pl.q2n};
+    const RT s10 = pl.a10 * h, s11 = pl.a11 * h, s12 = pl.a12 * h, s13 = pl.a13 * h;
+    const RT s20 = pl.a20 * h, s22 = pl.a22 * h, s30 = pl.a30 * h, s33 = pl.a33 * h;
+    const RT sg2 = pl.g2 * h, sg3 = pl.g3 * h;
+    RT sq[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sq[c] = qv[c] * h;
+    RT pm[4][4], px[4][4], pd[4];
+    {   // Q_M = M I + B
+        const RT m = RT(M);
+        pm[0][0] = m;   pm[0][1] = h;      pm[0][2] = RT(0);    pm[0][3] = RT(0);
+        pm[1][0] = s10; pm[1][1] = m + s11; pm[1][2] = s12;     pm[1][3] = s13;
+        pm[2][0] = s20; pm[2][1] = RT(0);  pm[2][2] = m + s22;  pm[2][3] = RT(0);
+        pm[3][0] = s30; pm[3][1] = RT(0);  pm[3][2] = RT(0);    pm[3][3] = m + s33;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            px[0][c] = RT(0); px[1][c] = RT(0);
+            px[2][c] = (c & 1) ? RT(0) : sg2;
+            px[3][c] = (c & 1) ? sg3 : RT(0);
+            pd[c] = m + sq[c];
+        }
+    }
+    RT ck = RT(M);
+#pragma unroll
+    for (int k = M - 1; k >= 1; --k) {
+        // k >= 2: Q_k = c_k I + B Q_{k+1};  k == 1: D = (B / M!) Q_2
+        RT one, t10, t11, t12, t13, t20, t22, t30, t33, tv, tg2, tg3, tq[4];
+        if (k >= 2) {
+            ck = ck * RT(k);
+            one = ck;
+            t10 = s10; t11 = s11; t12 = s12; t13 = s13; t20 = s20; t22 = s22; t30 = s30; t33 = s33;
+            tv = h; tg2 = sg2; tg3 = sg3;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) tq[c] = sq[c];
+        } else {
+            const RT f = RT(1) / ck;  // 1 / M! (exact power-of-two-free constant, rounded once)
+            one = RT(0);
+            t10 = s10 * f; t11 = s11 * f; t12 = s12 * f; t13 = s13 * f;
+            t20 = s20 * f; t22 = s22 * f; t30 = s30 * f; t33 = s33 * f;
+            tv = h * f; tg2 = sg2 * f; tg3 = sg3 * f;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) tq[c] = sq[c] * f;
+        }
+        RT nm[4][4], nx[4][4], nd[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            OPMM_MV(t10, t11, t12, t13, t20, t22, t30, t33, tv, pm[0][c], pm[1][c], pm[2][c], pm[3][c],
+                    nm[0][c], nm[1][c], nm[2][c], nm[3][c],
+                    c == 0 ? one : RT(0), c == 1 ? one : RT(0), c == 2 ? one : RT(0), c == 3 ? one : RT(0));
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const RT ga = (c & 1) ? RT(0) : tg2 * pd[c];
+            const RT gn = (c & 1) ? tg3 * pd[c] : RT(0);
+            OPMM_MV(t10, t11, t12, t13, t20, t22, t30, t33, tv, px[0][c], px[1][c], px[2][c], px[3][c],
+                    nx[0][c], nx[1][c], nx[2][c], nx[3][c], RT(0), RT(0), ga, gn);
+            nd[c] = fmr(tq[c], pd[c], one);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) { pm[i][c] = nm[i][c]; px[i][c] = nx[i][c]; }
+            pd[i] = nd[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pl.m[i][c] = pm[i][c];
+        pl.x1[i][0] = px[i][0]; pl.x1[i][1] = px[i][1];
+        pl.x2[i][0] = px[i][2]; pl.x2[i][1] = px[i][3];
+    }
+    pl.e1[0] = pd[0]; pl.e1[1] = pd[1];
+    pl.e2[0] = pd[2]; pl.e2[1] = pd[3];
+}
+
 template <class RT>
 __device__ __forceinline__ void transition_dform(PlantT<RT>& pl, RT hfull)
 {
@@ -409,7 +497,8 @@ __device__ __forceinline__ void plant_setup(const float p[P], float amp, float d
     pl.a20 = (RT)c.a20; pl.a22 = (RT)c.a22; pl.g2 = (RT)c.g2;
     pl.a30 = (RT)c.a30; pl.a33 = (RT)c.a33; pl.g3 = (RT)c.g3;
     pl.q1a = (RT)c.q1a; pl.q1n = (RT)c.q1n; pl.q2a = (RT)c.q2a; pl.q2n = (RT)c.q2n;
-    transition_dform(pl, (RT)dt);
+    if constexpr (Prec<RT>::scaled_horner) transition_dform_scaled(pl, (RT)dt);
+    else transition_dform(pl, (RT)dt);
     pl.th1 = (RT)c.th1;
     pl.amp = amp;
 #pragma unroll
