@@ -272,9 +272,15 @@ def uneven_leg(a, ctx, opmm, torch, synth):
     opc = torch.zeros(S, 18, device="cuda")
     rm = torch.zeros(S, device="cuda")
     out = {"saccades": S, "rounds": R, "candidate_sims_per_step": sims, "mean_T": float(np.mean(b["T"]))}
-    for name, mode in (("persistent", opmm.FIT_PERSISTENT), ("rounds", opmm.FIT_ROUNDS)):
+    variants = [("persistent", opmm.FIT_PERSISTENT, 0), ("rounds", opmm.FIT_ROUNDS, 0)]
+    if a.screen_rounds > 0:
+        variants.append(("rounds_screened", opmm.FIT_ROUNDS, min(a.screen_rounds, R)))
+    fitted = {}
+    for name, mode, scr in variants:
         p = opmm.fit_params(n_cand=4096, n_rounds=R, mode=mode)
         p.tile = ctx.autotune(pos, recs, p) if name == "persistent" else opmm.lib.opmm_tile_default()
+        if scr:
+            p.screen_rounds, p.screen_tol = scr, a.screen_tol
         pl = ctx.plan(pos, recs, p, opc, rm)
         pl.launch()
         torch.cuda.synchronize()
@@ -286,6 +292,9 @@ def uneven_leg(a, ctx, opmm, torch, synth):
         pl.close()
         out[name] = {"tile": opmm.tile_names()[p.tile], "ms_per_step": dt * 1e3, "candidate_sims_per_s": sims / dt,
                      "saccades_fitted_per_s": S / dt}
+        fitted[name] = opc.clone()
+        if scr:
+            out[name].update(screen_rounds=scr, same_opc_as_fp64=bool(torch.equal(fitted[name], fitted["rounds"])))
     return out
 
 
