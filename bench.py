@@ -196,9 +196,12 @@ def surrogate_leg(a, ctx, opmm, torch, synth, keep=False):
     pos = gpu_targets(ctx, opmm, torch, b)
     recs = opmm.saccade_records(b["T"], 2, b["amp"], b["dir_deg"], b["dur_ms"], b["seed"])
     S = a.heldout
-    plain = opmm.fit_params(n_cand=a.n_cand, n_rounds=a.rounds, mode=opmm.FIT_ROUNDS)
+    # both searches screen their rounds like the main fit (same results as FP64 only)
+    scr_plain, scr_seed = min(a.screen_rounds, a.rounds), min(a.screen_rounds, a.seed_rounds)
+    plain = opmm.fit_params(n_cand=a.n_cand, n_rounds=a.rounds, mode=opmm.FIT_ROUNDS, screen_rounds=scr_plain,
+                            screen_tol=a.screen_tol)
     seeded = opmm.fit_params(n_cand=a.seed_cand, n_rounds=a.seed_rounds, w_init_frac=a.seed_width,
-                             mode=opmm.FIT_ROUNDS)
+                             mode=opmm.FIT_ROUNDS, screen_rounds=scr_seed, screen_tol=a.screen_tol)
     opc = torch.zeros(S, 18, device="cuda")
     rm_plain = torch.zeros(S, device="cuda")
     rm_seed = torch.zeros(S, device="cuda")
@@ -242,9 +245,11 @@ def surrogate_leg(a, ctx, opmm, torch, synth, keep=False):
                       "loss_first": float(loss[:10].mean()), "loss_last": float(loss[-10:].mean()),
                       "step_ms": 1e3 * train_s / steps, "forward_backward": fb},
             "heldout_saccades": S,
-            "plain": {"n_cand": a.n_cand, "rounds": a.rounds, "saccades_fitted_per_s": S / plain_s,
+            "plain": {"n_cand": a.n_cand, "rounds": a.rounds, "screen_rounds": scr_plain,
+                      "saccades_fitted_per_s": S / plain_s,
                       "mean_rmse_deg": float(rp.mean()), "median_rmse_deg": float(np.median(rp))},
-            "surrogate": {"n_cand": a.seed_cand, "rounds": a.seed_rounds, "w_init_frac": a.seed_width,
+            "surrogate": {"n_cand": a.seed_cand, "rounds": a.seed_rounds, "screen_rounds": scr_seed,
+                          "w_init_frac": a.seed_width,
                           "fallback_rmse_deg": 1.5 * synth.SIGMA, "fallbacks": int(n_fb),
                           "saccades_fitted_per_s": S / seed_s, "mean_rmse_deg": float(rs.mean()),
                           "median_rmse_deg": float(np.median(rs))},
@@ -681,9 +686,10 @@ def main():
         out["batched_uneven"] = uneven_leg(a, ctx, opmm, torch, synth)
     if not a.no_model9:
         # the 9-parameter model (Table 2) on the same batch and launch
-        p9 = opmm.fit_params(n_cand=N, n_rounds=R, mode=modes[a.mode], tile=prm.tile, model=9)
+        p9 = opmm.fit_params(n_cand=N, n_rounds=R, mode=modes[a.mode], tile=prm.tile, model=9,
+                             screen_rounds=scr, screen_tol=prm.screen_tol)
         ms9 = time_plan(p9, reps=3)
-        out["model9"] = {"ms_per_step": ms9, "candidate_sims_per_s": sims / (ms9 * 1e-3),
+        out["model9"] = {"ms_per_step": ms9, "candidate_sims_per_s": sims / (ms9 * 1e-3), "screen_rounds": scr,
                          "mean_final_rmse_deg": float(rmse.mean().item())}
     if not a.no_ivt:
         note("I-VT")

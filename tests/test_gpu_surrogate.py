@@ -373,3 +373,33 @@ def test_predict_and_learned_fit_compose_the_pinned_parts(ctx, opmm):
     assert np.array_equal(rm1.cpu().numpy(), rm2.cpu().numpy())
     assert np.array_equal(st1.cpu().numpy(), st2.cpu().numpy())
     sg.close()
+
+
+def test_learned_fit_with_screened_rounds_equals_fp64(ctx, opmm):
+    """The learned fit with its seeded refine and its plain fallback screened in FP32 returns the same
+    OPC, RMSE and status words, bit for bit, as with every round in FP64: with no fallback and with
+    every saccade falling back."""
+    sg = opmm.Surrogate(ctx, init_seed=5)
+    sg.train(data_seed=21, batch=4096, n_steps=50, lr0=2e-3, lr_min=2e-5)
+    b, traces = make_batch(48, "full", seed=synth.BASE_SEED + 777)
+    S = b["S"]
+    recs = records(b, opmm)
+    pos = torch.from_numpy(opmm.pack_traces(traces)).cuda()
+
+    def run(scr_seed, scr_plain, thresh):
+        seeded = opmm.fit_params(n_cand=1024, n_rounds=3, w_init_frac=0.25, screen_rounds=scr_seed)
+        plain = opmm.fit_params(n_cand=4096, n_rounds=6, screen_rounds=scr_plain)
+        opc = torch.zeros(S, 18, device="cuda"); rm = torch.zeros(S, device="cuda")
+        st = torch.zeros(S, dtype=torch.int32, device="cuda")
+        nf = sg.fit(pos, recs, seeded, plain, thresh, opc, rm, st)
+        torch.cuda.synchronize()
+        return nf, opc.cpu().numpy(), rm.cpu().numpy(), st.cpu().numpy()
+
+    for thresh in (1e9, 0.0):
+        ref = run(0, 0, thresh)
+        got = run(3, 4, thresh)
+        assert ref[0] == got[0]
+        for x, y in zip(ref[1:], got[1:]):
+            assert np.array_equal(x.view(np.uint32) if x.dtype == np.float32 else x,
+                                  y.view(np.uint32) if y.dtype == np.float32 else y), thresh
+    sg.close()
