@@ -474,54 +474,38 @@ __global__ __launch_bounds__(TPB, OPMM_SCREEN_MIN_WAVES) void fit_screen_kernel(
     if (threadIdx.x == 0 && best != ~0ull) atomicMin((unsigned long long*)&smin[sd.slot], (unsigned long long)best);
 }
 
-// Screened round, second pass.  The block of tile t with t % VG == 0 takes tiles t .. t + VG - 1 of
-// its saccade (the other blocks return at once, so fewer blocks pay the latency of an FP64
-// simulation): their candidates whose FP32 RMSE lies within tau of the saccade's FP32 best (or is
-// NaN) are simulated again exactly as the FP64 round kernel simulates them, in the first pass's
-// pulse-end order, and their FP64 keys go to keys[round][slot].  The FP32 best key fixes the
-// threshold: with n = T C samples and Q the orthogonal energy, RMSE = sqrt((SSE + Q) / n), so a
-// candidate passes when its FP32 SSE <= (RMSE_best + tau)^2 n - Q.  A tile whose least FP32 SSE
-// (tmin, 0 when one is NaN) misses that is left without reading its costs.
-#ifndef OPMM_VERIFY_TILES
-#define OPMM_VERIFY_TILES 1
-#endif
-constexpr int VG = OPMM_VERIFY_TILES;  // tiles per verifying block
-
-template <int TPB, int PASSES>
+// Screened round, second pass, one wave per tile (a tile's survivors are often fewer than one
+// block's lanes, and a one-wave block leaves no wave of it idle).  The tile's candidates whose FP32
+// RMSE lies within tau of the saccade's FP32 best (or is NaN) are simulated again exactly as the FP64
+// round kernel simulates them, in the first pass's pulse-end order, and their FP64 keys go to
+// keys[round][slot].  The FP32 best key fixes the threshold: with n = T C samples and Q the
+// orthogonal energy, RMSE = sqrt((SSE + Q) / n), so a candidate passes when its FP32 SSE <=
+// (RMSE_best + tau)^2 n - Q.  A tile whose least FP32 SSE (tmin, 0 when one is NaN) misses that is
+// left without reading its costs.
+template <int TILE>
 struct VerifySmem {
     R r[OPMM_MAX_T];
     Box box;
-    uint32_t list[VG * TPB * PASSES];  // candidate indices to verify
-    int wcnt[TPB / 64];
-    uint64_t red[TPB / 64];
+    uint16_t list[TILE];  // survivors' indices in the tile, in slot order
 };
 
-template <int TPB, int PASSES, int UNROLL>
-__global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_verify_kernel(const SacDev* __restrict__ sacs, int S,
-                                                         int round, int key_stride, float dt,
-                                                         const float* __restrict__ proj, const float* centre,
-                                                         const float* hw, const float* lo, const float* hi,
-                                                         const int32_t* __restrict__ status, uint64_t* keys,
-                                                         const int* __restrict__ ord, const int* __restrict__ obase,
-                                                         const uint64_t* __restrict__ costs,
-                                                         const uint32_t* __restrict__ tmin,
-                                                         const uint64_t* __restrict__ smin,
-                                                         const double* __restrict__ qorth, float tau)
+template <int TILE, int UNROLL>
+__global__ __launch_bounds__(64, OPMM_MIN_WAVES) void fit_verify_kernel(
+    const SacDev* __restrict__ sacs, int S, int round, int key_stride, float dt, const float* __restrict__ proj,
+    const float* centre, const float* hw, const float* lo, const float* hi, const int32_t* __restrict__ status,
+    uint64_t* keys, const int* __restrict__ ord, const int* __restrict__ obase, const uint64_t* __restrict__ costs,
+    const uint32_t* __restrict__ tmin, const uint64_t* __restrict__ smin, const double* __restrict__ qorth,
+    float tau)
 {
-    constexpr int TILE = TPB * PASSES, NW = TPB / 64;
-    __shared__ VerifySmem<TPB, PASSES> sm;
-    __shared__ int s_s;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid < 64) {
-        const int sw = saccade_of_tile(sacs, ord, obase, S, blockIdx.x);
-        if (tid == 0) s_s = sw;
-    }
-    __syncthreads();
-    const SacDev sd = sacs[s_s];
+    static_assert(TILE % 64 == 0 && TILE <= 65536, "tile");
+    constexpr int CH = TILE / 64;  // 64-slot chunks of the tile
+    constexpr int PFV = CH < 8 ? CH : 8;  // chunks loaded ahead
+    __shared__ VerifySmem<TILE> sm;
+    const int lane = threadIdx.x;
+    const int s = __builtin_amdgcn_readfirstlane(saccade_of_tile(sacs, ord, obase, S, blockIdx.x));
+    const SacDev sd = sacs[s];
     if (status[sd.slot] & OPMM_ST_NONFINITE_INPUT) return;
-    const int t0 = blockIdx.x - sd.tile_base;
-    if (t0 % VG != 0) return;
-    const int ng = min(VG, sd.tiles - t0);
+    const int t = blockIdx.x - sd.tile_base;
     const int T = sd.T;
     const float fbest = __uint_as_float((uint32_t)(smin[sd.slot] >> 32));
     double thr = __builtin_inf();  // no finite FP32 cost: every candidate is verified
@@ -530,48 +514,36 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_verify_kernel(const S
         const double rm = sqrt(((double)fbest + q) / n) + (double)tau;
         thr = rm * rm * n - q;
     }
-    // a tile whose least FP32 sum misses the threshold has nothing to verify: skip its costs
-    float tm = __builtin_inff();
-    for (int g = 0; g < ng; ++g) tm = fminf(tm, __uint_as_float(tmin[sd.tile_base + t0 + g]));
-    if (!((double)tm <= thr)) return;
-    // compaction in slot order, tile by tile, TPB slots at a time; every load is issued first
-    uint64_t vals[VG * PASSES];
+    if (!((double)__uint_as_float(tmin[sd.tile_base + t]) <= thr)) return;
+    // compaction in slot order, 64 slots at a time, PFV chunks of loads in flight
+    const uint64_t* tc = costs + (int64_t)(sd.tile_base + t) * TILE + lane;
+    uint64_t vals[PFV];
 #pragma unroll
-    for (int c = 0; c < VG * PASSES; ++c)
-        vals[c] = c < ng * PASSES ? costs[(int64_t)(sd.tile_base + t0 + c / PASSES) * TILE + (c % PASSES) * TPB + tid]
-                                  : ~0ull;
+    for (int c = 0; c < PFV; ++c) vals[c] = tc[64 * c];
     int nv = 0;
 #pragma unroll
-    for (int c = 0; c < VG * PASSES; ++c) {
-        const int g = c / PASSES;
-        const uint64_t v = vals[c];
+    for (int c = 0; c < CH; ++c) {
+        const uint64_t v = vals[c % PFV];
+        if (c + PFV < CH) vals[c % PFV] = tc[64 * (c + PFV)];
         const uint32_t j = (uint32_t)v;
         const float f = __uint_as_float((uint32_t)(v >> 32));
         const bool pass = j != 0xFFFFFFFFu && ((double)f <= thr || f != f);
         const uint64_t m = __ballot(pass);
-        if (lane == 0) sm.wcnt[wave] = __popcll(m);
-        __syncthreads();
-        int off = nv, tot = nv;
-        for (int w = 0; w < NW; ++w) {
-            if (w < wave) off += sm.wcnt[w];
-            tot += sm.wcnt[w];
-        }
-        if (pass) sm.list[off + __popcll(m & ((1ull << lane) - 1))] = (uint32_t)(t0 + g) * TILE + j;
-        nv = tot;
-        __syncthreads();
+        if (pass) sm.list[nv + __popcll(m & ((1ull << lane) - 1))] = (uint16_t)j;
+        nv += __popcll(m);
     }
     if (nv == 0) return;
-    for (int k = tid; k < T; k += TPB) sm.r[k] = (R)proj[sd.proj_off + k];
+    for (int k = lane; k < T; k += 64) sm.r[k] = (R)proj[sd.proj_off + k];
     load_box(sm.box, sd.slot, centre, hw, lo, hi);
     __syncthreads();
+    const uint32_t base = (uint32_t)t * TILE;
     uint64_t best = ~0ull;
 #pragma unroll 1
-    for (int i0 = 0; i0 < nv; i0 += TPB) {
+    for (int i0 = 0; i0 < nv; i0 += 64) {
         asm volatile("" ::: "memory");
-        const int i = i0 + tid;
+        const int i = i0 + lane;
         const bool valid = i < nv;
-        if (!__any(valid)) continue;
-        const uint32_t idx = valid ? sm.list[i] : 0u;
+        const uint32_t idx = base + (valid ? (uint32_t)sm.list[i] : 0u);
         float p[P];
         draw_candidate(sd.seed, (uint32_t)round, idx, sm.box, p, sd.model);
         Plant pl;
@@ -590,13 +562,8 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_verify_kernel(const S
         }
     }
     best = wave_min_u64(best);
-    if (lane == 0) sm.red[wave] = best;
-    __syncthreads();
-    if (tid == 0) {
-        for (int w = 1; w < NW; ++w) best = sm.red[w] < best ? sm.red[w] : best;
-        if (best != ~0ull)
-            atomicMin((unsigned long long*)&keys[(int64_t)round * key_stride + sd.slot], (unsigned long long)best);
-    }
+    if (lane == 0 && best != ~0ull)
+        atomicMin((unsigned long long*)&keys[(int64_t)round * key_stride + sd.slot], (unsigned long long)best);
 }
 
 // Every round of every saccade in one launch: a work queue of (round, tile)
@@ -883,7 +850,7 @@ hipError_t launch_screened(const FitLaunch& L, int round, hipStream_t st)
     }
     {
         TimedLaunch tl(L.timer, OPMM_KERNEL_VERIFY, st);
-        hipLaunchKernelGGL((fit_verify_kernel<TPB, PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(TPB), 0, st,
+        hipLaunchKernelGGL((fit_verify_kernel<TPB * PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(64), 0, st,
                            L.sacs, L.S, round, L.key_stride, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status,
                            L.keys, L.ord, L.obase, L.costs, L.tmin, L.smin, L.qorth, L.tau);
     }
