@@ -55,10 +55,6 @@ struct Prec {
     static constexpr int expmv_m = sizeof(RT) == 8 ? 11 : OPMM_F32_EXPMV_M;
     using scalar = RT;  // type of plant_scalars
     using acc = RT;     // type of the squared-residual sum
-#ifndef OPMM_F32_SCALED_HORNER
-#define OPMM_F32_SCALED_HORNER 1
-#endif
-    static constexpr bool scaled_horner = sizeof(RT) == 4 && OPMM_F32_SCALED_HORNER;  // transition_dform_scaled
 };
 
 // Table 1 nominal values, in the table's order and units.  The pulse width
@@ -240,15 +236,16 @@ template <> struct LitT<float> { using type = float; };
 // Horner evaluation of D = sum_{k=1..M} (hA)^k / k! for the augmented block
 // matrix [[Mech, G1, G2], [0, Q1, 0], [0, 0, Q2]] whose off-diagonal blocks
 // give the pulse-piece and post-piece coupling columns at once, on the step
-// h/2^SQ, then SQ squarings in D-form: D_2h = D_h^2 + 2 D_h.
-// FP32 form of the same polynomial without squarings: with B = hA, the Horner iterates scaled as
-// Q_k = c_k P_k, c_M = M, c_k = k c_{k+1}, obey Q_M = M I + B, Q_k = c_k I + B Q_{k+1} (the scaled
-// coefficients are formed once instead of once per step), and D = B Q_2 / M!.
+// h/2^SQ, then SQ squarings in D-form: D_2h = D_h^2 + 2 D_h.  The Horner
+// iterates P_k = I + (B/k) P_{k+1} (B = hA) are carried scaled, Q_k = c_k P_k
+// with c_M = M and c_k = k c_{k+1}: then Q_M = M I + B, Q_k = c_k I + B Q_{k+1}
+// and D = B Q_2 / M!, so the entries of B are formed once instead of once per
+// step (fewer instructions and fewer live registers).
 template <class RT>
-__device__ __forceinline__ void transition_dform_scaled(PlantT<RT>& pl, RT h)
+__device__ __forceinline__ void transition_dform(PlantT<RT>& pl, RT hfull)
 {
-    constexpr int M = Prec<RT>::taylor_m;
-    static_assert(Prec<RT>::taylor_sq == 0, "the scaled form takes no squarings");
+    constexpr int M = Prec<RT>::taylor_m, SQ = Prec<RT>::taylor_sq;
+    const RT h = hfull * (RT(1) / RT(1 << SQ));
     const RT qv[4] = {pl.q1a, pl.q1n, pl.q2a, pl.q2n};
     const RT s10 = pl.a10 * h, s11 = pl.a11 * h, s12 = pl.a12 * h, s13 = pl.a13 * h;
     const RT s20 = pl.a20 * h, s22 = pl.a22 * h, s30 = pl.a30 * h, s33 = pl.a33 * h;
@@ -284,7 +281,7 @@ __device__ __forceinline__ void transition_dform_scaled(PlantT<RT>& pl, RT h)
 #pragma unroll
             for (int c = 0; c < 4; ++c) tq[c] = sq[c];
         } else {
-            const RT f = RT(1) / ck;  // 1 / M! (exact power-of-two-free constant, rounded once)
+            const RT f = RT(1) / ck;  // 1 / M!, rounded once
             one = RT(0);
             t10 = s10 * f; t11 = s11 * f; t12 = s12 * f; t13 = s13 * f;
             t20 = s20 * f; t22 = s22 * f; t30 = s30 * f; t33 = s33 * f;
@@ -306,73 +303,6 @@ __device__ __forceinline__ void transition_dform_scaled(PlantT<RT>& pl, RT h)
             OPMM_MV(t10, t11, t12, t13, t20, t22, t30, t33, tv, px[0][c], px[1][c], px[2][c], px[3][c],
                     nx[0][c], nx[1][c], nx[2][c], nx[3][c], RT(0), RT(0), ga, gn);
             nd[c] = fmr(tq[c], pd[c], one);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) { pm[i][c] = nm[i][c]; px[i][c] = nx[i][c]; }
-            pd[i] = nd[i];
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) pl.m[i][c] = pm[i][c];
-        pl.x1[i][0] = px[i][0]; pl.x1[i][1] = px[i][1];
-        pl.x2[i][0] = px[i][2]; pl.x2[i][1] = px[i][3];
-    }
-    pl.e1[0] = pd[0]; pl.e1[1] = pd[1];
-    pl.e2[0] = pd[2]; pl.e2[1] = pd[3];
-}
-
-template <class RT>
-__device__ __forceinline__ void transition_dform(PlantT<RT>& pl, RT hfull)
-{
-    constexpr int M = Prec<RT>::taylor_m, SQ = Prec<RT>::taylor_sq;
-    const RT h = hfull * (RT(1) / RT(1 << SQ));
-    RT pm[4][4], px[4][4], pd[4];
-    const RT qv[4] = {pl.q1a, pl.q1n, pl.q2a, pl.q2n};
-    {   // P_M = I + hA/M
-        const RT s = h * (RT(1) / RT(M));
-        const RT s10 = pl.a10 * s, s11 = pl.a11 * s, s12 = pl.a12 * s, s13 = pl.a13 * s;
-        const RT s20 = pl.a20 * s, s22 = pl.a22 * s, s30 = pl.a30 * s, s33 = pl.a33 * s;
-        pm[0][0] = RT(1); pm[0][1] = s;    pm[0][2] = RT(0); pm[0][3] = RT(0);
-        pm[1][0] = s10;  pm[1][1] = RT(1) + s11; pm[1][2] = s12; pm[1][3] = s13;
-        pm[2][0] = s20;  pm[2][1] = RT(0); pm[2][2] = RT(1) + s22; pm[2][3] = RT(0);
-        pm[3][0] = s30;  pm[3][1] = RT(0); pm[3][2] = RT(0); pm[3][3] = RT(1) + s33;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            px[0][c] = RT(0); px[1][c] = RT(0);
-            px[2][c] = (c & 1) ? RT(0) : pl.g2 * s;
-            px[3][c] = (c & 1) ? pl.g3 * s : RT(0);
-            pd[c] = fmr(qv[c], s, RT(1));
-        }
-    }
-#pragma unroll
-    for (int k = M - 1; k >= 1; --k) {
-        // k >= 2: P <- I + (h/k) A P ;  k == 1: D <- h A P
-        RT s = (k == 1) ? h : h * (RT(1) / RT(k));
-        // opaque per step: stops the compiler from forming every step's scaled
-        // coefficients up front, which would pin ~10 registers per step
-        asm volatile("" : "+v"(s));
-        const RT one = (k == 1) ? RT(0) : RT(1);
-        const RT s10 = pl.a10 * s, s11 = pl.a11 * s, s12 = pl.a12 * s, s13 = pl.a13 * s;
-        const RT s20 = pl.a20 * s, s22 = pl.a22 * s, s30 = pl.a30 * s, s33 = pl.a33 * s;
-        const RT sg2 = pl.g2 * s, sg3 = pl.g3 * s;
-        RT nm[4][4], nx[4][4], nd[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            OPMM_MV(s10, s11, s12, s13, s20, s22, s30, s33, s, pm[0][c], pm[1][c], pm[2][c], pm[3][c],
-                    nm[0][c], nm[1][c], nm[2][c], nm[3][c],
-                    c == 0 ? one : RT(0), c == 1 ? one : RT(0), c == 2 ? one : RT(0), c == 3 ? one : RT(0));
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const RT ga = (c & 1) ? RT(0) : sg2 * pd[c];
-            const RT gn = (c & 1) ? sg3 * pd[c] : RT(0);
-            OPMM_MV(s10, s11, s12, s13, s20, s22, s30, s33, s, px[0][c], px[1][c], px[2][c], px[3][c],
-                    nx[0][c], nx[1][c], nx[2][c], nx[3][c], RT(0), RT(0), ga, gn);
-            nd[c] = fmr(qv[c] * s, pd[c], one);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -415,6 +345,7 @@ __device__ __forceinline__ void transition_dform(PlantT<RT>& pl, RT hfull)
     pl.e1[0] = pd[0]; pl.e1[1] = pd[1];
     pl.e2[0] = pd[2]; pl.e2[1] = pd[3];
 }
+
 
 // Continuous-time coefficients (per ms) and the statics of candidate p for a
 // saccade of amplitude amp (deg): the matrix entries of the mechanical block,
@@ -497,8 +428,7 @@ __device__ __forceinline__ void plant_setup(const float p[P], float amp, float d
     pl.a20 = (RT)c.a20; pl.a22 = (RT)c.a22; pl.g2 = (RT)c.g2;
     pl.a30 = (RT)c.a30; pl.a33 = (RT)c.a33; pl.g3 = (RT)c.g3;
     pl.q1a = (RT)c.q1a; pl.q1n = (RT)c.q1n; pl.q2a = (RT)c.q2a; pl.q2n = (RT)c.q2n;
-    if constexpr (Prec<RT>::scaled_horner) transition_dform_scaled(pl, (RT)dt);
-    else transition_dform(pl, (RT)dt);
+    transition_dform(pl, (RT)dt);
     pl.th1 = (RT)c.th1;
     pl.amp = amp;
 #pragma unroll
