@@ -484,10 +484,12 @@ __global__ __launch_bounds__(TPB, OPMM_SCREEN_MIN_WAVES) void fit_screen_kernel(
 // left without reading its costs.
 template <int TILE>
 struct VerifySmem {
-    R r[OPMM_MAX_T];
     Box box;
     uint16_t list[TILE];  // survivors' indices in the tile, in slot order
 };
+// The projected trace of the verifying wave's saccade, [max_T] of dynamic LDS (max_T: the batch's
+// longest trace), so that short traces leave room for more waves per CU.
+extern __shared__ R verify_trace[];
 
 template <int TILE, int UNROLL>
 __global__ __launch_bounds__(64, OPMM_MIN_WAVES) void fit_verify_kernel(
@@ -495,7 +497,7 @@ __global__ __launch_bounds__(64, OPMM_MIN_WAVES) void fit_verify_kernel(
     const float* centre, const float* hw, const float* lo, const float* hi, const int32_t* __restrict__ status,
     uint64_t* keys, const int* __restrict__ ord, const int* __restrict__ obase, const uint64_t* __restrict__ costs,
     const uint32_t* __restrict__ tmin, const uint64_t* __restrict__ smin, const double* __restrict__ qorth,
-    float tau)
+    float tau, int max_T)
 {
     static_assert(TILE % 64 == 0 && TILE <= 65536, "tile");
     constexpr int CH = TILE / 64;  // 64-slot chunks of the tile
@@ -504,7 +506,7 @@ __global__ __launch_bounds__(64, OPMM_MIN_WAVES) void fit_verify_kernel(
     const int lane = threadIdx.x;
     const int s = __builtin_amdgcn_readfirstlane(saccade_of_tile(sacs, ord, obase, S, blockIdx.x));
     const SacDev sd = sacs[s];
-    if (status[sd.slot] & OPMM_ST_NONFINITE_INPUT) return;
+    if ((status[sd.slot] & OPMM_ST_NONFINITE_INPUT) || sd.T > max_T) return;  // max_T bounds the trace's LDS
     const int t = blockIdx.x - sd.tile_base;
     const int T = sd.T;
     const float fbest = __uint_as_float((uint32_t)(smin[sd.slot] >> 32));
@@ -533,7 +535,8 @@ __global__ __launch_bounds__(64, OPMM_MIN_WAVES) void fit_verify_kernel(
         nv += __popcll(m);
     }
     if (nv == 0) return;
-    for (int k = lane; k < T; k += 64) sm.r[k] = (R)proj[sd.proj_off + k];
+    R* const r = verify_trace;
+    for (int k = lane; k < T; k += 64) r[k] = (R)proj[sd.proj_off + k];
     load_box(sm.box, sd.slot, centre, hw, lo, hi);
     __syncthreads();
     const uint32_t base = (uint32_t)t * TILE;
@@ -554,7 +557,7 @@ __global__ __launch_bounds__(64, OPMM_MIN_WAVES) void fit_verify_kernel(
         int kmax = wave_max(valid ? k0 : -0x7FFFFFFF);
         kmin = __builtin_amdgcn_readfirstlane(kmin);
         kmax = __builtin_amdgcn_readfirstlane(kmax);
-        SseSink sink{sm.r, 0.0};
+        SseSink sink{r, 0.0};
         if (valid) {
             run_trajectory<UNROLL>(pl, T, (R)dt, k0, frac, kmin, kmax, sink);
             const uint64_t key = cost_key(sink.sse, idx);
@@ -801,6 +804,7 @@ struct FitLaunch {
     // screened rounds: FP32 costs of every candidate, FP32 best per saccade, orthogonal energies
     uint64_t* costs;  // [tiles_per_round * tile]: FP32 cost and index of every slot (process_tile)
     uint32_t* tmin;   // [tiles_per_round]: least FP32 cost of each tile (process_tile)
+    int max_T;        // longest trace of the batch (0: unknown, OPMM_MAX_T assumed)
     uint64_t* smin;   // [S]: FP32 best key per saccade
     const double* qorth;
     float tau;
@@ -850,9 +854,11 @@ hipError_t launch_screened(const FitLaunch& L, int round, hipStream_t st)
     }
     {
         TimedLaunch tl(L.timer, OPMM_KERNEL_VERIFY, st);
-        hipLaunchKernelGGL((fit_verify_kernel<TPB * PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(64), 0, st,
-                           L.sacs, L.S, round, L.key_stride, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status,
-                           L.keys, L.ord, L.obase, L.costs, L.tmin, L.smin, L.qorth, L.tau);
+        const int max_T = L.max_T > 0 && L.max_T <= OPMM_MAX_T ? L.max_T : OPMM_MAX_T;
+        hipLaunchKernelGGL((fit_verify_kernel<TPB * PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(64),
+                           sizeof(R) * (size_t)max_T, st, L.sacs, L.S, round, L.key_stride, L.dt, L.proj, L.centre,
+                           L.hw, L.lo, L.hi, L.status, L.keys, L.ord, L.obase, L.costs, L.tmin, L.smin, L.qorth,
+                           L.tau, max_T);
     }
     return hipGetLastError();
 }
@@ -937,6 +943,7 @@ struct DevBuf {
 struct FitScratch {
     DevBuf sacs, proj, qorth, box, keys, status, counters, order;
     DevBuf costs, tmin, smin;  // screened rounds (see FitBufs)
+    int max_T = 0;             // longest trace of the last uploaded batch
     // Pinned host staging of the record upload (records, then dispatch order and tile bases), kept
     // between calls: the upload is a direct DMA and no batch pays for fresh pages.
     DevBuf stage;
@@ -1214,6 +1221,7 @@ int upload_saccades(opmm_ctx* ctx, FitScratch& sc, const opmm_saccade* sacs, int
     int64_t toff, tiles;
     build_records(sacs, S, prm, tile_size, h, ob, sc.h_count.data(), &toff, &tiles);
     if (tiles > 0x7FFFFFFF / 8) return fail(ctx, OPMM_EINVAL, "too many candidate tiles in one batch");
+    sc.max_T = S > 0 ? sacs[ob[0]].T : 0;  // the dispatch order is longest trace first
     if ((rc = ensure(ctx, sc.sacs, rec_bytes)) != OPMM_OK) return rc;
     if ((rc = ensure(ctx, sc.order, ord_bytes)) != OPMM_OK) return rc;
     OPMM_HIP(ctx, hipMemcpyAsync(sc.sacs.p, h, rec_bytes, hipMemcpyHostToDevice, st));
@@ -1241,6 +1249,7 @@ struct FitBufs {
     uint64_t* costs = nullptr;
     uint32_t* tmin = nullptr;
     uint64_t* smin = nullptr;
+    int max_T = 0;  // longest trace (0: unknown)
 };
 
 int enqueue_fit_bufs(opmm_ctx* ctx, const FitBufs& B, const float* pos, int S, int tiles_per_round,
@@ -1281,6 +1290,7 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
         if ((rc = ensure(ctx, sc.smin, sizeof(uint64_t) * (size_t)S)) != OPMM_OK) return rc;
         B.costs = (uint64_t*)sc.costs.p;
         B.tmin = (uint32_t*)sc.tmin.p;
+        B.max_T = sc.max_T;
         B.smin = (uint64_t*)sc.smin.p;
     }
     return enqueue_fit_bufs(ctx, B, pos, S, tiles_per_round, prm, shape, seed_opc, opc_out, rmse_out, mae_out,
@@ -1327,6 +1337,7 @@ int enqueue_fit_bufs(opmm_ctx* ctx, const FitBufs& B, const float* pos, int S, i
     L.wait_limit = ctx->wait_limit;
     L.costs = B.costs;
     L.tmin = B.tmin;
+    L.max_T = B.max_T;
     L.smin = B.smin;
     L.qorth = qorth;
     L.tau = prm->screen_tol;
