@@ -150,3 +150,26 @@ def test_screening_error_below_half_tolerance(ctx, opmm):
     print("screening error per round (max over saccades):", " ".join("%.2e" % e for e in eps.max(axis=0)))
     tau = opmm.fit_params().screen_tol
     assert np.all(np.isfinite(eps)) and eps.max() <= tau / 2, eps.max()
+
+
+def test_screened_longest_traces_equal_fp64(ctx, opmm):
+    """Traces up to the longest the library accepts (the verify wave's trace in dynamic LDS is sized
+    to the batch's longest trace): a screened fit of three saccades with T = 2048, 700 and 90 equals
+    the FP64-only fit bit for bit, alone and with the longest trace absent from the batch."""
+    b = synth.draw_saccades(3, "full", seed=synth.BASE_SEED + 31)
+    b["amp"], b["dir_deg"], b["dur_ms"] = (np.asarray(b[k], np.float32) for k in ("amp", "dir_deg", "dur_ms"))
+    b["T"] = np.array([opmm.MAX_T, 700, 90])
+    rng = np.random.default_rng(31)
+    traces = []
+    for i in range(3):
+        p = oracle.true_opc(b["mult"][i], b["dur_ms"][i])
+        z = rng.standard_normal((int(b["T"][i]), b["C"]))
+        traces.append(oracle.make_target(p, b["amp"][i], b["dir_deg"][i], int(b["T"][i]), b["C"], z,
+                                         b["sigma"][i]))
+    for keep in ([0, 1, 2], [1, 2]):
+        bb = {k: (v[keep] if isinstance(v, np.ndarray) and v.shape[:1] == (3,) else v) for k, v in b.items()}
+        bb["S"] = len(keep)
+        tr = [traces[i] for i in keep]
+        ref = fit(ctx, opmm, bb, tr, opmm.fit_params(n_cand=4096, n_rounds=4))
+        got = fit(ctx, opmm, bb, tr, opmm.fit_params(n_cand=4096, n_rounds=4, screen_rounds=4))
+        same(got, ref, ("longest traces", keep))
