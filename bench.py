@@ -106,11 +106,17 @@ KERNEL_SOURCES = ("paper_2007_09884_amd/csrc/plant.hpp", "paper_2007_09884_amd/c
 
 
 def sources_digest():
+    """SHA-256 of the kernel sources with their comments removed: a counter summary stays valid across
+    comment edits and goes stale with any change to the code."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update(text.encode())
     return h.hexdigest()
 
 

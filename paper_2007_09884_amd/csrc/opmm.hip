@@ -445,8 +445,8 @@ __global__ __launch_bounds__(TPB, OPMM_MIN_WAVES) void fit_round_kernel(const Sa
 
 // Screened round, first pass: the round's tiles with the recurrence in FP32.  Every candidate's
 // squared-residual sum goes to costs; each saccade's FP32 best key to smin[slot].
-// The FP32 pass needs ~172 registers as compiled for 2 waves per SIMD; held to 168 it runs 3 (one
-// spilled register) and took 14.3-14.4 instead of 15.4 ms per full-estimation step (4 waves: 14.5).
+// With its FP32 setup and the scaled Horner transition the FP32 pass needs 125 registers, so 4
+// waves fit per SIMD; the bound only caps it at 168 (3 waves).  A 5-wave bound spills 23 registers.
 #ifndef OPMM_SCREEN_MIN_WAVES
 #define OPMM_SCREEN_MIN_WAVES 3
 #endif
