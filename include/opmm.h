@@ -135,13 +135,15 @@ typedef struct {
                             and the neural parameters (tau_AC/DE, N_SAC, PW)
                             held at nominal (half-width 0)                   */
     int32_t screen_rounds; /* rounds 0..screen_rounds-1 are screened: every
-                            candidate is simulated with an FP32 recurrence,
-                            and only those whose FP32 RMSE lies within
-                            screen_tol of the round's FP32 best are simulated
-                            again in FP64, which decides the argmin.  The
-                            winner is the FP64 argmin whenever the FP32 RMSE
-                            errors stay below screen_tol / 2 (measured: below
-                            4.4e-6 deg).  0 = every round in FP64 only.
+                            candidate is simulated with an FP32 recurrence;
+                            the FP32 best b is simulated again in FP64, and
+                            only the candidates whose FP32 RMSE is at most
+                            RMSE64(b) + screen_tol / 2 are simulated again
+                            in FP64, which decides the argmin.  The winner
+                            is the FP64 argmin whenever the FP32 RMSE
+                            errors stay below screen_tol / 2 (measured:
+                            below 8.6e-6 deg; opmm_score_screen measures
+                            them).  0 = every round in FP64 only.
                             Per-round mode only; 0..n_rounds           [0]   */
     float screen_tol;    /* deg of RMSE, > 0                         [5e-5]  */
 } opmm_fit_params;

@@ -474,14 +474,68 @@ __global__ __launch_bounds__(TPB, OPMM_SCREEN_MIN_WAVES) void fit_screen_kernel(
     if (threadIdx.x == 0 && best != ~0ull) atomicMin((unsigned long long*)&smin[sd.slot], (unsigned long long)best);
 }
 
+// Screened round, between the passes: one lane per saccade re-simulates the FP32 pass's best
+// candidate b in FP64, exactly as the round kernel would, and sets the verify threshold in SSE
+// terms: FP32 RMSE <= RMSE64(b) + tau / 2.  The FP64 argmin x* passes it whenever the FP32 error
+// eps stays below tau / 2: RMSE32(x*) <= RMSE64(x*) + eps <= RMSE64(b) + eps.  (With the FP32 best
+// itself as the anchor the bound would need RMSE32(b) + 2 eps, a threshold about tau / 2 wider.)
+struct GlobalTraceSink {  // squared residual against the projected trace read from global memory
+    const float* r;
+    double sse;
+    __device__ __forceinline__ void operator()(int k, R dth, R theq)
+    {
+        R e = ((R)r[k] - theq) - dth;
+        sse = fmr(e, e, sse);
+    }
+};
+
+__global__ __launch_bounds__(64) void screen_anchor_kernel(int S, const SacDev* __restrict__ sacs, int round,
+                                                           float dt, const float* __restrict__ proj,
+                                                           const float* centre, const float* hw, const float* lo,
+                                                           const float* hi, const int32_t* __restrict__ status,
+                                                           const double* __restrict__ qorth,
+                                                           const uint64_t* __restrict__ smin, float tau,
+                                                           double* __restrict__ thr)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S) return;
+    const SacDev sd = sacs[s];
+    const int slot = sd.slot;
+    const uint64_t key = smin[slot];
+    const float fbest = __uint_as_float((uint32_t)(key >> 32));
+    double t = __builtin_inf();  // no finite FP32 cost: every candidate is verified
+    if (!(status[slot] & OPMM_ST_NONFINITE_INPUT) && fbest <= 3.402823466e38f) {
+        Box b;
+        for (int j = 0; j < P; ++j) {
+            b.c[j] = centre[slot * P + j];
+            b.w[j] = hw[slot * P + j];
+            b.lo[j] = lo[slot * P + j];
+            b.hi[j] = hi[slot * P + j];
+        }
+        const uint32_t idx = (uint32_t)key;
+        float p[P];
+        draw_candidate(sd.seed, (uint32_t)round, idx, b, p, sd.model);
+        Plant pl;
+        plant_setup(p, sd.amp, dt, pl);
+        R frac;
+        const int k0 = pulse_end_sample(pl.pwd, sd.T, frac);
+        GlobalTraceSink sink{proj + sd.proj_off, 0.0};
+        run_trajectory<1>(pl, sd.T, (R)dt, k0, frac, k0, k0, sink);
+        const double n = (double)sd.T * sd.C, q = qorth[slot];
+        const double rm = sqrt((sink.sse + q) / n) + 0.5 * (double)tau;
+        if (rm <= 1e300) t = rm * rm * n - q;  // a non-finite anchor leaves every candidate to verify
+    }
+    thr[slot] = t;
+}
+
 // Screened round, second pass, one wave per tile (a tile's survivors are often fewer than one
 // block's lanes, and a one-wave block leaves no wave of it idle).  The tile's candidates whose FP32
 // RMSE lies within tau of the saccade's FP32 best (or is NaN) are simulated again exactly as the FP64
 // round kernel simulates them, in the first pass's pulse-end order, and their FP64 keys go to
-// keys[round][slot].  The FP32 best key fixes the threshold: with n = T C samples and Q the
+// keys[round][slot].  The threshold comes from screen_anchor_kernel: with n = T C samples and Q the
 // orthogonal energy, RMSE = sqrt((SSE + Q) / n), so a candidate passes when its FP32 SSE <=
-// (RMSE_best + tau)^2 n - Q.  A tile whose least FP32 SSE (tmin, 0 when one is NaN) misses that is
-// left without reading its costs.
+// (RMSE64(b) + tau / 2)^2 n - Q.  A tile whose least FP32 SSE (tmin, 0 when one is NaN) misses that
+// is left without reading its costs.
 template <int TILE>
 struct VerifySmem {
     Box box;
@@ -496,8 +550,7 @@ __global__ __launch_bounds__(64, OPMM_MIN_WAVES) void fit_verify_kernel(
     const SacDev* __restrict__ sacs, int S, int round, int key_stride, float dt, const float* __restrict__ proj,
     const float* centre, const float* hw, const float* lo, const float* hi, const int32_t* __restrict__ status,
     uint64_t* keys, const int* __restrict__ ord, const int* __restrict__ obase, const uint64_t* __restrict__ costs,
-    const uint32_t* __restrict__ tmin, const uint64_t* __restrict__ smin, const double* __restrict__ qorth,
-    float tau, int max_T)
+    const uint32_t* __restrict__ tmin, const double* __restrict__ vthr, int max_T)
 {
     static_assert(TILE % 64 == 0 && TILE <= 65536, "tile");
     constexpr int CH = TILE / 64;  // 64-slot chunks of the tile
@@ -509,13 +562,7 @@ __global__ __launch_bounds__(64, OPMM_MIN_WAVES) void fit_verify_kernel(
     if ((status[sd.slot] & OPMM_ST_NONFINITE_INPUT) || sd.T > max_T) return;  // max_T bounds the trace's LDS
     const int t = blockIdx.x - sd.tile_base;
     const int T = sd.T;
-    const float fbest = __uint_as_float((uint32_t)(smin[sd.slot] >> 32));
-    double thr = __builtin_inf();  // no finite FP32 cost: every candidate is verified
-    if (fbest <= 3.402823466e38f) {
-        const double n = (double)T * sd.C, q = qorth[sd.slot];
-        const double rm = sqrt(((double)fbest + q) / n) + (double)tau;
-        thr = rm * rm * n - q;
-    }
+    const double thr = vthr[sd.slot];
     if (!((double)__uint_as_float(tmin[sd.tile_base + t]) <= thr)) return;
     // compaction in slot order, 64 slots at a time, PFV chunks of loads in flight
     const uint64_t* tc = costs + (int64_t)(sd.tile_base + t) * TILE + lane;
@@ -806,6 +853,7 @@ struct FitLaunch {
     uint32_t* tmin;   // [tiles_per_round]: least FP32 cost of each tile (process_tile)
     int max_T;        // longest trace of the batch (0: unknown, OPMM_MAX_T assumed)
     uint64_t* smin;   // [S]: FP32 best key per saccade
+    double* vthr;     // [S]: verify threshold per saccade (SSE units, screen_anchor_kernel)
     const double* qorth;
     float tau;
     KernelTimer* timer;  // non-null: record an event pair around each search-kernel launch
@@ -852,13 +900,14 @@ hipError_t launch_screened(const FitLaunch& L, int round, hipStream_t st)
                            L.sacs, L.S, round, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status, L.ord, L.obase,
                            L.costs, L.tmin, L.smin);
     }
+    hipLaunchKernelGGL(screen_anchor_kernel, dim3((L.S + 63) / 64), dim3(64), 0, st, L.S, L.sacs, round, L.dt,
+                       L.proj, L.centre, L.hw, L.lo, L.hi, L.status, L.qorth, L.smin, L.tau, L.vthr);
     {
         TimedLaunch tl(L.timer, OPMM_KERNEL_VERIFY, st);
         const int max_T = L.max_T > 0 && L.max_T <= OPMM_MAX_T ? L.max_T : OPMM_MAX_T;
         hipLaunchKernelGGL((fit_verify_kernel<TPB * PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(64),
                            sizeof(R) * (size_t)max_T, st, L.sacs, L.S, round, L.key_stride, L.dt, L.proj, L.centre,
-                           L.hw, L.lo, L.hi, L.status, L.keys, L.ord, L.obase, L.costs, L.tmin, L.smin, L.qorth,
-                           L.tau, max_T);
+                           L.hw, L.lo, L.hi, L.status, L.keys, L.ord, L.obase, L.costs, L.tmin, L.vthr, max_T);
     }
     return hipGetLastError();
 }
@@ -942,7 +991,7 @@ struct DevBuf {
 
 struct FitScratch {
     DevBuf sacs, proj, qorth, box, keys, status, counters, order;
-    DevBuf costs, tmin, smin;  // screened rounds (see FitBufs)
+    DevBuf costs, tmin, smin, vthr;  // screened rounds (see FitBufs)
     int max_T = 0;             // longest trace of the last uploaded batch
     // Pinned host staging of the record upload (records, then dispatch order and tile bases), kept
     // between calls: the upload is a direct DMA and no batch pays for fresh pages.
@@ -950,7 +999,7 @@ struct FitScratch {
     std::vector<int> h_count;
     ~FitScratch()
     {
-        for (DevBuf* b : {&sacs, &proj, &qorth, &box, &keys, &status, &counters, &order, &costs, &tmin, &smin})
+        for (DevBuf* b : {&sacs, &proj, &qorth, &box, &keys, &status, &counters, &order, &costs, &tmin, &smin, &vthr})
             if (b->p) (void)hipFree(b->p);
         if (stage.p) (void)hipHostFree(stage.p);
     }
@@ -1249,6 +1298,7 @@ struct FitBufs {
     uint64_t* costs = nullptr;
     uint32_t* tmin = nullptr;
     uint64_t* smin = nullptr;
+    double* vthr = nullptr;  // verify threshold per saccade [S]
     int max_T = 0;  // longest trace (0: unknown)
 };
 
@@ -1288,8 +1338,10 @@ int enqueue_fit(opmm_ctx* ctx, FitScratch& sc, const float* pos, int S, int64_t 
         if ((rc = ensure(ctx, sc.costs, sizeof(uint64_t) * slots)) != OPMM_OK) return rc;
         if ((rc = ensure(ctx, sc.tmin, sizeof(uint32_t) * (size_t)tiles_per_round)) != OPMM_OK) return rc;
         if ((rc = ensure(ctx, sc.smin, sizeof(uint64_t) * (size_t)S)) != OPMM_OK) return rc;
+        if ((rc = ensure(ctx, sc.vthr, sizeof(double) * (size_t)S)) != OPMM_OK) return rc;
         B.costs = (uint64_t*)sc.costs.p;
         B.tmin = (uint32_t*)sc.tmin.p;
+        B.vthr = (double*)sc.vthr.p;
         B.max_T = sc.max_T;
         B.smin = (uint64_t*)sc.smin.p;
     }
@@ -1337,6 +1389,7 @@ int enqueue_fit_bufs(opmm_ctx* ctx, const FitBufs& B, const float* pos, int S, i
     L.wait_limit = ctx->wait_limit;
     L.costs = B.costs;
     L.tmin = B.tmin;
+    L.vthr = B.vthr;
     L.max_T = B.max_T;
     L.smin = B.smin;
     L.qorth = qorth;
@@ -1360,7 +1413,7 @@ int enqueue_fit_bufs(opmm_ctx* ctx, const FitBufs& B, const float* pos, int S, i
         } else {
             for (int r = 0; r < R; ++r) {
                 if (r < prm->screen_rounds) {
-                    if (!B.costs || !B.tmin || !B.smin)
+                    if (!B.costs || !B.tmin || !B.smin || !B.vthr)
                         return fail(ctx, OPMM_EINVAL, "screened rounds need their buffers");
                     hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks_for(S, 256)), dim3(256), 0, st, B.smin, (int64_t)S,
                                        ~0ull);
