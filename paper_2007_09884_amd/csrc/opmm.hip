@@ -474,58 +474,47 @@ __global__ __launch_bounds__(TPB, OPMM_SCREEN_MIN_WAVES) void fit_screen_kernel(
     if (threadIdx.x == 0 && best != ~0ull) atomicMin((unsigned long long*)&smin[sd.slot], (unsigned long long)best);
 }
 
-// Screened round, between the passes: one lane per saccade re-simulates the FP32 pass's best
-// candidate b in FP64, exactly as the round kernel would, and sets the verify threshold in SSE
-// terms: FP32 RMSE <= RMSE64(b) + tau / 2.  The FP64 argmin x* passes it whenever the FP32 error
-// eps stays below tau / 2: RMSE32(x*) <= RMSE64(x*) + eps <= RMSE64(b) + eps.  (With the FP32 best
-// itself as the anchor the bound would need RMSE32(b) + 2 eps, a threshold about tau / 2 wider.)
-struct GlobalTraceSink {  // squared residual against the projected trace read from global memory
-    const float* r;
-    double sse;
-    __device__ __forceinline__ void operator()(int k, R dth, R theq)
-    {
-        R e = ((R)r[k] - theq) - dth;
-        sse = fmr(e, e, sse);
-    }
-};
+// Screened round, between the passes: one wave per saccade stages the trace in LDS, and its first
+// lane re-simulates the FP32 pass's best candidate b in FP64, exactly as the round kernel would, and
+// sets the verify threshold in SSE terms: FP32 RMSE <= RMSE64(b) + tau / 2.  The FP64 argmin x*
+// passes it whenever the FP32 error eps stays below tau / 2: RMSE32(x*) <= RMSE64(x*) + eps <=
+// RMSE64(b) + eps.  (With the FP32 best itself as the anchor the bound would need RMSE32(b) +
+// 2 eps, a threshold about tau / 2 wider.)  The trace sits in dynamic LDS of max_T doubles.
+extern __shared__ R anchor_trace[];
 
-__global__ __launch_bounds__(64) void screen_anchor_kernel(int S, const SacDev* __restrict__ sacs, int round,
-                                                           float dt, const float* __restrict__ proj,
-                                                           const float* centre, const float* hw, const float* lo,
-                                                           const float* hi, const int32_t* __restrict__ status,
+__global__ __launch_bounds__(64) void screen_anchor_kernel(const SacDev* __restrict__ sacs, int round, float dt,
+                                                           const float* __restrict__ proj, const float* centre,
+                                                           const float* hw, const float* lo, const float* hi,
+                                                           const int32_t* __restrict__ status,
                                                            const double* __restrict__ qorth,
-                                                           const uint64_t* __restrict__ smin, float tau,
+                                                           const uint64_t* __restrict__ smin, float tau, int max_T,
                                                            double* __restrict__ thr)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S) return;
-    const SacDev sd = sacs[s];
+    __shared__ Box box;
+    const SacDev sd = sacs[blockIdx.x];
     const int slot = sd.slot;
     const uint64_t key = smin[slot];
     const float fbest = __uint_as_float((uint32_t)(key >> 32));
-    double t = __builtin_inf();  // no finite FP32 cost: every candidate is verified
-    if (!(status[slot] & OPMM_ST_NONFINITE_INPUT) && fbest <= 3.402823466e38f) {
-        Box b;
-        for (int j = 0; j < P; ++j) {
-            b.c[j] = centre[slot * P + j];
-            b.w[j] = hw[slot * P + j];
-            b.lo[j] = lo[slot * P + j];
-            b.hi[j] = hi[slot * P + j];
-        }
-        const uint32_t idx = (uint32_t)key;
-        float p[P];
-        draw_candidate(sd.seed, (uint32_t)round, idx, b, p, sd.model);
-        Plant pl;
-        plant_setup(p, sd.amp, dt, pl);
-        R frac;
-        const int k0 = pulse_end_sample(pl.pwd, sd.T, frac);
-        GlobalTraceSink sink{proj + sd.proj_off, 0.0};
-        run_trajectory<1>(pl, sd.T, (R)dt, k0, frac, k0, k0, sink);
-        const double n = (double)sd.T * sd.C, q = qorth[slot];
-        const double rm = sqrt((sink.sse + q) / n) + 0.5 * (double)tau;
-        if (rm <= 1e300) t = rm * rm * n - q;  // a non-finite anchor leaves every candidate to verify
+    if ((status[slot] & OPMM_ST_NONFINITE_INPUT) || !(fbest <= 3.402823466e38f) || sd.T > max_T) {
+        if (threadIdx.x == 0) thr[slot] = __builtin_inf();  // every candidate is verified
+        return;
     }
-    thr[slot] = t;
+    R* const r = anchor_trace;
+    for (int k = threadIdx.x; k < sd.T; k += 64) r[k] = (R)proj[sd.proj_off + k];
+    load_box(box, slot, centre, hw, lo, hi);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    float p[P];
+    draw_candidate(sd.seed, (uint32_t)round, (uint32_t)key, box, p, sd.model);
+    Plant pl;
+    plant_setup(p, sd.amp, dt, pl);
+    R frac;
+    const int k0 = pulse_end_sample(pl.pwd, sd.T, frac);
+    SseSink sink{r, 0.0};
+    run_trajectory<1>(pl, sd.T, (R)dt, k0, frac, k0, k0, sink);
+    const double n = (double)sd.T * sd.C, q = qorth[slot];
+    const double rm = sqrt((sink.sse + q) / n) + 0.5 * (double)tau;
+    thr[slot] = rm <= 1e300 ? rm * rm * n - q : __builtin_inf();  // a non-finite anchor verifies all
 }
 
 // Screened round, second pass, one wave per tile (a tile's survivors are often fewer than one
@@ -900,11 +889,11 @@ hipError_t launch_screened(const FitLaunch& L, int round, hipStream_t st)
                            L.sacs, L.S, round, L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status, L.ord, L.obase,
                            L.costs, L.tmin, L.smin);
     }
-    hipLaunchKernelGGL(screen_anchor_kernel, dim3((L.S + 63) / 64), dim3(64), 0, st, L.S, L.sacs, round, L.dt,
-                       L.proj, L.centre, L.hw, L.lo, L.hi, L.status, L.qorth, L.smin, L.tau, L.vthr);
+    const int max_T = L.max_T > 0 && L.max_T <= OPMM_MAX_T ? L.max_T : OPMM_MAX_T;
+    hipLaunchKernelGGL(screen_anchor_kernel, dim3(L.S), dim3(64), sizeof(R) * (size_t)max_T, st, L.sacs, round,
+                       L.dt, L.proj, L.centre, L.hw, L.lo, L.hi, L.status, L.qorth, L.smin, L.tau, max_T, L.vthr);
     {
         TimedLaunch tl(L.timer, OPMM_KERNEL_VERIFY, st);
-        const int max_T = L.max_T > 0 && L.max_T <= OPMM_MAX_T ? L.max_T : OPMM_MAX_T;
         hipLaunchKernelGGL((fit_verify_kernel<TPB * PASSES, UNROLL>), dim3(L.tiles_per_round), dim3(64),
                            sizeof(R) * (size_t)max_T, st, L.sacs, L.S, round, L.key_stride, L.dt, L.proj, L.centre,
                            L.hw, L.lo, L.hi, L.status, L.keys, L.ord, L.obase, L.costs, L.tmin, L.vthr, max_T);
