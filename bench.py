@@ -180,7 +180,7 @@ def surrogate_leg(a, ctx, opmm, torch, synth, keep=False):
     train_s = time.perf_counter() - t0
     # the training kernels' share of the BF16 MFMA peak: forward + backward of one generated batch (one fused
     # kernel for the forward pass, the loss and the input gradients, one for the four layers' weight
-    # gradients, plus the loss reset), timed with HIP events
+    # gradients; the loss is not returned, so not reset), timed with HIP events
     feat = torch.empty(B, 256, dtype=torch.int16, device="cuda")
     target = torch.empty(B, 18, dtype=torch.float32, device="cuda")
     sg.generate(1, 0, feat, target)

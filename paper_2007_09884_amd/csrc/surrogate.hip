@@ -376,7 +376,7 @@ __global__ __launch_bounds__(FTHREADS) void mlp_pass_kernel(MlpArgs A)
 
 constexpr int DBM = 64, DBN = 64, DW_BK = 32, DROW = DW_BK + 8;
 constexpr int DW_CH = DBM * DW_BK / 8 / 256;  // 16-byte chunks per thread and operand tile
-constexpr int DW_SLICES = 8;                  // partial gradient slices (split-K over the batch)
+constexpr int DW_SLICES = 8;                  // partial gradient slices (split-K over the batch; 4 and 16 were slower)
 constexpr int DW_TILES[NL] = {(256 / 64) * (512 / 64), (512 / 64) * (512 / 64), (512 / 64) * (256 / 64),
                               (256 / 64) * 1};
 constexpr int DW_BLOCKS = DW_TILES[0] + DW_TILES[1] + DW_TILES[2] + DW_TILES[3];
@@ -1011,7 +1011,8 @@ int opmm_surrogate_backward(opmm_surrogate* sg, const uint16_t* feat, const floa
     SG_HIP(ord.error());
     int rc;
     if ((rc = sg_alloc(sg, B)) != OPMM_OK) return rc;
-    hipLaunchKernelGGL(fill_f32_kernel, dim3(1), dim3(64), 0, st, sg->loss, 1, 0.0f);
+    // the pass adds the batch's loss into sg->loss, which only a call that returns it reads: reset it then
+    if (loss_out) hipLaunchKernelGGL(fill_f32_kernel, dim3(1), dim3(64), 0, st, sg->loss, 1, 0.0f);
     if ((rc = sg_step<false>(sg, B, feat, target, sg->loss, 0.0f, st)) != OPMM_OK) return rc;
     if (loss_out) {
         SG_HIP(hipMemcpyAsync(loss_out, sg->loss, sizeof(float), hipMemcpyDeviceToHost, st));
