@@ -80,7 +80,8 @@ enum {
 enum {
     OPMM_KERNEL_ROUND = 0,       /* one FP64 round of every tile (per-round mode)       */
     OPMM_KERNEL_SCREEN = 1,      /* FP32 pass of a screened round                       */
-    OPMM_KERNEL_VERIFY = 2,      /* FP64 re-simulation of a screened round's survivors  */
+    OPMM_KERNEL_VERIFY = 2,      /* FP64 re-simulation of a screened round's survivors
+                                    (the FP64 anchor launch before it is not timed)     */
     OPMM_KERNEL_PERSISTENT = 3,  /* the work-queue launch of a persistent fit           */
     OPMM_KERNEL_KINDS = 4
 };
