@@ -94,7 +94,7 @@ __device__ __forceinline__ int acc_row(int j, int lane) { return 8 * (j >> 2) + 
 // A ring is started, i.e. its first PF fragments requested, before the product that uses it, so a
 // layer's first loads overlap the previous layer's epilogue and barrier.
 #ifndef OPMM_MLP_PF
-#define OPMM_MLP_PF 8  // contraction steps of B fragments in flight per product
+#define OPMM_MLP_PF 4  // contraction steps of B fragments in flight per product (2, 3, 6, 8, 16: slower)
 #endif
 
 template <int KC, int NT>
