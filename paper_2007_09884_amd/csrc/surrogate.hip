@@ -374,7 +374,7 @@ __global__ __launch_bounds__(FTHREADS) void mlp_pass_kernel(MlpArgs A)
 // bias gradient.
 // ---------------------------------------------------------------------------
 
-constexpr int DBM = 64, DBN = 64, DW_BK = 32, DROW = DW_BK + 8;
+constexpr int DBM = 64, DBN = 64, DW_BK = 32, DROW = DW_BK + 8;  // batch rows per step (64: slower)
 constexpr int DW_CH = DBM * DW_BK / 8 / 256;  // 16-byte chunks per thread and operand tile
 constexpr int DW_SLICES = 8;                  // partial gradient slices (split-K over the batch; 4 and 16 were slower)
 constexpr int DW_TILES[NL] = {(256 / 64) * (512 / 64), (512 / 64) * (512 / 64), (512 / 64) * (256 / 64),
@@ -417,7 +417,7 @@ __device__ __forceinline__ void dw_load(const uint16_t* __restrict__ X, int64_t 
         const int r = c / (DW_BK / 8), q = (c % (DW_BK / 8)) * 8;
         const int seg = seg0 + step;
         v[j] = (o0 + r < O && seg < seg_end)
-                   ? *reinterpret_cast<const u32x4_t*>(X + (int64_t)(o0 + r) * ld + 32 * seg + q)
+                   ? *reinterpret_cast<const u32x4_t*>(X + (int64_t)(o0 + r) * ld + DW_BK * seg + q)
                    : u32x4_t{0u, 0u, 0u, 0u};
     }
 }
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(256) void mlp_dw_kernel(int Bp, DwOperands ops, flo
     const uint16_t* G = ops.gt[l];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const int nseg_all = Bp / 32;                        // 32-row segments of the batch
+    const int nseg_all = Bp / DW_BK;                     // DW_BK-row segments of the batch
     const int per = (nseg_all + DW_SLICES - 1) / DW_SLICES;  // segments per slice
     const int seg0 = x * per, seg_end = min(nseg_all, seg0 + per);
     const int nsteps = max(0, seg_end - seg0);
